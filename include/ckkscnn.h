@@ -1,0 +1,168 @@
+/*
+ * ckkscnn.h -- C-ABI of the gfx950 leveled RNS-CKKS evaluator for private CNN
+ * inference with quadratic activations (arXiv 2509.22857).
+ *
+ * The problem statement (paper Section 2.1, Threat Model): a client holds an
+ * input image and the CKKS secret key, encrypts the image and sends only the
+ * ciphertext; the server holds a CNN with plaintext parameters, evaluates it
+ * under leveled FHE without bootstrapping, and returns encrypted logits that
+ * only the client decrypts.  The scheme is RNS-CKKS (Section 2.2): ring
+ * Z_Q[X]/(X^N+1), Q = q_0 ... q_L as 64-bit RNS words, a special modulus P for
+ * hybrid key switching, scale Delta, rescaling that drops one modulus.
+ *
+ * Conventions for every function below:
+ *  - Return value: CKC_OK (0) or a negative error code.  On error the outputs
+ *    are unspecified, the inputs are untouched, and ckc_last_error() returns a
+ *    message (per thread).  Nothing throws across the ABI.
+ *  - Ciphertext and plaintext buffers (ckc_ct.d, ckc_pt.d) are DEVICE memory
+ *    owned by the caller, sized with ckc_ct_words / ckc_pt_words.  Layout is
+ *    limb-major: [npoly][level+1][N] uint64, limb l reduced modulo q_l, every
+ *    limb in NTT form (the library's evaluation order; use ckc_ntt with
+ *    inverse=1 to obtain coefficient form).
+ *  - Host arrays passed in are read before the call returns.
+ *  - `stream` is a hipStream_t (may be NULL for the default stream).  All
+ *    work is enqueued asynchronously on it unless a function says otherwise.
+ *  - Handles (ckc_ctx, ckc_sk, ckc_evk, ckc_layer) are owned by the library
+ *    and freed by their *_destroy function.  ctx, evk and layers are
+ *    read-only after creation, so calls on different streams may share them.
+ */
+#ifndef CKKSCNN_H
+#define CKKSCNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CKC_OK = 0,
+    CKC_EINVAL = -1,      /* bad argument */
+    CKC_ELEVEL = -2,      /* level too low, or levels that cannot be aligned */
+    CKC_ESCALE = -3,      /* operand scales differ by more than 2^-30 relative */
+    CKC_ENOKEY = -4,      /* missing relinearisation or Galois key */
+    CKC_ENOMEM = -5,      /* device allocation failed */
+    CKC_EDEVICE = -6,     /* HIP runtime error */
+    CKC_ESHAPE = -7,      /* shape / layout mismatch */
+    CKC_EUNSUPPORTED = -8 /* parameters outside what the kernels support */
+};
+
+typedef struct ckc_ctx ckc_ctx;     /* parameters and device tables */
+typedef struct ckc_sk ckc_sk;       /* client secret key (ternary, host + device copy) */
+typedef struct ckc_evk ckc_evk;     /* device-resident relinearisation + Galois keys */
+typedef struct ckc_layer ckc_layer; /* device-resident conv / dense layer */
+
+/* Ciphertext: d = device [npoly][level+1][N]; scale is the CKKS scale. */
+typedef struct {
+    uint64_t *d;
+    int32_t level;
+    int32_t npoly;
+    double scale;
+} ckc_ct;
+
+/* Plaintext: d = device [level+1][N] (NTT form). */
+typedef struct {
+    uint64_t *d;
+    int32_t level;
+    double scale;
+} ckc_pt;
+
+const char *ckc_last_error(void);
+
+/* ------------------------------------------------------------------ context
+ * Section 2.2 and Appendix D: N = 2^log_n, moduli q_0..q_{n_q-1} (q_0 holds
+ * the output, q_{n_q-1} is dropped first), special primes p_0..p_{n_p-1}.
+ * Every modulus must be a prime < 2^62 with q = 1 mod 2N, all distinct.
+ * alpha = primes per key-switching digit (dnum = ceil(n_q / alpha)); the
+ * product of the special primes should exceed every digit's product for
+ * small key-switching noise.  log_n in [10, 16].  Errors: CKC_EINVAL,
+ * CKC_EUNSUPPORTED, CKC_ENOMEM, CKC_EDEVICE.
+ */
+int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint64_t *p, int n_p, int alpha,
+                   ckc_ctx **out);
+int ckc_ctx_destroy(ckc_ctx *ctx);
+/* words (uint64) of a ciphertext at `level` with `npoly` polynomials */
+size_t ckc_ct_words(const ckc_ctx *ctx, int level, int npoly);
+size_t ckc_pt_words(const ckc_ctx *ctx, int level);
+/* the primitive 2N-th root of unity the library uses for prime index t
+ * (Q primes first, then P), and its NTT order: output index k of a forward
+ * transform holds a(psi^(2*bitrev(k)+1)). */
+uint64_t ckc_ctx_root(const ckc_ctx *ctx, int t);
+
+/* ------------------------------------------------------------------ NTT
+ * Negacyclic NTT over Z_q[X]/(X^N+1) (Section 2.2, NTT-based polynomial
+ * arithmetic), in place.  d holds n_blocks blocks of n_limbs limbs (each N
+ * words, contiguous); limb l of every block is taken modulo q_l.
+ * inverse = 0: coefficient -> NTT form; inverse = 1: NTT -> coefficient form.
+ */
+int ckc_ntt(const ckc_ctx *ctx, uint64_t *d, int n_blocks, int n_limbs, int inverse, void *stream);
+
+/* ------------------------------------------------------------------ keys
+ * Client key generation (Section 2.1: the client holds the secret key).
+ * Secret: ternary s from a counter-based SplitMix64 stream of `seed`.
+ * Evaluation keys (server side, device resident): one relinearisation key
+ * (s^2 -> s) and one Galois key per rotation step (left rotation of the
+ * N/2 slots by steps[i], Section 2.2), hybrid key switching with the
+ * special modulus P.  Step 0 and duplicate Galois elements are ignored.
+ * Errors: CKC_EINVAL, CKC_ENOMEM, CKC_EDEVICE.
+ */
+int ckc_keygen(ckc_ctx *ctx, uint64_t seed, const int32_t *steps, int n_steps, ckc_sk **sk_out,
+               ckc_evk **evk_out, void *stream);
+/* add Galois keys for more rotation steps to an existing key set */
+int ckc_evk_add_rotations(ckc_ctx *ctx, const ckc_sk *sk, ckc_evk *evk, const int32_t *steps, int n_steps,
+                          void *stream);
+int ckc_sk_destroy(ckc_sk *sk);
+int ckc_evk_destroy(ckc_evk *evk);
+size_t ckc_evk_bytes(const ckc_evk *evk);
+
+/* ------------------------------------------------------------------ client
+ * Encoding (Section 2.2): n <= N/2 real slot values (host array), scaled by
+ * `scale`, rounded to integers, reduced modulo q_0..q_level, NTT form.
+ * The remaining slots are zero.  out->d must hold ckc_pt_words(level).
+ */
+int ckc_encode(ckc_ctx *ctx, const double *slots, size_t n, int level, double scale, ckc_pt *out,
+               void *stream);
+/* Symmetric RLWE encryption (Section 2.2): ct = (-a s + m + e, a) over
+ * q_0..q_{pt.level}; stream_id selects the PRNG streams of a and e and must
+ * be unique per ciphertext under one key. */
+int ckc_encrypt(ckc_ctx *ctx, const ckc_sk *sk, const ckc_pt *pt, uint64_t stream_id, ckc_ct *out,
+                void *stream);
+/* m = c0 + c1 s (+ c2 s^2 for 3-polynomial ciphertexts) at the ciphertext's level. */
+int ckc_decrypt(ckc_ctx *ctx, const ckc_sk *sk, const ckc_ct *ct, ckc_pt *out, void *stream);
+/* Decoding: limb q_0 of pt, centred, mapped to n real slot values divided by
+ * pt->scale, written to the host array `slots`.  Synchronises `stream`. */
+int ckc_decode(ckc_ctx *ctx, const ckc_pt *pt, double *slots, size_t n, void *stream);
+
+/* ------------------------------------------------------------------ arithmetic
+ * Section 2.2: slot-wise addition and multiplication, rotation, rescale.
+ * Binary operations need equal levels and scales within 2^-30 (CKC_ELEVEL /
+ * CKC_ESCALE).  `out` may alias an input unless stated otherwise.
+ */
+int ckc_add(ckc_ctx *ctx, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, void *stream);
+int ckc_sub(ckc_ctx *ctx, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, void *stream);
+/* add a plaintext (its level >= the ciphertext's; extra limbs ignored) */
+int ckc_add_plain(ckc_ctx *ctx, const ckc_ct *a, const ckc_pt *p, ckc_ct *out, void *stream);
+/* add round(value * a.scale) to every slot */
+int ckc_add_const(ckc_ctx *ctx, const ckc_ct *a, double value, ckc_ct *out, void *stream);
+/* multiply by a plaintext; result scale = a.scale * p.scale (no rescale) */
+int ckc_mul_plain(ckc_ctx *ctx, const ckc_ct *a, const ckc_pt *p, ckc_ct *out, void *stream);
+/* tensor product of two 2-polynomial ciphertexts -> 3 polynomials; out must not alias */
+int ckc_tensor(ckc_ctx *ctx, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, void *stream);
+/* relinearise a 3-polynomial ciphertext (s^2 -> s) into a 2-polynomial one */
+int ckc_relin(ckc_ctx *ctx, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream);
+/* Hoisted rotations: one ModUp of in->c1 shared by every step; out[i] is the
+ * left rotation of the slots by steps[i] (0 = copy).  The Galois
+ * automorphism is applied after ModUp.  out[i] must not alias in. */
+int ckc_rotate(ckc_ctx *ctx, const ckc_evk *evk, const ckc_ct *in, const int32_t *steps, int n_steps,
+               ckc_ct *out, void *stream);
+/* Rescale (Section 2.2): divide by q_level with rounding, drop that limb;
+ * scale /= q_level.  out->d must not alias in->d. */
+int ckc_rescale(ckc_ctx *ctx, const ckc_ct *in, ckc_ct *out, void *stream);
+/* keep limbs q_0..q_to_level (value and scale unchanged) */
+int ckc_mod_drop(ckc_ctx *ctx, const ckc_ct *in, int to_level, ckc_ct *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CKKSCNN_H */

@@ -1,0 +1,350 @@
+"""Thin Python binding of the C-ABI in include/ckkscnn.h.
+
+Argument marshalling only: every homomorphic step runs in the HIP kernels of
+libckkscnn.so.  PyTorch supplies device memory (ciphertext and plaintext
+buffers are torch tensors on the GPU) and streams.  Loading fails loudly when
+the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libckkscnn.so")
+
+CKC_ERRORS = {
+    -1: "CKC_EINVAL", -2: "CKC_ELEVEL", -3: "CKC_ESCALE", -4: "CKC_ENOKEY",
+    -5: "CKC_ENOMEM", -6: "CKC_EDEVICE", -7: "CKC_ESHAPE", -8: "CKC_EUNSUPPORTED",
+}
+
+
+class CkcError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn}: {CKC_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ckc_ct(C.Structure):
+    _fields_ = [("d", C.c_void_p), ("level", C.c_int32), ("npoly", C.c_int32), ("scale", C.c_double)]
+
+
+class ckc_pt(C.Structure):
+    _fields_ = [("d", C.c_void_p), ("level", C.c_int32), ("scale", C.c_double)]
+
+
+_lib = None
+_u64p = C.POINTER(C.c_uint64)
+_i32p = C.POINTER(C.c_int32)
+_dblp = C.POINTER(C.c_double)
+_vp = C.c_void_p
+
+# (name, restype, argtypes) for every entry point declared in include/ckkscnn.h
+_SIGS = [
+    ("ckc_last_error", C.c_char_p, []),
+    ("ckc_ctx_create", C.c_int, [C.c_int, _u64p, C.c_int, _u64p, C.c_int, C.c_int, C.POINTER(_vp)]),
+    ("ckc_ctx_destroy", C.c_int, [_vp]),
+    ("ckc_ct_words", C.c_size_t, [_vp, C.c_int, C.c_int]),
+    ("ckc_pt_words", C.c_size_t, [_vp, C.c_int]),
+    ("ckc_ctx_root", C.c_uint64, [_vp, C.c_int]),
+    ("ckc_ntt", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp]),
+    ("ckc_keygen", C.c_int, [_vp, C.c_uint64, _i32p, C.c_int, C.POINTER(_vp), C.POINTER(_vp), _vp]),
+    ("ckc_evk_add_rotations", C.c_int, [_vp, _vp, _vp, _i32p, C.c_int, _vp]),
+    ("ckc_sk_destroy", C.c_int, [_vp]),
+    ("ckc_evk_destroy", C.c_int, [_vp]),
+    ("ckc_evk_bytes", C.c_size_t, [_vp]),
+    ("ckc_encode", C.c_int, [_vp, _dblp, C.c_size_t, C.c_int, C.c_double, C.POINTER(ckc_pt), _vp]),
+    ("ckc_encrypt", C.c_int, [_vp, _vp, C.POINTER(ckc_pt), C.c_uint64, C.POINTER(ckc_ct), _vp]),
+    ("ckc_decrypt", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), C.POINTER(ckc_pt), _vp]),
+    ("ckc_decode", C.c_int, [_vp, C.POINTER(ckc_pt), _dblp, C.c_size_t, _vp]),
+    ("ckc_add", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
+    ("ckc_sub", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
+    ("ckc_add_plain", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_pt), C.POINTER(ckc_ct), _vp]),
+    ("ckc_add_const", C.c_int, [_vp, C.POINTER(ckc_ct), C.c_double, C.POINTER(ckc_ct), _vp]),
+    ("ckc_mul_plain", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_pt), C.POINTER(ckc_ct), _vp]),
+    ("ckc_tensor", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
+    ("ckc_relin", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
+    ("ckc_rotate", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), _i32p, C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_rescale", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
+    ("ckc_mod_drop", C.c_int, [_vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
+]
+
+
+def exported_names() -> list[str]:
+    return [n for n, _, _ in _SIGS]
+
+
+def lib():
+    """Load libckkscnn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int):
+    if rc != 0:
+        raise CkcError(fn, rc, lib().ckc_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class Ciphertext:
+    """Device ciphertext: `buf` is a torch int64 tensor holding [npoly][level+1][N] words."""
+    buf: object
+    level: int
+    npoly: int
+    scale: float
+
+    def c(self) -> ckc_ct:
+        return ckc_ct(self.buf.data_ptr(), self.level, self.npoly, self.scale)
+
+    def update(self, s: ckc_ct):
+        self.level, self.npoly, self.scale = int(s.level), int(s.npoly), float(s.scale)
+
+
+@dataclass
+class Plaintext:
+    buf: object
+    level: int
+    scale: float
+
+    def c(self) -> ckc_pt:
+        return ckc_pt(self.buf.data_ptr(), self.level, self.scale)
+
+
+class Context:
+    """ckc_ctx: parameters and device tables."""
+
+    def __init__(self, logN: int, q, p, alpha: int, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.logN, self.N = int(logN), 1 << int(logN)
+        self.q, self.p, self.alpha = [int(x) for x in q], [int(x) for x in p], int(alpha)
+        qa = (C.c_uint64 * len(self.q))(*self.q)
+        pa = (C.c_uint64 * len(self.p))(*self.p)
+        h = _vp()
+        _check("ckc_ctx_create", lib().ckc_ctx_create(self.logN, qa, len(self.q), pa, len(self.p), self.alpha, C.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_params(cls, ps, device: str = "cuda") -> "Context":
+        return cls(ps.logN, ps.q, ps.p, ps.alpha, device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ckc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------- buffers
+    def ct_words(self, level: int, npoly: int = 2) -> int:
+        return int(lib().ckc_ct_words(self.h, level, npoly))
+
+    def new_ct(self, level: int, npoly: int = 2, scale: float = 1.0) -> Ciphertext:
+        buf = self.torch.empty(self.ct_words(level, npoly), dtype=self.torch.int64, device=self.device)
+        return Ciphertext(buf, level, npoly, scale)
+
+    def new_pt(self, level: int, scale: float = 1.0) -> Plaintext:
+        buf = self.torch.empty(int(lib().ckc_pt_words(self.h, level)), dtype=self.torch.int64, device=self.device)
+        return Plaintext(buf, level, scale)
+
+    def upload_words(self, arr: np.ndarray):
+        a = np.ascontiguousarray(arr, dtype=np.uint64).reshape(-1).view(np.int64)
+        return self.torch.from_numpy(a.copy()).to(self.device)
+
+    @staticmethod
+    def download_words(buf) -> np.ndarray:
+        return buf.detach().cpu().numpy().view(np.uint64).copy()
+
+    def root(self, t: int) -> int:
+        return int(lib().ckc_ctx_root(self.h, t))
+
+    # --------------------------------------------------------- NTT
+    def ntt(self, buf, n_blocks: int, n_limbs: int, inverse: bool, stream=None):
+        _check("ckc_ntt", lib().ckc_ntt(self.h, buf.data_ptr(), n_blocks, n_limbs, int(inverse), _stream(stream)))
+
+    def ct_from_coeff(self, data: np.ndarray, level: int, scale: float) -> Ciphertext:
+        """Upload a coefficient-form ciphertext [npoly][level+1][N] and move it to NTT form."""
+        npoly = data.shape[0]
+        buf = self.upload_words(data)
+        self.ntt(buf, npoly, level + 1, False)
+        return Ciphertext(buf, level, npoly, scale)
+
+    def pt_from_coeff(self, data: np.ndarray, level: int, scale: float) -> Plaintext:
+        buf = self.upload_words(data[:level + 1])
+        self.ntt(buf, 1, level + 1, False)
+        return Plaintext(buf, level, scale)
+
+    def ct_to_coeff(self, ct: Ciphertext) -> np.ndarray:
+        tmp = ct.buf.clone()
+        self.ntt(tmp, ct.npoly, ct.level + 1, True)
+        self.torch.cuda.synchronize()
+        return self.download_words(tmp).reshape(ct.npoly, ct.level + 1, self.N)
+
+    def pt_to_coeff(self, pt: Plaintext) -> np.ndarray:
+        tmp = pt.buf.clone()
+        self.ntt(tmp, 1, pt.level + 1, True)
+        self.torch.cuda.synchronize()
+        return self.download_words(tmp).reshape(pt.level + 1, self.N)
+
+    # --------------------------------------------------------- keys
+    def keygen(self, seed: int, steps=(), stream=None):
+        st = np.ascontiguousarray(np.array(list(steps), dtype=np.int32))
+        sk, evk = _vp(), _vp()
+        _check("ckc_keygen", lib().ckc_keygen(self.h, seed, st.ctypes.data_as(_i32p), len(st), C.byref(sk),
+                                              C.byref(evk), _stream(stream)))
+        return KeyPair(self, sk, evk)
+
+    # --------------------------------------------------------- client
+    def encode(self, slots, level: int, scale: float, out: Plaintext | None = None, stream=None) -> Plaintext:
+        z = np.ascontiguousarray(np.asarray(slots, dtype=np.float64))
+        pt = out or self.new_pt(level, scale)
+        s = pt.c()
+        _check("ckc_encode", lib().ckc_encode(self.h, z.ctypes.data_as(_dblp), len(z), level, float(scale),
+                                              C.byref(s), _stream(stream)))
+        pt.level, pt.scale = int(s.level), float(s.scale)
+        return pt
+
+    def encrypt(self, keys: "KeyPair", pt: Plaintext, stream_id: int, out: Ciphertext | None = None,
+                stream=None) -> Ciphertext:
+        ct = out or self.new_ct(pt.level, 2, pt.scale)
+        s, p = ct.c(), pt.c()
+        _check("ckc_encrypt", lib().ckc_encrypt(self.h, keys.sk, C.byref(p), stream_id, C.byref(s), _stream(stream)))
+        ct.update(s)
+        return ct
+
+    def decrypt(self, keys: "KeyPair", ct: Ciphertext, stream=None) -> Plaintext:
+        pt = self.new_pt(ct.level, ct.scale)
+        s, p = ct.c(), pt.c()
+        _check("ckc_decrypt", lib().ckc_decrypt(self.h, keys.sk, C.byref(s), C.byref(p), _stream(stream)))
+        pt.level, pt.scale = int(p.level), float(p.scale)
+        return pt
+
+    def decode(self, pt: Plaintext, n: int | None = None, stream=None) -> np.ndarray:
+        n = self.N // 2 if n is None else n
+        out = np.empty(n, dtype=np.float64)
+        p = pt.c()
+        _check("ckc_decode", lib().ckc_decode(self.h, C.byref(p), out.ctypes.data_as(_dblp), n, _stream(stream)))
+        return out
+
+    # --------------------------------------------------------- arithmetic
+    def _binop(self, fn, a: Ciphertext, b: Ciphertext, out: Ciphertext | None, npoly_out: int, stream):
+        out = out or self.new_ct(a.level, npoly_out, a.scale)
+        sa, sb, so = a.c(), b.c(), out.c()
+        _check(fn, getattr(lib(), fn)(self.h, C.byref(sa), C.byref(sb), C.byref(so), _stream(stream)))
+        out.update(so)
+        return out
+
+    def add(self, a, b, out=None, stream=None):
+        return self._binop("ckc_add", a, b, out, max(a.npoly, b.npoly), stream)
+
+    def sub(self, a, b, out=None, stream=None):
+        return self._binop("ckc_sub", a, b, out, max(a.npoly, b.npoly), stream)
+
+    def tensor(self, a, b, out=None, stream=None):
+        return self._binop("ckc_tensor", a, b, out, 3, stream)
+
+    def add_plain(self, a: Ciphertext, p: Plaintext, out=None, stream=None):
+        out = out or self.new_ct(a.level, a.npoly, a.scale)
+        sa, sp, so = a.c(), p.c(), out.c()
+        _check("ckc_add_plain", lib().ckc_add_plain(self.h, C.byref(sa), C.byref(sp), C.byref(so), _stream(stream)))
+        out.update(so)
+        return out
+
+    def mul_plain(self, a: Ciphertext, p: Plaintext, out=None, stream=None):
+        out = out or self.new_ct(a.level, a.npoly, a.scale)
+        sa, sp, so = a.c(), p.c(), out.c()
+        _check("ckc_mul_plain", lib().ckc_mul_plain(self.h, C.byref(sa), C.byref(sp), C.byref(so), _stream(stream)))
+        out.update(so)
+        return out
+
+    def add_const(self, a: Ciphertext, value: float, out=None, stream=None):
+        out = out or self.new_ct(a.level, a.npoly, a.scale)
+        sa, so = a.c(), out.c()
+        _check("ckc_add_const", lib().ckc_add_const(self.h, C.byref(sa), float(value), C.byref(so), _stream(stream)))
+        out.update(so)
+        return out
+
+    def relin(self, keys: "KeyPair", a: Ciphertext, out=None, stream=None):
+        out = out or self.new_ct(a.level, 2, a.scale)
+        sa, so = a.c(), out.c()
+        _check("ckc_relin", lib().ckc_relin(self.h, keys.evk, C.byref(sa), C.byref(so), _stream(stream)))
+        out.update(so)
+        return out
+
+    def rotate(self, keys: "KeyPair", a: Ciphertext, steps, outs=None, stream=None):
+        steps = list(steps)
+        outs = outs or [self.new_ct(a.level, 2, a.scale) for _ in steps]
+        arr = (ckc_ct * len(steps))(*[o.c() for o in outs])
+        st = (C.c_int32 * len(steps))(*steps)
+        sa = a.c()
+        _check("ckc_rotate", lib().ckc_rotate(self.h, keys.evk, C.byref(sa), st, len(steps), arr, _stream(stream)))
+        for o, s in zip(outs, arr):
+            o.update(s)
+        return outs
+
+    def rescale(self, a: Ciphertext, out=None, stream=None):
+        out = out or self.new_ct(max(a.level - 1, 0), a.npoly, a.scale)
+        sa, so = a.c(), out.c()
+        _check("ckc_rescale", lib().ckc_rescale(self.h, C.byref(sa), C.byref(so), _stream(stream)))
+        out.update(so)
+        return out
+
+    def mod_drop(self, a: Ciphertext, to_level: int, out=None, stream=None):
+        out = out or self.new_ct(to_level, a.npoly, a.scale)
+        sa, so = a.c(), out.c()
+        _check("ckc_mod_drop", lib().ckc_mod_drop(self.h, C.byref(sa), to_level, C.byref(so), _stream(stream)))
+        out.update(so)
+        return out
+
+
+class KeyPair:
+    """ckc_sk + ckc_evk handles from ckc_keygen."""
+
+    def __init__(self, ctx: Context, sk, evk):
+        self.ctx, self.sk, self.evk = ctx, sk, evk
+
+    def add_rotations(self, steps, stream=None):
+        st = (C.c_int32 * len(steps))(*steps)
+        _check("ckc_evk_add_rotations", lib().ckc_evk_add_rotations(self.ctx.h, self.sk, self.evk, st, len(steps),
+                                                                    _stream(stream)))
+
+    def evk_bytes(self) -> int:
+        return int(lib().ckc_evk_bytes(self.evk))
+
+    def close(self):
+        if self.sk:
+            lib().ckc_sk_destroy(self.sk)
+            self.sk = None
+        if self.evk:
+            lib().ckc_evk_destroy(self.evk)
+            self.evk = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

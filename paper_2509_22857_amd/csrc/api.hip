@@ -1,0 +1,549 @@
+// C-ABI entry points: context set-up, keys, client operations and
+// homomorphic arithmetic.  Argument checking happens here; the kernels live in
+// ntt.hip, rns.hip and client.hip.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <set>
+
+#include "ckc_internal.h"
+
+static thread_local std::string g_err;
+void ckc_set_error(const std::string &msg) { g_err = msg; }
+extern "C" const char *ckc_last_error(void) { return g_err.c_str(); }
+
+int copy_limbs(const uint64_t *src, size_t src_ps, uint64_t *dst, size_t dst_ps, size_t words, int npoly,
+               hipStream_t s);
+int encode_impl(ckc_ctx *c, const double *slots_h, size_t nslots, int level, double scale, uint64_t *m,
+                hipStream_t s);
+int decode_impl(ckc_ctx *c, const uint64_t *m, double scale, double *out_h, size_t nslots, hipStream_t s);
+int secret_impl(ckc_ctx *c, ckc_sk *sk, uint64_t seed, hipStream_t s);
+int switch_key_impl(ckc_ctx *c, const ckc_sk *sk, uint64_t key_id, const uint64_t *sprime, uint64_t *key,
+                    hipStream_t s);
+int encrypt_impl(ckc_ctx *c, const ckc_sk *sk, const uint64_t *m, int level, uint64_t stream_id, uint64_t *ct,
+                 hipStream_t s);
+int decrypt_impl(ckc_ctx *c, const ckc_sk *sk, const uint64_t *ct, int level, int npoly, uint64_t *m,
+                 hipStream_t s);
+int permute_limbs(const ckc_ctx *c, const uint64_t *src, uint64_t *dst, int nlimbs, const uint32_t *perm,
+                  hipStream_t s);
+
+namespace {
+
+using u128 = unsigned __int128;
+uint64_t hmul(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)(((u128)a * b) % q); }
+uint64_t hpow(uint64_t a, uint64_t e, uint64_t q) {
+    uint64_t r = 1 % q;
+    a %= q;
+    while (e) {
+        if (e & 1) r = hmul(r, a, q);
+        a = hmul(a, a, q);
+        e >>= 1;
+    }
+    return r;
+}
+uint64_t hinv(uint64_t a, uint64_t q) { return hpow(a, q - 2, q); }
+uint64_t hshoup(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+
+bool is_prime_u64(uint64_t n) {
+    if (n < 2) return false;
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t p : bases)
+        if (n % p == 0) return n == p;
+    uint64_t d = n - 1;
+    int r = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++r;
+    }
+    for (uint64_t a : bases) {
+        uint64_t x = hpow(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < r; ++i) {
+            x = hmul(x, x, n);
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+Prime make_prime(uint64_t q) {
+    Prime P{};
+    P.q = q;
+    int k = 64 - __builtin_clzll(q);
+    P.k = k;
+    P.mu = (uint64_t)(((u128)1 << (2 * k)) / q);
+    P.r2 = (uint64_t)(((u128)1 << 64) % q);
+    P.r2p = hshoup(P.r2, q);
+    P.onep = (uint64_t)(((u128)1 << 64) / q);
+    return P;
+}
+
+uint64_t brev_bits(uint64_t x, int bits) {
+    uint64_t r = 0;
+    for (int i = 0; i < bits; ++i) r = (r << 1) | ((x >> i) & 1);
+    return r;
+}
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+int check_ct(const ckc_ctx *c, const ckc_ct *a, const char *what) {
+    CKC_REQUIRE(a && a->d, CKC_EINVAL, std::string(what) + ": null ciphertext");
+    CKC_REQUIRE(a->level >= 0 && a->level < c->nq, CKC_ELEVEL, std::string(what) + ": level out of range");
+    CKC_REQUIRE(a->npoly >= 2 && a->npoly <= 3, CKC_ESHAPE, std::string(what) + ": npoly must be 2 or 3");
+    return CKC_OK;
+}
+int check_scales(double a, double b) {
+    CKC_REQUIRE(fabs(a / b - 1.0) <= ldexp(1.0, -30), CKC_ESCALE, "operand scales differ");
+    return CKC_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ctx
+extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint64_t *p, int n_p, int alpha,
+                              ckc_ctx **out) {
+    CKC_REQUIRE(out && q && p, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(log_n >= 12 && log_n <= 16, CKC_EUNSUPPORTED, "log_n must be in [12, 16]");
+    CKC_REQUIRE(n_q >= 1 && n_p >= 1 && n_q + n_p <= 96, CKC_EINVAL, "bad prime counts");
+    CKC_REQUIRE(alpha >= 1 && alpha <= n_q, CKC_EINVAL, "bad alpha");
+    const size_t N = size_t(1) << log_n;
+    std::set<uint64_t> seen;
+    for (int i = 0; i < n_q + n_p; ++i) {
+        const uint64_t m = i < n_q ? q[i] : p[i - n_q];
+        CKC_REQUIRE(m < (uint64_t(1) << 62) && m > (1u << 20), CKC_EUNSUPPORTED, "moduli must lie in (2^20, 2^62)");
+        CKC_REQUIRE((m - 1) % (2 * N) == 0, CKC_EINVAL, "modulus not 1 mod 2N");
+        CKC_REQUIRE(is_prime_u64(m), CKC_EINVAL, "modulus not prime");
+        CKC_REQUIRE(seen.insert(m).second, CKC_EINVAL, "duplicate modulus");
+    }
+    auto c = std::make_unique<ckc_ctx>();
+    c->logN = log_n;
+    c->N = N;
+    c->nq = n_q;
+    c->np = n_p;
+    c->alpha = alpha;
+    for (int i = 0; i < n_q; ++i) c->mods.push_back(q[i]);
+    for (int i = 0; i < n_p; ++i) c->mods.push_back(p[i]);
+    const int np = c->nprimes();
+    for (int t = 0; t < np; ++t) c->primes_h.push_back(make_prime(c->mods[t]));
+    CKC_TRY(c->primes_d.upload(c->primes_h.data(), sizeof(Prime) * np));
+
+    // NTT tables
+    std::vector<uint64_t> tw(N * np), twp(N * np), itw(N * np), itwp(N * np), ninv(2 * np);
+    for (int t = 0; t < np; ++t) {
+        const uint64_t m = c->mods[t];
+        uint64_t psi = 0;
+        for (uint64_t x = 2;; ++x) {
+            const uint64_t g = hpow(x, (m - 1) / (2 * N), m);
+            if (hpow(g, N, m) == m - 1) {
+                psi = g;
+                break;
+            }
+        }
+        c->psi_h.push_back(psi);
+        const uint64_t ipsi = hinv(psi, m);
+        std::vector<uint64_t> pw(N), ipw(N);
+        uint64_t x = 1, y = 1;
+        for (size_t i = 0; i < N; ++i) {
+            pw[i] = x;
+            ipw[i] = y;
+            x = hmul(x, psi, m);
+            y = hmul(y, ipsi, m);
+        }
+        for (size_t k = 0; k < N; ++k) {
+            const uint64_t r = brev_bits(k, log_n);
+            tw[t * N + k] = pw[r];
+            twp[t * N + k] = hshoup(pw[r], m);
+            itw[t * N + k] = ipw[r];
+            itwp[t * N + k] = hshoup(ipw[r], m);
+        }
+        ninv[2 * t] = hinv(N % m, m);
+        ninv[2 * t + 1] = hshoup(ninv[2 * t], m);
+    }
+    CKC_TRY(c->tw.upload(tw.data(), 8 * tw.size()));
+    CKC_TRY(c->twp.upload(twp.data(), 8 * twp.size()));
+    CKC_TRY(c->itw.upload(itw.data(), 8 * itw.size()));
+    CKC_TRY(c->itwp.upload(itwp.data(), 8 * itwp.size()));
+    CKC_TRY(c->ninv.upload(ninv.data(), 8 * ninv.size()));
+
+    // FFT tables: twiddles of the length-n DFT and the zeta^k twist (libm, host)
+    const size_t n = N / 2;
+    std::vector<double> fw(2 * (n / 2)), tws(2 * n);
+    for (size_t e = 0; e < n / 2; ++e) {
+        const double ang = (double(2 * e) / double(n)) * M_PI;
+        fw[2 * e] = cos(ang);
+        fw[2 * e + 1] = sin(ang);
+    }
+    for (size_t k = 0; k < n; ++k) {
+        const double ang = (double(k) / double(N)) * M_PI;
+        tws[2 * k] = cos(ang);
+        tws[2 * k + 1] = sin(ang);
+    }
+    std::vector<uint32_t> sidx(n);
+    uint64_t g = 1;
+    for (size_t j = 0; j < n; ++j) {
+        sidx[j] = uint32_t((g - 1) / 4);
+        g = (g * 5) % (2 * N);
+    }
+    CKC_TRY(c->fft_w.upload(fw.data(), 8 * fw.size()));
+    CKC_TRY(c->twist.upload(tws.data(), 8 * tws.size()));
+    CKC_TRY(c->slot_idx.upload(sidx.data(), 4 * sidx.size()));
+
+    // rescale constants q_l^-1 mod q_i
+    std::vector<uint64_t> rinv(size_t(n_q) * n_q * 2, 0);
+    for (int l = 1; l < n_q; ++l)
+        for (int i = 0; i < l; ++i) {
+            const uint64_t qi = c->mods[i];
+            const uint64_t v = hinv(c->mods[l] % qi, qi);
+            rinv[(size_t(l) * n_q + i) * 2] = v;
+            rinv[(size_t(l) * n_q + i) * 2 + 1] = hshoup(v, qi);
+        }
+    CKC_TRY(c->rescale_inv.upload(rinv.data(), 8 * rinv.size()));
+
+    // ModDown: P^-1 mod q_i, and P -> q_i conversion constants
+    std::vector<uint64_t> pinv(2 * n_q), inv(n_p), invp(n_p), hat(size_t(n_q) * n_p);
+    for (int i = 0; i < n_q; ++i) {
+        const uint64_t qi = c->mods[i];
+        uint64_t P = 1 % qi;
+        for (int k = 0; k < n_p; ++k) P = hmul(P, p[k] % qi, qi);
+        pinv[2 * i] = hinv(P, qi);
+        pinv[2 * i + 1] = hshoup(pinv[2 * i], qi);
+        for (int a = 0; a < n_p; ++a) {
+            uint64_t h = 1 % qi;
+            for (int b = 0; b < n_p; ++b)
+                if (b != a) h = hmul(h, p[b] % qi, qi);
+            hat[size_t(i) * n_p + a] = h;
+        }
+    }
+    for (int a = 0; a < n_p; ++a) {
+        const uint64_t pa = p[a];
+        uint64_t h = 1 % pa;
+        for (int b = 0; b < n_p; ++b)
+            if (b != a) h = hmul(h, p[b] % pa, pa);
+        inv[a] = hinv(h, pa);
+        invp[a] = hshoup(inv[a], pa);
+    }
+    CKC_TRY(c->pinv.upload(pinv.data(), 8 * pinv.size()));
+    c->p_to_q.ns = n_p;
+    c->p_to_q.nt = n_q;
+    CKC_TRY(c->p_to_q.inv.upload(inv.data(), 8 * n_p));
+    CKC_TRY(c->p_to_q.invp.upload(invp.data(), 8 * n_p));
+    CKC_TRY(c->p_to_q.hat.upload(hat.data(), 8 * hat.size()));
+    *out = c.release();
+    return CKC_OK;
+}
+
+extern "C" int ckc_ctx_destroy(ckc_ctx *c) {
+    delete c;
+    return CKC_OK;
+}
+extern "C" size_t ckc_ct_words(const ckc_ctx *c, int level, int npoly) { return words_ct(c, level, npoly); }
+extern "C" size_t ckc_pt_words(const ckc_ctx *c, int level) { return size_t(level + 1) * c->N; }
+extern "C" uint64_t ckc_ctx_root(const ckc_ctx *c, int t) {
+    return (t >= 0 && t < c->nprimes()) ? c->psi_h[t] : 0;
+}
+
+extern "C" int ckc_ntt(const ckc_ctx *c, uint64_t *d, int n_blocks, int n_limbs, int inverse, void *stream) {
+    CKC_REQUIRE(c && d, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(n_limbs >= 1 && n_limbs <= c->nq && n_blocks >= 0, CKC_EINVAL, "bad limb count");
+    const size_t stride = size_t(n_limbs) * c->N;
+    // grid.z is limited to 65535 blocks per launch
+    for (int b0 = 0; b0 < n_blocks; b0 += 65535) {
+        const int nb = std::min(65535, n_blocks - b0);
+        uint64_t *p = d + size_t(b0) * stride;
+        if (inverse)
+            CKC_TRY(ntt_inverse(c, p, n_limbs, qmap(), nb, stride, S(stream)));
+        else
+            CKC_TRY(ntt_forward(c, p, n_limbs, qmap(), nb, stride, S(stream)));
+    }
+    return CKC_OK;
+}
+
+// ======================================================================= keys
+static int add_galois(ckc_ctx *c, const ckc_sk *sk, ckc_evk *evk, const int32_t *steps, int n, hipStream_t s) {
+    const size_t N = c->N;
+    const int np = c->nprimes();
+    for (int i = 0; i < n; ++i) {
+        const uint64_t g = galois_element(c, steps[i]);
+        if (g == 1 || evk->galois.count(g)) continue;
+        int rc;
+        const uint32_t *perm = (const uint32_t *)galois_table(c, g, &rc);
+        if (!perm) return rc;
+        DevBuf sp;
+        CKC_TRY(sp.alloc(8 * N * np, s));
+        // sigma_g(s) in the NTT domain: a gather through the permutation, every prime
+        CKC_TRY(permute_limbs(c, sk->s_ntt.u64(), sp.u64(), np, perm, s));
+        auto key = std::make_unique<DevMem>();
+        CKC_TRY(key->alloc(8 * evk->key_words));
+        CKC_TRY(switch_key_impl(c, sk, g, sp.u64(), key->u64(), s));
+        evk->galois[g] = std::move(key);
+    }
+    return CKC_OK;
+}
+
+extern "C" int ckc_keygen(ckc_ctx *c, uint64_t seed, const int32_t *steps, int n_steps, ckc_sk **sk_out,
+                          ckc_evk **evk_out, void *stream) {
+    CKC_REQUIRE(c && sk_out && evk_out, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(n_steps >= 0 && (n_steps == 0 || steps), CKC_EINVAL, "bad steps");
+    hipStream_t s = S(stream);
+    auto sk = std::make_unique<ckc_sk>();
+    CKC_TRY(secret_impl(c, sk.get(), seed, s));
+    auto evk = std::make_unique<ckc_evk>();
+    const size_t N = c->N;
+    const int np = c->nprimes();
+    evk->dnum = c->dnum_at(c->nq - 1);
+    evk->key_words = size_t(evk->dnum) * 2 * np * N;
+    // relinearisation key: s' = s^2 (pointwise in the NTT domain)
+    DevBuf s2;
+    CKC_TRY(s2.alloc(8 * N * np, s));
+    CKC_TRY(ew_binary(c, EW_MUL, s2.u64(), sk->s_ntt.u64(), sk->s_ntt.u64(), 1, np, 0, 0, 0, qmap(), s));
+    evk->relin = std::make_unique<DevMem>();
+    CKC_TRY(evk->relin->alloc(8 * evk->key_words));
+    CKC_TRY(switch_key_impl(c, sk.get(), 0, s2.u64(), evk->relin->u64(), s));
+    CKC_TRY(add_galois(c, sk.get(), evk.get(), steps, n_steps, s));
+    CKC_HIP(hipStreamSynchronize(s));
+    *sk_out = sk.release();
+    *evk_out = evk.release();
+    return CKC_OK;
+}
+
+extern "C" int ckc_evk_add_rotations(ckc_ctx *c, const ckc_sk *sk, ckc_evk *evk, const int32_t *steps, int n_steps,
+                                     void *stream) {
+    CKC_REQUIRE(c && sk && evk, CKC_EINVAL, "null argument");
+    CKC_TRY(add_galois(c, sk, evk, steps, n_steps, S(stream)));
+    CKC_HIP(hipStreamSynchronize(S(stream)));
+    return CKC_OK;
+}
+
+extern "C" int ckc_sk_destroy(ckc_sk *sk) {
+    delete sk;
+    return CKC_OK;
+}
+extern "C" int ckc_evk_destroy(ckc_evk *e) {
+    delete e;
+    return CKC_OK;
+}
+extern "C" size_t ckc_evk_bytes(const ckc_evk *e) {
+    if (!e) return 0;
+    size_t n = e->galois.size() + (e->relin ? 1 : 0);
+    return n * e->key_words * 8;
+}
+
+// ======================================================================= client
+extern "C" int ckc_encode(ckc_ctx *c, const double *slots, size_t n, int level, double scale, ckc_pt *out,
+                          void *stream) {
+    CKC_REQUIRE(c && out && out->d && (n == 0 || slots), CKC_EINVAL, "null argument");
+    CKC_REQUIRE(n <= c->N / 2, CKC_EINVAL, "too many slots");
+    CKC_REQUIRE(level >= 0 && level < c->nq, CKC_ELEVEL, "level out of range");
+    CKC_REQUIRE(scale > 0 && isfinite(scale), CKC_EINVAL, "bad scale");
+    CKC_TRY(encode_impl(c, slots, n, level, scale, out->d, S(stream)));
+    out->level = level;
+    out->scale = scale;
+    return CKC_OK;
+}
+
+extern "C" int ckc_encrypt(ckc_ctx *c, const ckc_sk *sk, const ckc_pt *pt, uint64_t stream_id, ckc_ct *out,
+                           void *stream) {
+    CKC_REQUIRE(c && sk && pt && pt->d && out && out->d, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(pt->level >= 0 && pt->level < c->nq, CKC_ELEVEL, "level out of range");
+    CKC_TRY(encrypt_impl(c, sk, pt->d, pt->level, stream_id, out->d, S(stream)));
+    out->level = pt->level;
+    out->npoly = 2;
+    out->scale = pt->scale;
+    return CKC_OK;
+}
+
+extern "C" int ckc_decrypt(ckc_ctx *c, const ckc_sk *sk, const ckc_ct *ct, ckc_pt *out, void *stream) {
+    CKC_REQUIRE(c && sk && out && out->d, CKC_EINVAL, "null argument");
+    CKC_TRY(check_ct(c, ct, "decrypt"));
+    CKC_TRY(decrypt_impl(c, sk, ct->d, ct->level, ct->npoly, out->d, S(stream)));
+    out->level = ct->level;
+    out->scale = ct->scale;
+    return CKC_OK;
+}
+
+extern "C" int ckc_decode(ckc_ctx *c, const ckc_pt *pt, double *slots, size_t n, void *stream) {
+    CKC_REQUIRE(c && pt && pt->d && (n == 0 || slots), CKC_EINVAL, "null argument");
+    CKC_REQUIRE(n <= c->N / 2, CKC_EINVAL, "too many slots");
+    return decode_impl(c, pt->d, pt->scale, slots, n, S(stream));
+}
+
+// ======================================================================= arithmetic
+static int addsub(ckc_ctx *c, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, EwOp op, void *stream) {
+    CKC_TRY(check_ct(c, a, "add"));
+    CKC_TRY(check_ct(c, b, "add"));
+    CKC_REQUIRE(out && out->d, CKC_EINVAL, "null output");
+    CKC_REQUIRE(a->level == b->level, CKC_ELEVEL, "levels differ");
+    CKC_TRY(check_scales(a->scale, b->scale));
+    const size_t N = c->N, ps = size_t(a->level + 1) * N;
+    const int nl = a->level + 1, common = std::min(a->npoly, b->npoly);
+    hipStream_t s = S(stream);
+    CKC_TRY(ew_binary(c, op, out->d, a->d, b->d, common, nl, ps, ps, ps, qmap(), s));
+    if (a->npoly > common)
+        CKC_TRY(copy_limbs(a->d + common * ps, 0, out->d + common * ps, 0, ps, 1, s));
+    if (b->npoly > common) {
+        if (op == EW_ADD)
+            CKC_TRY(copy_limbs(b->d + common * ps, 0, out->d + common * ps, 0, ps, 1, s));
+        else
+            CKC_TRY(ew_binary(c, EW_NEG, out->d + common * ps, b->d + common * ps, nullptr, 1, nl, 0, 0, 0, qmap(), s));
+    }
+    out->level = a->level;
+    out->npoly = std::max(a->npoly, b->npoly);
+    out->scale = a->scale;
+    return CKC_OK;
+}
+
+extern "C" int ckc_add(ckc_ctx *c, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, void *stream) {
+    return addsub(c, a, b, out, EW_ADD, stream);
+}
+extern "C" int ckc_sub(ckc_ctx *c, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, void *stream) {
+    return addsub(c, a, b, out, EW_SUB, stream);
+}
+
+extern "C" int ckc_add_plain(ckc_ctx *c, const ckc_ct *a, const ckc_pt *p, ckc_ct *out, void *stream) {
+    CKC_TRY(check_ct(c, a, "add_plain"));
+    CKC_REQUIRE(p && p->d && out && out->d, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(p->level >= a->level, CKC_ELEVEL, "plaintext level too low");
+    CKC_TRY(check_scales(a->scale, p->scale));
+    const size_t ps = size_t(a->level + 1) * c->N;
+    hipStream_t s = S(stream);
+    CKC_TRY(ew_binary(c, EW_ADD, out->d, a->d, p->d, 1, a->level + 1, 0, 0, 0, qmap(), s));
+    if (out->d != a->d) CKC_TRY(copy_limbs(a->d + ps, 0, out->d + ps, 0, ps * (a->npoly - 1), 1, s));
+    out->level = a->level;
+    out->npoly = a->npoly;
+    out->scale = a->scale;
+    return CKC_OK;
+}
+
+int add_const_impl(ckc_ctx *c, const ckc_ct *a, double value, ckc_ct *out, hipStream_t s);
+
+extern "C" int ckc_add_const(ckc_ctx *c, const ckc_ct *a, double value, ckc_ct *out, void *stream) {
+    CKC_TRY(check_ct(c, a, "add_const"));
+    CKC_REQUIRE(out && out->d, CKC_EINVAL, "null output");
+    CKC_REQUIRE(isfinite(value), CKC_EINVAL, "non-finite constant");
+    return add_const_impl(c, a, value, out, S(stream));
+}
+
+extern "C" int ckc_mul_plain(ckc_ctx *c, const ckc_ct *a, const ckc_pt *p, ckc_ct *out, void *stream) {
+    CKC_TRY(check_ct(c, a, "mul_plain"));
+    CKC_REQUIRE(p && p->d && out && out->d, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(p->level >= a->level, CKC_ELEVEL, "plaintext level too low");
+    const size_t ps = size_t(a->level + 1) * c->N;
+    CKC_TRY(ew_binary(c, EW_MUL, out->d, a->d, p->d, a->npoly, a->level + 1, ps, 0, ps, qmap(), S(stream)));
+    out->level = a->level;
+    out->npoly = a->npoly;
+    out->scale = a->scale * p->scale;
+    return CKC_OK;
+}
+
+int tensor_impl(ckc_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, int level, hipStream_t s);
+
+extern "C" int ckc_tensor(ckc_ctx *c, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, void *stream) {
+    CKC_TRY(check_ct(c, a, "tensor"));
+    CKC_TRY(check_ct(c, b, "tensor"));
+    CKC_REQUIRE(out && out->d && out->d != a->d && out->d != b->d, CKC_EINVAL, "output must not alias");
+    CKC_REQUIRE(a->npoly == 2 && b->npoly == 2, CKC_ESHAPE, "tensor needs 2-poly inputs");
+    CKC_REQUIRE(a->level == b->level, CKC_ELEVEL, "levels differ");
+    CKC_TRY(tensor_impl(c, a->d, b->d, out->d, a->level, S(stream)));
+    out->level = a->level;
+    out->npoly = 3;
+    out->scale = a->scale * b->scale;
+    return CKC_OK;
+}
+
+extern "C" int ckc_relin(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream) {
+    CKC_TRY(check_ct(c, in, "relin"));
+    CKC_REQUIRE(evk && out && out->d, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(in->npoly == 3, CKC_ESHAPE, "relin needs a 3-poly ciphertext");
+    CKC_REQUIRE(evk->relin, CKC_ENOKEY, "no relinearisation key");
+    hipStream_t s = S(stream);
+    const size_t N = c->N;
+    const int nl = in->level + 1, nt = nl + c->np;
+    DevBuf digits;
+    CKC_TRY(digits.alloc(8 * N * nt * size_t(c->dnum_at(in->level)), s));
+    const size_t ps = size_t(nl) * N;
+    CKC_TRY(ks_modup(c, in->d + 2 * ps, in->level, digits.u64(), s));
+    CKC_TRY(ks_apply(c, digits.u64(), in->level, evk->relin->u64(), 1, in->d, in->d + ps, out->d, out->d + ps, s));
+    out->level = in->level;
+    out->npoly = 2;
+    out->scale = in->scale;
+    return CKC_OK;
+}
+
+extern "C" int ckc_rotate(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, const int32_t *steps, int n_steps,
+                          ckc_ct *out, void *stream) {
+    CKC_TRY(check_ct(c, in, "rotate"));
+    CKC_REQUIRE(evk && out && (n_steps == 0 || steps), CKC_EINVAL, "null argument");
+    CKC_REQUIRE(in->npoly == 2, CKC_ESHAPE, "rotation needs a 2-poly ciphertext");
+    hipStream_t s = S(stream);
+    const size_t N = c->N;
+    const int nl = in->level + 1, nt = nl + c->np;
+    const size_t ps = size_t(nl) * N;
+    bool need_ks = false;
+    for (int i = 0; i < n_steps; ++i) {
+        CKC_REQUIRE(out[i].d && out[i].d != in->d, CKC_EINVAL, "rotation output missing or aliasing the input");
+        const uint64_t g = galois_element(c, steps[i]);
+        if (g != 1) {
+            need_ks = true;
+            CKC_REQUIRE(evk->galois.count(g), CKC_ENOKEY, "missing Galois key for step " + std::to_string(steps[i]));
+        }
+    }
+    DevBuf digits;
+    if (need_ks) {
+        CKC_TRY(digits.alloc(8 * N * nt * size_t(c->dnum_at(in->level)), s));
+        CKC_TRY(ks_modup(c, in->d + ps, in->level, digits.u64(), s));
+    }
+    for (int i = 0; i < n_steps; ++i) {
+        const uint64_t g = galois_element(c, steps[i]);
+        if (g == 1) {
+            CKC_TRY(copy_limbs(in->d, 0, out[i].d, 0, 2 * ps, 1, s));
+        } else {
+            const uint64_t *key = evk->galois.at(g)->u64();
+            CKC_TRY(ks_apply_perm_add(c, digits.u64(), in->level, key, g, in->d, out[i].d, out[i].d + ps, s));
+        }
+        out[i].level = in->level;
+        out[i].npoly = 2;
+        out[i].scale = in->scale;
+    }
+    return CKC_OK;
+}
+
+extern "C" int ckc_rescale(ckc_ctx *c, const ckc_ct *in, ckc_ct *out, void *stream) {
+    CKC_TRY(check_ct(c, in, "rescale"));
+    CKC_REQUIRE(in->level >= 1, CKC_ELEVEL, "cannot rescale at level 0");
+    CKC_REQUIRE(out && out->d && out->d != in->d, CKC_EINVAL, "output missing or aliasing the input");
+    CKC_TRY(rescale_impl(c, in->d, in->npoly, in->level, out->d, S(stream)));
+    out->scale = in->scale / double(c->mods[in->level]);
+    out->level = in->level - 1;
+    out->npoly = in->npoly;
+    return CKC_OK;
+}
+
+extern "C" int ckc_mod_drop(ckc_ctx *c, const ckc_ct *in, int to_level, ckc_ct *out, void *stream) {
+    CKC_TRY(check_ct(c, in, "mod_drop"));
+    CKC_REQUIRE(out && out->d, CKC_EINVAL, "null output");
+    CKC_REQUIRE(to_level >= 0 && to_level <= in->level, CKC_ELEVEL, "bad target level");
+    const size_t N = c->N;
+    const size_t in_ps = size_t(in->level + 1) * N, out_ps = size_t(to_level + 1) * N;
+    hipStream_t s = S(stream);
+    if (out->d == in->d) {
+        // compact in place, poly by poly (poly 0 needs no move)
+        for (int p = 1; p < in->npoly; ++p) {
+            DevBuf tmp;
+            CKC_TRY(tmp.alloc(8 * out_ps, s));
+            CKC_TRY(copy_limbs(in->d + p * in_ps, 0, tmp.u64(), 0, out_ps, 1, s));
+            CKC_TRY(copy_limbs(tmp.u64(), 0, out->d + p * out_ps, 0, out_ps, 1, s));
+        }
+    } else {
+        CKC_TRY(copy_limbs(in->d, in_ps, out->d, out_ps, out_ps, in->npoly, s));
+    }
+    out->level = to_level;
+    out->npoly = in->npoly;
+    out->scale = in->scale;
+    return CKC_OK;
+}

@@ -1,0 +1,182 @@
+// Internal declarations of the gfx950 RNS-CKKS library (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ckkscnn.h"
+#include "modarith.h"
+
+// ---------------------------------------------------------------- errors
+void ckc_set_error(const std::string &msg);
+
+#define CKC_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t _e = (call);                                              \
+        if (_e != hipSuccess) {                                              \
+            ckc_set_error(std::string(#call) + ": " + hipGetErrorString(_e)); \
+            return CKC_EDEVICE;                                              \
+        }                                                                    \
+    } while (0)
+
+#define CKC_REQUIRE(cond, code, msg)  \
+    do {                              \
+        if (!(cond)) {                \
+            ckc_set_error(msg);       \
+            return (code);            \
+        }                             \
+    } while (0)
+
+#define CKC_TRY(expr)              \
+    do {                           \
+        int _rc = (expr);          \
+        if (_rc != CKC_OK) return _rc; \
+    } while (0)
+
+// ---------------------------------------------------------------- limb maps
+// Limb i of an array maps to prime index (i < nlow ? i : pbase + i - nlow).
+// A Q-only array uses nlow = INT32_MAX.  An extended basis at level l uses
+// nlow = l + 1, pbase = number of Q primes.
+struct LimbMap {
+    int32_t nlow;
+    int32_t pbase;
+    CKC_HD int prime(int i) const { return i < nlow ? i : pbase + (i - nlow); }
+};
+static inline LimbMap qmap() { return LimbMap{0x7fffffff, 0}; }
+
+// RAII device buffer from the stream-ordered allocator.
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    int alloc(size_t bytes, hipStream_t st) {
+        s = st;
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMallocAsync(&p, bytes, st);
+        if (e != hipSuccess) {
+            p = nullptr;
+            ckc_set_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
+            return CKC_ENOMEM;
+        }
+        return CKC_OK;
+    }
+    uint64_t *u64() const { return (uint64_t *)p; }
+};
+
+// Persistent device allocation owned by a handle.
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevMem() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t b) {
+        bytes = b;
+        hipError_t e = hipMalloc(&p, b ? b : 256);
+        if (e != hipSuccess) {
+            p = nullptr;
+            ckc_set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+            return CKC_ENOMEM;
+        }
+        return CKC_OK;
+    }
+    int upload(const void *h, size_t b) {
+        CKC_TRY(alloc(b));
+        CKC_HIP(hipMemcpy(p, h, b, hipMemcpyHostToDevice));
+        return CKC_OK;
+    }
+    uint64_t *u64() const { return (uint64_t *)p; }
+};
+
+// Fast basis conversion constants for a source set of primes S -> targets T:
+//   y_i = [x_i * (S/s_i)^-1]_{s_i};   out_t = sum_i y_i * (S/s_i mod t)  (mod t)
+struct BconvTable {
+    int ns = 0, nt = 0;
+    DevMem inv;   // [ns] (S/s_i)^-1 mod s_i
+    DevMem invp;  // [ns] Shoup companions
+    DevMem hat;   // [nt][ns] S/s_i mod t
+};
+
+struct ckc_ctx {
+    int logN = 0;
+    size_t N = 0;
+    int nq = 0, np = 0, alpha = 1;
+    std::vector<uint64_t> mods;     // Q primes then P primes
+    std::vector<Prime> primes_h;
+    std::vector<uint64_t> psi_h;    // chosen 2N-th roots
+    DevMem primes_d;                // Prime[nprimes]
+    DevMem tw, twp, itw, itwp;      // [nprimes][N] bit-reversed psi powers (+Shoup)
+    DevMem ninv;                    // [nprimes][2] N^-1 and its Shoup companion
+    // encoding FFT tables (host-computed with libm, uploaded)
+    DevMem fft_w;                   // [n/2] double2 (cos, sin) of 2 pi e / n
+    DevMem twist;                   // [n]   double2 (cos, sin) of pi k / N
+    DevMem slot_idx;                // [n]   uint32  t_j = (5^j mod 2N - 1)/4
+    // rescale: for level l, [i < l] (q_l^-1 mod q_i, Shoup)
+    DevMem rescale_inv;             // [nq][nq][2]
+    // ModDown P -> Q constants for every Q prime: P^-1 mod q_i (Shoup)
+    DevMem pinv;                    // [nq][2]
+    BconvTable p_to_q;              // P -> q_0..q_{nq-1}
+    // ModUp tables per (level, digit)
+    std::mutex mu;
+    std::map<std::pair<int, int>, std::unique_ptr<BconvTable>> modup_tabs;
+    std::map<uint64_t, std::unique_ptr<DevMem>> galois_perm;   // NTT-domain permutations
+
+    int nprimes() const { return nq + np; }
+    const Prime *dprimes() const { return (const Prime *)primes_d.p; }
+    int dnum_at(int level) const { return (level + 1 + alpha - 1) / alpha; }
+};
+
+struct ckc_sk {
+    uint64_t seed = 0;
+    std::vector<int8_t> s;          // ternary coefficients (host, client side)
+    DevMem s_ntt;                   // [nprimes][N] s in NTT form, every prime
+};
+
+struct ckc_evk {
+    int dnum = 0;
+    size_t key_words = 0;           // words per key: dnum * 2 * nprimes * N
+    std::unique_ptr<DevMem> relin;  // may be null
+    std::map<uint64_t, std::unique_ptr<DevMem>> galois;  // Galois element -> key
+};
+
+// ---------------------------------------------------------------- launchers
+// (all asynchronous on the given stream; data pointers are device pointers)
+int ntt_forward(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
+                hipStream_t s, int skip_lo = -1, int skip_hi = -1);
+int ntt_inverse(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
+                hipStream_t s);
+
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4 };
+// out[p][l] = a[p][l] op b[bp][l] over npoly polys of nlimbs limbs (prime l via map);
+// b_poly_stride = 0 broadcasts one b polynomial to every poly of a.
+int ew_binary(const ckc_ctx *c, EwOp op, uint64_t *out, const uint64_t *a, const uint64_t *b, int npoly,
+              int nlimbs, size_t a_poly_stride, size_t b_poly_stride, size_t out_poly_stride, LimbMap map,
+              hipStream_t s);
+
+const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc);
+const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc);
+uint64_t galois_element(const ckc_ctx *c, int64_t step);
+
+// Key switching pieces.
+// ModUp of d (NTT form, level+1 limbs) into digits [dnum_l][level+1+np][N] (NTT form).
+int ks_modup(ckc_ctx *c, const uint64_t *d, int level, uint64_t *digits, hipStream_t s);
+// Key inner product + ModDown: u_b = ModDown(sum_j sigma_g(digit_j) * key_j[b]),
+// then out0 = u_0 + add0, out1 = u_1 + add1 (add may be null).  NTT form.
+int ks_apply(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g,
+             const uint64_t *add0, const uint64_t *add1, uint64_t *out0, uint64_t *out1, hipStream_t s);
+int ks_apply_perm_add(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g,
+                      const uint64_t *c0_for_perm, uint64_t *out0, uint64_t *out1, hipStream_t s);
+
+int rescale_impl(ckc_ctx *c, const uint64_t *in, int npoly, int level, uint64_t *out, hipStream_t s);
+
+size_t words_ct(const ckc_ctx *c, int level, int npoly);

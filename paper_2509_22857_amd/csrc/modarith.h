@@ -1,0 +1,98 @@
+// Exact modular arithmetic on 64-bit RNS words for gfx950.
+//
+// Every prime q satisfies q < 2^62, so sums of two residues never wrap and
+// Shoup products land in [0, 2q).  All reductions are integer VALU work; no
+// floating point touches a residue.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CKC_HD __host__ __device__ __forceinline__
+
+struct u128v {
+    uint64_t lo, hi;
+};
+
+CKC_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+CKC_HD u128v mul64x64(uint64_t a, uint64_t b) {
+    u128v r;
+    r.lo = a * b;
+    r.hi = mulhi64(a, b);
+    return r;
+}
+
+CKC_HD u128v add128(u128v x, u128v y) {
+    u128v r;
+    r.lo = x.lo + y.lo;
+    r.hi = x.hi + y.hi + (r.lo < x.lo ? 1ull : 0ull);
+    return r;
+}
+
+// Per-prime constants.
+struct Prime {
+    uint64_t q;
+    uint64_t mu;    // floor(2^(2k) / q), k = bit length of q (Barrett)
+    uint64_t r2;    // 2^64 mod q
+    uint64_t r2p;   // floor(r2 * 2^64 / q)   (Shoup companion of r2)
+    uint64_t onep;  // floor(2^64 / q)        (Shoup companion of 1)
+    int32_t k;      // bit length of q
+    int32_t pad;
+};
+
+CKC_HD uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) {
+    uint64_t s = a + b;
+    return s >= q ? s - q : s;
+}
+CKC_HD uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) {
+    return a >= b ? a - b : a + q - b;
+}
+CKC_HD uint64_t neg_mod(uint64_t a, uint64_t q) { return a ? q - a : 0; }
+
+// Barrett reduction of x < 2^(2k) (k = bit length of q <= 62) into [0, q).
+CKC_HD uint64_t barrett128(u128v x, const Prime &P) {
+    const int k = P.k;
+    // x >> (k-1): < 2^(k+1)
+    uint64_t x1 = (x.lo >> (k - 1)) | (x.hi << (65 - k));
+    u128v t = mul64x64(x1, P.mu);
+    // >> (k+1)
+    uint64_t qh = (t.lo >> (k + 1)) | (t.hi << (63 - k));
+    uint64_t r = x.lo - qh * P.q;
+    if (r >= P.q) r -= P.q;
+    if (r >= P.q) r -= P.q;
+    return r;
+}
+
+CKC_HD uint64_t mul_mod(uint64_t a, uint64_t b, const Prime &P) {
+    return barrett128(mul64x64(a, b), P);
+}
+
+
+// Shoup multiplication by a constant w (w < q) with w' = floor(w 2^64 / q).
+// a may be any 64-bit word; result in [0, q).
+CKC_HD uint64_t mul_shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    uint64_t qh = mulhi64(a, wp);
+    uint64_t r = a * w - qh * q;
+    return r >= q ? r - q : r;
+}
+// Lazy variant: result in [0, 2q).
+CKC_HD uint64_t mul_shoup_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    uint64_t qh = mulhi64(a, wp);
+    return a * w - qh * q;
+}
+
+// Reduce any 128-bit value: hi*2^64 + lo = hi*(2^64 mod q) + lo  (mod q).
+CKC_HD uint64_t reduce128(u128v x, const Prime &P) {
+    uint64_t a = mul_shoup(x.hi, P.r2, P.r2p, P.q);
+    uint64_t b = mul_shoup(x.lo, 1, P.onep, P.q);
+    return add_mod(a, b, P.q);
+}
+
+// Reduce an arbitrary 64-bit word into [0, q) (Shoup multiplication by 1).
+CKC_HD uint64_t reduce64(uint64_t a, const Prime &P) { return mul_shoup(a, 1, P.onep, P.q); }

@@ -1,0 +1,461 @@
+// RNS kernels: limb-wise arithmetic, fast basis conversion, hybrid key
+// switching (ModUp, key inner product, ModDown) and rescale.
+//
+// Hybrid key switching (the special modulus P of Section 2.2): a polynomial d
+// at level l is split into digits of alpha primes; ModUp extends each digit to
+// every other prime of Q_l and P by fast basis conversion (no correction);
+// the key inner product sums digit x key over the digits; ModDown divides by
+// P with the floor-type conversion back from P.  For a rotation the Galois
+// automorphism acts on the ModUp output (in the NTT domain it is a
+// permutation of evaluation points), so one ModUp serves every step.
+#include <math.h>
+
+#include <algorithm>
+
+#include "ckc_internal.h"
+
+namespace {
+
+constexpr int kEwThreads = 256;
+
+__global__ __launch_bounds__(kEwThreads) void k_ew(int op, uint64_t *__restrict__ out,
+                                                   const uint64_t *__restrict__ a,
+                                                   const uint64_t *__restrict__ b, int nlimbs,
+                                                   size_t a_ps, size_t b_ps, size_t o_ps, LimbMap map,
+                                                   const Prime *__restrict__ primes, int logN) {
+    const int limb = blockIdx.y, poly = blockIdx.z;
+    const Prime P = primes[map.prime(limb)];
+    const size_t N = size_t(1) << logN;
+    const uint64_t *al = a + poly * a_ps + size_t(limb) * N;
+    const uint64_t *bl = b ? b + poly * b_ps + size_t(limb) * N : nullptr;
+    uint64_t *ol = out + poly * o_ps + size_t(limb) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        const uint64_t x = al[k];
+        uint64_t r;
+        switch (op) {
+            case EW_ADD: r = add_mod(x, bl[k], P.q); break;
+            case EW_SUB: r = sub_mod(x, bl[k], P.q); break;
+            case EW_MUL: r = mul_mod(x, bl[k], P); break;
+            case EW_NEG: r = neg_mod(x, P.q); break;
+            default: r = x; break;
+        }
+        ol[k] = r;
+    }
+}
+
+// Fast basis conversion: src limbs (coefficient form, consecutive, primes
+// given by src_map starting at src_first) -> target limb tt of dst.
+//   y_i = [x_i * inv_i]_{s_i};  out_t = sum_i y_i * hat[t][i]  (mod t)
+// Targets in [skip_lo, skip_hi) are left untouched.
+__global__ __launch_bounds__(256) void k_bconv(const uint64_t *__restrict__ src, int ns, int src_first,
+                                               LimbMap src_map, uint64_t *__restrict__ dst, LimbMap dst_map,
+                                               int skip_lo, int skip_hi, const uint64_t *__restrict__ inv,
+                                               const uint64_t *__restrict__ invp,
+                                               const uint64_t *__restrict__ hat,
+                                               const Prime *__restrict__ primes, int logN) {
+    const int tt = blockIdx.y;
+    if (tt >= skip_lo && tt < skip_hi) return;
+    const size_t N = size_t(1) << logN;
+    const Prime T = primes[dst_map.prime(tt)];
+    const uint64_t *h = hat + size_t(tt) * ns;
+    uint64_t *o = dst + size_t(tt) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        u128v acc{0, 0};
+        for (int i = 0; i < ns; ++i) {
+            const uint64_t si = primes[src_map.prime(src_first + i)].q;
+            const uint64_t y = mul_shoup(src[size_t(i) * N + k], inv[i], invp[i], si);
+            acc = add128(acc, mul64x64(y, h[i]));
+        }
+        o[k] = reduce128(acc, T);
+    }
+}
+
+// Key inner product over the extended basis of level l (nt = l+1+np limbs):
+//   acc_b[tt][k] = sum_j digit_j[tt][perm(k)] * key_j[b][prime(tt)][k]
+__global__ __launch_bounds__(256) void k_kip(const uint64_t *__restrict__ digits, int dnum, int nt,
+                                             const uint64_t *__restrict__ key, int nprimes, LimbMap map,
+                                             const uint32_t *__restrict__ perm, uint64_t *__restrict__ acc,
+                                             const Prime *__restrict__ primes, int logN) {
+    const int tt = blockIdx.y;
+    const size_t N = size_t(1) << logN;
+    const int pi = map.prime(tt);
+    const Prime P = primes[pi];
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        const size_t src = perm ? perm[k] : k;
+        u128v a0{0, 0}, a1{0, 0};
+        for (int j = 0; j < dnum; ++j) {
+            const uint64_t d = digits[(size_t(j) * nt + tt) * N + src];
+            const uint64_t kb = key[((size_t(j) * 2 + 0) * nprimes + pi) * N + k];
+            const uint64_t ka = key[((size_t(j) * 2 + 1) * nprimes + pi) * N + k];
+            a0 = add128(a0, mul64x64(d, kb));
+            a1 = add128(a1, mul64x64(d, ka));
+        }
+        acc[size_t(tt) * N + k] = reduce128(a0, P);
+        acc[(size_t(nt) + tt) * N + k] = reduce128(a1, P);
+    }
+}
+
+// ModDown combine: out_b[i] = (acc_b[i] - conv_b[i]) * P^-1 + add_b[perm(k)] (NTT form)
+__global__ __launch_bounds__(256) void k_moddown_combine(const uint64_t *__restrict__ acc, int nt,
+                                                         const uint64_t *__restrict__ conv, int nl,
+                                                         const uint64_t *__restrict__ pinv,
+                                                         const uint64_t *__restrict__ add0,
+                                                         const uint64_t *__restrict__ add1,
+                                                         const uint32_t *__restrict__ add_perm,
+                                                         uint64_t *__restrict__ out0, uint64_t *__restrict__ out1,
+                                                         const Prime *__restrict__ primes, int logN) {
+    const int i = blockIdx.y, b = blockIdx.z;
+    const size_t N = size_t(1) << logN;
+    const uint64_t q = primes[i].q;
+    const uint64_t pv = pinv[2 * i], pvp = pinv[2 * i + 1];
+    const uint64_t *x = acc + (size_t(b) * nt + i) * N;
+    const uint64_t *cv = conv + (size_t(b) * nl + i) * N;
+    const uint64_t *ad = b == 0 ? add0 : add1;
+    uint64_t *o = (b == 0 ? out0 : out1) + size_t(i) * N;
+    if (ad) ad += size_t(i) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        uint64_t r = mul_shoup(sub_mod(x[k], cv[k], q), pv, pvp, q);
+        if (ad) r = add_mod(r, ad[add_perm ? add_perm[k] : k], q);
+        o[k] = r;
+    }
+}
+
+// Rescale: centred top limb t (coefficient form) -> t mod q_i for i < l.
+__global__ __launch_bounds__(256) void k_rescale_lift(const uint64_t *__restrict__ top, int npoly,
+                                                      size_t top_ps, uint64_t *__restrict__ dst, int level,
+                                                      const Prime *__restrict__ primes, int logN) {
+    const int i = blockIdx.y, p = blockIdx.z;
+    const size_t N = size_t(1) << logN;
+    const uint64_t ql = primes[level].q, half = ql >> 1;
+    const Prime P = primes[i];
+    const uint64_t qlm = reduce64(ql, P);
+    const uint64_t *t = top + p * top_ps;
+    uint64_t *o = dst + (size_t(p) * level + i) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        const uint64_t v = t[k];
+        const uint64_t vm = reduce64(v, P);
+        o[k] = v > half ? sub_mod(vm, qlm, P.q) : vm;
+    }
+}
+
+// out[p][i] = (in[p][i] - lift[p][i]) * q_l^-1 mod q_i
+__global__ __launch_bounds__(256) void k_rescale_combine(const uint64_t *__restrict__ in, size_t in_ps,
+                                                         const uint64_t *__restrict__ lift,
+                                                         uint64_t *__restrict__ out, size_t out_ps, int level,
+                                                         const uint64_t *__restrict__ rinv,
+                                                         const Prime *__restrict__ primes, int logN, int nq) {
+    const int i = blockIdx.y, p = blockIdx.z;
+    const size_t N = size_t(1) << logN;
+    const uint64_t q = primes[i].q;
+    const uint64_t iv = rinv[(size_t(level) * nq + i) * 2], ivp = rinv[(size_t(level) * nq + i) * 2 + 1];
+    const uint64_t *x = in + p * in_ps + size_t(i) * N;
+    const uint64_t *t = lift + (size_t(p) * level + i) * N;
+    uint64_t *o = out + p * out_ps + size_t(i) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x)
+        o[k] = mul_shoup(sub_mod(x[k], t[k], q), iv, ivp, q);
+}
+
+__global__ void k_copy_limbs(const uint64_t *__restrict__ src, size_t src_ps, uint64_t *__restrict__ dst,
+                             size_t dst_ps, size_t words) {
+    const int p = blockIdx.y;
+    const uint64_t *s = src + p * src_ps;
+    uint64_t *d = dst + p * dst_ps;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += size_t(gridDim.x) * blockDim.x)
+        d[k] = s[k];
+}
+
+// out[t][k] = in[t][perm[k]]
+__global__ void k_permute(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+                          const uint32_t *__restrict__ perm, int logN) {
+    const int t = blockIdx.y;
+    const size_t N = size_t(1) << logN;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x)
+        out[size_t(t) * N + k] = in[size_t(t) * N + perm[k]];
+}
+
+// d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (NTT form)
+__global__ void k_tensor(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b, uint64_t *__restrict__ o,
+                         int nl, const Prime *__restrict__ primes, int logN) {
+    const int t = blockIdx.y;
+    const size_t N = size_t(1) << logN, ps = size_t(nl) * N;
+    const Prime P = primes[t];
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        const size_t i = size_t(t) * N + k;
+        const uint64_t a0 = a[i], a1 = a[ps + i], b0 = b[i], b1 = b[ps + i];
+        o[i] = mul_mod(a0, b0, P);
+        o[ps + i] = reduce128(add128(mul64x64(a0, b1), mul64x64(a1, b0)), P);
+        o[2 * ps + i] = mul_mod(a1, b1, P);
+    }
+}
+
+// c0 += v (the same residue at every NTT point: a constant polynomial)
+__global__ void k_add_const(const uint64_t *__restrict__ a, uint64_t *__restrict__ o,
+                            const uint64_t *__restrict__ v, const Prime *__restrict__ primes, int logN) {
+    const int t = blockIdx.y;
+    const size_t N = size_t(1) << logN;
+    const uint64_t q = primes[t].q, c = v[t];
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x)
+        o[size_t(t) * N + k] = add_mod(a[size_t(t) * N + k], c, q);
+}
+
+unsigned tiles_for(size_t N) { return unsigned(std::min<size_t>(N / 256, 64)); }
+
+// host helpers ------------------------------------------------------------
+uint64_t h_mulmod(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)(((unsigned __int128)a * b) % q); }
+uint64_t h_powmod(uint64_t a, uint64_t e, uint64_t q) {
+    uint64_t r = 1 % q;
+    a %= q;
+    while (e) {
+        if (e & 1) r = h_mulmod(r, a, q);
+        a = h_mulmod(a, a, q);
+        e >>= 1;
+    }
+    return r;
+}
+uint64_t h_inv(uint64_t a, uint64_t q) { return h_powmod(a, q - 2, q); }
+uint64_t h_shoup(uint64_t w, uint64_t q) { return (uint64_t)(((unsigned __int128)w << 64) / q); }
+
+}  // namespace
+
+int copy_limbs(const uint64_t *src, size_t src_ps, uint64_t *dst, size_t dst_ps, size_t words, int npoly,
+               hipStream_t s) {
+    if (words == 0 || npoly == 0) return CKC_OK;
+    hipLaunchKernelGGL(k_copy_limbs, dim3(unsigned(std::min<size_t>((words + 255) / 256, 2048)), unsigned(npoly)),
+                       dim3(256), 0, s, src, src_ps, dst, dst_ps, words);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+size_t words_ct(const ckc_ctx *c, int level, int npoly) { return size_t(npoly) * size_t(level + 1) * c->N; }
+
+int ew_binary(const ckc_ctx *c, EwOp op, uint64_t *out, const uint64_t *a, const uint64_t *b, int npoly,
+              int nlimbs, size_t a_ps, size_t b_ps, size_t o_ps, LimbMap map, hipStream_t s) {
+    if (npoly <= 0 || nlimbs <= 0) return CKC_OK;
+    hipLaunchKernelGGL(k_ew, dim3(tiles_for(c->N), unsigned(nlimbs), unsigned(npoly)), dim3(kEwThreads), 0, s,
+                       int(op), out, a, b, nlimbs, a_ps, b_ps, o_ps, map, c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+// Constants for ModUp of digit `digit` at `level`: source = the digit's
+// primes, targets = every limb of the extended basis (l+1 Q limbs, then P).
+const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc) {
+    std::lock_guard<std::mutex> g(c->mu);
+    auto key = std::make_pair(level, digit);
+    auto it = c->modup_tabs.find(key);
+    if (it != c->modup_tabs.end()) return it->second.get();
+    auto t = std::make_unique<BconvTable>();
+    const int lo = digit * c->alpha, hi = std::min(lo + c->alpha - 1, level);
+    const int ns = hi - lo + 1, nt = level + 1 + c->np;
+    std::vector<uint64_t> inv(ns), invp(ns), hat(size_t(nt) * ns);
+    for (int i = 0; i < ns; ++i) {
+        const uint64_t qi = c->mods[lo + i];
+        uint64_t prod = 1 % qi;
+        for (int j = 0; j < ns; ++j)
+            if (j != i) prod = h_mulmod(prod, c->mods[lo + j] % qi, qi);
+        inv[i] = h_inv(prod, qi);
+        invp[i] = h_shoup(inv[i], qi);
+    }
+    LimbMap m{level + 1, c->nq};
+    for (int tt = 0; tt < nt; ++tt) {
+        const uint64_t qt = c->mods[m.prime(tt)];
+        for (int i = 0; i < ns; ++i) {
+            uint64_t prod = 1 % qt;
+            for (int j = 0; j < ns; ++j)
+                if (j != i) prod = h_mulmod(prod, c->mods[lo + j] % qt, qt);
+            hat[size_t(tt) * ns + i] = prod;
+        }
+    }
+    t->ns = ns;
+    t->nt = nt;
+    if ((*rc = t->inv.upload(inv.data(), 8 * ns)) != CKC_OK) return nullptr;
+    if ((*rc = t->invp.upload(invp.data(), 8 * ns)) != CKC_OK) return nullptr;
+    if ((*rc = t->hat.upload(hat.data(), 8 * hat.size())) != CKC_OK) return nullptr;
+    const BconvTable *r = t.get();
+    c->modup_tabs[key] = std::move(t);
+    *rc = CKC_OK;
+    return r;
+}
+
+uint64_t galois_element(const ckc_ctx *c, int64_t step) {
+    const int64_t n = int64_t(c->N / 2);
+    const int64_t r = ((step % n) + n) % n;
+    const uint64_t M = 2 * c->N;
+    uint64_t g = 1;
+    for (int64_t i = 0; i < r; ++i) g = (g * 5) % M;
+    return g;
+}
+
+// NTT-domain permutation of sigma_g: index k holds a(psi^(2 brev(k) + 1)),
+// so sigma_g(a) at k is a at the index whose exponent is g (2 brev(k) + 1).
+const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->galois_perm.find(g);
+    if (it != c->galois_perm.end()) return it->second->u64();
+    const size_t N = c->N;
+    const int logN = c->logN;
+    auto brev = [logN](uint64_t x) {
+        uint64_t r = 0;
+        for (int i = 0; i < logN; ++i) r = (r << 1) | ((x >> i) & 1);
+        return r;
+    };
+    std::vector<uint32_t> perm(N);
+    const uint64_t mask = 2 * N - 1;
+    for (size_t k = 0; k < N; ++k) {
+        const uint64_t e = ((2 * brev(k) + 1) * g) & mask;
+        perm[k] = uint32_t(brev((e - 1) / 2));
+    }
+    auto m = std::make_unique<DevMem>();
+    if ((*rc = m->upload(perm.data(), 4 * N)) != CKC_OK) return nullptr;
+    const uint64_t *r = m->u64();
+    c->galois_perm[g] = std::move(m);
+    *rc = CKC_OK;
+    return r;
+}
+
+int ks_modup(ckc_ctx *c, const uint64_t *d, int level, uint64_t *digits, hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
+    DevBuf coeff;
+    CKC_TRY(coeff.alloc(8 * N * nl, s));
+    CKC_TRY(copy_limbs(d, 0, coeff.u64(), 0, N * nl, 1, s));
+    CKC_TRY(ntt_inverse(c, coeff.u64(), nl, qmap(), 1, 0, s));
+    const LimbMap ext{nl, c->nq};
+    for (int j = 0; j < dnum; ++j) {
+        int rc;
+        const BconvTable *t = modup_table(c, level, j, &rc);
+        if (!t) return rc;
+        const int lo = j * c->alpha, ns = t->ns;
+        uint64_t *dj = digits + size_t(j) * nt * N;
+        hipLaunchKernelGGL(k_bconv, dim3(tiles_for(N), unsigned(nt)), dim3(256), 0, s, coeff.u64() + size_t(lo) * N,
+                           ns, lo, qmap(), dj, ext, lo, lo + ns, t->inv.u64(), t->invp.u64(), t->hat.u64(),
+                           c->dprimes(), c->logN);
+        CKC_HIP(hipGetLastError());
+        CKC_TRY(ntt_forward(c, dj, nt, ext, 1, 0, s, lo, lo + ns));
+        // the digit's own limbs: the input limbs, already in NTT form
+        CKC_TRY(copy_limbs(d + size_t(lo) * N, 0, dj + size_t(lo) * N, 0, N * ns, 1, s));
+    }
+    return CKC_OK;
+}
+
+// Shared tail of key switching: KIP over digits, ModDown, combine.
+static int ks_core(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g,
+                   const uint64_t *add0, const uint64_t *add1, const uint32_t *add_perm, uint64_t *out0,
+                   uint64_t *out1, hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
+    const uint32_t *perm = nullptr;
+    if (g != 1) {
+        int rc;
+        perm = (const uint32_t *)galois_table(c, g, &rc);
+        if (!perm) return rc;
+    }
+    DevBuf acc, conv;
+    CKC_TRY(acc.alloc(8 * N * nt * 2, s));
+    CKC_TRY(conv.alloc(8 * N * nl * 2, s));
+    const LimbMap ext{nl, c->nq};
+    hipLaunchKernelGGL(k_kip, dim3(tiles_for(N), unsigned(nt)), dim3(256), 0, s, digits, dnum, nt, key,
+                       c->nprimes(), ext, perm, acc.u64(), c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    // ModDown: P limbs of both accumulators -> coefficient form -> convert to Q -> NTT
+    DevBuf pl;
+    CKC_TRY(pl.alloc(8 * N * c->np * 2, s));
+    CKC_TRY(copy_limbs(acc.u64() + size_t(nl) * N, size_t(nt) * N, pl.u64(), size_t(c->np) * N, N * c->np, 2, s));
+    const LimbMap pmap{0, c->nq};
+    CKC_TRY(ntt_inverse(c, pl.u64(), c->np, pmap, 2, size_t(c->np) * N, s));
+    for (int b = 0; b < 2; ++b) {
+        hipLaunchKernelGGL(k_bconv, dim3(tiles_for(N), unsigned(nl)), dim3(256), 0, s,
+                           pl.u64() + size_t(b) * c->np * N, c->np, 0, pmap, conv.u64() + size_t(b) * nl * N,
+                           qmap(), -1, -1, c->p_to_q.inv.u64(), c->p_to_q.invp.u64(), c->p_to_q.hat.u64(),
+                           c->dprimes(), c->logN);
+        CKC_HIP(hipGetLastError());
+    }
+    CKC_TRY(ntt_forward(c, conv.u64(), nl, qmap(), 2, size_t(nl) * N, s));
+    hipLaunchKernelGGL(k_moddown_combine, dim3(tiles_for(N), unsigned(nl), 2), dim3(256), 0, s, acc.u64(), nt,
+                       conv.u64(), nl, c->pinv.u64(), add0, add1, add_perm, out0, out1, c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+int ks_apply(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g, const uint64_t *add0,
+             const uint64_t *add1, uint64_t *out0, uint64_t *out1, hipStream_t s) {
+    return ks_core(c, digits, level, key, g, add0, add1, nullptr, out0, out1, s);
+}
+
+int ks_apply_perm_add(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g,
+                      const uint64_t *c0_for_perm, uint64_t *out0, uint64_t *out1, hipStream_t s) {
+    int rc;
+    const uint32_t *perm = (const uint32_t *)galois_table(c, g, &rc);
+    if (!perm) return rc;
+    return ks_core(c, digits, level, key, g, c0_for_perm, nullptr, perm, out0, out1, s);
+}
+
+int rescale_impl(ckc_ctx *c, const uint64_t *in, int npoly, int level, uint64_t *out, hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1;
+    DevBuf top, lift;
+    CKC_TRY(top.alloc(8 * N * npoly, s));
+    CKC_TRY(lift.alloc(8 * N * npoly * level, s));
+    CKC_TRY(copy_limbs(in + size_t(level) * N, size_t(nl) * N, top.u64(), N, N, npoly, s));
+    const LimbMap one{0, level};  // every limb of `top` is prime q_level
+    CKC_TRY(ntt_inverse(c, top.u64(), 1, one, npoly, N, s));
+    hipLaunchKernelGGL(k_rescale_lift, dim3(tiles_for(N), unsigned(level), unsigned(npoly)), dim3(256), 0, s,
+                       top.u64(), npoly, N, lift.u64(), level, c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    CKC_TRY(ntt_forward(c, lift.u64(), level, qmap(), npoly, size_t(level) * N, s));
+    hipLaunchKernelGGL(k_rescale_combine, dim3(tiles_for(N), unsigned(level), unsigned(npoly)), dim3(256), 0, s,
+                       in, size_t(nl) * N, lift.u64(), out, size_t(level) * N, level, c->rescale_inv.u64(),
+                       c->dprimes(), c->logN, c->nq);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+int permute_limbs(const ckc_ctx *c, const uint64_t *src, uint64_t *dst, int nlimbs, const uint32_t *perm,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_permute, dim3(tiles_for(c->N), unsigned(nlimbs)), dim3(256), 0, s, src, dst, perm, c->logN);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+int tensor_impl(ckc_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, int level, hipStream_t s) {
+    hipLaunchKernelGGL(k_tensor, dim3(tiles_for(c->N), unsigned(level + 1)), dim3(256), 0, s, a, b, out, level + 1,
+                       c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+// exact residues of round(value * scale) (an integer-valued double) per Q prime
+static uint64_t h_dint_mod(double v, uint64_t q) {
+    const double av = fabs(v);
+    uint64_t r;
+    if (av < 9.2e18) {
+        r = uint64_t(av) % q;
+    } else {
+        int e;
+        const double mant = frexp(av, &e);
+        const uint64_t M = uint64_t(ldexp(mant, 53));
+        r = h_mulmod(M % q, h_powmod(2, uint64_t(e - 53), q), q);
+    }
+    return (v < 0 && r) ? q - r : r;
+}
+
+int add_const_impl(ckc_ctx *c, const ckc_ct *a, double value, ckc_ct *out, hipStream_t s) {
+    const int nl = a->level + 1;
+    const size_t ps = size_t(nl) * c->N;
+    const double v = round(value * a->scale);
+    std::vector<uint64_t> res(nl);
+    for (int t = 0; t < nl; ++t) res[t] = h_dint_mod(v, c->mods[t]);
+    DevBuf rb;
+    CKC_TRY(rb.alloc(8 * nl, s));
+    CKC_HIP(hipMemcpyAsync(rb.p, res.data(), 8 * nl, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_add_const, dim3(tiles_for(c->N), unsigned(nl)), dim3(256), 0, s, a->d, out->d, rb.u64(),
+                       c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    if (out->d != a->d) CKC_TRY(copy_limbs(a->d + ps, 0, out->d + ps, 0, ps * (a->npoly - 1), 1, s));
+    // the host residues must outlive the async copy
+    CKC_HIP(hipStreamSynchronize(s));
+    out->level = a->level;
+    out->npoly = a->npoly;
+    out->scale = a->scale;
+    return CKC_OK;
+}

@@ -1,0 +1,167 @@
+"""GPU <-> oracle parity of the RNS-CKKS primitives, through the C-ABI.
+
+Every comparison is bit-exact in coefficient form (the GPU keeps ciphertexts
+in NTT form; the test converts them back with the library's own inverse NTT,
+whose correctness is pinned separately against direct evaluation).
+"""
+import numpy as np
+import pytest
+
+from workloads import gen
+from workloads.params import tiny, micro
+
+pytestmark = pytest.mark.gpu
+
+
+def _bitrev(x, bits):
+    r = 0
+    for _ in range(bits):
+        r = (r << 1) | (x & 1)
+        x >>= 1
+    return r
+
+
+def _eval(a, x, q):
+    v = 0
+    for c in reversed([int(t) for t in a]):
+        v = (v * x + c) % q
+    return v
+
+
+@pytest.fixture(scope="module", params=["tiny", "micro"])
+def env(request):
+    import torch
+    from paper_2509_22857_amd.ckks import Context
+    from oracle.ckks import Oracle
+    ps = tiny() if request.param == "tiny" else micro()
+    print(f"[env] params={ps.name} N={ps.N} nq={len(ps.q)} np={len(ps.p)}", flush=True)
+    ctx = Context.from_params(ps)
+    orc = Oracle.from_params(ps)
+    return ps, ctx, orc, torch
+
+
+def test_ntt_evaluation_order_and_roundtrip(env):
+    ps, ctx, orc, torch = env
+    nl = len(ps.q)
+    a = gen.random_limbs(101, ps.q, ps.N)
+    buf = ctx.upload_words(a)
+    ctx.ntt(buf, 1, nl, False)
+    torch.cuda.synchronize()
+    A = ctx.download_words(buf).reshape(nl, ps.N)
+    for l in (0, nl - 1):
+        q, psi = ps.q[l], ctx.root(l)
+        assert pow(psi, ps.N, q) == q - 1
+        for k in (0, 1, ps.N // 2 + 3, ps.N - 1):
+            assert int(A[l, k]) == _eval(a[l], pow(psi, 2 * _bitrev(k, ps.logN) + 1, q), q)
+    ctx.ntt(buf, 1, nl, True)
+    torch.cuda.synchronize()
+    assert np.array_equal(ctx.download_words(buf).reshape(nl, ps.N), a)
+
+
+def test_mul_plain_matches_oracle_products(env):
+    ps, ctx, orc, torch = env
+    level = len(ps.q) - 1 if ps.name == "tiny" else 3
+    ct = gen.random_ct(7, ps.q, level, ps.N)
+    pt = gen.random_limbs(8, ps.q[:level + 1], ps.N)
+    g = ctx.mul_plain(ctx.ct_from_coeff(ct, level, 1.0), ctx.pt_from_coeff(pt, level, 1.0))
+    got = ctx.ct_to_coeff(g)
+    from oracle.ckks import Ct, Pt
+    want = orc.mul_plain(Ct(ct, level, 1.0), Pt(pt, level, 1.0))
+    assert np.array_equal(got, want.data)
+
+
+def test_secret_encode_encrypt_bit_exact(env):
+    ps, ctx, orc, torch = env
+    seed = 4242
+    keys = ctx.keygen(seed, [])
+    sk = orc.secret_key(seed)
+    level = len(ps.q) - 1
+    z = gen.uniform_slots(5, ps.N // 2)
+    pt = ctx.encode(z, level, 2.0 ** 40)
+    opt = orc.encode(z, level, 2.0 ** 40)
+    assert np.array_equal(ctx.pt_to_coeff(pt), opt.data)
+    ct = ctx.encrypt(keys, pt, 77)
+    oct_ = orc.encrypt(opt, sk, 77)
+    assert np.array_equal(ctx.ct_to_coeff(ct), oct_.data)
+    dec = ctx.decrypt(keys, ct)
+    assert np.array_equal(ctx.pt_to_coeff(dec), orc.decrypt(oct_, sk))
+    zz = ctx.decode(dec)
+    assert np.max(np.abs(zz - z)) < 1e-6
+    assert np.max(np.abs(zz - orc.decode(orc.decrypt(oct_, sk), oct_.scale))) < 1e-9
+
+
+def test_tensor_relin_rescale_bit_exact(env):
+    ps, ctx, orc, torch = env
+    from oracle.ckks import Ct
+    seed = 99
+    keys = ctx.keygen(seed, [])
+    sk = orc.secret_key(seed)
+    level = len(ps.q) - 1 if ps.name == "tiny" else 5
+    a = gen.random_ct(11, ps.q, level, ps.N)
+    b = gen.random_ct(12, ps.q, level, ps.N)
+    ga, gb = ctx.ct_from_coeff(a, level, 2.0 ** 40), ctx.ct_from_coeff(b, level, 2.0 ** 40)
+    t = ctx.tensor(ga, gb)
+    ot = orc.tensor(Ct(a, level, 2.0 ** 40), Ct(b, level, 2.0 ** 40))
+    assert np.array_equal(ctx.ct_to_coeff(t), ot.data)
+    r = ctx.relin(keys, t)
+    orr = orc.relin(ot, orc.relin_key(sk))
+    assert np.array_equal(ctx.ct_to_coeff(r), orr.data)
+    rs = ctx.rescale(r)
+    ors = orc.rescale(orr)
+    assert rs.level == ors.level and rs.scale == ors.scale
+    assert np.array_equal(ctx.ct_to_coeff(rs), ors.data)
+
+
+def test_hoisted_rotations_bit_exact(env):
+    ps, ctx, orc, torch = env
+    from oracle.ckks import Ct
+    seed = 5
+    steps = [1, -1, 31, 0] if ps.name == "tiny" else [1, -33]
+    keys = ctx.keygen(seed, steps)
+    sk = orc.secret_key(seed)
+    level = len(ps.q) - 1 if ps.name == "tiny" else 4
+    a = gen.random_ct(13, ps.q, level, ps.N)
+    outs = ctx.rotate(keys, ctx.ct_from_coeff(a, level, 1.0), steps)
+    for r, o in zip(steps, outs):
+        g = orc.galois_elt(r)
+        gk = orc.galois_key(sk, g) if g != 1 else None
+        want = orc.rotate(Ct(a, level, 1.0), r, gk)
+        assert np.array_equal(ctx.ct_to_coeff(o), want.data), r
+
+
+def test_add_const_mod_drop_add_plain(env):
+    ps, ctx, orc, torch = env
+    from oracle.ckks import Ct, Pt
+    level = len(ps.q) - 1 if ps.name == "tiny" else 3
+    a = gen.random_ct(21, ps.q, level, ps.N)
+    b = gen.random_ct(22, ps.q, level, ps.N)
+    s = 2.0 ** 70
+    ga = ctx.ct_from_coeff(a, level, s)
+    gc = ctx.add_const(ga, -0.3125)
+    assert np.array_equal(ctx.ct_to_coeff(gc), orc.add_const(Ct(a, level, s), -0.3125).data)
+    gs = ctx.sub(ga, ctx.ct_from_coeff(b, level, s))
+    assert np.array_equal(ctx.ct_to_coeff(gs), orc.sub(Ct(a, level, s), Ct(b, level, s)).data)
+    p = gen.random_limbs(23, ps.q[:level + 1], ps.N)
+    gp = ctx.add_plain(ga, ctx.pt_from_coeff(p, level, s))
+    assert np.array_equal(ctx.ct_to_coeff(gp), orc.add_plain(Ct(a, level, s), Pt(p, level, s)).data)
+    gd = ctx.mod_drop(ga, level - 1)
+    assert np.array_equal(ctx.ct_to_coeff(gd), orc.mod_drop(Ct(a, level, s), level - 1).data)
+
+
+def test_errors_are_reported(env):
+    ps, ctx, orc, torch = env
+    from paper_2509_22857_amd.ckks import CkcError
+    level = 1
+    a = ctx.ct_from_coeff(gen.random_ct(1, ps.q, level, ps.N), level, 1.0)
+    b = ctx.ct_from_coeff(gen.random_ct(2, ps.q, level, ps.N), level, 2.0)
+    with pytest.raises(CkcError) as e:
+        ctx.add(a, b)
+    assert e.value.code == -3
+    keys = ctx.keygen(1, [])
+    with pytest.raises(CkcError) as e:
+        ctx.rotate(keys, a, [3])
+    assert e.value.code == -4
+    z = ctx.mod_drop(a, 0)
+    with pytest.raises(CkcError) as e:
+        ctx.rescale(z)
+    assert e.value.code == -2
