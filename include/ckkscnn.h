@@ -76,7 +76,7 @@ const char *ckc_last_error(void);
  * Every modulus must be a prime < 2^62 with q = 1 mod 2N, all distinct.
  * alpha = primes per key-switching digit (dnum = ceil(n_q / alpha)); the
  * product of the special primes should exceed every digit's product for
- * small key-switching noise.  log_n in [10, 16].  Errors: CKC_EINVAL,
+ * small key-switching noise.  log_n in [12, 16].  Errors: CKC_EINVAL,
  * CKC_EUNSUPPORTED, CKC_ENOMEM, CKC_EDEVICE.
  */
 int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint64_t *p, int n_p, int alpha,
@@ -161,6 +161,104 @@ int ckc_rotate(ckc_ctx *ctx, const ckc_evk *evk, const ckc_ct *in, const int32_t
 int ckc_rescale(ckc_ctx *ctx, const ckc_ct *in, ckc_ct *out, void *stream);
 /* keep limbs q_0..q_to_level (value and scale unchanged) */
 int ckc_mod_drop(ckc_ctx *ctx, const ckc_ct *in, int to_level, ckc_ct *out, void *stream);
+
+
+/* ------------------------------------------------------------------ batches
+ * Batched forms of rescale and addition (one launch per 64 ciphertexts).
+ * ckc_rescale_many: out[i] = rescale(in[i]); out[i].d must not alias in[j].d.
+ * ckc_add_many: out[i] = a[i] + b[i] (equal levels, scales within 2^-30;
+ * out may alias a or b). */
+int ckc_rescale_many(ckc_ctx *ctx, const ckc_ct *in, int n, ckc_ct *out, void *stream);
+int ckc_add_many(ckc_ctx *ctx, const ckc_ct *a, const ckc_ct *b, int n, ckc_ct *out, void *stream);
+
+/* ------------------------------------------------------------------ layers
+ * HW layout (Section 5.1, Data Layout): every channel is its own
+ * ciphertext.  Ensemble member m (Section 5.3) owns the slot block
+ * [m*block, (m+1)*block); logical pixel (r, c) of a channel with valid grid
+ * height x width sits at slot m*block + gap*(r*row_stride + c).  Convolution
+ * and pooling leave gaps instead of re-packing (lazy mapping): the output of a
+ * stride-s layer has gap*s.  Slots outside the valid grid hold values that
+ * no consumer reads (every mask is zero there).
+ */
+typedef struct {
+    int32_t block;      /* slots per ensemble member (power of two) */
+    int32_t row_stride; /* slot distance of vertically adjacent pixels at gap 1 */
+    int32_t gap;        /* current gap */
+    int32_t height;     /* valid grid height */
+    int32_t width;      /* valid grid width */
+    int32_t members;    /* ensemble members packed side by side */
+} ckc_layout;
+
+/*
+ * Convolution layer, ksize in {1, 3}, 'same' zero padding, stride in {1, 2},
+ * with clustered weights (Section 5.2, slice clustering; slice ensemble
+ * clustering in Section 5.3).  codebook: [ksize][n_centroids][members] -- one codebook per kernel
+ * column (a slice), each centroid a vector over the ensemble members; idx:
+ * [out_ch][in_ch][ksize][ksize] centroid indices into the codebook of the
+ * tap's column.  bias: [members][out_ch] or NULL.
+ * Every (tap, centroid) pair is encoded once into a plaintext codebook at
+ * `level` and scale pt_scale: the centroid's member values on the slots of
+ * the output grid whose input pixel for that tap lies inside the image.
+ * The bias plaintext is encoded at bias_scale on the output grid.
+ * The layer copies every host array.  Errors: CKC_EINVAL, CKC_ESHAPE,
+ * CKC_ENOMEM, CKC_EDEVICE.
+ */
+int ckc_layer_create_conv(ckc_ctx *ctx, const ckc_layout *in, int out_ch, int in_ch, int ksize, int stride,
+                          int n_centroids, const double *codebook, const uint16_t *idx, const double *bias,
+                          int level, double pt_scale, double bias_scale, ckc_layer **out, void *stream);
+/*
+ * out[img][o] = sum_t sum_c PT[t][c] * (sum_{i : idx[o][i][t] = c} Rot_{step(t)}(in[img][i])) + bias_o
+ * with step(t) = gap*(dh*row_stride + dw) for tap t = (dh, dw); one hoisted
+ * rotation group per input ciphertext.  in: [n_img][in_ch] 2-poly
+ * ciphertexts at the layer's level with equal scales; out: [n_img][out_ch]
+ * caller buffers of ckc_ct_words(level, 2).  Result scale = in scale *
+ * pt_scale, level unchanged (no rescale).  CKC_ENOKEY if a tap's Galois key
+ * is missing.
+ */
+int ckc_eval_conv(ckc_ctx *ctx, const ckc_evk *evk, const ckc_layer *layer, const ckc_ct *in, int n_img,
+                  ckc_ct *out, void *stream);
+
+/*
+ * Quadratic activation (Section 2.3; weight redistribution, Section 4.2,
+ * makes it monic): y = x^2 + b x + c per (channel, member),
+ * evaluated as t = x + b, y = Relin(x * t) + c.  b and c: [members][channels];
+ * for members == 1 they are added as constant polynomials, otherwise as
+ * block-constant plaintexts.  The leading coefficient a_absorb is absorbed
+ * into the scale: result scale = in_scale^2 / a_absorb (1.0 when the
+ * coefficient was redistributed into the next layer).  Consumes no level.
+ */
+int ckc_layer_create_act(ckc_ctx *ctx, const ckc_layout *layout, int channels, const double *b, const double *c,
+                         double a_absorb, int level, double in_scale, ckc_layer **out, void *stream);
+int ckc_eval_quad_act(ckc_ctx *ctx, const ckc_evk *evk, const ckc_layer *layer, const ckc_ct *in, int n_img,
+                      ckc_ct *out, void *stream);
+
+/*
+ * Dense layer after a global average pooling whose divisor is folded into
+ * w (Section 4.2): for every input channel S_c = rotation-sum of in[c] over
+ * the valid grid (steps gap*2^j, then gap*row_stride*2^j, ascending), then
+ * out[k] = sum_c PT[k][c] * S_c + bias_k, where PT[k][c] holds w[m][k][c] in
+ * slot m*block of member m.  w: [members][classes][in_ch]; bias:
+ * [members][classes] or NULL.  Member m's logit for class k is slot m*block
+ * of out[img][k].  Result scale = in scale * pt_scale.
+ */
+int ckc_layer_create_dense(ckc_ctx *ctx, const ckc_layout *in, int classes, int in_ch, const double *w,
+                           const double *bias, int level, double pt_scale, double bias_scale, ckc_layer **out,
+                           void *stream);
+int ckc_eval_dense(ckc_ctx *ctx, const ckc_evk *evk, const ckc_layer *layer, const ckc_ct *in, int n_img,
+                   ckc_ct *out, void *stream);
+
+/* 2x2 sum pooling (average pooling with the divisor folded into the next
+ * layer, Section 4.2): y = x + Rot_g x + Rot_{g*row_stride} x +
+ * Rot_{g*(row_stride+1)} x; the output layout has gap 2g. */
+int ckc_eval_avgpool2(ckc_ctx *ctx, const ckc_evk *evk, const ckc_layout *layout, const ckc_ct *in, int n,
+                      ckc_ct *out, void *stream);
+
+/* rotation steps a layer needs Galois keys for (returns the count; writes at
+ * most max of them), and the layout of its output */
+int ckc_layer_steps(const ckc_layer *layer, int32_t *steps, int max);
+int ckc_layer_out_layout(const ckc_layer *layer, ckc_layout *out);
+size_t ckc_layer_bytes(const ckc_layer *layer);
+int ckc_layer_destroy(ckc_layer *layer);
 
 #ifdef __cplusplus
 }

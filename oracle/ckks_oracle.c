@@ -548,6 +548,62 @@ void oc_rescale(const oc_ctx *c, const uint64_t *x, int npoly, int level, uint64
 /*   y[t_j] = z_j;  Y = unnormalised inverse DFT (radix-2 DIT below);         */
 /*   w_k = Y_k * (cos(pi k/N)/n, -sin(pi k/N)/n);  m = round(Delta * w).       */
 /* ------------------------------------------------------------------------ */
+/*
+ * Canonical twiddles: (cos, sin)(2 pi j / M) for integers 0 <= j < M/2 and
+ * M a power of two, computed with IEEE +, -, *, / only in one fixed order so
+ * that every implementation gets the same bits (libm's cos/sin are not
+ * bitwise reproducible across compilers).  The angle is folded into
+ * [0, pi/4] by octant symmetry; cos and sin there are Taylor series
+ * (12 terms) evaluated by Horner's rule.
+ */
+static void taylor_cs(double x, double *c, double *s) {
+    /* signed coefficients (-1)^i / (2i)! and (-1)^i / (2i+1)!, by a chain of divisions */
+    double ca[12], sa[12];
+    double fc = 1.0, fs = 1.0;
+    for (int i = 0; i < 12; ++i) {
+        if (i > 0) {
+            fc = fc / (double)((2 * i - 1) * (2 * i));
+            fs = fs / (double)((2 * i) * (2 * i + 1));
+        }
+        ca[i] = (i & 1) ? -fc : fc;
+        sa[i] = (i & 1) ? -fs : fs;
+    }
+    double y = x * x, pc = ca[11], ps = sa[11];
+    for (int i = 10; i >= 0; --i) {
+        pc = pc * y;
+        pc = pc + ca[i];
+        ps = ps * y;
+        ps = ps + sa[i];
+    }
+    *c = pc;
+    *s = x * ps;
+}
+
+static void canon_cs(uint64_t j, uint64_t M, double *c, double *s) {
+    const double step = (2.0 * OC_PI) / (double)M;
+    uint64_t o8 = M / 8, o4 = M / 4, o38 = 3 * (M / 8), o2 = M / 2;
+    double a, b;
+    if (j <= o8) {
+        taylor_cs((double)j * step, &a, &b);
+        *c = a;
+        *s = b;
+    } else if (j <= o4) {
+        taylor_cs((double)(o4 - j) * step, &a, &b);
+        *c = b;
+        *s = a;
+    } else if (j <= o38) {
+        taylor_cs((double)(j - o4) * step, &a, &b);
+        *c = -b;
+        *s = a;
+    } else {
+        taylor_cs((double)(o2 - j) * step, &a, &b);
+        *c = -a;
+        *s = b;
+    }
+}
+
+void oc_canon_cs(uint64_t j, uint64_t M, double *c, double *s) { canon_cs(j, M, c, s); }
+
 static void fft_dit(double *re, double *im, size_t n, int inverse) {
     /* bit-reversal permutation */
     for (size_t i = 1, j = 0; i < n; ++i) {
@@ -568,8 +624,9 @@ static void fft_dit(double *re, double *im, size_t n, int inverse) {
         for (size_t i = 0; i < n; i += len) {
             for (size_t j = 0; j < half; ++j) {
                 size_t e = j * step; /* twiddle exponent, < n/2 */
-                double ang = ((double)(2 * e) / (double)n) * OC_PI;
-                double wr = cos(ang), wi = inverse ? -sin(ang) : sin(ang);
+                double wr, ws;
+                canon_cs(e, n, &wr, &ws);
+                double wi = inverse ? -ws : ws;
                 double xr = re[i + j + half], xi = im[i + j + half];
                 double vr = xr * wr - xi * wi;
                 double vi = xr * wi + xi * wr;
@@ -609,8 +666,9 @@ void oc_encode(const oc_ctx *c, const double *z_re, const double *z_im, size_t n
     }
     fft_dit(re, im, n, 1);
     for (size_t k = 0; k < n; ++k) {
-        double ang = ((double)k / (double)N) * OC_PI;
-        double tr = cos(ang) * (1.0 / (double)n), ti = -sin(ang) * (1.0 / (double)n);
+        double cz, sz;
+        canon_cs(k, 2 * N, &cz, &sz);
+        double tr = cz * (1.0 / (double)n), ti = -sz * (1.0 / (double)n);
         double wr = re[k] * tr - im[k] * ti;
         double wi = re[k] * ti + im[k] * tr;
         re[k] = wr;
@@ -637,8 +695,8 @@ void oc_decode(const oc_ctx *c, const double *mcoef /* [N] */, double scale, dou
     size_t N = c->N, n = N / 2;
     double *re = (double *)malloc(n * sizeof(double)), *im = (double *)malloc(n * sizeof(double));
     for (size_t k = 0; k < n; ++k) {
-        double ang = ((double)k / (double)N) * OC_PI;
-        double tr = cos(ang), ti = sin(ang);
+        double tr, ti;
+        canon_cs(k, 2 * N, &tr, &ti);
         double ar = mcoef[k], ai = mcoef[k + n];
         re[k] = ar * tr - ai * ti;
         im[k] = ar * ti + ai * tr;

@@ -1,0 +1,246 @@
+"""Oracle evaluation of an encrypted CNN -- TEST INFRASTRUCTURE ONLY.
+
+Written independently of the GPU runner from the paper's method:
+  * HW layout (Section 5.1): channel -> ciphertext, member m's copy of the
+    grid in slot block m, pixel (r, c) at slot m*block + gap*(r*row_stride + c);
+  * convolution: every weight w[o][i][dh][dw] (a vector over members, taken
+    from the clustered codebook, Sections 5.2-5.3) is encoded on the output
+    slots whose input pixel lies inside the image, and multiplies the input
+    rotated by gap*(dh*row_stride + dw); all products are summed, plus the
+    bias on the output grid.  This is the unclustered sum; grouping equal
+    centroids first gives the same ring element;
+  * activation x^2 + b x + c: t = x + b, y = Relin(x * t) + c (Section 4.2
+    makes it monic), scale s^2 / a_absorb;
+  * dense: rotation sums over the grid, then per class the weighted sum of
+    the channel sums, plus bias (member values at slot m*block);
+  * tower reuse (Section 4.3): rescale after a multiplicative layer iff the
+    sublevel of its scale exceeds the sublevel of the prime to drop.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .ckks import Oracle, Ct, Pt, SecretKey
+
+
+def _lam(s, delta):
+    return int(round(math.log2(s) / math.log2(delta)))
+
+
+class OracleNetwork:
+    def __init__(self, orc: Oracle, spec: dict, delta: float, target: float, in_scale: float):
+        self.o, self.spec = orc, spec
+        self.delta, self.target, self.in_scale = delta, target, in_scale
+        C, H, W = spec["image"]
+        self.B = spec["layout"]["block"]
+        self.W0 = spec["layout"]["row_stride"]
+        self.M = spec["members"]
+        self.input_grid = dict(gap=1, H=H, W=W)
+
+    # ------------------------------------------------------------ slots
+    def _slot(self, m, r, c, gap):
+        return m * self.B + gap * (r * self.W0 + c)
+
+    def _vec(self):
+        return np.zeros(self.o.N // 2)
+
+    def encode(self, v, level, scale) -> Pt:
+        return self.o.encode(v, level, scale)
+
+    def _rescale_needed(self, level, scale):
+        return level >= 1 and _lam(scale, self.delta) > _lam(float(self.o.q[level]), self.delta)
+
+    # ------------------------------------------------------------ client
+    def encrypt_image(self, sk: SecretKey, img: np.ndarray, stream_base: int):
+        C, H, W = self.spec["image"]
+        cts = []
+        for c in range(C):
+            v = self._vec()
+            for m in range(self.M):
+                for r in range(H):
+                    for col in range(W):
+                        v[self._slot(m, r, col, 1)] = img[c, r, col]
+            pt = self.encode(v, self.o.L, self.in_scale)
+            cts.append(self.o.encrypt(pt, sk, stream_base + c))
+        return cts
+
+    # ------------------------------------------------------------ layers
+    def conv(self, xs, grid, ly, pt_scale, bias_scale, gkeys, with_bias=True):
+        o = self.o
+        k = ly["ksize"]
+        half = k // 2
+        s = ly["stride"]
+        g, H, W = grid["gap"], grid["H"], grid["W"]
+        Ho, Wo, go = H // s, W // s, g * s
+        level = xs[0].level
+        cb, idx = ly["codebook"], ly["idx"]
+        # rotated inputs per tap
+        rot = {}
+        for i, x in enumerate(xs):
+            for dh in range(-half, half + 1):
+                for dw in range(-half, half + 1):
+                    step = g * (dh * self.W0 + dw)
+                    gk = gkeys.get(o.galois_elt(step)) if step else None
+                    rot[(i, dh, dw)] = o.rotate(x, step, gk)
+        # plaintext of a weight vector on a tap's mask
+        cache = {}
+
+        def wpt(dh, dw, wvec):
+            key = (dh, dw, tuple(wvec))
+            if key not in cache:
+                v = self._vec()
+                for m in range(self.M):
+                    for r in range(Ho):
+                        if not 0 <= s * r + dh < H:
+                            continue
+                        for c in range(Wo):
+                            if 0 <= s * c + dw < W:
+                                v[self._slot(m, r, c, go)] = wvec[m]
+                cache[key] = self.encode(v, level, pt_scale)
+            return cache[key]
+
+        outs = []
+        for oc in range(ly["out_ch"]):
+            acc = None
+            for i in range(ly["in_ch"]):
+                for dh in range(-half, half + 1):
+                    for dw in range(-half, half + 1):
+                        wvec = cb[dw + half][idx[oc, i, dh + half, dw + half]]
+                        term = o.mul_plain(rot[(i, dh, dw)], wpt(dh, dw, wvec))
+                        acc = term if acc is None else o.add(acc, term)
+            if with_bias and ly.get("bias") is not None:
+                v = self._vec()
+                for m in range(self.M):
+                    for r in range(Ho):
+                        for c in range(Wo):
+                            v[self._slot(m, r, c, go)] = ly["bias"][m, oc]
+                acc = o.add_plain(acc, self.encode(v, level, bias_scale))
+            outs.append(acc)
+        return outs, dict(gap=go, H=Ho, W=Wo)
+
+    def act(self, xs, ly, rlk):
+        o = self.o
+        out = []
+        for ch, x in enumerate(xs):
+            if self.M == 1:
+                t = o.add_const(x, float(ly["b"][0, ch]))
+            else:
+                v = self._vec()
+                for m in range(self.M):
+                    v[m * self.B:(m + 1) * self.B] = ly["b"][m, ch]
+                t = o.add_plain(x, self.encode(v, x.level, x.scale))
+            y = o.relin(o.tensor(x, t), rlk)
+            if self.M == 1:
+                y = o.add_const(y, float(ly["c"][0, ch]))
+            else:
+                v = self._vec()
+                for m in range(self.M):
+                    v[m * self.B:(m + 1) * self.B] = ly["c"][m, ch]
+                y = o.add_plain(y, self.encode(v, y.level, y.scale))
+            y = Ct(y.data, y.level, (x.scale * x.scale) / float(ly.get("a_absorb", 1.0)))
+            out.append(y)
+        return out
+
+    def dense(self, xs, grid, ly, pt_scale, bias_scale, gkeys):
+        o = self.o
+        g, H, W = grid["gap"], grid["H"], grid["W"]
+        steps = [g * (1 << j) for j in range(int(math.log2(W)))] + \
+                [g * self.W0 * (1 << j) for j in range(int(math.log2(H)))]
+        sums = []
+        for x in xs:
+            S = x
+            for st in steps:
+                S = o.add(S, o.rotate(S, st, gkeys[o.galois_elt(st)]))
+            sums.append(S)
+        K = ly["w"].shape[1]
+        level = xs[0].level
+        outs = []
+        for kk in range(K):
+            acc = None
+            for c, S in enumerate(sums):
+                v = self._vec()
+                for m in range(self.M):
+                    v[m * self.B] = ly["w"][m, kk, c]
+                term = o.mul_plain(S, self.encode(v, level, pt_scale))
+                acc = term if acc is None else o.add(acc, term)
+            if ly.get("bias") is not None:
+                v = self._vec()
+                for m in range(self.M):
+                    v[m * self.B] = ly["bias"][m, kk]
+                acc = o.add_plain(acc, self.encode(v, level, bias_scale))
+            outs.append(acc)
+        return outs
+
+    def pool(self, xs, grid, gkeys):
+        o = self.o
+        g = grid["gap"]
+        out = []
+        for x in xs:
+            y = x
+            for st in (g, g * self.W0, g * (self.W0 + 1)):
+                y = o.add(y, o.rotate(x, st, gkeys[o.galois_elt(st)]))
+            out.append(y)
+        return out, dict(gap=2 * g, H=grid["H"] // 2, W=grid["W"] // 2)
+
+    # ------------------------------------------------------------ whole network
+    def run(self, sk: SecretKey, inputs, rlk, gkeys, hook=None):
+        """inputs: list of channel ciphertexts for ONE image."""
+        o = self.o
+        tensors = {"x": (inputs, dict(self.input_grid))}
+        for ly in self.spec["layers"]:
+            xs, grid = tensors[ly["inp"]]
+            level, s = xs[0].level, xs[0].scale
+            op = ly["op"]
+            if op == "conv":
+                pt = (self.target * float(o.q[level])) / s
+                S = s * pt
+                outs, ngrid = self.conv(xs, grid, ly, pt, S, gkeys)
+                if ly.get("short") is not None:
+                    sxs, sgrid = tensors[ly["short"]["inp"]]
+                    sxs = [o.mod_drop(c, level) for c in sxs]
+                    spt = S / sxs[0].scale
+                    souts, _ = self.conv(sxs, sgrid, ly["short"], spt, 1.0, gkeys, with_bias=False)
+                    outs = [o.add(a, b) for a, b in zip(outs, souts)]
+            elif op == "act":
+                outs, ngrid = self.act(xs, ly, rlk), grid
+            elif op == "dense":
+                pt = (self.target * float(o.q[level])) / s
+                outs, ngrid = self.dense(xs, grid, ly, pt, s * pt, gkeys), dict(gap=grid["gap"], H=1, W=1)
+            elif op == "pool":
+                outs, ngrid = self.pool(xs, grid, gkeys)
+            else:
+                raise ValueError(op)
+            if op != "pool" and self._rescale_needed(outs[0].level, outs[0].scale):
+                outs = [o.rescale(c) for c in outs]
+            tensors[ly["out"]] = (outs, ngrid)
+            if hook is not None:
+                hook(ly, outs)
+        return tensors[self.spec["layers"][-1]["out"]]
+
+    def steps(self):
+        """Rotation steps the network needs (for key generation)."""
+        st = set()
+        grid = dict(self.input_grid)
+        grids = {"x": grid}
+        for ly in self.spec["layers"]:
+            g = grids[ly["inp"]]
+            if ly["op"] == "conv":
+                half = ly["ksize"] // 2
+                for dh in range(-half, half + 1):
+                    for dw in range(-half, half + 1):
+                        if dh or dw:
+                            st.add(g["gap"] * (dh * self.W0 + dw))
+                s = ly["stride"]
+                grids[ly["out"]] = dict(gap=g["gap"] * s, H=g["H"] // s, W=g["W"] // s)
+            elif ly["op"] == "pool":
+                st.update([g["gap"], g["gap"] * self.W0, g["gap"] * (self.W0 + 1)])
+                grids[ly["out"]] = dict(gap=2 * g["gap"], H=g["H"] // 2, W=g["W"] // 2)
+            elif ly["op"] == "dense":
+                st.update(g["gap"] * (1 << j) for j in range(int(math.log2(g["W"]))))
+                st.update(g["gap"] * self.W0 * (1 << j) for j in range(int(math.log2(g["H"]))))
+                grids[ly["out"]] = dict(gap=g["gap"], H=1, W=1)
+            else:
+                grids[ly["out"]] = g
+        return sorted(st)

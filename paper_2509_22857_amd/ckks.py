@@ -36,6 +36,14 @@ class ckc_pt(C.Structure):
     _fields_ = [("d", C.c_void_p), ("level", C.c_int32), ("scale", C.c_double)]
 
 
+class ckc_layout(C.Structure):
+    _fields_ = [("block", C.c_int32), ("row_stride", C.c_int32), ("gap", C.c_int32), ("height", C.c_int32),
+                ("width", C.c_int32), ("members", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.block, self.row_stride, self.gap, self.height, self.width, self.members)
+
+
 _lib = None
 _u64p = C.POINTER(C.c_uint64)
 _i32p = C.POINTER(C.c_int32)
@@ -70,6 +78,24 @@ _SIGS = [
     ("ckc_rotate", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), _i32p, C.c_int, C.POINTER(ckc_ct), _vp]),
     ("ckc_rescale", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
     ("ckc_mod_drop", C.c_int, [_vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_rescale_many", C.c_int, [_vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_add_many", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_layer_create_conv", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                        _dblp, C.POINTER(C.c_uint16), _dblp, C.c_int, C.c_double, C.c_double,
+                                        C.POINTER(_vp), _vp]),
+    ("ckc_eval_conv", C.c_int, [_vp, _vp, _vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_layer_create_act", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, _dblp, _dblp, C.c_double, C.c_int,
+                                       C.c_double, C.POINTER(_vp), _vp]),
+    ("ckc_eval_quad_act", C.c_int, [_vp, _vp, _vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_layer_create_dense", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, C.c_int, _dblp, _dblp, C.c_int,
+                                         C.c_double, C.c_double, C.POINTER(_vp), _vp]),
+    ("ckc_eval_dense", C.c_int, [_vp, _vp, _vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_eval_avgpool2", C.c_int, [_vp, _vp, C.POINTER(ckc_layout), C.POINTER(ckc_ct), C.c_int,
+                                    C.POINTER(ckc_ct), _vp]),
+    ("ckc_layer_steps", C.c_int, [_vp, _i32p, C.c_int]),
+    ("ckc_layer_out_layout", C.c_int, [_vp, C.POINTER(ckc_layout)]),
+    ("ckc_layer_bytes", C.c_size_t, [_vp]),
+    ("ckc_layer_destroy", C.c_int, [_vp]),
 ]
 
 
@@ -348,3 +374,137 @@ class KeyPair:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- layers
+def _dbl(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a, a.ctypes.data_as(_dblp)
+
+
+def _ct_array(cts):
+    arr = (ckc_ct * len(cts))(*[c.c() for c in cts])
+    return arr
+
+
+def _update_all(cts, arr):
+    for c, s in zip(cts, arr):
+        c.update(s)
+
+
+class Layer:
+    """ckc_layer handle (conv, activation or dense)."""
+
+    def __init__(self, ctx: Context, h, kind: str):
+        self.ctx, self.h, self.kind = ctx, h, kind
+
+    def steps(self) -> list[int]:
+        n = lib().ckc_layer_steps(self.h, None, 0)
+        buf = (C.c_int32 * max(n, 1))()
+        lib().ckc_layer_steps(self.h, buf, n)
+        return [int(buf[i]) for i in range(n)]
+
+    def out_layout(self) -> ckc_layout:
+        L = ckc_layout()
+        _check("ckc_layer_out_layout", lib().ckc_layer_out_layout(self.h, C.byref(L)))
+        return L
+
+    def nbytes(self) -> int:
+        return int(lib().ckc_layer_bytes(self.h))
+
+    def close(self):
+        if self.h:
+            lib().ckc_layer_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_layout(block, row_stride, gap, height, width, members) -> ckc_layout:
+    return ckc_layout(int(block), int(row_stride), int(gap), int(height), int(width), int(members))
+
+
+def layer_create_conv(ctx: Context, layout: ckc_layout, out_ch, in_ch, ksize, stride, codebook, idx, bias,
+                      level, pt_scale, bias_scale, stream=None) -> Layer:
+    cb, cbp = _dbl(codebook)
+    ix = np.ascontiguousarray(np.asarray(idx, dtype=np.uint16))
+    if bias is not None:
+        bb, bbp = _dbl(bias)
+    else:
+        bbp = None
+    k = int(cb.shape[1])
+    h = _vp()
+    _check("ckc_layer_create_conv", lib().ckc_layer_create_conv(
+        ctx.h, C.byref(layout), out_ch, in_ch, ksize, stride, k, cbp, ix.ctypes.data_as(C.POINTER(C.c_uint16)),
+        bbp, level, float(pt_scale), float(bias_scale), C.byref(h), _stream(stream)))
+    return Layer(ctx, h, "conv")
+
+
+def layer_create_act(ctx: Context, layout: ckc_layout, channels, b, c, a_absorb, level, in_scale,
+                     stream=None) -> Layer:
+    bb, bbp = _dbl(b)
+    cc, ccp = _dbl(c)
+    h = _vp()
+    _check("ckc_layer_create_act", lib().ckc_layer_create_act(ctx.h, C.byref(layout), channels, bbp, ccp,
+                                                              float(a_absorb), level, float(in_scale), C.byref(h),
+                                                              _stream(stream)))
+    return Layer(ctx, h, "act")
+
+
+def layer_create_dense(ctx: Context, layout: ckc_layout, classes, in_ch, w, bias, level, pt_scale, bias_scale,
+                       stream=None) -> Layer:
+    ww, wp = _dbl(w)
+    if bias is not None:
+        bb, bbp = _dbl(bias)
+    else:
+        bbp = None
+    h = _vp()
+    _check("ckc_layer_create_dense", lib().ckc_layer_create_dense(ctx.h, C.byref(layout), classes, in_ch, wp, bbp,
+                                                                  level, float(pt_scale), float(bias_scale),
+                                                                  C.byref(h), _stream(stream)))
+    return Layer(ctx, h, "dense")
+
+
+def _eval(fn, ctx, keys, layer, ins, n_img, outs, stream):
+    ia, oa = _ct_array(ins), _ct_array(outs)
+    _check(fn, getattr(lib(), fn)(ctx.h, keys.evk, layer.h, ia, n_img, oa, _stream(stream)))
+    _update_all(outs, oa)
+    return outs
+
+
+def eval_conv(ctx, keys, layer, ins, n_img, outs, stream=None):
+    return _eval("ckc_eval_conv", ctx, keys, layer, ins, n_img, outs, stream)
+
+
+def eval_quad_act(ctx, keys, layer, ins, n_img, outs, stream=None):
+    return _eval("ckc_eval_quad_act", ctx, keys, layer, ins, n_img, outs, stream)
+
+
+def eval_dense(ctx, keys, layer, ins, n_img, outs, stream=None):
+    return _eval("ckc_eval_dense", ctx, keys, layer, ins, n_img, outs, stream)
+
+
+def eval_avgpool2(ctx, keys, layout: ckc_layout, ins, outs, stream=None):
+    ia, oa = _ct_array(ins), _ct_array(outs)
+    _check("ckc_eval_avgpool2", lib().ckc_eval_avgpool2(ctx.h, keys.evk, C.byref(layout), ia, len(ins), oa,
+                                                        _stream(stream)))
+    _update_all(outs, oa)
+    return outs
+
+
+def rescale_many(ctx, ins, outs, stream=None):
+    ia, oa = _ct_array(ins), _ct_array(outs)
+    _check("ckc_rescale_many", lib().ckc_rescale_many(ctx.h, ia, len(ins), oa, _stream(stream)))
+    _update_all(outs, oa)
+    return outs
+
+
+def add_many(ctx, a, b, outs, stream=None):
+    aa, ba, oa = _ct_array(a), _ct_array(b), _ct_array(outs)
+    _check("ckc_add_many", lib().ckc_add_many(ctx.h, aa, ba, len(a), oa, _stream(stream)))
+    _update_all(outs, oa)
+    return outs

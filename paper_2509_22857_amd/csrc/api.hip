@@ -90,6 +90,57 @@ uint64_t brev_bits(uint64_t x, int bits) {
     return r;
 }
 
+// (cos, sin)(2 pi j / M), 0 <= j < M/2, M a power of two: folded into
+// [0, pi/4] by octant symmetry, then 12-term Taylor series by Horner's rule,
+// using IEEE +, -, *, / only, in one fixed order (the encoding's rounding
+// depends on every bit of these tables, and libm's cos/sin differ across
+// compilers in the last bit).
+void series_cs(double x, double &c, double &s) {
+    double cf[12], sf[12];
+    double fc = 1.0, fs = 1.0;
+    for (int i = 0; i < 12; ++i) {
+        if (i > 0) {
+            fc = fc / double((2 * i - 1) * (2 * i));
+            fs = fs / double((2 * i) * (2 * i + 1));
+        }
+        cf[i] = (i & 1) ? -fc : fc;
+        sf[i] = (i & 1) ? -fs : fs;
+    }
+    const double y = x * x;
+    double pc = cf[11], ps = sf[11];
+    for (int i = 10; i >= 0; --i) {
+        pc = pc * y;
+        pc = pc + cf[i];
+        ps = ps * y;
+        ps = ps + sf[i];
+    }
+    c = pc;
+    s = x * ps;
+}
+
+void twiddle(uint64_t j, uint64_t M, double &c, double &s) {
+    const double step = (2.0 * M_PI) / double(M);
+    const uint64_t e8 = M / 8, e4 = M / 4, e38 = 3 * (M / 8), e2 = M / 2;
+    double a, b;
+    if (j <= e8) {
+        series_cs(double(j) * step, a, b);
+        c = a;
+        s = b;
+    } else if (j <= e4) {
+        series_cs(double(e4 - j) * step, a, b);
+        c = b;
+        s = a;
+    } else if (j <= e38) {
+        series_cs(double(j - e4) * step, a, b);
+        c = -b;
+        s = a;
+    } else {
+        series_cs(double(e2 - j) * step, a, b);
+        c = -a;
+        s = b;
+    }
+}
+
 hipStream_t S(void *s) { return (hipStream_t)s; }
 
 int check_ct(const ckc_ctx *c, const ckc_ct *a, const char *what) {
@@ -120,6 +171,17 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
         CKC_REQUIRE((m - 1) % (2 * N) == 0, CKC_EINVAL, "modulus not 1 mod 2N");
         CKC_REQUIRE(is_prime_u64(m), CKC_EINVAL, "modulus not prime");
         CKC_REQUIRE(seen.insert(m).second, CKC_EINVAL, "duplicate modulus");
+    }
+    // sums of up to dnum (key inner product) or alpha / n_p (basis conversion)
+    // products of residues are accumulated in 128 bits without reduction
+    {
+        uint64_t qmax = 0;
+        for (int i = 0; i < n_q; ++i) qmax = std::max(qmax, q[i]);
+        for (int i = 0; i < n_p; ++i) qmax = std::max(qmax, p[i]);
+        const int dnum = (n_q + alpha - 1) / alpha;
+        const long double bound = (long double)qmax * (long double)qmax * (long double)std::max(dnum, std::max(alpha, n_p));
+        CKC_REQUIRE(bound < 0x1p127L * 2.0L, CKC_EUNSUPPORTED, "moduli too large for 128-bit accumulation of the digits");
+        CKC_REQUIRE(dnum <= 16, CKC_EUNSUPPORTED, "at most 16 key-switching digits");
     }
     auto c = std::make_unique<ckc_ctx>();
     c->logN = log_n;
@@ -171,19 +233,11 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
     CKC_TRY(c->itwp.upload(itwp.data(), 8 * itwp.size()));
     CKC_TRY(c->ninv.upload(ninv.data(), 8 * ninv.size()));
 
-    // FFT tables: twiddles of the length-n DFT and the zeta^k twist (libm, host)
+    // FFT tables: twiddles of the length-n DFT and the zeta^k twist
     const size_t n = N / 2;
     std::vector<double> fw(2 * (n / 2)), tws(2 * n);
-    for (size_t e = 0; e < n / 2; ++e) {
-        const double ang = (double(2 * e) / double(n)) * M_PI;
-        fw[2 * e] = cos(ang);
-        fw[2 * e + 1] = sin(ang);
-    }
-    for (size_t k = 0; k < n; ++k) {
-        const double ang = (double(k) / double(N)) * M_PI;
-        tws[2 * k] = cos(ang);
-        tws[2 * k + 1] = sin(ang);
-    }
+    for (size_t e = 0; e < n / 2; ++e) twiddle(e, n, fw[2 * e], fw[2 * e + 1]);
+    for (size_t k = 0; k < n; ++k) twiddle(k, 2 * N, tws[2 * k], tws[2 * k + 1]);
     std::vector<uint32_t> sidx(n);
     uint64_t g = 1;
     for (size_t j = 0; j < n; ++j) {

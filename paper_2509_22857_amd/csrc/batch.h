@@ -1,0 +1,37 @@
+// Batched building blocks: kernel-argument pointer tables and batched key
+// switching shared by the layer kernels.
+#pragma once
+#include "ckc_internal.h"
+
+// Up to kMaxBatch device pointers passed by value as a kernel argument (no
+// host->device copy of pointer tables).
+constexpr int kMaxBatch = 64;
+struct Ptrs {
+    uint64_t *p[kMaxBatch];
+};
+
+int copy_limbs(const uint64_t *src, size_t src_ps, uint64_t *dst, size_t dst_ps, size_t words, int npoly,
+               hipStream_t s);
+
+// dst (contiguous, stride dst_bs words) <- src.p[b] + src_off for b < nb, `words` words each.
+int gather(const Ptrs &src, size_t src_off, uint64_t *dst, size_t dst_bs, size_t words, int nb, hipStream_t s);
+
+// Batched ModUp of nb polynomials x[b] = x + b*xs (NTT form, level+1 limbs)
+// into digits[b] = digits + b*dnum*nt*N, layout [dnum][nt][N] (NTT form).
+int ks_modup_b(ckc_ctx *c, const uint64_t *x, size_t xs, int nb, int level, uint64_t *digits, hipStream_t s);
+
+// Batched key inner product + ModDown.  For b < nb:
+//   u = ModDown(sum_j sigma_g(digit_j[b]) * key_j)
+//   out0.p[b] = u_0 + (add0 ? add0.p[b][perm(k)] : 0), out1.p[b] = u_1 + (add1 ? add1.p[b] : 0)
+// perm is the NTT-domain permutation of g (g = 1: none); `perm_add0` applies
+// the permutation to add0 as well (rotations add sigma_g(c0)).
+int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint64_t *key, uint64_t g,
+               const Ptrs *add0, const Ptrs *add1, bool perm_add0, const Ptrs &out0, const Ptrs &out1,
+               hipStream_t s);
+
+// Batched rescale: out.p[b] <- rescale(in.p[b]) (npoly polys at `level`); out must not alias in.
+int rescale_b(ckc_ctx *c, const Ptrs &in, const Ptrs &out, int nb, int npoly, int level, hipStream_t s);
+
+// Batched limb-wise op over whole ciphertexts: out.p[b] = a.p[b] op b.p[b] (npoly polys, nl limbs)
+int ew_b(ckc_ctx *c, EwOp op, const Ptrs &out, const Ptrs &a, const Ptrs *b, int nb, int npoly, int nl,
+         hipStream_t s);

@@ -1,0 +1,273 @@
+// Batched hybrid key switching and batched ciphertext kernels.
+//
+// One launch covers up to kMaxBatch ciphertexts.  The key inner product keeps
+// each key word in registers and loops over the batch, so a Galois or
+// relinearisation key is read from HBM once per launch instead of once per
+// ciphertext.
+#include <algorithm>
+
+#include "batch.h"
+
+const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc);
+const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc);
+
+namespace {
+
+unsigned tiles(size_t N) { return unsigned(std::min<size_t>(N / 256, 64)); }
+
+__global__ void k_gather(Ptrs src, size_t src_off, uint64_t *__restrict__ dst, size_t dst_bs, size_t words) {
+    const int b = blockIdx.y;
+    const uint64_t *s = src.p[b] + src_off;
+    uint64_t *d = dst + b * dst_bs;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += size_t(gridDim.x) * blockDim.x)
+        d[k] = s[k];
+}
+
+// batched fast basis conversion (coefficient form), grid (tiles, targets, batch)
+__global__ __launch_bounds__(256) void k_bconv_b(const uint64_t *__restrict__ src, size_t src_bs, int ns,
+                                                 int src_first, LimbMap src_map, uint64_t *__restrict__ dst,
+                                                 size_t dst_bs, LimbMap dst_map, int skip_lo, int skip_hi,
+                                                 const uint64_t *__restrict__ inv, const uint64_t *__restrict__ invp,
+                                                 const uint64_t *__restrict__ hat, const Prime *__restrict__ primes,
+                                                 int logN) {
+    const int tt = blockIdx.y;
+    if (tt >= skip_lo && tt < skip_hi) return;
+    const size_t N = size_t(1) << logN;
+    const uint64_t *sb = src + blockIdx.z * src_bs;
+    uint64_t *o = dst + blockIdx.z * dst_bs + size_t(tt) * N;
+    const Prime T = primes[dst_map.prime(tt)];
+    const uint64_t *h = hat + size_t(tt) * ns;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        u128v acc{0, 0};
+        for (int i = 0; i < ns; ++i) {
+            const uint64_t si = primes[src_map.prime(src_first + i)].q;
+            const uint64_t y = mul_shoup(sb[size_t(i) * N + k], inv[i], invp[i], si);
+            acc = add128(acc, mul64x64(y, h[i]));
+        }
+        o[k] = reduce128(acc, T);
+    }
+}
+
+constexpr int kMaxDnum = 16;
+
+// key inner product with key reuse across the batch
+// acc[b][p][tt][k] = sum_j digits[b][j][tt][perm(k)] * key[j][p][prime(tt)][k]
+__global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digits, int nb, int dnum, int nt,
+                                               const uint64_t *__restrict__ key, int nprimes, LimbMap map,
+                                               const uint32_t *__restrict__ perm, uint64_t *__restrict__ acc,
+                                               const Prime *__restrict__ primes, int logN) {
+    const int tt = blockIdx.y;
+    const size_t N = size_t(1) << logN;
+    const int pi = map.prime(tt);
+    const Prime P = primes[pi];
+    const size_t dig_bs = size_t(dnum) * nt * N, acc_bs = size_t(2) * nt * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        uint64_t kb[kMaxDnum], ka[kMaxDnum];
+#pragma unroll
+        for (int j = 0; j < kMaxDnum; ++j) {
+            if (j < dnum) {
+                kb[j] = key[((size_t(j) * 2 + 0) * nprimes + pi) * N + k];
+                ka[j] = key[((size_t(j) * 2 + 1) * nprimes + pi) * N + k];
+            }
+        }
+        const size_t src = perm ? perm[k] : k;
+        for (int b = 0; b < nb; ++b) {
+            const uint64_t *dg = digits + b * dig_bs + size_t(tt) * N + src;
+            u128v a0{0, 0}, a1{0, 0};
+#pragma unroll
+            for (int j = 0; j < kMaxDnum; ++j) {
+                if (j < dnum) {
+                    const uint64_t d = dg[size_t(j) * nt * N];
+                    a0 = add128(a0, mul64x64(d, kb[j]));
+                    a1 = add128(a1, mul64x64(d, ka[j]));
+                }
+            }
+            uint64_t *ab = acc + b * acc_bs;
+            ab[size_t(tt) * N + k] = reduce128(a0, P);
+            ab[(size_t(nt) + tt) * N + k] = reduce128(a1, P);
+        }
+    }
+}
+
+// out_p[b][i] = (acc[b][p][i] - conv[b][p][i]) * P^-1 + add_p[b][perm?(k)]
+__global__ __launch_bounds__(256) void k_moddown_combine_b(const uint64_t *__restrict__ acc, int nt,
+                                                           const uint64_t *__restrict__ conv, int nl,
+                                                           const uint64_t *__restrict__ pinv, Ptrs add0, Ptrs add1,
+                                                           int has_add0, int has_add1,
+                                                           const uint32_t *__restrict__ perm0, Ptrs out0, Ptrs out1,
+                                                           const Prime *__restrict__ primes, int logN) {
+    const int i = blockIdx.y, b = blockIdx.z >> 1, p = blockIdx.z & 1;
+    const size_t N = size_t(1) << logN;
+    const uint64_t q = primes[i].q;
+    const uint64_t pv = pinv[2 * i], pvp = pinv[2 * i + 1];
+    const uint64_t *x = acc + (size_t(b) * 2 + p) * nt * N + size_t(i) * N;
+    const uint64_t *cv = conv + (size_t(b) * 2 + p) * nl * N + size_t(i) * N;
+    const bool has = p == 0 ? has_add0 : has_add1;
+    const uint64_t *ad = has ? (p == 0 ? add0.p[b] : add1.p[b]) + size_t(i) * N : nullptr;
+    const uint32_t *pm = p == 0 ? perm0 : nullptr;
+    uint64_t *o = (p == 0 ? out0.p[b] : out1.p[b]) + size_t(i) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        uint64_t r = mul_shoup(sub_mod(x[k], cv[k], q), pv, pvp, q);
+        if (ad) r = add_mod(r, ad[pm ? pm[k] : k], q);
+        o[k] = r;
+    }
+}
+
+// rescale lift for a batch: top[b][p] (coefficient form) -> lift[b][p][i] = centred(top) mod q_i
+__global__ __launch_bounds__(256) void k_rescale_lift_b(const uint64_t *__restrict__ top, int npoly,
+                                                        uint64_t *__restrict__ lift, int level,
+                                                        const Prime *__restrict__ primes, int logN) {
+    const int i = blockIdx.y, bp = blockIdx.z;
+    const size_t N = size_t(1) << logN;
+    const uint64_t ql = primes[level].q, half = ql >> 1;
+    const Prime P = primes[i];
+    const uint64_t qlm = reduce64(ql, P);
+    const uint64_t *t = top + size_t(bp) * N;
+    uint64_t *o = lift + (size_t(bp) * level + i) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        const uint64_t v = t[k];
+        const uint64_t vm = reduce64(v, P);
+        o[k] = v > half ? sub_mod(vm, qlm, P.q) : vm;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rescale_combine_b(Ptrs in, int npoly, const uint64_t *__restrict__ lift,
+                                                           Ptrs out, int level, const uint64_t *__restrict__ rinv,
+                                                           const Prime *__restrict__ primes, int logN, int nq) {
+    const int i = blockIdx.y, bp = blockIdx.z;
+    const int b = bp / npoly, p = bp - b * npoly;
+    const size_t N = size_t(1) << logN;
+    const uint64_t q = primes[i].q;
+    const uint64_t iv = rinv[(size_t(level) * nq + i) * 2], ivp = rinv[(size_t(level) * nq + i) * 2 + 1];
+    const uint64_t *x = in.p[b] + (size_t(p) * (level + 1) + i) * N;
+    const uint64_t *t = lift + (size_t(bp) * level + i) * N;
+    uint64_t *o = out.p[b] + (size_t(p) * level + i) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x)
+        o[k] = mul_shoup(sub_mod(x[k], t[k], q), iv, ivp, q);
+}
+
+__global__ __launch_bounds__(256) void k_ew_b(int op, Ptrs out, Ptrs a, Ptrs bb, int has_b, int nl,
+                                              const Prime *__restrict__ primes, int logN) {
+    const int limb = blockIdx.y % nl, poly = blockIdx.y / nl, b = blockIdx.z;
+    const size_t N = size_t(1) << logN;
+    const Prime P = primes[limb];
+    const size_t off = (size_t(poly) * nl + limb) * N;
+    const uint64_t *al = a.p[b] + off;
+    const uint64_t *bl = has_b ? bb.p[b] + off : nullptr;
+    uint64_t *ol = out.p[b] + off;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        const uint64_t x = al[k];
+        uint64_t r;
+        switch (op) {
+            case EW_ADD: r = add_mod(x, bl[k], P.q); break;
+            case EW_SUB: r = sub_mod(x, bl[k], P.q); break;
+            case EW_MUL: r = mul_mod(x, bl[k], P); break;
+            case EW_NEG: r = neg_mod(x, P.q); break;
+            default: r = x; break;
+        }
+        ol[k] = r;
+    }
+}
+
+}  // namespace
+
+int gather(const Ptrs &src, size_t src_off, uint64_t *dst, size_t dst_bs, size_t words, int nb, hipStream_t s) {
+    if (nb <= 0) return CKC_OK;
+    hipLaunchKernelGGL(k_gather, dim3(unsigned(std::min<size_t>((words + 255) / 256, 1024)), unsigned(nb)), dim3(256),
+                       0, s, src, src_off, dst, dst_bs, words);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+int ks_modup_b(ckc_ctx *c, const uint64_t *x, size_t xs, int nb, int level, uint64_t *digits, hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
+    CKC_REQUIRE(dnum <= kMaxDnum, CKC_EUNSUPPORTED, "too many key-switching digits");
+    const size_t dig_bs = size_t(dnum) * nt * N;
+    DevBuf coeff;
+    CKC_TRY(coeff.alloc(8 * N * nl * nb, s));
+    CKC_TRY(copy_limbs(x, xs, coeff.u64(), size_t(nl) * N, size_t(nl) * N, nb, s));
+    CKC_TRY(ntt_inverse(c, coeff.u64(), nl, qmap(), nb, size_t(nl) * N, s));
+    const LimbMap ext{nl, c->nq};
+    for (int j = 0; j < dnum; ++j) {
+        int rc;
+        const BconvTable *t = modup_table(c, level, j, &rc);
+        if (!t) return rc;
+        const int lo = j * c->alpha, ns = t->ns;
+        uint64_t *dj = digits + size_t(j) * nt * N;
+        hipLaunchKernelGGL(k_bconv_b, dim3(tiles(N), unsigned(nt), unsigned(nb)), dim3(256), 0, s,
+                           coeff.u64() + size_t(lo) * N, size_t(nl) * N, ns, lo, qmap(), dj, dig_bs, ext, lo, lo + ns,
+                           t->inv.u64(), t->invp.u64(), t->hat.u64(), c->dprimes(), c->logN);
+        CKC_HIP(hipGetLastError());
+        CKC_TRY(ntt_forward(c, dj, nt, ext, nb, dig_bs, s, lo, lo + ns));
+        CKC_TRY(copy_limbs(x + size_t(lo) * N, xs, dj + size_t(lo) * N, dig_bs, N * ns, nb, s));
+    }
+    return CKC_OK;
+}
+
+int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint64_t *key, uint64_t g,
+               const Ptrs *add0, const Ptrs *add1, bool perm_add0, const Ptrs &out0, const Ptrs &out1,
+               hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1, np = c->np, nt = nl + np, dnum = c->dnum_at(level);
+    const uint32_t *perm = nullptr;
+    if (g != 1) {
+        int rc;
+        perm = (const uint32_t *)galois_table(c, g, &rc);
+        if (!perm) return rc;
+    }
+    DevBuf acc, pl, conv;
+    CKC_TRY(acc.alloc(8 * N * nt * 2 * nb, s));
+    CKC_TRY(pl.alloc(8 * N * np * 2 * nb, s));
+    CKC_TRY(conv.alloc(8 * N * nl * 2 * nb, s));
+    const LimbMap ext{nl, c->nq};
+    hipLaunchKernelGGL(k_kip_b, dim3(tiles(N), unsigned(nt)), dim3(256), 0, s, digits, nb, dnum, nt, key,
+                       c->nprimes(), ext, perm, acc.u64(), c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    // P limbs of every accumulator (2 nb of them) -> coefficient form -> convert to Q -> NTT
+    CKC_TRY(copy_limbs(acc.u64() + size_t(nl) * N, size_t(nt) * N, pl.u64(), size_t(np) * N, N * np, 2 * nb, s));
+    const LimbMap pmap{0, c->nq};
+    CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * nb, size_t(np) * N, s));
+    hipLaunchKernelGGL(k_bconv_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s, pl.u64(),
+                       size_t(np) * N, np, 0, pmap, conv.u64(), size_t(nl) * N, qmap(), -1, -1, c->p_to_q.inv.u64(),
+                       c->p_to_q.invp.u64(), c->p_to_q.hat.u64(), c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    CKC_TRY(ntt_forward(c, conv.u64(), nl, qmap(), 2 * nb, size_t(nl) * N, s));
+    Ptrs none{};
+    hipLaunchKernelGGL(k_moddown_combine_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s,
+                       acc.u64(), nt, conv.u64(), nl, c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none,
+                       add0 ? 1 : 0, add1 ? 1 : 0, perm_add0 ? perm : nullptr, out0, out1, c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+int rescale_b(ckc_ctx *c, const Ptrs &in, const Ptrs &out, int nb, int npoly, int level, hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1, nbp = nb * npoly;
+    DevBuf top, lift;
+    CKC_TRY(top.alloc(8 * N * nbp, s));
+    CKC_TRY(lift.alloc(8 * N * nbp * level, s));
+    // gather the top limb of every polynomial: [b][p]
+    for (int p = 0; p < npoly; ++p)
+        CKC_TRY(gather(in, (size_t(p) * nl + level) * N, top.u64() + size_t(p) * N, size_t(npoly) * N, N, nb, s));
+    const LimbMap one{0, level};
+    CKC_TRY(ntt_inverse(c, top.u64(), 1, one, nbp, N, s));
+    hipLaunchKernelGGL(k_rescale_lift_b, dim3(tiles(N), unsigned(level), unsigned(nbp)), dim3(256), 0, s, top.u64(),
+                       npoly, lift.u64(), level, c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    CKC_TRY(ntt_forward(c, lift.u64(), level, qmap(), nbp, size_t(level) * N, s));
+    hipLaunchKernelGGL(k_rescale_combine_b, dim3(tiles(N), unsigned(level), unsigned(nbp)), dim3(256), 0, s, in,
+                       npoly, lift.u64(), out, level, c->rescale_inv.u64(), c->dprimes(), c->logN, c->nq);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+int ew_b(ckc_ctx *c, EwOp op, const Ptrs &out, const Ptrs &a, const Ptrs *b, int nb, int npoly, int nl,
+         hipStream_t s) {
+    if (nb <= 0) return CKC_OK;
+    Ptrs none{};
+    hipLaunchKernelGGL(k_ew_b, dim3(tiles(c->N), unsigned(nl * npoly), unsigned(nb)), dim3(256), 0, s, int(op), out, a,
+                       b ? *b : none, b ? 1 : 0, nl, c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}

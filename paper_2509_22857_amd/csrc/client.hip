@@ -7,9 +7,10 @@
 // polynomial has m_k = Re w_k and m_{k+n} = Im w_k.  Encoding scatters the
 // slots to y[t_j], runs an unnormalised inverse DFT (iterative radix-2
 // decimation in time, bit-reversed input), twists by zeta^-k / n, scales by
-// Delta and rounds half away from zero.  The FFT has one fixed operation order
-// and is compiled without FMA contraction, so the rounded integers are a
-// deterministic function of the slots and the twiddle tables.
+// Delta and rounds half away from zero.  The FFT has one fixed operation order,
+// is compiled without FMA contraction, and its twiddle tables come from a
+// fixed series evaluation (not libm), so the rounded integers are a
+// deterministic function of the slots.
 #include <math.h>
 
 #include <algorithm>

@@ -1,0 +1,785 @@
+// CNN layers over the HW layout: clustered convolution, quadratic
+// activation, dense layer with rotation sums, 2x2 sum pooling.
+//
+// Convolution (Sections 5.1-5.3): for every input channel one hoisted group
+// of rotations yields R[i][t] = Rot_{step(t)}(x_i) for the taps t of the
+// kernel.  Weights are clustered per kernel column, so the layer stores one
+// plaintext per (tap, centroid) -- the centroid's per-member values on the
+// output slots whose input pixel is inside the image.  The contraction
+//   y_o = sum_t sum_c PT[t][c] * (sum_{i : idx[o][i][t] = c} R[i][t]) + bias_o
+// adds the rotated inputs that share a centroid before the single plaintext
+// product, which is exact ring arithmetic (the same residues as multiplying
+// every weight separately).
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "batch.h"
+
+int encode_impl(ckc_ctx *c, const double *slots_h, size_t nslots, int level, double scale, uint64_t *m,
+                hipStream_t s);
+uint64_t galois_element(const ckc_ctx *c, int64_t step);
+
+enum LayerKind { LK_CONV = 0, LK_ACT = 1, LK_DENSE = 2 };
+
+struct ckc_layer {
+    int kind = 0;
+    ckc_layout lin{}, lout{};
+    int level = 0;
+    // conv
+    int O = 0, I = 0, ksz = 0, stride = 1, ntap = 0, kcent = 0;
+    double pt_scale = 1.0, bias_scale = 1.0;
+    bool has_bias = false;
+    std::vector<int32_t> tap_step;
+    DevMem pts;                        // conv: [ntap][kcent][nl][N]; dense: [K][C][nl][N]
+    DevMem bias;                       // conv: [O][nl][N]; dense: [K][nl][N]
+    DevMem og_off, g_c, g_moff, m_i;   // conv group lists
+    // act
+    int C = 0;
+    double a_absorb = 1.0, in_scale = 1.0;
+    DevMem bpt, cpt;                   // [C][nl][N] NTT-form plaintexts (constants or block-constant vectors)
+    // dense
+    int K = 0;
+    std::vector<int32_t> sum_steps;
+    size_t bytes = 0;
+};
+
+namespace {
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+unsigned tiles(size_t N) { return unsigned(std::min<size_t>(N / 256, 64)); }
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int check_layout(const ckc_ctx *c, const ckc_layout *L) {
+    CKC_REQUIRE(L, CKC_EINVAL, "null layout");
+    CKC_REQUIRE(is_pow2(L->block) && L->members >= 1 && size_t(L->block) * L->members <= c->N / 2, CKC_ESHAPE,
+                "layout: block must be a power of two with members*block <= N/2");
+    CKC_REQUIRE(L->gap >= 1 && L->height >= 1 && L->width >= 1 && L->row_stride >= L->width, CKC_ESHAPE,
+                "layout: bad grid");
+    const int64_t last = int64_t(L->gap) * (int64_t(L->row_stride) * (L->height - 1) + (L->width - 1));
+    CKC_REQUIRE(last < L->block, CKC_ESHAPE, "layout: grid does not fit in a block");
+    return CKC_OK;
+}
+
+size_t slot_of(const ckc_layout &L, int m, int r, int col) {
+    return size_t(m) * L.block + size_t(L.gap) * (size_t(r) * L.row_stride + col);
+}
+
+// constant polynomial value*scale (rounded) in NTT form: the same residue at every point
+void const_residues(const ckc_ctx *c, double value, double scale, int nl, std::vector<uint64_t> &out) {
+    const double v = round(value * scale);
+    out.resize(nl);
+    for (int t = 0; t < nl; ++t) {
+        const uint64_t q = c->mods[t];
+        const double av = fabs(v);
+        uint64_t r;
+        if (av < 9.2e18) {
+            r = uint64_t(av) % q;
+        } else {
+            int e;
+            const double mant = frexp(av, &e);
+            const uint64_t M = uint64_t(ldexp(mant, 53));
+            uint64_t pw = 1, base = 2 % q;
+            unsigned ex = unsigned(e - 53);
+            while (ex) {
+                if (ex & 1) pw = (uint64_t)(((unsigned __int128)pw * base) % q);
+                base = (uint64_t)(((unsigned __int128)base * base) % q);
+                ex >>= 1;
+            }
+            r = (uint64_t)(((unsigned __int128)(M % q) * pw) % q);
+        }
+        out[t] = (v < 0 && r) ? q - r : r;
+    }
+}
+
+__global__ void k_fill_limbs(uint64_t *__restrict__ d, const uint64_t *__restrict__ vals, int nl, int logN) {
+    const int t = blockIdx.y;
+    const size_t N = size_t(1) << logN;
+    const uint64_t v = vals[t];
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x)
+        d[size_t(t) * N + k] = v;
+}
+
+int fill_const_pt(ckc_ctx *c, uint64_t *d, double value, double scale, int nl, hipStream_t s) {
+    std::vector<uint64_t> r;
+    const_residues(c, value, scale, nl, r);
+    DevBuf rb;
+    CKC_TRY(rb.alloc(8 * nl, s));
+    CKC_HIP(hipMemcpyAsync(rb.p, r.data(), 8 * nl, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_limbs, dim3(tiles(c->N), unsigned(nl)), dim3(256), 0, s, d, rb.u64(), nl, c->logN);
+    CKC_HIP(hipGetLastError());
+    CKC_HIP(hipStreamSynchronize(s));
+    return CKC_OK;
+}
+
+__global__ void k_copy_pp(Ptrs src, Ptrs dst, size_t words) {
+    const int b = blockIdx.y;
+    const uint64_t *sp = src.p[b];
+    uint64_t *d = dst.p[b];
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += size_t(gridDim.x) * blockDim.x)
+        d[k] = sp[k];
+}
+
+__global__ void k_scatter(const uint64_t *__restrict__ src, size_t src_bs, Ptrs dst, size_t words) {
+    const int b = blockIdx.y;
+    const uint64_t *sp = src + b * src_bs;
+    uint64_t *d = dst.p[b];
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += size_t(gridDim.x) * blockDim.x)
+        d[k] = sp[k];
+}
+
+// ----------------------------------------------------------------------- conv
+constexpr int kTile = 64;        // coefficients per workgroup
+constexpr int kOutPerWave = 8;   // outputs accumulated per wave
+constexpr int kOutPerWg = 4 * kOutPerWave;
+
+// One workgroup: 64 coefficients of one limb of one polynomial, 32 outputs.
+// R_img: [I][ntap][2][nl][N]; pts: [ntap][kcent][nl][N]; bias: [O][nl][N].
+__global__ __launch_bounds__(256) void k_conv_contract(
+    const uint64_t *__restrict__ R, int I, int ntap, int nl, const uint64_t *__restrict__ pts, int kcent,
+    const int32_t *__restrict__ og_off, const int32_t *__restrict__ g_c, const int32_t *__restrict__ g_moff,
+    const int32_t *__restrict__ m_i, const uint64_t *__restrict__ bias, Ptrs outs, int o_base, int o_count,
+    const Prime *__restrict__ primes, int logN) {
+    extern __shared__ uint64_t sR[];  // [I][kTile]
+    const size_t N = size_t(1) << logN;
+    const int limb = blockIdx.y;
+    const int poly = blockIdx.z & 1, ogrp = blockIdx.z >> 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t k = size_t(blockIdx.x) * kTile + lane;
+    const Prime P = primes[limb];
+    // a sum of n residues stays below 2^64 while (n + 1) q <= 2^64; a sum of
+    // products (each < q^2) plus one residue stays below 2^128 for
+    // prod_cap <= 2^(128 - 2k) - 1 (k = bit length of q)
+    const uint64_t add_cap = P.onep - 1;
+    const int prod_cap = P.k >= 61 ? (1 << (128 - 2 * P.k)) - 1 : 64;
+    u128v acc[kOutPerWave];
+    int cnt[kOutPerWave];
+#pragma unroll
+    for (int j = 0; j < kOutPerWave; ++j) {
+        acc[j] = u128v{0, 0};
+        cnt[j] = 0;
+    }
+    for (int t = 0; t < ntap; ++t) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < I * kTile; e += 256) {
+            const int i = e / kTile, l = e - i * kTile;
+            sR[e] = R[((size_t(i) * ntap + t) * 2 + poly) * nl * N + size_t(limb) * N + size_t(blockIdx.x) * kTile + l];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kOutPerWave; ++j) {
+            const int ol = ogrp * kOutPerWg + wave + 4 * j;  // local output index
+            if (ol >= o_count) continue;
+            const int o = o_base + ol;
+            const int g0 = og_off[o * ntap + t], g1 = og_off[o * ntap + t + 1];
+            for (int g = g0; g < g1; ++g) {
+                const int cc = g_c[g];
+                const int m0 = g_moff[g], m1 = g_moff[g + 1];
+                uint64_t s = 0;
+                uint64_t nadd = 0;
+                for (int m = m0; m < m1; ++m) {
+                    s += sR[m_i[m] * kTile + lane];
+                    if (++nadd == add_cap) {
+                        s = reduce64(s, P);
+                        nadd = 0;
+                    }
+                }
+                s = reduce64(s, P);
+                const uint64_t pv = pts[((size_t(t) * kcent + cc) * nl + limb) * N + k];
+                acc[j] = add128(acc[j], mul64x64(s, pv));
+                if (++cnt[j] == prod_cap) {
+                    acc[j] = u128v{reduce128(acc[j], P), 0};
+                    cnt[j] = 0;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kOutPerWave; ++j) {
+        const int ol = ogrp * kOutPerWg + wave + 4 * j;
+        if (ol >= o_count) continue;
+        const int o = o_base + ol;
+        uint64_t y = reduce128(acc[j], P);
+        if (poly == 0 && bias) y = add_mod(y, bias[(size_t(o) * nl + limb) * N + k], P.q);
+        outs.p[ol][(size_t(poly) * nl + limb) * N + k] = y;
+    }
+}
+
+int check_inputs(const ckc_ct *in, int n, int level, const char *what) {
+    for (int i = 0; i < n; ++i) {
+        CKC_REQUIRE(in[i].d, CKC_EINVAL, std::string(what) + ": null input");
+        CKC_REQUIRE(in[i].level == level, CKC_ELEVEL, std::string(what) + ": input level differs from the layer's");
+        CKC_REQUIRE(in[i].npoly == 2, CKC_ESHAPE, std::string(what) + ": inputs must be 2-poly ciphertexts");
+        CKC_REQUIRE(fabs(in[i].scale / in[0].scale - 1.0) <= ldexp(1.0, -30), CKC_ESCALE,
+                    std::string(what) + ": input scales differ");
+    }
+    return CKC_OK;
+}
+
+}  // namespace
+
+// ============================================================= layer creation
+extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_ch, int in_ch, int ksize, int stride,
+                                     int n_centroids, const double *codebook, const uint16_t *idx, const double *bias,
+                                     int level, double pt_scale, double bias_scale, ckc_layer **out, void *stream) {
+    CKC_REQUIRE(c && out && codebook && idx, CKC_EINVAL, "null argument");
+    CKC_TRY(check_layout(c, in));
+    CKC_REQUIRE(ksize == 1 || ksize == 3, CKC_EUNSUPPORTED, "kernel size must be 1 or 3");
+    CKC_REQUIRE(stride == 1 || stride == 2, CKC_EUNSUPPORTED, "stride must be 1 or 2");
+    CKC_REQUIRE(out_ch >= 1 && in_ch >= 1 && in_ch <= 128, CKC_EUNSUPPORTED, "1 <= in_ch <= 128 required");
+    CKC_REQUIRE(n_centroids >= 1 && n_centroids <= 65535, CKC_EINVAL, "bad centroid count");
+    CKC_REQUIRE(level >= 0 && level < c->nq, CKC_ELEVEL, "level out of range");
+    CKC_REQUIRE(in->height % stride == 0 && in->width % stride == 0, CKC_ESHAPE, "grid not divisible by stride");
+    hipStream_t s = S(stream);
+    auto L = std::make_unique<ckc_layer>();
+    L->kind = LK_CONV;
+    L->lin = *in;
+    L->lout = *in;
+    L->lout.gap = in->gap * stride;
+    L->lout.height = in->height / stride;
+    L->lout.width = in->width / stride;
+    L->level = level;
+    L->O = out_ch;
+    L->I = in_ch;
+    L->ksz = ksize;
+    L->stride = stride;
+    L->ntap = ksize * ksize;
+    L->kcent = n_centroids;
+    L->pt_scale = pt_scale;
+    L->bias_scale = bias_scale;
+    const int nl = level + 1, M = in->members, half = ksize / 2;
+    const size_t N = c->N, n = N / 2, pw = size_t(nl) * N;
+    for (int t = 0; t < L->ntap; ++t) {
+        const int dh = t / ksize - half, dw = t % ksize - half;
+        L->tap_step.push_back(in->gap * (dh * in->row_stride + dw));
+    }
+    // codebook plaintexts: PT[t][c] = centroid c of column(t), per member, on the tap's mask
+    CKC_TRY(L->pts.alloc(8 * pw * L->ntap * n_centroids));
+    std::vector<double> v(n);
+    const ckc_layout &Lo = L->lout;
+    for (int t = 0; t < L->ntap; ++t) {
+        const int dh = t / ksize - half, dw = t % ksize - half, col = t % ksize;
+        for (int cc = 0; cc < n_centroids; ++cc) {
+            std::fill(v.begin(), v.end(), 0.0);
+            for (int m = 0; m < M; ++m) {
+                const double w = codebook[(size_t(col) * n_centroids + cc) * M + m];
+                for (int r = 0; r < Lo.height; ++r) {
+                    const int ri = stride * r + dh;
+                    if (ri < 0 || ri >= in->height) continue;
+                    for (int q = 0; q < Lo.width; ++q) {
+                        const int ci = stride * q + dw;
+                        if (ci < 0 || ci >= in->width) continue;
+                        v[slot_of(Lo, m, r, q)] = w;
+                    }
+                }
+            }
+            CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(t) * n_centroids + cc) * pw, s));
+        }
+    }
+    if (bias) {
+        L->has_bias = true;
+        CKC_TRY(L->bias.alloc(8 * pw * out_ch));
+        for (int o = 0; o < out_ch; ++o) {
+            std::fill(v.begin(), v.end(), 0.0);
+            for (int m = 0; m < M; ++m)
+                for (int r = 0; r < Lo.height; ++r)
+                    for (int q = 0; q < Lo.width; ++q) v[slot_of(Lo, m, r, q)] = bias[size_t(m) * out_ch + o];
+            CKC_TRY(encode_impl(c, v.data(), n, level, bias_scale, L->bias.u64() + size_t(o) * pw, s));
+        }
+    }
+    // group lists: for each (o, t) the centroids used and the inputs per centroid
+    std::vector<int32_t> og_off{0}, g_c, g_moff{0}, m_i;
+    std::vector<std::vector<int32_t>> members(n_centroids);
+    for (int o = 0; o < out_ch; ++o)
+        for (int t = 0; t < L->ntap; ++t) {
+            for (auto &mv : members) mv.clear();
+            for (int i = 0; i < in_ch; ++i) {
+                const int ci = idx[(size_t(o) * in_ch + i) * L->ntap + t];
+                CKC_REQUIRE(ci < n_centroids, CKC_EINVAL, "centroid index out of range");
+                members[ci].push_back(i);
+            }
+            for (int cc = 0; cc < n_centroids; ++cc) {
+                if (members[cc].empty()) continue;
+                g_c.push_back(cc);
+                for (int i : members[cc]) m_i.push_back(i);
+                g_moff.push_back(int32_t(m_i.size()));
+            }
+            og_off.push_back(int32_t(g_c.size()));
+        }
+    if (g_c.empty()) g_c.push_back(0);
+    if (m_i.empty()) m_i.push_back(0);
+    CKC_TRY(L->og_off.upload(og_off.data(), 4 * og_off.size()));
+    CKC_TRY(L->g_c.upload(g_c.data(), 4 * g_c.size()));
+    CKC_TRY(L->g_moff.upload(g_moff.data(), 4 * g_moff.size()));
+    CKC_TRY(L->m_i.upload(m_i.data(), 4 * m_i.size()));
+    L->bytes = L->pts.bytes + L->bias.bytes + 4 * (og_off.size() + g_c.size() + g_moff.size() + m_i.size());
+    CKC_HIP(hipStreamSynchronize(s));
+    *out = L.release();
+    return CKC_OK;
+}
+
+extern "C" int ckc_layer_create_act(ckc_ctx *c, const ckc_layout *layout, int channels, const double *b,
+                                    const double *cc, double a_absorb, int level, double in_scale, ckc_layer **out,
+                                    void *stream) {
+    CKC_REQUIRE(c && out && b && cc, CKC_EINVAL, "null argument");
+    CKC_TRY(check_layout(c, layout));
+    CKC_REQUIRE(channels >= 1, CKC_EINVAL, "bad channel count");
+    CKC_REQUIRE(level >= 0 && level < c->nq, CKC_ELEVEL, "level out of range");
+    CKC_REQUIRE(a_absorb != 0.0 && isfinite(a_absorb) && in_scale > 0, CKC_EINVAL, "bad scale arguments");
+    hipStream_t s = S(stream);
+    auto L = std::make_unique<ckc_layer>();
+    L->kind = LK_ACT;
+    L->lin = L->lout = *layout;
+    L->level = level;
+    L->C = channels;
+    L->a_absorb = a_absorb;
+    L->in_scale = in_scale;
+    const int nl = level + 1, M = layout->members;
+    const size_t N = c->N, n = N / 2, pw = size_t(nl) * N;
+    const double s2 = in_scale * in_scale;
+    CKC_TRY(L->bpt.alloc(8 * pw * channels));
+    CKC_TRY(L->cpt.alloc(8 * pw * channels));
+    std::vector<double> v(n);
+    for (int ch = 0; ch < channels; ++ch) {
+        if (M == 1) {
+            CKC_TRY(fill_const_pt(c, L->bpt.u64() + size_t(ch) * pw, b[ch], in_scale, nl, s));
+            CKC_TRY(fill_const_pt(c, L->cpt.u64() + size_t(ch) * pw, cc[ch], s2, nl, s));
+        } else {
+            for (int which = 0; which < 2; ++which) {
+                const double *src = which == 0 ? b : cc;
+                std::fill(v.begin(), v.end(), 0.0);
+                for (int m = 0; m < M; ++m)
+                    for (int j = 0; j < layout->block; ++j) v[size_t(m) * layout->block + j] = src[size_t(m) * channels + ch];
+                uint64_t *dst = (which == 0 ? L->bpt.u64() : L->cpt.u64()) + size_t(ch) * pw;
+                CKC_TRY(encode_impl(c, v.data(), n, level, which == 0 ? in_scale : s2, dst, s));
+            }
+        }
+    }
+    L->bytes = L->bpt.bytes + L->cpt.bytes;
+    *out = L.release();
+    return CKC_OK;
+}
+
+extern "C" int ckc_layer_create_dense(ckc_ctx *c, const ckc_layout *in, int classes, int in_ch, const double *w,
+                                      const double *bias, int level, double pt_scale, double bias_scale,
+                                      ckc_layer **out, void *stream) {
+    CKC_REQUIRE(c && out && w, CKC_EINVAL, "null argument");
+    CKC_TRY(check_layout(c, in));
+    CKC_REQUIRE(is_pow2(in->height) && is_pow2(in->width), CKC_EUNSUPPORTED, "dense: grid sides must be powers of two");
+    CKC_REQUIRE(classes >= 1 && in_ch >= 1, CKC_EINVAL, "bad sizes");
+    CKC_REQUIRE(level >= 0 && level < c->nq, CKC_ELEVEL, "level out of range");
+    hipStream_t s = S(stream);
+    auto L = std::make_unique<ckc_layer>();
+    L->kind = LK_DENSE;
+    L->lin = *in;
+    L->lout = *in;
+    L->lout.height = L->lout.width = 1;
+    L->level = level;
+    L->K = classes;
+    L->C = in_ch;
+    L->pt_scale = pt_scale;
+    L->bias_scale = bias_scale;
+    for (int j = 1; j < in->width; j <<= 1) L->sum_steps.push_back(in->gap * j);
+    for (int j = 1; j < in->height; j <<= 1) L->sum_steps.push_back(in->gap * in->row_stride * j);
+    const int nl = level + 1, M = in->members;
+    const size_t N = c->N, n = N / 2, pw = size_t(nl) * N;
+    CKC_TRY(L->pts.alloc(8 * pw * classes * in_ch));
+    std::vector<double> v(n, 0.0);
+    for (int k = 0; k < classes; ++k)
+        for (int ch = 0; ch < in_ch; ++ch) {
+            for (int m = 0; m < M; ++m) v[size_t(m) * in->block] = w[(size_t(m) * classes + k) * in_ch + ch];
+            CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(k) * in_ch + ch) * pw, s));
+        }
+    if (bias) {
+        L->has_bias = true;
+        CKC_TRY(L->bias.alloc(8 * pw * classes));
+        for (int k = 0; k < classes; ++k) {
+            for (int m = 0; m < M; ++m) v[size_t(m) * in->block] = bias[size_t(m) * classes + k];
+            CKC_TRY(encode_impl(c, v.data(), n, level, bias_scale, L->bias.u64() + size_t(k) * pw, s));
+        }
+    }
+    L->bytes = L->pts.bytes + L->bias.bytes;
+    *out = L.release();
+    return CKC_OK;
+}
+
+extern "C" int ckc_layer_steps(const ckc_layer *L, int32_t *steps, int max) {
+    if (!L) return 0;
+    std::vector<int32_t> st;
+    if (L->kind == LK_CONV)
+        for (int32_t x : L->tap_step)
+            if (x != 0) st.push_back(x);
+    if (L->kind == LK_DENSE) st = L->sum_steps;
+    for (int i = 0; i < int(st.size()) && i < max; ++i) steps[i] = st[i];
+    return int(st.size());
+}
+
+extern "C" int ckc_layer_out_layout(const ckc_layer *L, ckc_layout *out) {
+    CKC_REQUIRE(L && out, CKC_EINVAL, "null argument");
+    *out = L->lout;
+    return CKC_OK;
+}
+
+extern "C" size_t ckc_layer_bytes(const ckc_layer *L) { return L ? L->bytes : 0; }
+
+extern "C" int ckc_layer_destroy(ckc_layer *L) {
+    delete L;
+    return CKC_OK;
+}
+
+// ============================================================= evaluation
+// Hoisted rotations of nb inputs (pointer table) for every nonzero step;
+// results to dst(b, step index) pointers.  The identity step is a copy.
+static int hoisted_group(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int level,
+                         const std::vector<int32_t> &steps, const std::vector<Ptrs> &dst, hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
+    const size_t pw = size_t(nl) * N;
+    bool any = false;
+    for (int32_t st : steps) any |= galois_element(c, st) != 1;
+    DevBuf x1, digits;
+    if (any) {
+        CKC_TRY(x1.alloc(8 * pw * nb, s));
+        CKC_TRY(gather(in, pw, x1.u64(), pw, pw, nb, s));
+        CKC_TRY(digits.alloc(8 * N * nt * dnum * nb, s));
+        CKC_TRY(ks_modup_b(c, x1.u64(), pw, nb, level, digits.u64(), s));
+    }
+    for (size_t si = 0; si < steps.size(); ++si) {
+        const uint64_t g = galois_element(c, steps[si]);
+        if (g == 1) {
+            hipLaunchKernelGGL(k_copy_pp, dim3(1024, unsigned(nb)), dim3(256), 0, s, in, dst[si], 2 * pw);
+            CKC_HIP(hipGetLastError());
+            continue;
+        }
+        auto it = evk->galois.find(g);
+        CKC_REQUIRE(it != evk->galois.end(), CKC_ENOKEY, "missing Galois key for step " + std::to_string(steps[si]));
+        Ptrs o1;
+        for (int b = 0; b < nb; ++b) o1.p[b] = dst[si].p[b] + pw;
+        CKC_TRY(ks_apply_b(c, digits.u64(), nb, level, it->second->u64(), g, &in, nullptr, true, dst[si], o1, s));
+    }
+    return CKC_OK;
+}
+
+extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L, const ckc_ct *in, int n_img,
+                             ckc_ct *out, void *stream) {
+    CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(L->kind == LK_CONV, CKC_EINVAL, "not a convolution layer");
+    if (n_img == 0) return CKC_OK;
+    CKC_TRY(check_inputs(in, n_img * L->I, L->level, "eval_conv"));
+    for (int i = 0; i < n_img * L->O; ++i) CKC_REQUIRE(out[i].d, CKC_EINVAL, "eval_conv: null output");
+    const double out_scale = in[0].scale * L->pt_scale;
+    if (L->has_bias)
+        CKC_REQUIRE(fabs(out_scale / L->bias_scale - 1.0) <= ldexp(1.0, -30), CKC_ESCALE,
+                    "eval_conv: bias scale does not match in.scale * pt_scale");
+    hipStream_t s = S(stream);
+    const size_t N = c->N;
+    const int nl = L->level + 1, I = L->I, ntap = L->ntap;
+    const size_t pw = size_t(nl) * N, ctw = 2 * pw;
+    // images per chunk: KS batches of at most kMaxBatch ciphertexts
+    const int chunk = std::max(1, kMaxBatch / I);
+    DevBuf R;
+    CKC_TRY(R.alloc(8 * ctw * ntap * I * std::min(chunk, n_img), s));
+    const size_t lds = size_t(I) * kTile * 8;
+    for (int img0 = 0; img0 < n_img; img0 += chunk) {
+        const int ni = std::min(chunk, n_img - img0);
+        // rotations, in KS batches of <= kMaxBatch inputs
+        const int total = ni * I;
+        for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
+            const int nb = std::min(kMaxBatch, total - b0);
+            Ptrs ip;
+            std::vector<Ptrs> dst(ntap);
+            for (int b = 0; b < nb; ++b) {
+                const int flat = b0 + b;  // (image in chunk, input channel)
+                ip.p[b] = in[size_t(img0) * I + flat].d;
+                for (int t = 0; t < ntap; ++t)
+                    dst[t].p[b] = R.u64() + (size_t(flat) * ntap + t) * ctw;
+            }
+            CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
+        }
+        // contraction per image, outputs in groups of kMaxBatch
+        for (int ii = 0; ii < ni; ++ii) {
+            const uint64_t *Rimg = R.u64() + size_t(ii) * I * ntap * ctw;
+            for (int o0 = 0; o0 < L->O; o0 += kMaxBatch) {
+                const int oc = std::min(kMaxBatch, L->O - o0);
+                Ptrs op;
+                for (int j = 0; j < oc; ++j) op.p[j] = out[size_t(img0 + ii) * L->O + o0 + j].d;
+                const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
+                hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups), dim3(256),
+                                   lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent, (const int32_t *)L->og_off.p,
+                                   (const int32_t *)L->g_c.p, (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p,
+                                   L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, c->dprimes(), c->logN);
+                CKC_HIP(hipGetLastError());
+            }
+        }
+    }
+    for (int i = 0; i < n_img * L->O; ++i) {
+        out[i].level = L->level;
+        out[i].npoly = 2;
+        out[i].scale = out_scale;
+    }
+    return CKC_OK;
+}
+
+namespace {
+// D[b] = (x0 t0, x0 x1 + x1 t0, x1 x1) with t0 = x0 + bpt[b]  (NTT form)
+__global__ __launch_bounds__(256) void k_act_tensor(Ptrs x, Ptrs bp, uint64_t *__restrict__ D, int nl,
+                                                    const Prime *__restrict__ primes, int logN) {
+    const int t = blockIdx.y, b = blockIdx.z;
+    const size_t N = size_t(1) << logN, pw = size_t(nl) * N;
+    const Prime P = primes[t];
+    const uint64_t *x0 = x.p[b] + size_t(t) * N, *x1 = x.p[b] + pw + size_t(t) * N;
+    const uint64_t *bb = bp.p[b] + size_t(t) * N;
+    uint64_t *d = D + b * 3 * pw + size_t(t) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        const uint64_t a0 = x0[k], a1 = x1[k];
+        const uint64_t t0 = add_mod(a0, bb[k], P.q);
+        d[k] = mul_mod(a0, t0, P);
+        d[pw + k] = reduce128(add128(mul64x64(a0, a1), mul64x64(a1, t0)), P);
+        d[2 * pw + k] = mul_mod(a1, a1, P);
+    }
+}
+}  // namespace
+
+extern "C" int ckc_eval_quad_act(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L, const ckc_ct *in, int n_img,
+                                 ckc_ct *out, void *stream) {
+    CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(L->kind == LK_ACT, CKC_EINVAL, "not an activation layer");
+    CKC_REQUIRE(evk->relin, CKC_ENOKEY, "no relinearisation key");
+    if (n_img == 0) return CKC_OK;
+    const int total = n_img * L->C;
+    CKC_TRY(check_inputs(in, total, L->level, "eval_quad_act"));
+    CKC_REQUIRE(fabs(in[0].scale / L->in_scale - 1.0) <= ldexp(1.0, -30), CKC_ESCALE,
+                "eval_quad_act: input scale differs from the layer's");
+    for (int i = 0; i < total; ++i) CKC_REQUIRE(out[i].d, CKC_EINVAL, "eval_quad_act: null output");
+    hipStream_t s = S(stream);
+    const size_t N = c->N;
+    const int nl = L->level + 1, nt = nl + c->np, dnum = c->dnum_at(L->level);
+    const size_t pw = size_t(nl) * N;
+    const int nbmax = std::min(kMaxBatch, total);
+    DevBuf D, digits;
+    CKC_TRY(D.alloc(8 * 3 * pw * nbmax, s));
+    CKC_TRY(digits.alloc(8 * N * nt * dnum * nbmax, s));
+    for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
+        const int nb = std::min(kMaxBatch, total - b0);
+        Ptrs xp, bp, cp, a0, a1, o0, o1;
+        for (int b = 0; b < nb; ++b) {
+            const int ch = (b0 + b) % L->C;
+            xp.p[b] = in[b0 + b].d;
+            bp.p[b] = L->bpt.u64() + size_t(ch) * pw;
+            cp.p[b] = L->cpt.u64() + size_t(ch) * pw;
+            a0.p[b] = D.u64() + size_t(b) * 3 * pw;
+            a1.p[b] = a0.p[b] + pw;
+            o0.p[b] = out[b0 + b].d;
+            o1.p[b] = out[b0 + b].d + pw;
+        }
+        hipLaunchKernelGGL(k_act_tensor, dim3(tiles(N), unsigned(nl), unsigned(nb)), dim3(256), 0, s, xp, bp, D.u64(),
+                           nl, c->dprimes(), c->logN);
+        CKC_HIP(hipGetLastError());
+        CKC_TRY(ks_modup_b(c, D.u64() + 2 * pw, 3 * pw, nb, L->level, digits.u64(), s));
+        CKC_TRY(ks_apply_b(c, digits.u64(), nb, L->level, evk->relin->u64(), 1, &a0, &a1, false, o0, o1, s));
+        CKC_TRY(ew_b(c, EW_ADD, o0, o0, &cp, nb, 1, nl, s));
+    }
+    const double sc = (in[0].scale * in[0].scale) / L->a_absorb;
+    for (int i = 0; i < total; ++i) {
+        out[i].level = L->level;
+        out[i].npoly = 2;
+        out[i].scale = sc;
+    }
+    return CKC_OK;
+}
+
+namespace {
+// Z[img][k][p] = sum_c PT[k][c] * S[img][c][p] (+ bias[k] on p = 0); images of one launch: up to 8
+constexpr int kDenseImg = 8;
+__global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ Sb, int nimg, int C, int nl,
+                                                   const uint64_t *__restrict__ pts, const uint64_t *__restrict__ bias,
+                                                   uint64_t *__restrict__ Z, int K, const Prime *__restrict__ primes,
+                                                   int logN) {
+    const int limb = blockIdx.y, kk = blockIdx.z >> 1, poly = blockIdx.z & 1;
+    const size_t N = size_t(1) << logN, pw = size_t(nl) * N;
+    const Prime P = primes[limb];
+    const int prod_cap = P.k >= 61 ? (1 << (128 - 2 * P.k)) - 1 : 64;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        u128v acc[kDenseImg];
+        for (int i = 0; i < kDenseImg; ++i) acc[i] = u128v{0, 0};
+        int cnt = 0;
+        for (int ch = 0; ch < C; ++ch) {
+            const uint64_t pv = pts[(size_t(kk) * C + ch) * pw + size_t(limb) * N + k];
+#pragma unroll
+            for (int i = 0; i < kDenseImg; ++i)
+                if (i < nimg)
+                    acc[i] = add128(acc[i], mul64x64(Sb[((size_t(i) * C + ch) * 2 + poly) * pw + size_t(limb) * N + k], pv));
+            if (++cnt == prod_cap) {
+#pragma unroll
+                for (int i = 0; i < kDenseImg; ++i) acc[i] = u128v{reduce128(acc[i], P), 0};
+                cnt = 0;
+            }
+        }
+        for (int i = 0; i < nimg; ++i) {
+            uint64_t y = reduce128(acc[i], P);
+            if (poly == 0 && bias) y = add_mod(y, bias[size_t(kk) * pw + size_t(limb) * N + k], P.q);
+            Z[((size_t(i) * K + kk) * 2 + poly) * pw + size_t(limb) * N + k] = y;
+        }
+    }
+}
+}  // namespace
+
+extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L, const ckc_ct *in, int n_img,
+                              ckc_ct *out, void *stream) {
+    CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(L->kind == LK_DENSE, CKC_EINVAL, "not a dense layer");
+    if (n_img == 0) return CKC_OK;
+    const int C = L->C, K = L->K;
+    CKC_TRY(check_inputs(in, n_img * C, L->level, "eval_dense"));
+    for (int i = 0; i < n_img * K; ++i) CKC_REQUIRE(out[i].d, CKC_EINVAL, "eval_dense: null output");
+    const double out_scale = in[0].scale * L->pt_scale;
+    if (L->has_bias)
+        CKC_REQUIRE(fabs(out_scale / L->bias_scale - 1.0) <= ldexp(1.0, -30), CKC_ESCALE,
+                    "eval_dense: bias scale does not match in.scale * pt_scale");
+    hipStream_t s = S(stream);
+    const size_t N = c->N;
+    const int nl = L->level + 1;
+    const size_t pw = size_t(nl) * N, ctw = 2 * pw;
+    for (int img0 = 0; img0 < n_img; img0 += kDenseImg) {
+        const int ni = std::min(kDenseImg, n_img - img0);
+        const int total = ni * C;
+        DevBuf Sb, Tb, Z;
+        CKC_TRY(Sb.alloc(8 * ctw * total, s));
+        CKC_TRY(Tb.alloc(8 * ctw * std::min(total, kMaxBatch), s));
+        CKC_TRY(Z.alloc(8 * ctw * ni * K, s));
+        // S = inputs
+        for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
+            const int nb = std::min(kMaxBatch, total - b0);
+            Ptrs ip;
+            for (int b = 0; b < nb; ++b) ip.p[b] = in[size_t(img0) * C + b0 + b].d;
+            CKC_TRY(gather(ip, 0, Sb.u64() + size_t(b0) * ctw, ctw, ctw, nb, s));
+        }
+        // rotation sums: S <- S + Rot_step(S), steps in order
+        for (int32_t st : L->sum_steps) {
+            for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
+                const int nb = std::min(kMaxBatch, total - b0);
+                Ptrs sp, tp;
+                for (int b = 0; b < nb; ++b) {
+                    sp.p[b] = Sb.u64() + size_t(b0 + b) * ctw;
+                    tp.p[b] = Tb.u64() + size_t(b) * ctw;
+                }
+                std::vector<Ptrs> dst{tp};
+                CKC_TRY(hoisted_group(c, evk, sp, nb, L->level, std::vector<int32_t>{st}, dst, s));
+                CKC_TRY(ew_b(c, EW_ADD, sp, sp, &tp, nb, 2, nl, s));
+            }
+        }
+        hipLaunchKernelGGL(k_dense_mac, dim3(tiles(N), unsigned(nl), unsigned(2 * K)), dim3(256), 0, s, Sb.u64(), ni, C,
+                           nl, L->pts.u64(), L->has_bias ? L->bias.u64() : nullptr, Z.u64(), K, c->dprimes(), c->logN);
+        CKC_HIP(hipGetLastError());
+        for (int b0 = 0; b0 < ni * K; b0 += kMaxBatch) {
+            const int nb = std::min(kMaxBatch, ni * K - b0);
+            Ptrs op;
+            for (int b = 0; b < nb; ++b) op.p[b] = out[size_t(img0) * K + b0 + b].d;
+            hipLaunchKernelGGL(k_scatter, dim3(1024, unsigned(nb)), dim3(256), 0, s, Z.u64() + size_t(b0) * ctw, ctw, op,
+                               ctw);
+            CKC_HIP(hipGetLastError());
+        }
+    }
+    for (int i = 0; i < n_img * K; ++i) {
+        out[i].level = L->level;
+        out[i].npoly = 2;
+        out[i].scale = out_scale;
+    }
+    return CKC_OK;
+}
+
+extern "C" int ckc_eval_avgpool2(ckc_ctx *c, const ckc_evk *evk, const ckc_layout *layout, const ckc_ct *in, int n,
+                                 ckc_ct *out, void *stream) {
+    CKC_REQUIRE(c && evk && layout && in && out && n >= 0, CKC_EINVAL, "null argument");
+    CKC_TRY(check_layout(c, layout));
+    CKC_REQUIRE(layout->height % 2 == 0 && layout->width % 2 == 0, CKC_ESHAPE, "pool: odd grid");
+    if (n == 0) return CKC_OK;
+    CKC_TRY(check_inputs(in, n, in[0].level, "eval_avgpool2"));
+    hipStream_t s = S(stream);
+    const int level = in[0].level, nl = level + 1;
+    const size_t pw = size_t(nl) * c->N, ctw = 2 * pw;
+    const int g = layout->gap, W0 = layout->row_stride;
+    const std::vector<int32_t> steps{g, g * W0, g * (W0 + 1)};
+    const int nbmax = std::min(kMaxBatch, n);
+    DevBuf T;
+    CKC_TRY(T.alloc(8 * ctw * 3 * nbmax, s));
+    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
+        const int nb = std::min(kMaxBatch, n - b0);
+        Ptrs ip, op;
+        std::vector<Ptrs> dst(3);
+        for (int b = 0; b < nb; ++b) {
+            ip.p[b] = in[b0 + b].d;
+            op.p[b] = out[b0 + b].d;
+            for (int j = 0; j < 3; ++j) dst[j].p[b] = T.u64() + (size_t(b) * 3 + j) * ctw;
+        }
+        CKC_TRY(hoisted_group(c, evk, ip, nb, level, steps, dst, s));
+        CKC_TRY(ew_b(c, EW_ADD, op, ip, &dst[0], nb, 2, nl, s));
+        CKC_TRY(ew_b(c, EW_ADD, op, op, &dst[1], nb, 2, nl, s));
+        CKC_TRY(ew_b(c, EW_ADD, op, op, &dst[2], nb, 2, nl, s));
+    }
+    for (int i = 0; i < n; ++i) {
+        out[i].level = level;
+        out[i].npoly = 2;
+        out[i].scale = in[i].scale;
+    }
+    return CKC_OK;
+}
+
+extern "C" int ckc_rescale_many(ckc_ctx *c, const ckc_ct *in, int n, ckc_ct *out, void *stream) {
+    CKC_REQUIRE(c && in && out && n >= 0, CKC_EINVAL, "null argument");
+    if (n == 0) return CKC_OK;
+    const int level = in[0].level, npoly = in[0].npoly;
+    CKC_REQUIRE(level >= 1, CKC_ELEVEL, "cannot rescale at level 0");
+    for (int i = 0; i < n; ++i) {
+        CKC_REQUIRE(in[i].d && out[i].d && in[i].level == level && in[i].npoly == npoly, CKC_ESHAPE,
+                    "rescale_many: inputs must share level and npoly");
+        for (int j = 0; j < n; ++j) CKC_REQUIRE(out[i].d != in[j].d, CKC_EINVAL, "rescale_many: output aliases an input");
+    }
+    hipStream_t s = S(stream);
+    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
+        const int nb = std::min(kMaxBatch, n - b0);
+        Ptrs ip, op;
+        for (int b = 0; b < nb; ++b) {
+            ip.p[b] = in[b0 + b].d;
+            op.p[b] = out[b0 + b].d;
+        }
+        CKC_TRY(rescale_b(c, ip, op, nb, npoly, level, s));
+    }
+    for (int i = 0; i < n; ++i) {
+        out[i].scale = in[i].scale / double(c->mods[level]);
+        out[i].level = level - 1;
+        out[i].npoly = npoly;
+    }
+    return CKC_OK;
+}
+
+extern "C" int ckc_add_many(ckc_ctx *c, const ckc_ct *a, const ckc_ct *b, int n, ckc_ct *out, void *stream) {
+    CKC_REQUIRE(c && a && b && out && n >= 0, CKC_EINVAL, "null argument");
+    if (n == 0) return CKC_OK;
+    const int level = a[0].level;
+    for (int i = 0; i < n; ++i) {
+        CKC_REQUIRE(a[i].d && b[i].d && out[i].d, CKC_EINVAL, "add_many: null buffer");
+        CKC_REQUIRE(a[i].level == level && b[i].level == level, CKC_ELEVEL, "add_many: levels differ");
+        CKC_REQUIRE(a[i].npoly == 2 && b[i].npoly == 2, CKC_ESHAPE, "add_many: 2-poly ciphertexts only");
+        CKC_REQUIRE(fabs(a[i].scale / b[i].scale - 1.0) <= ldexp(1.0, -30), CKC_ESCALE, "add_many: scales differ");
+    }
+    hipStream_t s = S(stream);
+    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
+        const int nb = std::min(kMaxBatch, n - b0);
+        Ptrs ap, bp, op;
+        for (int j = 0; j < nb; ++j) {
+            ap.p[j] = a[b0 + j].d;
+            bp.p[j] = b[b0 + j].d;
+            op.p[j] = out[b0 + j].d;
+        }
+        CKC_TRY(ew_b(c, EW_ADD, op, ap, &bp, nb, 2, level + 1, s));
+    }
+    for (int i = 0; i < n; ++i) {
+        out[i].level = level;
+        out[i].npoly = 2;
+        out[i].scale = a[i].scale;
+    }
+    return CKC_OK;
+}

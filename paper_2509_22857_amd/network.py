@@ -1,0 +1,240 @@
+"""Encrypted CNN evaluation over the C-ABI: level/scale planner and runner.
+
+Planner (tower reuse, Section 4.3): every prime q_i of the chain has a
+sublevel lambda(q_i) = round(log_Delta q_i); a ciphertext of scale s has
+lambda(s) = round(log_Delta s).  After every multiplicative layer
+(convolution, activation, dense) the ciphertext is rescaled iff
+lambda(s) > lambda(q_level).  A convolution or dense layer on an input of
+scale s at level l encodes its plaintexts at scale (target * q_l) / s so
+that its output returns to the target scale after that rescale; its bias
+is encoded at s * pt_scale.  A residual shortcut (a 1x1 convolution on the
+block input, mod-dropped to the branch's level) encodes at
+(s_branch * pt_branch) / s_input so both summands share one scale.  An
+activation leaves the level unchanged and squares the scale.
+
+Every homomorphic step runs in libckkscnn.so; this module only sequences the
+calls and holds the device buffers (torch tensors).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import ckks
+
+
+def sublevel(scale: float, delta: float) -> int:
+    return int(round(math.log2(scale) / math.log2(delta)))
+
+
+@dataclass
+class LayerPlan:
+    op: str
+    level: int            # level of the layer's input
+    in_scale: float
+    pt_scale: float = 1.0
+    bias_scale: float = 1.0
+    out_scale: float = 1.0   # before the optional rescale
+    rescale: bool = False
+    short_level: int = -1
+    short_pt_scale: float = 1.0
+
+
+def plan_network(spec: dict, q, delta: float, target: float, in_scale: float) -> tuple[list, dict]:
+    """Returns (plans per layer, final tensor states {name: (level, scale)})."""
+    L = len(q) - 1
+    state = {"x": (L, float(in_scale))}
+    plans = []
+
+    def after(level, scale):
+        if level >= 1 and sublevel(scale, delta) > sublevel(float(q[level]), delta):
+            return level - 1, scale / float(q[level]), True
+        return level, scale, False
+
+    for ly in spec["layers"]:
+        op = ly["op"]
+        lv, s = state[ly["inp"]]
+        if op in ("conv", "dense"):
+            pt = (target * float(q[lv])) / s
+            S = s * pt
+            p = LayerPlan(op, lv, s, pt_scale=pt, bias_scale=S, out_scale=S)
+            if op == "conv" and ly.get("short") is not None:
+                ls, ss = state[ly["short"]["inp"]]
+                if ls < lv:
+                    raise ValueError("shortcut input below the branch level")
+                p.short_level = lv
+                p.short_pt_scale = S / ss
+            nl, ns, p.rescale = after(lv, S)
+            state[ly["out"]] = (nl, ns)
+        elif op == "act":
+            S = (s * s) / float(ly.get("a_absorb", 1.0))
+            p = LayerPlan(op, lv, s, out_scale=S)
+            nl, ns, p.rescale = after(lv, S)
+            state[ly["out"]] = (nl, ns)
+        elif op == "pool":
+            p = LayerPlan(op, lv, s, out_scale=s)
+            state[ly["out"]] = (lv, s)
+        else:
+            raise ValueError(op)
+        if min(state[ly["out"]][0], lv) < 0:
+            raise ValueError("chain too short for this network")
+        plans.append(p)
+    return plans, state
+
+
+def input_layout(spec: dict) -> ckks.ckc_layout:
+    C, H, W = spec["image"]
+    lay = spec["layout"]
+    return ckks.make_layout(lay["block"], lay["row_stride"], 1, H, W, spec["members"])
+
+
+def image_slots(spec: dict, img: np.ndarray, N: int) -> list[np.ndarray]:
+    """Client-side HW packing: channel c -> slot vector with the image copied
+    into each member block (all members share the input ciphertexts)."""
+    C, H, W = spec["image"]
+    B, W0, M = spec["layout"]["block"], spec["layout"]["row_stride"], spec["members"]
+    out = []
+    for c in range(C):
+        v = np.zeros(M * B)
+        for m in range(M):
+            for r in range(H):
+                v[m * B + r * W0: m * B + r * W0 + W] = img[c, r]
+        out.append(v)
+    return out
+
+
+class GpuNetwork:
+    """Device-resident layers of one network under one parameter set."""
+
+    def __init__(self, ctx: ckks.Context, spec: dict, delta: float, target: float, in_scale: float):
+        self.ctx, self.spec = ctx, spec
+        self.delta, self.target, self.in_scale = delta, target, in_scale
+        self.plans, self.final = plan_network(spec, ctx.q, delta, target, in_scale)
+        self.layers = []
+        self.layouts = {"x": input_layout(spec)}
+        steps = set()
+        for ly, p in zip(spec["layers"], self.plans):
+            lay = self.layouts[ly["inp"]]
+            entry = {"main": None, "short": None}
+            if ly["op"] == "conv":
+                entry["main"] = ckks.layer_create_conv(ctx, lay, ly["out_ch"], ly["in_ch"], ly["ksize"], ly["stride"],
+                                                       ly["codebook"], ly["idx"], ly["bias"], p.level, p.pt_scale,
+                                                       p.bias_scale)
+                if ly.get("short") is not None:
+                    sh = ly["short"]
+                    slay = self.layouts[sh["inp"]]
+                    entry["short"] = ckks.layer_create_conv(ctx, slay, sh["out_ch"], sh["in_ch"], sh["ksize"],
+                                                            sh["stride"], sh["codebook"], sh["idx"], None,
+                                                            p.short_level, p.short_pt_scale, 1.0)
+                self.layouts[ly["out"]] = entry["main"].out_layout()
+            elif ly["op"] == "act":
+                C = ly["b"].shape[1]
+                entry["main"] = ckks.layer_create_act(ctx, lay, C, ly["b"], ly["c"], ly.get("a_absorb", 1.0), p.level,
+                                                      p.in_scale)
+                self.layouts[ly["out"]] = lay
+            elif ly["op"] == "dense":
+                K, C = ly["w"].shape[1], ly["w"].shape[2]
+                entry["main"] = ckks.layer_create_dense(ctx, lay, K, C, ly["w"], ly["bias"], p.level, p.pt_scale,
+                                                        p.bias_scale)
+                self.layouts[ly["out"]] = entry["main"].out_layout()
+            elif ly["op"] == "pool":
+                self.layouts[ly["out"]] = ckks.make_layout(lay.block, lay.row_stride, 2 * lay.gap, lay.height // 2,
+                                                           lay.width // 2, lay.members)
+                steps.update([lay.gap, lay.gap * lay.row_stride, lay.gap * (lay.row_stride + 1)])
+            for e in entry.values():
+                if e is not None and e.kind in ("conv", "dense"):
+                    steps.update(e.steps())
+            self.layers.append(entry)
+        self.steps = sorted(steps)
+
+    def device_bytes(self) -> int:
+        return sum(e.nbytes() for ent in self.layers for e in ent.values() if e is not None)
+
+    # --------------------------------------------------------- client side
+    def encrypt_images(self, keys: ckks.KeyPair, imgs: np.ndarray, stream_base: int = 0):
+        """imgs: [n][C][H][W] -> [n][C] ciphertexts at the top level."""
+        L = len(self.ctx.q) - 1
+        out = []
+        for n, img in enumerate(imgs):
+            row = []
+            for c, v in enumerate(image_slots(self.spec, img, self.ctx.N)):
+                pt = self.ctx.encode(v, L, self.in_scale)
+                row.append(self.ctx.encrypt(keys, pt, stream_base + n * 4096 + c))
+            out.append(row)
+        return out
+
+    def decrypt_logits(self, keys: ckks.KeyPair, cts) -> np.ndarray:
+        """One image's class ciphertexts -> logits [M][K] (slot m*block)."""
+        B, M = self.spec["layout"]["block"], self.spec["members"]
+        res = []
+        for ct in cts:
+            z = self.ctx.decode(self.ctx.decrypt(keys, ct), M * B)
+            res.append([z[m * B] for m in range(M)])
+        return np.array(res).T
+
+    def decrypt_grid(self, keys: ckks.KeyPair, ct, layout) -> np.ndarray:
+        """One channel ciphertext -> values on the valid grid [M][H][W]."""
+        L = layout
+        z = self.ctx.decode(self.ctx.decrypt(keys, ct), L.members * L.block)
+        out = np.zeros((L.members, L.height, L.width))
+        for m in range(L.members):
+            for r in range(L.height):
+                for c in range(L.width):
+                    out[m, r, c] = z[m * L.block + L.gap * (r * L.row_stride + c)]
+        return out
+
+    # --------------------------------------------------------- server side
+    def run(self, keys: ckks.KeyPair, inputs, stream=None, keep=False, hook=None):
+        """inputs: [n_img][C] ciphertexts -> {"out": [n_img][K or C] ciphertexts}.
+        Every tensor of the network is evaluated for all images per call."""
+        ctx = self.ctx
+        n_img = len(inputs)
+        tensors = {"x": [c for row in inputs for c in row]}
+        for ly, p, ent in zip(self.spec["layers"], self.plans, self.layers):
+            xin = tensors[ly["inp"]]
+            op = ly["op"]
+            if op == "conv":
+                O = ly["out_ch"]
+                outs = [ctx.new_ct(p.level) for _ in range(n_img * O)]
+                ckks.eval_conv(ctx, keys, ent["main"], xin, n_img, outs, stream)
+                if ent["short"] is not None:
+                    xs = tensors[ly["short"]["inp"]]
+                    if xs[0].level != p.short_level:
+                        xs = [ctx.mod_drop(c, p.short_level, stream=stream) for c in xs]
+                    souts = [ctx.new_ct(p.short_level) for _ in range(n_img * O)]
+                    ckks.eval_conv(ctx, keys, ent["short"], xs, n_img, souts, stream)
+                    ckks.add_many(ctx, outs, souts, outs, stream)
+            elif op == "act":
+                outs = [ctx.new_ct(p.level) for _ in range(len(xin))]
+                ckks.eval_quad_act(ctx, keys, ent["main"], xin, n_img, outs, stream)
+            elif op == "dense":
+                K = ly["w"].shape[1]
+                outs = [ctx.new_ct(p.level) for _ in range(n_img * K)]
+                ckks.eval_dense(ctx, keys, ent["main"], xin, n_img, outs, stream)
+            elif op == "pool":
+                outs = [ctx.new_ct(p.level) for _ in range(len(xin))]
+                ckks.eval_avgpool2(ctx, keys, self.layouts[ly["inp"]], xin, outs, stream)
+            if p.rescale:
+                r = [ctx.new_ct(p.level - 1) for _ in range(len(outs))]
+                ckks.rescale_many(ctx, outs, r, stream)
+                outs = r
+            tensors[ly["out"]] = outs
+            if hook is not None:
+                hook(ly, outs)
+            if not keep:
+                # drop tensors no later layer reads
+                later = set()
+                idx = self.spec["layers"].index(ly)
+                for l2 in self.spec["layers"][idx + 1:]:
+                    later.add(l2["inp"])
+                    if l2.get("short"):
+                        later.add(l2["short"]["inp"])
+                for name in list(tensors):
+                    if name not in later and name != ly["out"]:
+                        del tensors[name]
+        last = self.spec["layers"][-1]["out"]
+        flat = tensors[last]
+        per = len(flat) // n_img
+        return [flat[i * per:(i + 1) * per] for i in range(n_img)], tensors

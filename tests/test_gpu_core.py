@@ -90,6 +90,21 @@ def test_secret_encode_encrypt_bit_exact(env):
     assert np.max(np.abs(zz - orc.decode(orc.decrypt(oct_, sk), oct_.scale))) < 1e-9
 
 
+def test_encode_bit_exact_at_large_scales(env):
+    """Encodings at scales where the FFT's last bits decide the integers."""
+    ps, ctx, orc, torch = env
+    level = min(2, len(ps.q) - 1)
+    n = ps.N // 2
+    z = gen.uniform_slots(31, n, -3, 3)
+    blk = np.zeros(n)
+    blk[: n // 4] = 0.37
+    blk[n // 4: n // 2] = -1.25
+    for vec in (z, blk):
+        for scale in (2.0 ** 30, 2.0 ** 60, 2.0 ** 90):
+            got = ctx.pt_to_coeff(ctx.encode(vec, level, scale))
+            assert np.array_equal(got, orc.encode(vec, level, scale).data), scale
+
+
 def test_tensor_relin_rescale_bit_exact(env):
     ps, ctx, orc, torch = env
     from oracle.ckks import Ct

@@ -1,0 +1,83 @@
+"""GPU network evaluation vs the oracle: bit-exact ciphertexts at every
+layer, decryptions vs the FP64 forward, and batch independence."""
+import numpy as np
+import pytest
+
+from workloads import gen, nets
+from workloads.params import tiny, small_tower
+
+pytestmark = pytest.mark.gpu
+
+
+def _coeff(ctx, ct):
+    return ctx.ct_to_coeff(ct)
+
+
+def _setup(ps, spec, delta, target, in_scale, seed):
+    from paper_2509_22857_amd.ckks import Context
+    from paper_2509_22857_amd.network import GpuNetwork
+    from oracle.ckks import Oracle
+    from oracle.network import OracleNetwork
+    ctx = Context.from_params(ps)
+    gnet = GpuNetwork(ctx, spec, delta, target, in_scale)
+    keys = ctx.keygen(seed, gnet.steps)
+    o = Oracle.from_params(ps)
+    onet = OracleNetwork(o, spec, delta, target, in_scale)
+    assert sorted(onet.steps()) == gnet.steps
+    sk = o.secret_key(seed)
+    rlk = o.relin_key(sk)
+    gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in onet.steps()}
+    return ctx, gnet, keys, o, onet, sk, rlk, gk
+
+
+def test_tiny_network_bit_exact():
+    ps = tiny()
+    spec = nets.tiny_spec(0)
+    print("[tiny_network] N=2^12 conv3x3+act", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, 2.0 ** 40, 2.0 ** 34, 2.0 ** 40, 77)
+    img = gen.images(5, 1, 1, 8, 8)
+    gin = gnet.encrypt_images(keys, img, 500)
+    oin = onet.encrypt_image(sk, img[0], 500)
+    for g, c in zip(gin[0], oin):
+        assert np.array_equal(_coeff(ctx, g), c.data)
+    gl, ol = [], []
+    gout, _ = gnet.run(keys, gin, hook=lambda ly, outs: gl.append(_coeff(ctx, outs[0])))
+    oout, grid = onet.run(sk, oin, rlk, gk, hook=lambda ly, outs: ol.append(outs[0].data))
+    for a, b in zip(gl, ol):
+        assert np.array_equal(a, b)
+    from oracle.forward import forward
+    ref = forward(spec, img[0])[0, 0]
+    lay = gnet.layouts["y"]
+    got = gnet.decrypt_grid(keys, gout[0][0], lay)[0]
+    assert np.max(np.abs(got - ref)) < 1e-5
+
+
+def test_small_resnet_ensemble_bit_exact_and_batch_independent():
+    spec = nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8, calib=4)
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[small_resnet] N=2^12 M=2 widths=(4,8)", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 9)
+    imgs = gen.images(3, 2, 3, 16, 16)
+    gin = gnet.encrypt_images(keys, imgs, 100)
+    # layer-by-layer capture for image 0 (first channel) in a batch of two
+    gl = []
+    gout, _ = gnet.run(keys, gin, hook=lambda ly, outs: gl.append((ly["name"], _coeff(ctx, outs[0]))))
+    oin = onet.encrypt_image(sk, imgs[0], 100)
+    ol = []
+    oout, _ = onet.run(sk, oin, rlk, gk, hook=lambda ly, outs: ol.append((ly["name"], outs[0].data)))
+    for (n1, a), (n2, b) in zip(gl, ol):
+        assert n1 == n2
+        assert np.array_equal(a, b), n1
+    for k, (g, c) in enumerate(zip(gout[0], oout)):
+        assert np.array_equal(_coeff(ctx, g), c.data), k
+    # image 1 alone gives the same ciphertexts as in the batch
+    alone, _ = gnet.run(keys, [gin[1]])
+    for a, b in zip(alone[0], gout[1]):
+        assert np.array_equal(_coeff(ctx, a), _coeff(ctx, b))
+    from oracle.forward import forward
+    for n in range(2):
+        ref = forward(spec, imgs[n])
+        got = gnet.decrypt_logits(keys, gout[n])
+        assert np.max(np.abs(got - ref)) < 1e-3
+        assert got.mean(0).argmax() == ref.mean(0).argmax()

@@ -1,0 +1,121 @@
+"""Oracle network evaluation against the FP64 forward, the generator's
+independent forward, and the paper's level counts."""
+import numpy as np
+import pytest
+
+from oracle.ckks import Oracle
+from oracle.forward import forward
+from oracle.network import OracleNetwork
+from workloads import gen
+from workloads import nets
+from workloads.params import tiny, small_tower, resnet20_tower
+
+
+def test_forward_matches_generator_forward():
+    """Two independent numpy paths of the same network agree (calibration
+    forward of the generator vs the oracle's forward)."""
+    spec = nets.resnet_spec(seed=3, members=2, widths=(4, 8), blocks=1, classes=5, image=(3, 8, 8), k=6, calib=2)
+    img = gen.images(11, 1, 3, 8, 8)[0]
+    ref = forward(spec, img)
+    M = spec["members"]
+    t = {"x": np.broadcast_to(img[None, None], (M, 1) + img.shape).copy()}
+    for ly in spec["layers"]:
+        x = t[ly["inp"]]
+        if ly["op"] == "conv":
+            y = nets._conv_fwd(x, nets.conv_weights(ly["codebook"], ly["idx"]), ly["bias"], ly["stride"])
+            if ly.get("short"):
+                sh = ly["short"]
+                y = y + nets._conv_fwd(t[sh["inp"]], nets.conv_weights(sh["codebook"], sh["idx"]), None, sh["stride"])
+        elif ly["op"] == "act":
+            y = ly["a_absorb"] * (x * x + ly["b"][:, None, :, None, None] * x + ly["c"][:, None, :, None, None])
+        elif ly["op"] == "dense":
+            y = np.einsum("mbc,mkc->mbk", x.sum(axis=(3, 4)), ly["w"]) + ly["bias"][:, None, :]
+        t[ly["out"]] = y
+    assert np.allclose(t["logits"][:, 0], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_clustering_respects_slices():
+    spec = nets.resnet_spec(seed=4, members=3, widths=(4,), blocks=1, classes=3, image=(3, 8, 8), k=5, calib=2)
+    for ly in spec["layers"]:
+        if ly["op"] == "conv":
+            assert ly["codebook"].shape[1] == 5 and ly["codebook"].shape[2] == 3
+            assert ly["idx"].max() < 5
+            W = nets.conv_weights(ly["codebook"], ly["idx"])
+            # one codebook per kernel column: each column uses at most k distinct member vectors
+            for col in range(ly["ksize"]):
+                rows = W[:, :, :, :, col].reshape(3, -1).T
+                assert len(np.unique(rows, axis=0)) <= 5
+
+
+def test_kmeans_recovers_separated_clusters():
+    g = gen.rng(0)
+    centres = np.array([[-1.0, 0.5], [0.0, 0.0], [2.0, -1.0]])
+    X = np.concatenate([c + 0.01 * g.standard_normal((50, 2)) for c in centres])
+    C, lab = nets.kmeans_rows(X, 3)
+    got = C[np.argsort(C[:, 0])]
+    assert np.allclose(got, centres[np.argsort(centres[:, 0])], atol=0.01)
+    assert len(set(lab[:50])) == 1 and len(set(lab[50:100])) == 1
+
+
+def test_tiny_network_decrypts_to_forward():
+    ps = tiny()
+    spec = nets.tiny_spec(0)
+    o = Oracle.from_params(ps)
+    net = OracleNetwork(o, spec, delta=2.0 ** 40, target=2.0 ** 34, in_scale=2.0 ** 40)
+    sk = o.secret_key(7)
+    rlk = o.relin_key(sk)
+    gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in net.steps()}
+    img = gen.images(5, 1, 1, 8, 8)[0]
+    outs, grid = net.run(sk, net.encrypt_image(sk, img, 100), rlk, gk)
+    assert outs[0].level == 0
+    z = o.decrypt_decode(outs[0], sk)
+    got = np.array([[z[grid["gap"] * (r * 8 + c)] for c in range(8)] for r in range(8)])
+    ref = forward(spec, img)[0, 0]
+    assert np.max(np.abs(got - ref)) < 1e-5
+
+
+@pytest.mark.slow
+def test_small_resnet_ensemble_decrypts_to_forward():
+    spec = nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8, calib=4)
+    ps = small_tower(logN=12, levels=6)
+    o = Oracle.from_params(ps)
+    D = 2.0 ** 30
+    net = OracleNetwork(o, spec, delta=D, target=D, in_scale=D)
+    sk = o.secret_key(9)
+    rlk = o.relin_key(sk)
+    gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in net.steps()}
+    img = gen.images(3, 1, 3, 16, 16)[0]
+    outs, _ = net.run(sk, net.encrypt_image(sk, img, 100), rlk, gk)
+    assert outs[0].level == 0
+    B = spec["layout"]["block"]
+    got = np.array([[o.decrypt_decode(c, sk)[m * B] for c in outs] for m in range(2)])
+    ref = forward(spec, img)
+    assert np.max(np.abs(got - ref)) < 1e-3
+    assert got.mean(0).argmax() == ref.mean(0).argmax()
+
+
+def _count_levels(spec, ps, delta):
+    from paper_2509_22857_amd.network import plan_network
+    plans, state = plan_network(spec, ps.q, delta, delta, delta)
+    return len(ps.q) - 1 - state[spec["layers"][-1]["out"]][0], sum(p.rescale for p in plans)
+
+
+def test_tower_reuse_level_count_resnet20():
+    """Section 4.4 (levels table): ResNet-20 needs 20 levels with every
+    optimisation (tower reuse halves the per-layer count)."""
+    spec = nets.resnet_spec(seed=0, members=1, widths=(16, 32, 64), blocks=3, classes=10, image=(3, 32, 32), k=4,
+                            calib=1)
+    ps = resnet20_tower()
+    used, rescales = _count_levels(spec, ps, 2.0 ** 30)
+    assert used == 20 and rescales == 20
+
+
+def test_standard_chain_rescales_after_every_product():
+    """With every prime ~ Delta (sublevel 1) the rule degenerates to the
+    standard chain: one rescale per multiplicative layer (the tiny case)."""
+    ps = tiny()
+    spec = nets.tiny_spec(0)
+    from paper_2509_22857_amd.network import plan_network
+    plans, state = plan_network(spec, ps.q, 2.0 ** 40, 2.0 ** 34, 2.0 ** 40)
+    assert [p.rescale for p in plans] == [True, True]
+    assert state["y"][0] == 0

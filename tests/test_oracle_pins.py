@@ -203,6 +203,21 @@ def test_encode_decode_roundtrip_and_constant():
     assert np.all(c.data[0, 1:] == 0)
 
 
+def test_canonical_twiddles_match_libm():
+    """The series-based twiddles used by the encoding FFT equal cos/sin to
+    within a few ulp over every table the transforms use."""
+    import ctypes as C
+    L = lib()
+    L.oc_canon_cs.argtypes = [C.c_uint64, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    c, s = C.c_double(), C.c_double()
+    for M in (1 << 12, 1 << 16, 1 << 17):
+        js = list(range(0, M // 2, max(1, M // 4096))) + [M // 8, M // 4, 3 * M // 8, M // 2 - 1]
+        for j in js:
+            L.oc_canon_cs(j, M, C.byref(c), C.byref(s))
+            ang = 2 * np.pi * j / M
+            assert abs(c.value - np.cos(ang)) < 1e-15 and abs(s.value - np.sin(ang)) < 1e-15, (j, M)
+
+
 def test_const_residue_of_large_values():
     o = small_oracle(logN=4, bits=(60, 61, 40))
     v, s = -0.3125, 2.0 ** 90

@@ -1,0 +1,250 @@
+"""Synthetic polynomial-activation CNNs, generated from a seed.
+
+No trained weights or datasets exist here, so every network is drawn at
+random with the shapes of the paper's models and then put into the form the
+encrypted evaluator consumes (Sections 4 and 5 of the paper):
+  * batch normalisation already folded into the convolutions (node fusing,
+    Case 2): each convolution carries a bias;
+  * quadratic activations a x^2 + b x + c with per-(channel, member)
+    coefficients, made monic by weight redistribution (Section 4.2): the
+    leading coefficient a moves forward into every consumer of the
+    activation (the next convolution, the shortcut, the dense layer);
+  * slice ensemble clustering (Sections 5.2-5.3): for every layer and kernel
+    column, the weight vectors over the M ensemble members are replaced by
+    the nearest of k centroids found by Lloyd's k-means (l2).
+Before redistribution and clustering each layer is rescaled so that its
+pre-activation RMS over the calibration images is 1, which keeps a random
+network with quadratic activations from escaping or vanishing.
+
+The spec is a plain dict of numpy arrays.  The calibration forward below is
+this module's own and serves only to scale the random weights; the oracle
+has an independent forward used for accuracy checks.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .gen import rng, images
+
+
+# ----------------------------------------------------------------- k-means
+def kmeans_rows(X: np.ndarray, k: int, iters: int = 50, seed: int = 0):
+    """Lloyd's algorithm on the rows of X (n x M): returns (centroids k x M, labels n)."""
+    n = X.shape[0]
+    k = min(k, n)
+    order = np.argsort(X.mean(axis=1), kind="stable")
+    init = order[np.linspace(0, n - 1, k).round().astype(int)]
+    C = X[init].copy()
+    labels = np.zeros(n, dtype=np.int64)
+    for _ in range(iters):
+        d = ((X[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
+        labels = d.argmin(axis=1)
+        for j in range(k):
+            sel = labels == j
+            if sel.any():
+                C[j] = X[sel].mean(axis=0)
+    d = ((X[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
+    labels = d.argmin(axis=1)
+    return C, labels
+
+
+def cluster_conv(W: np.ndarray, k: int, seed: int = 0):
+    """W: [M][O][I][kh][kw] -> codebook [kw][k][M], idx [O][I][kh][kw] (slice ensemble clustering)."""
+    M, O, I, kh, kw = W.shape
+    codebook = np.zeros((kw, k, M))
+    idx = np.zeros((O, I, kh, kw), dtype=np.uint16)
+    for col in range(kw):
+        X = W[:, :, :, :, col].reshape(M, -1).T  # rows = (o, i, h), columns = members
+        C, lab = kmeans_rows(X, k, seed=seed + col)
+        codebook[col, :C.shape[0]] = C
+        idx[:, :, :, col] = lab.reshape(O, I, kh)
+    return codebook, idx
+
+
+def conv_weights(codebook: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """Expand a clustered convolution back to [M][O][I][kh][kw]."""
+    kw = idx.shape[3]
+    cols = [codebook[col][idx[:, :, :, col]] for col in range(kw)]  # each [O][I][kh][M]
+    W = np.stack(cols, axis=3)  # [O][I][kh][kw][M]
+    return np.moveaxis(W, -1, 0)
+
+
+# ----------------------------------------------------------------- calibration forward
+def _conv_fwd(x, W, b, stride):
+    """x: [M][B][I][H][W]; W: [M][O][I][k][k]; b: [M][O] or None (zero 'same' padding)."""
+    M, Bn, I, H, Wd = x.shape
+    O, k = W.shape[1], W.shape[3]
+    p = k // 2
+    xp = np.pad(x, ((0, 0), (0, 0), (0, 0), (p, p), (p, p)))
+    Ho, Wo = H // stride, Wd // stride
+    y = np.zeros((M, Bn, O, Ho, Wo))
+    for dh in range(k):
+        for dw in range(k):
+            patch = xp[:, :, :, dh:dh + H:stride, dw:dw + Wd:stride][:, :, :, :Ho, :Wo]
+            y += np.einsum("mbihw,moi->mbohw", patch, W[:, :, :, dh, dw])
+    if b is not None:
+        y += b[:, None, :, None, None]
+    return y
+
+
+def _rms(x):
+    return float(np.sqrt(np.mean(x * x)))
+
+
+# ----------------------------------------------------------------- network builders
+def _act_coeffs(g, M, C):
+    a = g.uniform(0.05, 0.2, (M, C))
+    b = g.uniform(-0.5, 0.5, (M, C))
+    c = g.uniform(-0.5, 0.5, (M, C))
+    return a, b, c
+
+
+def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: int = 3, classes: int = 100,
+                image=(3, 32, 32), k: int = 64, calib: int = 8, name: str | None = None,
+                block_slots: int | None = None) -> dict:
+    """ResNet-style ensemble: conv1, len(widths) stages x `blocks` basic blocks
+    (stride 2 at each new stage, 1x1 stride-2 projection shortcuts), global
+    average pooling folded into the dense layer."""
+    g = rng(seed)
+    M = members
+    Cin, H, W = image
+    x = np.broadcast_to(images(seed + 1000, calib, Cin, H, W)[None], (M, calib, Cin, H, W)).copy()
+    layers = []
+    raw = []  # (kind, dict) before redistribution
+
+    def new_conv(O, I, ksz, fan_scale=0.05):
+        return g.normal(0.0, fan_scale, (M, O, I, ksz, ksz))
+
+    # ---- raw network with calibration, stored as a list of ops
+    def calibrate_conv(xin, Wc, bc, stride, target=1.0, extra=None):
+        y = _conv_fwd(xin, Wc, None, stride)
+        if extra is None:
+            s = target / max(_rms(y), 1e-12)
+            return Wc * s, bc * s
+        # pick s so that RMS(s*y + extra) = target
+        u, v = y.ravel(), extra.ravel()
+        A, Bq, Cq = np.mean(u * u), 2 * np.mean(u * v), np.mean(v * v) - target ** 2
+        disc = max(Bq * Bq - 4 * A * Cq, 0.0)
+        s = (-Bq + np.sqrt(disc)) / (2 * A) if A > 0 else 1.0
+        if s <= 0:
+            s = target / max(_rms(y), 1e-12)
+        return Wc * s, bc * s
+
+    def act_raw(xin, a, b, c):
+        return a[:, None, :, None, None] * xin ** 2 + b[:, None, :, None, None] * xin + c[:, None, :, None, None]
+
+    tensors = {"x": x}
+    # conv1
+    C0 = widths[0]
+    W1 = new_conv(C0, Cin, 3)
+    b1 = g.normal(0.0, 0.05, (M, C0))
+    W1, b1 = calibrate_conv(x, W1, b1, 1)
+    y = _conv_fwd(x, W1, b1, 1)
+    a, b, c = _act_coeffs(g, M, C0)
+    raw.append(("conv", dict(name="conv1", inp="x", out="c1", W=W1, b=b1, stride=1)))
+    raw.append(("act", dict(name="act1", inp="c1", out="a1", a=a, b=b, c=c)))
+    cur = act_raw(y, a, b, c)
+    cur_name, cur_ch = "a1", C0
+    for si, width in enumerate(widths):
+        for bi in range(blocks):
+            stride = 2 if (si > 0 and bi == 0) else 1
+            tag = f"s{si}b{bi}"
+            Wa = new_conv(width, cur_ch, 3)
+            ba = g.normal(0.0, 0.05, (M, width))
+            Wa, ba = calibrate_conv(cur, Wa, ba, stride)
+            ya = _conv_fwd(cur, Wa, ba, stride)
+            aa, bb_, cc_ = _act_coeffs(g, M, width)
+            ha = act_raw(ya, aa, bb_, cc_)
+            if stride == 1 and width == cur_ch:
+                Ws = np.broadcast_to(np.eye(width)[None, :, :, None, None], (M, width, width, 1, 1)).copy()
+            else:
+                Ws = g.normal(0.0, 0.05, (M, width, cur_ch, 1, 1))
+                Ws, _ = calibrate_conv(cur, Ws, np.zeros((M, width)), stride, target=0.5)
+            short = _conv_fwd(cur, Ws, None, stride)
+            Wb = new_conv(width, width, 3)
+            bbias = g.normal(0.0, 0.05, (M, width))
+            Wb, bbias = calibrate_conv(ha, Wb, bbias, 1, extra=short)
+            z = _conv_fwd(ha, Wb, bbias, 1) + short
+            a2, b2, c2 = _act_coeffs(g, M, width)
+            raw.append(("conv", dict(name=f"{tag}a", inp=cur_name, out=f"{tag}ca", W=Wa, b=ba, stride=stride)))
+            raw.append(("act", dict(name=f"{tag}acta", inp=f"{tag}ca", out=f"{tag}ha", a=aa, b=bb_, c=cc_)))
+            raw.append(("conv", dict(name=f"{tag}b", inp=f"{tag}ha", out=f"{tag}z", W=Wb, b=bbias, stride=1,
+                                     short=dict(inp=cur_name, W=Ws, stride=stride))))
+            raw.append(("act", dict(name=f"{tag}actb", inp=f"{tag}z", out=f"{tag}y", a=a2, b=b2, c=c2)))
+            cur = act_raw(z, a2, b2, c2)
+            cur_name, cur_ch = f"{tag}y", width
+    # dense after global average pooling (divisor folded into w)
+    Hf, Wf = cur.shape[3], cur.shape[4]
+    pooled = cur.sum(axis=(3, 4))  # [M][B][C]
+    Wd = g.normal(0.0, 0.05, (M, classes, cur_ch)) / (Hf * Wf)
+    bd = g.normal(0.0, 0.05, (M, classes))
+    logits = np.einsum("mbc,mkc->mbk", pooled, Wd)
+    s = 1.0 / max(_rms(logits), 1e-12)
+    Wd, bd = Wd * s, bd * s
+    raw.append(("dense", dict(name="fc", inp=cur_name, out="logits", W=Wd, b=bd)))
+    return _finalise(raw, name or f"resnet_{'-'.join(map(str, widths))}x{blocks}_M{M}_k{k}", M, classes, image,
+                     k, seed, block_slots)
+
+
+def _finalise(raw, name, M, classes, image, k, seed, block_slots):
+    """Weight redistribution (monic activations, a pushed forward) + clustering."""
+    # consumers of each tensor: convs (main or shortcut) and dense
+    act_scale = {}  # tensor name -> a [M][C] to multiply into consumers' input-channel weights
+    for kind, d in raw:
+        if kind == "act":
+            act_scale[d["out"]] = d["a"]
+    layers = []
+    for li, (kind, d) in enumerate(raw):
+        if kind == "conv":
+            W = d["W"].copy()
+            if d["inp"] in act_scale:
+                W = W * act_scale[d["inp"]][:, None, :, None, None]
+            cb, ix = cluster_conv(W, k, seed=seed * 131 + li)
+            L = dict(op="conv", name=d["name"], inp=d["inp"], out=d["out"], out_ch=W.shape[1], in_ch=W.shape[2],
+                     ksize=W.shape[3], stride=d["stride"], codebook=cb, idx=ix, bias=d["b"].copy())
+            if "short" in d:
+                sh = d["short"]
+                Ws = sh["W"].copy()
+                if sh["inp"] in act_scale:
+                    Ws = Ws * act_scale[sh["inp"]][:, None, :, None, None]
+                scb, six = cluster_conv(Ws, k, seed=seed * 131 + li + 7)
+                L["short"] = dict(inp=sh["inp"], ksize=1, stride=sh["stride"], out_ch=Ws.shape[1], in_ch=Ws.shape[2],
+                                  codebook=scb, idx=six)
+            layers.append(L)
+        elif kind == "act":
+            a = d["a"]
+            layers.append(dict(op="act", name=d["name"], inp=d["inp"], out=d["out"], b=d["b"] / a, c=d["c"] / a,
+                               a_absorb=1.0))
+        elif kind == "dense":
+            W = d["W"].copy()
+            if d["inp"] in act_scale:
+                W = W * act_scale[d["inp"]][:, None, :]
+            layers.append(dict(op="dense", name=d["name"], inp=d["inp"], out=d["out"], w=W, bias=d["b"].copy()))
+        elif kind == "pool":
+            layers.append(dict(op="pool", name=d["name"], inp=d["inp"], out=d["out"]))
+    Cin, H, W = image
+    B = block_slots or (1 << int(np.ceil(np.log2(H * W))))
+    return dict(name=name, members=M, classes=classes, image=tuple(image), layout=dict(block=B, row_stride=W),
+                layers=layers, k=k)
+
+
+def tiny_spec(seed: int = 0) -> dict:
+    """8x8x1 input, one 3x3 convolution with weights U[-1, 1], then the
+    activation 0.125 x^2 + 0.5 x + 0.25 (leading coefficient absorbed into the
+    scale; no next layer to receive it)."""
+    g = rng(seed)
+    w = g.uniform(-1.0, 1.0, (3, 3))
+    codebook = np.zeros((3, 3, 1))
+    idx = np.zeros((1, 1, 3, 3), dtype=np.uint16)
+    for col in range(3):
+        for h in range(3):
+            codebook[col, h, 0] = w[h, col]
+            idx[0, 0, h, col] = h
+    a = 0.125
+    layers = [
+        dict(op="conv", name="conv", inp="x", out="c", out_ch=1, in_ch=1, ksize=3, stride=1, codebook=codebook,
+             idx=idx, bias=None),
+        dict(op="act", name="act", inp="c", out="y", b=np.array([[0.5 / a]]), c=np.array([[0.25 / a]]), a_absorb=a),
+    ]
+    return dict(name="tiny_conv_act", members=1, classes=0, image=(1, 8, 8), layout=dict(block=64, row_stride=8),
+                layers=layers, k=3)
