@@ -1,0 +1,216 @@
+"""Benchmark: encrypted images/s of a ResNet-20-style ensemble at N = 2^16.
+
+One step = the whole encrypted network (every convolution, activation,
+rescale and the dense layer) over one batch of client-encrypted images that
+are already resident in HBM.  The same kernels also run one image at a time
+("plain") for the batched-vs-plain comparison.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_workload(args):
+    from workloads import nets
+    from workloads.params import resnet20_tower
+    ps = resnet20_tower()
+    spec = nets.resnet_spec(seed=0, members=4, widths=(16, 32, 64), blocks=3, classes=100, image=(3, 32, 32),
+                            k=64, calib=8)
+    return ps, spec
+
+
+def cpu_baseline(ps, spec, gpu_share_ratio: float):
+    """Oracle (as it stands) on a bounded sample: one key switch (rotation) at
+    the top level of the same parameters, scaled to a whole image by the
+    GPU's own ratio (image time / top-level rotation time)."""
+    from oracle.ckks import Oracle, Ct
+    from workloads import gen
+    o = Oracle.from_params(ps)
+    t0 = time.time()
+    sk = o.secret_key(1)
+    g = o.galois_elt(1)
+    gk = o.galois_key(sk, g)
+    t_key = time.time() - t0
+    ct = Ct(gen.random_ct(3, ps.q, ps.L, ps.N), ps.L, 2.0 ** 30)
+    t1 = time.time()
+    o.rotate(ct, 1, gk)
+    t_rot = time.time() - t1
+    sec_per_image = t_rot * gpu_share_ratio
+    return {"value": 1.0 / sec_per_image, "unit": "images/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one top-level rotation (hybrid key switch, N=2^16, {len(ps.q)}+{len(ps.p)} primes) on the "
+                       f"oracle took {t_rot:.2f} s (its key generation {t_key:.2f} s, untimed); scaled to one image "
+                       f"by the GPU's image-time / top-level-rotation-time ratio {gpu_share_ratio:.1f}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--plain", type=int, default=2, help="images timed one at a time")
+    ap.add_argument("--check", type=int, default=4, help="images whose logits are checked against FP64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="resnet20", choices=["resnet20", "micro"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X; "
+              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "micro":
+        from paper_2509_22857_amd import microbench
+        print(json.dumps(microbench.run(args)))
+        return
+
+    import torch
+    from paper_2509_22857_amd import ckks
+    from paper_2509_22857_amd.ckks import Context
+    from paper_2509_22857_amd.network import GpuNetwork
+    from workloads import gen
+
+    t0 = time.time()
+    ps, spec = build_workload(args)
+    log(f"spec built in {time.time() - t0:.1f}s; params {ps.name}: N=2^{ps.logN}, {len(ps.q)} Q + {len(ps.p)} P primes")
+    ctx = Context.from_params(ps)
+    delta = 2.0 ** ps.delta_log2
+    t0 = time.time()
+    net = GpuNetwork(ctx, spec, delta, delta, delta)
+    torch.cuda.synchronize()
+    log(f"layers on device in {time.time() - t0:.1f}s ({net.device_bytes() / 2**30:.1f} GiB plaintext codebooks)")
+    t0 = time.time()
+    keys = ctx.keygen(12345, net.steps)
+    log(f"keys: {len(net.steps)} rotations + relin, {keys.evk_bytes() / 2**30:.1f} GiB, {time.time() - t0:.1f}s")
+    B = args.batch
+    imgs = gen.images(777, B, *spec["image"])
+    t0 = time.time()
+    cts = net.encrypt_images(keys, imgs, stream_base=1 << 20)
+    torch.cuda.synchronize()
+    log(f"encrypted {B} images in {time.time() - t0:.1f}s")
+
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        t0 = time.time()
+        out, _ = net.run(keys, cts)
+        torch.cuda.synchronize()
+        log(f"warmup {w}: {time.time() - t0:.2f}s")
+
+    ckks.prof_enable(True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.time()
+    ev0.record(stream)
+    for k in range(args.steps):
+        out, _ = net.run(keys, cts)
+        log(f"step {k} enqueued")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - t_wall
+    ms = ev0.elapsed_time(ev1)
+    prof = {k: ckks.prof_query(k) for k in ckks.PROF_KERNELS}
+    ckks.prof_enable(False)
+    sec_per_step = ms / 1e3 / args.steps
+    ips = B / sec_per_step
+    log(f"batched: {sec_per_step:.2f}s per step of {B} images -> {ips:.3f} images/s (wall {wall:.1f}s)")
+
+    # plain: one image at a time through the same kernels
+    t_plain = 0.0
+    nplain = min(args.plain, B)
+    for i in range(nplain):
+        torch.cuda.synchronize()
+        a = time.time()
+        net.run(keys, [cts[i]])
+        torch.cuda.synchronize()
+        t_plain += time.time() - a
+    plain_ips = nplain / t_plain if nplain else None
+    log(f"plain: {plain_ips:.3f} images/s")
+
+    # accuracy of the timed outputs against the FP64 forward
+    from oracle.forward import forward
+    max_err, agree = 0.0, 0
+    nchk = min(args.check, B)
+    for i in range(nchk):
+        got = net.decrypt_logits(keys, out[i])
+        ref = forward(spec, imgs[i])
+        max_err = max(max_err, float(np.max(np.abs(got - ref))))
+        agree += int(got.mean(0).argmax() == ref.mean(0).argmax())
+    log(f"logits vs FP64: max abs err {max_err:.2e}, top-1 agree {agree}/{nchk}")
+
+    # roofline of the dominant kernel class
+    tot = {k: v["ms"] for k, v in prof.items()}
+    dom = max(tot, key=tot.get)
+    kip = prof["kip"]
+    kip_gbs = kip["bytes"] / (kip["ms"] / 1e3) / 1e9 if kip["ms"] > 0 else 0.0
+    d = prof[dom]
+    launches = max(d["launches"], 1)
+    achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(d["ms"] / launches, 4), "launches": d["launches"]}
+    shares = {k: round(v / max(sum(tot.values()), 1e-9), 3) for k, v in tot.items()}
+    log(f"kernel time shares: {shares}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # GPU time of one top-level rotation group member: measure a single rotation
+        one = ctx.new_ct(len(ps.q) - 1)
+        one.buf.copy_(cts[0][0].buf)
+        one.scale = cts[0][0].scale
+        ctx.rotate(keys, one, [1])
+        torch.cuda.synchronize()
+        a = time.time()
+        for _ in range(5):
+            ctx.rotate(keys, one, [1])
+        torch.cuda.synchronize()
+        t_rot_gpu = (time.time() - a) / 5
+        ratio = (sec_per_step / B) / t_rot_gpu
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(ps, spec, ratio)
+
+    res = {
+        "metric": "encrypted images/s (ResNet-20-style ensemble, N=2^16, batched)",
+        "value": round(ips, 4),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "resnet20_ensemble_N65536", "images_per_step": B, "members": spec["members"],
+                   "classes": spec["classes"], "k": spec["k"], "image": list(spec["image"]),
+                   "levels": len(ps.q) - 1, "primes_q": len(ps.q), "primes_p": len(ps.p), "alpha": ps.alpha},
+        "plain_images_per_s": round(plain_ips, 4) if plain_ips else None,
+        "batched_over_plain": round(ips / plain_ips, 3) if plain_ips else None,
+        "key_switch_hbm": {"kernel": "kip", "achieved_GBs": round(kip_gbs, 1),
+                           "frac": round(kip_gbs / HBM_PEAK_GBS, 4)},
+        "accuracy": {"max_abs_logit_err": max_err, "top1_agree": f"{agree}/{nchk}"},
+        "kernel_time_share": shares,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -260,6 +260,18 @@ int ckc_layer_out_layout(const ckc_layer *layer, ckc_layout *out);
 size_t ckc_layer_bytes(const ckc_layer *layer);
 int ckc_layer_destroy(ckc_layer *layer);
 
+/* ------------------------------------------------------------------ profiling
+ * Opt-in launch timing for measurement: while enabled, the library records a
+ * HIP event pair around every launch of the named kernel classes ("ntt_fwd",
+ * "ntt_inv", "bconv", "kip", "moddown", "conv_contract", "act_tensor",
+ * "dense_mac", "ew") on the stream the kernel runs on, together with the
+ * algorithmic bytes (each word read or written once) and work (butterflies
+ * for the NTT, 64-bit products for the key inner product) of the launch.
+ * ckc_prof_enable clears the records; ckc_prof_query waits for the recorded
+ * events and sums them for one class. */
+int ckc_prof_enable(int on);
+int ckc_prof_query(const char *kernel, int64_t *launches, double *total_ms, double *bytes, double *work);
+
 #ifdef __cplusplus
 }
 #endif

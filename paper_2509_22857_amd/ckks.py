@@ -96,6 +96,8 @@ _SIGS = [
     ("ckc_layer_out_layout", C.c_int, [_vp, C.POINTER(ckc_layout)]),
     ("ckc_layer_bytes", C.c_size_t, [_vp]),
     ("ckc_layer_destroy", C.c_int, [_vp]),
+    ("ckc_prof_enable", C.c_int, [C.c_int]),
+    ("ckc_prof_query", C.c_int, [C.c_char_p, C.POINTER(C.c_int64), _dblp, _dblp, _dblp]),
 ]
 
 
@@ -508,3 +510,17 @@ def add_many(ctx, a, b, outs, stream=None):
     _check("ckc_add_many", lib().ckc_add_many(ctx.h, aa, ba, len(a), oa, _stream(stream)))
     _update_all(outs, oa)
     return outs
+
+
+def prof_enable(on: bool = True):
+    _check("ckc_prof_enable", lib().ckc_prof_enable(int(on)))
+
+
+def prof_query(name: str) -> dict:
+    n = C.c_int64()
+    ms, by, wk = C.c_double(), C.c_double(), C.c_double()
+    _check("ckc_prof_query", lib().ckc_prof_query(name.encode(), C.byref(n), C.byref(ms), C.byref(by), C.byref(wk)))
+    return {"launches": int(n.value), "ms": ms.value, "bytes": by.value, "work": wk.value}
+
+
+PROF_KERNELS = ("ntt_fwd", "ntt_inv", "bconv", "kip", "moddown", "conv_contract", "act_tensor", "dense_mac", "ew")

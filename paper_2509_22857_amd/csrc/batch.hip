@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "batch.h"
+#include "prof.h"
 
 const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc);
 const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc);
@@ -195,9 +196,12 @@ int ks_modup_b(ckc_ctx *c, const uint64_t *x, size_t xs, int nb, int level, uint
         if (!t) return rc;
         const int lo = j * c->alpha, ns = t->ns;
         uint64_t *dj = digits + size_t(j) * nt * N;
+        {
+            CKC_PROF(PK_BCONV, s, 8.0 * N * (ns + nt - ns) * nb, 0.0);
         hipLaunchKernelGGL(k_bconv_b, dim3(tiles(N), unsigned(nt), unsigned(nb)), dim3(256), 0, s,
                            coeff.u64() + size_t(lo) * N, size_t(nl) * N, ns, lo, qmap(), dj, dig_bs, ext, lo, lo + ns,
                            t->inv.u64(), t->invp.u64(), t->hat.u64(), c->dprimes(), c->logN);
+        }
         CKC_HIP(hipGetLastError());
         CKC_TRY(ntt_forward(c, dj, nt, ext, nb, dig_bs, s, lo, lo + ns));
         CKC_TRY(copy_limbs(x + size_t(lo) * N, xs, dj + size_t(lo) * N, dig_bs, N * ns, nb, s));
@@ -221,8 +225,13 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
     CKC_TRY(pl.alloc(8 * N * np * 2 * nb, s));
     CKC_TRY(conv.alloc(8 * N * nl * 2 * nb, s));
     const LimbMap ext{nl, c->nq};
+    {
+        // algorithmic bytes: every digit word, every key word and every accumulator word once
+        const double bytes = 8.0 * N * nt * (double(nb) * dnum + 2.0 * dnum + 2.0 * nb);
+        CKC_PROF(PK_KIP, s, bytes, 2.0 * N * nt * dnum * nb);
     hipLaunchKernelGGL(k_kip_b, dim3(tiles(N), unsigned(nt)), dim3(256), 0, s, digits, nb, dnum, nt, key,
                        c->nprimes(), ext, perm, acc.u64(), c->dprimes(), c->logN);
+    }
     CKC_HIP(hipGetLastError());
     // P limbs of every accumulator (2 nb of them) -> coefficient form -> convert to Q -> NTT
     CKC_TRY(copy_limbs(acc.u64() + size_t(nl) * N, size_t(nt) * N, pl.u64(), size_t(np) * N, N * np, 2 * nb, s));
@@ -234,6 +243,7 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
     CKC_HIP(hipGetLastError());
     CKC_TRY(ntt_forward(c, conv.u64(), nl, qmap(), 2 * nb, size_t(nl) * N, s));
     Ptrs none{};
+    CKC_PROF(PK_MODDOWN, s, 8.0 * N * nl * 2 * nb * (3.0 + (add0 ? 0.5 : 0) + (add1 ? 0.5 : 0)), 0.0);
     hipLaunchKernelGGL(k_moddown_combine_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s,
                        acc.u64(), nt, conv.u64(), nl, c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none,
                        add0 ? 1 : 0, add1 ? 1 : 0, perm_add0 ? perm : nullptr, out0, out1, c->dprimes(), c->logN);
@@ -266,6 +276,7 @@ int ew_b(ckc_ctx *c, EwOp op, const Ptrs &out, const Ptrs &a, const Ptrs *b, int
          hipStream_t s) {
     if (nb <= 0) return CKC_OK;
     Ptrs none{};
+    CKC_PROF(PK_EW, s, 8.0 * c->N * nl * npoly * nb * (b ? 3.0 : 2.0), 0.0);
     hipLaunchKernelGGL(k_ew_b, dim3(tiles(c->N), unsigned(nl * npoly), unsigned(nb)), dim3(256), 0, s, int(op), out, a,
                        b ? *b : none, b ? 1 : 0, nl, c->dprimes(), c->logN);
     CKC_HIP(hipGetLastError());

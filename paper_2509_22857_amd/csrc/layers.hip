@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "prof.h"
 
 int encode_impl(ckc_ctx *c, const double *slots_h, size_t nslots, int level, double scale, uint64_t *m,
                 hipStream_t s);
@@ -506,6 +507,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                 Ptrs op;
                 for (int j = 0; j < oc; ++j) op.p[j] = out[size_t(img0 + ii) * L->O + o0 + j].d;
                 const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
+                CKC_PROF(PK_CONV_CONTRACT, s, 8.0 * N * nl * 2 * (double(I) * ntap + oc), 0.0);
                 hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups), dim3(256),
                                    lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent, (const int32_t *)L->og_off.p,
                                    (const int32_t *)L->g_c.p, (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p,
@@ -574,8 +576,11 @@ extern "C" int ckc_eval_quad_act(ckc_ctx *c, const ckc_evk *evk, const ckc_layer
             o0.p[b] = out[b0 + b].d;
             o1.p[b] = out[b0 + b].d + pw;
         }
+        {
+            CKC_PROF(PK_ACT_TENSOR, s, 8.0 * N * nl * nb * 6.0, 0.0);
         hipLaunchKernelGGL(k_act_tensor, dim3(tiles(N), unsigned(nl), unsigned(nb)), dim3(256), 0, s, xp, bp, D.u64(),
                            nl, c->dprimes(), c->logN);
+        }
         CKC_HIP(hipGetLastError());
         CKC_TRY(ks_modup_b(c, D.u64() + 2 * pw, 3 * pw, nb, L->level, digits.u64(), s));
         CKC_TRY(ks_apply_b(c, digits.u64(), nb, L->level, evk->relin->u64(), 1, &a0, &a1, false, o0, o1, s));
@@ -670,8 +675,11 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
                 CKC_TRY(ew_b(c, EW_ADD, sp, sp, &tp, nb, 2, nl, s));
             }
         }
+        {
+            CKC_PROF(PK_DENSE_MAC, s, 8.0 * N * nl * (2.0 * ni * C + double(K) * C + 2.0 * ni * K), 0.0);
         hipLaunchKernelGGL(k_dense_mac, dim3(tiles(N), unsigned(nl), unsigned(2 * K)), dim3(256), 0, s, Sb.u64(), ni, C,
                            nl, L->pts.u64(), L->has_bias ? L->bias.u64() : nullptr, Z.u64(), K, c->dprimes(), c->logN);
+        }
         CKC_HIP(hipGetLastError());
         for (int b0 = 0; b0 < ni * K; b0 += kMaxBatch) {
             const int nb = std::min(kMaxBatch, ni * K - b0);

@@ -12,6 +12,7 @@
 // through LDS and runs its stages there, so a transform reads and writes the
 // limb twice.
 #include "ckc_internal.h"
+#include "prof.h"
 
 namespace {
 
@@ -150,6 +151,8 @@ int ntt_forward(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbat
     if (nlimbs <= 0 || nbatch <= 0) return CKC_OK;
     CKC_REQUIRE(c->logN >= 12 && c->logN <= 17, CKC_EUNSUPPORTED, "NTT supports 2^12 <= N <= 2^17");
     dim3 grid(unsigned(c->N / kElems), unsigned(nlimbs), unsigned(nbatch));
+    const int active = nlimbs - ((skip_lo >= 0 && skip_hi > skip_lo) ? (skip_hi - skip_lo) : 0);
+    CKC_PROF(PK_NTT_FWD, s, 16.0 * double(c->N) * active * nbatch, 0.5 * double(c->N) * c->logN * active * nbatch);
     hipLaunchKernelGGL(k_ntt_cols<false>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
                        c->tw.u64(), c->twp.u64(), c->ninv.u64(), c->logN, skip_lo, skip_hi);
     hipLaunchKernelGGL(k_ntt_rows<false>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
@@ -163,6 +166,7 @@ int ntt_inverse(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbat
     if (nlimbs <= 0 || nbatch <= 0) return CKC_OK;
     CKC_REQUIRE(c->logN >= 12 && c->logN <= 17, CKC_EUNSUPPORTED, "NTT supports 2^12 <= N <= 2^17");
     dim3 grid(unsigned(c->N / kElems), unsigned(nlimbs), unsigned(nbatch));
+    CKC_PROF(PK_NTT_INV, s, 16.0 * double(c->N) * nlimbs * nbatch, 0.5 * double(c->N) * c->logN * nlimbs * nbatch);
     hipLaunchKernelGGL(k_ntt_rows<true>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
                        c->itw.u64(), c->itwp.u64(), c->logN, -1, -1);
     hipLaunchKernelGGL(k_ntt_cols<true>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),

@@ -12,9 +12,10 @@ encrypted evaluator consumes (Sections 4 and 5 of the paper):
   * slice ensemble clustering (Sections 5.2-5.3): for every layer and kernel
     column, the weight vectors over the M ensemble members are replaced by
     the nearest of k centroids found by Lloyd's k-means (l2).
-Before redistribution and clustering each layer is rescaled so that its
-pre-activation RMS over the calibration images is 1, which keeps a random
-network with quadratic activations from escaping or vanishing.
+Before redistribution and clustering each convolution is standardised per
+(member, output channel) over the calibration images -- what a folded batch
+normalisation does -- which keeps the random network's signal input-dependent
+and bounded.
 
 The spec is a plain dict of numpy arrays.  The calibration forward below is
 this module's own and serves only to scale the random weights; the oracle
@@ -35,16 +36,21 @@ def kmeans_rows(X: np.ndarray, k: int, iters: int = 50, seed: int = 0):
     order = np.argsort(X.mean(axis=1), kind="stable")
     init = order[np.linspace(0, n - 1, k).round().astype(int)]
     C = X[init].copy()
+    x2 = (X * X).sum(axis=1)[:, None]
+
+    def assign(C):
+        d = x2 - 2.0 * (X @ C.T) + (C * C).sum(axis=1)[None, :]
+        return d.argmin(axis=1)
+
     labels = np.zeros(n, dtype=np.int64)
     for _ in range(iters):
-        d = ((X[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
-        labels = d.argmin(axis=1)
-        for j in range(k):
-            sel = labels == j
-            if sel.any():
-                C[j] = X[sel].mean(axis=0)
-    d = ((X[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
-    labels = d.argmin(axis=1)
+        labels = assign(C)
+        counts = np.bincount(labels, minlength=k)
+        sums = np.zeros_like(C)
+        np.add.at(sums, labels, X)
+        nz = counts > 0
+        C[nz] = sums[nz] / counts[nz, None]
+    labels = assign(C)
     return C, labels
 
 
@@ -92,20 +98,27 @@ def _rms(x):
 
 
 # ----------------------------------------------------------------- network builders
-def _act_coeffs(g, M, C):
+def _act_coeffs(g, M, C, b_range=(-0.5, 0.5), c_range=(-0.5, 0.5)):
     a = g.uniform(0.05, 0.2, (M, C))
-    b = g.uniform(-0.5, 0.5, (M, C))
-    c = g.uniform(-0.5, 0.5, (M, C))
+    b = g.uniform(*b_range, (M, C))
+    c = g.uniform(*c_range, (M, C))
     return a, b, c
 
 
 def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: int = 3, classes: int = 100,
-                image=(3, 32, 32), k: int = 64, calib: int = 8, name: str | None = None,
-                block_slots: int | None = None) -> dict:
+                image=(3, 32, 32), k: int = 64, calib: int = 16, name: str | None = None,
+                block_slots: int | None = None, pre_std: float = 0.5) -> dict:
     """ResNet-style ensemble: conv1, len(widths) stages x `blocks` basic blocks
     (stride 2 at each new stage, 1x1 stride-2 projection shortcuts), global
-    average pooling folded into the dense layer."""
+    average pooling folded into the dense layer.
+
+    Activations are ReLU-like quadratics (a in [0.05, 0.2], b in [0.4, 0.6],
+    c in [-0.1, 0.1]) on pre-activations standardised to `pre_std`: deep
+    random quadratic networks with larger curvature are chaotic (tiny input
+    changes escape the fitted range, Section 2.3), which would make the FP64
+    reference itself ill-conditioned."""
     g = rng(seed)
+    act_b, act_c = (0.4, 0.6), (-0.1, 0.1)
     M = members
     Cin, H, W = image
     x = np.broadcast_to(images(seed + 1000, calib, Cin, H, W)[None], (M, calib, Cin, H, W)).copy()
@@ -115,20 +128,28 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
     def new_conv(O, I, ksz, fan_scale=0.05):
         return g.normal(0.0, fan_scale, (M, O, I, ksz, ksz))
 
-    # ---- raw network with calibration, stored as a list of ops
-    def calibrate_conv(xin, Wc, bc, stride, target=1.0, extra=None):
-        y = _conv_fwd(xin, Wc, None, stride)
+    # ---- raw network with calibration, stored as a list of ops.  Each
+    # convolution is standardised per (member, output channel) over the
+    # calibration images, as a folded batch normalisation would do: zero mean,
+    # unit variance, plus a small random shift (the BN offset).
+    def calibrate_conv(xin, Wc, stride, extra=None):
+        y = _conv_fwd(xin, Wc, None, stride)  # [M][B][O][H][W]
+        Mm, Bn, O = y.shape[0], y.shape[1], y.shape[2]
+        u = np.moveaxis(y, 2, 1).reshape(Mm, O, -1)
+        shift = g.normal(0.0, 0.1 * pre_std, (Mm, O))
         if extra is None:
-            s = target / max(_rms(y), 1e-12)
-            return Wc * s, bc * s
-        # pick s so that RMS(s*y + extra) = target
-        u, v = y.ravel(), extra.ravel()
-        A, Bq, Cq = np.mean(u * u), 2 * np.mean(u * v), np.mean(v * v) - target ** 2
-        disc = max(Bq * Bq - 4 * A * Cq, 0.0)
-        s = (-Bq + np.sqrt(disc)) / (2 * A) if A > 0 else 1.0
-        if s <= 0:
-            s = target / max(_rms(y), 1e-12)
-        return Wc * s, bc * s
+            mu, sd = u.mean(axis=2), u.std(axis=2) + 1e-12
+            s = pre_std / sd
+            return Wc * s[:, :, None, None, None], -mu * s + shift
+        v = np.moveaxis(extra, 2, 1).reshape(Mm, O, -1)
+        uc = u - u.mean(axis=2, keepdims=True)
+        vc = v - v.mean(axis=2, keepdims=True)
+        A, Bq, Cq = (uc * uc).mean(axis=2), 2 * (uc * vc).mean(axis=2), (vc * vc).mean(axis=2) - pre_std ** 2
+        disc = np.maximum(Bq * Bq - 4 * A * Cq, 0.0)
+        s = (-Bq + np.sqrt(disc)) / (2 * A + 1e-30)
+        s = np.where(s > 0, s, 0.5 * pre_std / np.sqrt(A + 1e-30))
+        mean_z = s * u.mean(axis=2) + v.mean(axis=2)
+        return Wc * s[:, :, None, None, None], -mean_z + shift
 
     def act_raw(xin, a, b, c):
         return a[:, None, :, None, None] * xin ** 2 + b[:, None, :, None, None] * xin + c[:, None, :, None, None]
@@ -136,11 +157,9 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
     tensors = {"x": x}
     # conv1
     C0 = widths[0]
-    W1 = new_conv(C0, Cin, 3)
-    b1 = g.normal(0.0, 0.05, (M, C0))
-    W1, b1 = calibrate_conv(x, W1, b1, 1)
+    W1, b1 = calibrate_conv(x, new_conv(C0, Cin, 3), 1)
     y = _conv_fwd(x, W1, b1, 1)
-    a, b, c = _act_coeffs(g, M, C0)
+    a, b, c = _act_coeffs(g, M, C0, act_b, act_c)
     raw.append(("conv", dict(name="conv1", inp="x", out="c1", W=W1, b=b1, stride=1)))
     raw.append(("act", dict(name="act1", inp="c1", out="a1", a=a, b=b, c=c)))
     cur = act_raw(y, a, b, c)
@@ -149,23 +168,19 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
         for bi in range(blocks):
             stride = 2 if (si > 0 and bi == 0) else 1
             tag = f"s{si}b{bi}"
-            Wa = new_conv(width, cur_ch, 3)
-            ba = g.normal(0.0, 0.05, (M, width))
-            Wa, ba = calibrate_conv(cur, Wa, ba, stride)
+            Wa, ba = calibrate_conv(cur, new_conv(width, cur_ch, 3), stride)
             ya = _conv_fwd(cur, Wa, ba, stride)
-            aa, bb_, cc_ = _act_coeffs(g, M, width)
+            aa, bb_, cc_ = _act_coeffs(g, M, width, act_b, act_c)
             ha = act_raw(ya, aa, bb_, cc_)
             if stride == 1 and width == cur_ch:
                 Ws = np.broadcast_to(np.eye(width)[None, :, :, None, None], (M, width, width, 1, 1)).copy()
             else:
-                Ws = g.normal(0.0, 0.05, (M, width, cur_ch, 1, 1))
-                Ws, _ = calibrate_conv(cur, Ws, np.zeros((M, width)), stride, target=0.5)
+                Ws, _ = calibrate_conv(cur, g.normal(0.0, 0.05, (M, width, cur_ch, 1, 1)), stride)
+                Ws = 0.5 * Ws
             short = _conv_fwd(cur, Ws, None, stride)
-            Wb = new_conv(width, width, 3)
-            bbias = g.normal(0.0, 0.05, (M, width))
-            Wb, bbias = calibrate_conv(ha, Wb, bbias, 1, extra=short)
+            Wb, bbias = calibrate_conv(ha, new_conv(width, width, 3), 1, extra=short)
             z = _conv_fwd(ha, Wb, bbias, 1) + short
-            a2, b2, c2 = _act_coeffs(g, M, width)
+            a2, b2, c2 = _act_coeffs(g, M, width, act_b, act_c)
             raw.append(("conv", dict(name=f"{tag}a", inp=cur_name, out=f"{tag}ca", W=Wa, b=ba, stride=stride)))
             raw.append(("act", dict(name=f"{tag}acta", inp=f"{tag}ca", out=f"{tag}ha", a=aa, b=bb_, c=cc_)))
             raw.append(("conv", dict(name=f"{tag}b", inp=f"{tag}ha", out=f"{tag}z", W=Wb, b=bbias, stride=1,
@@ -177,10 +192,11 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
     Hf, Wf = cur.shape[3], cur.shape[4]
     pooled = cur.sum(axis=(3, 4))  # [M][B][C]
     Wd = g.normal(0.0, 0.05, (M, classes, cur_ch)) / (Hf * Wf)
-    bd = g.normal(0.0, 0.05, (M, classes))
-    logits = np.einsum("mbc,mkc->mbk", pooled, Wd)
-    s = 1.0 / max(_rms(logits), 1e-12)
-    Wd, bd = Wd * s, bd * s
+    logits = np.einsum("mbc,mkc->mbk", pooled, Wd)  # [M][B][K]
+    centred = logits - logits.mean(axis=1, keepdims=True)
+    s = 1.0 / max(_rms(centred), 1e-12)
+    Wd = Wd * s
+    bd = -logits.mean(axis=1) * s + g.normal(0.0, 0.1, (M, classes))
     raw.append(("dense", dict(name="fc", inp=cur_name, out="logits", W=Wd, b=bd)))
     return _finalise(raw, name or f"resnet_{'-'.join(map(str, widths))}x{blocks}_M{M}_k{k}", M, classes, image,
                      k, seed, block_slots)
