@@ -192,11 +192,10 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
     Hf, Wf = cur.shape[3], cur.shape[4]
     pooled = cur.sum(axis=(3, 4))  # [M][B][C]
     Wd = g.normal(0.0, 0.05, (M, classes, cur_ch)) / (Hf * Wf)
-    logits = np.einsum("mbc,mkc->mbk", pooled, Wd)  # [M][B][K]
-    centred = logits - logits.mean(axis=1, keepdims=True)
-    s = 1.0 / max(_rms(centred), 1e-12)
-    Wd = Wd * s
-    bd = -logits.mean(axis=1) * s + g.normal(0.0, 0.1, (M, classes))
+    bd = g.normal(0.0, 0.1, (M, classes))
+    logits = np.einsum("mbc,mkc->mbk", pooled, Wd) + bd[:, None, :]  # [M][B][K]
+    s = 1.0 / max(_rms(logits), 1e-12)  # logit RMS 1 over the calibration images
+    Wd, bd = Wd * s, bd * s
     raw.append(("dense", dict(name="fc", inp=cur_name, out="logits", W=Wd, b=bd)))
     return _finalise(raw, name or f"resnet_{'-'.join(map(str, widths))}x{blocks}_M{M}_k{k}", M, classes, image,
                      k, seed, block_slots)
