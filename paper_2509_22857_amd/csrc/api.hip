@@ -182,6 +182,9 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
         const long double bound = (long double)qmax * (long double)qmax * (long double)std::max(dnum, std::max(alpha, n_p));
         CKC_REQUIRE(bound < 0x1p127L * 2.0L, CKC_EUNSUPPORTED, "moduli too large for 128-bit accumulation of the digits");
         CKC_REQUIRE(dnum <= 16, CKC_EUNSUPPORTED, "at most 16 key-switching digits");
+        const int kmax = 64 - __builtin_clzll(qmax);
+        CKC_REQUIRE(std::max(dnum, std::max(alpha, n_p)) <= prod_cap(kmax), CKC_EUNSUPPORTED,
+                    "too many digits for the carry-free accumulator at this modulus size");
     }
     auto c = std::make_unique<ckc_ctx>();
     c->logN = log_n;

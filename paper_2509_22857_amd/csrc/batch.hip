@@ -74,18 +74,18 @@ __global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digi
         const size_t src = perm ? perm[k] : k;
         for (int b = 0; b < nb; ++b) {
             const uint64_t *dg = digits + b * dig_bs + size_t(tt) * N + src;
-            u128v a0{0, 0}, a1{0, 0};
+            acc3 a0{0, 0, 0}, a1{0, 0, 0};
 #pragma unroll
             for (int j = 0; j < kMaxDnum; ++j) {
                 if (j < dnum) {
                     const uint64_t d = dg[size_t(j) * nt * N];
-                    a0 = add128(a0, mul64x64(d, kb[j]));
-                    a1 = add128(a1, mul64x64(d, ka[j]));
+                    mac3(a0, d, kb[j]);
+                    mac3(a1, d, ka[j]);
                 }
             }
             uint64_t *ab = acc + b * acc_bs;
-            ab[size_t(tt) * N + k] = reduce128(a0, P);
-            ab[(size_t(nt) + tt) * N + k] = reduce128(a1, P);
+            ab[size_t(tt) * N + k] = reduce128(acc3_value(a0), P);
+            ab[(size_t(nt) + tt) * N + k] = reduce128(acc3_value(a1), P);
         }
     }
 }

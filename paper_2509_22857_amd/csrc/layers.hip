@@ -35,7 +35,9 @@ struct ckc_layer {
     std::vector<int32_t> tap_step;
     DevMem pts;                        // conv: [ntap][kcent][nl][N]; dense: [K][C][nl][N]
     DevMem bias;                       // conv: [O][nl][N]; dense: [K][nl][N]
-    DevMem og_off, g_c, g_moff, m_i;   // conv group lists
+    DevMem og_off, g_c, g_moff, m_i;   // conv group lists (grouped form, any codebook size)
+    DevMem idx8;                       // conv: [ntap][I][Opad] centroid indices (direct form)
+    int Opad = 0;
     // act
     int C = 0;
     double a_absorb = 1.0, in_scale = 1.0;
@@ -208,6 +210,85 @@ __global__ __launch_bounds__(256) void k_conv_contract(
     }
 }
 
+// Direct form of the same contraction for codebooks of at most kMaxCentLds
+// centroids: y_o = sum_t sum_i PT[t][idx[o][i][t]] * R[i][t] + bias_o.
+// Per tap the workgroup stages the tap's whole plaintext codebook tile
+// (kcent x 64 words) and up to 64 rotated inputs (64 x 64 words) in LDS; the
+// centroid index is wave-uniform (a scalar load), so every lane does one LDS
+// read of R, one of the codebook and a 64x64->128 multiply-accumulate.
+// Wave w owns the 8 consecutive outputs 32*group + 8w .. +7.
+// idx8: [ntap][I][Opad] uint8.
+constexpr int kMaxCentLds = 64;
+constexpr int kIChunk = 64;
+__global__ __launch_bounds__(256) void k_conv_mac(const uint64_t *__restrict__ R, int I, int ntap, int nl,
+                                                  const uint64_t *__restrict__ pts, int kcent,
+                                                  const uint8_t *__restrict__ idx8, int Opad,
+                                                  const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
+                                                  int o_count, const Prime *__restrict__ primes, int logN) {
+    extern __shared__ uint64_t lds[];
+    uint64_t *sP = lds;                   // [kcent][kTile]
+    uint64_t *sR = lds + kcent * kTile;   // [kIChunk][kTile]
+    const size_t N = size_t(1) << logN;
+    const int limb = blockIdx.y;
+    const int poly = blockIdx.z & 1, ogrp = blockIdx.z >> 1;
+    const int lane = threadIdx.x & 63;
+    // wave index as a wave-uniform (scalar) value, so per-wave control flow and
+    // index loads stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const size_t col0 = size_t(blockIdx.x) * kTile;
+    const Prime P = primes[limb];
+    const int pcap = prod_cap(P.k);
+    const int ol0 = ogrp * kOutPerWg + wave * kOutPerWave;  // first local output of this wave
+    const int my_out = min(kOutPerWave, o_count - ol0);      // outputs this wave owns (may be <= 0)
+    const int ostride = Opad / 8;                             // idx rows in 8-byte words
+    acc3 acc[kOutPerWave];
+#pragma unroll
+    for (int j = 0; j < kOutPerWave; ++j) acc[j] = acc3{0, 0, 0};
+    int cnt = 0;
+    for (int t = 0; t < ntap; ++t) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kcent * kTile; e += 256) {
+            const int c = e / kTile, l = e - c * kTile;
+            sP[e] = pts[((size_t(t) * kcent + c) * nl + limb) * N + col0 + l];
+        }
+        for (int i0 = 0; i0 < I; i0 += kIChunk) {
+            const int ni = min(kIChunk, I - i0);
+            if (i0 > 0) __syncthreads();
+            for (int e = threadIdx.x; e < ni * kTile; e += 256) {
+                const int i = e / kTile, l = e - i * kTile;
+                sR[e] = R[(((size_t(i0 + i) * ntap + t) * 2 + poly) * nl + limb) * N + col0 + l];
+            }
+            __syncthreads();
+            if (my_out > 0) {
+                // 8 consecutive output indices of this wave, one 8-byte scalar load per input
+                const uint64_t *ix = (const uint64_t *)(idx8 + (size_t(t) * I + i0) * Opad + o_base + ol0);
+                for (int ii = 0; ii < ni; ++ii) {
+                    const uint64_t r = sR[ii * kTile + lane];
+                    const uint64_t packed = ix[size_t(ii) * ostride];
+#pragma unroll
+                    for (int j = 0; j < kOutPerWave; ++j) {
+                        const int c = int((packed >> (8 * j)) & 0xff);
+                        mac3(acc[j], r, sP[c * kTile + lane]);
+                    }
+                    if (++cnt == pcap) {
+#pragma unroll
+                        for (int j = 0; j < kOutPerWave; ++j) acc[j] = acc3{0, 0, reduce128(acc3_value(acc[j]), P)};
+                        cnt = 0;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kOutPerWave; ++j) {
+        if (j >= my_out) continue;
+        const int ol = ol0 + j, o = o_base + ol;
+        uint64_t y = reduce128(acc3_value(acc[j]), P);
+        if (poly == 0 && bias) y = add_mod(y, bias[(size_t(o) * nl + limb) * N + col0 + lane], P.q);
+        outs.p[ol][(size_t(poly) * nl + limb) * N + col0 + lane] = y;
+    }
+}
+
 int check_inputs(const ckc_ct *in, int n, int level, const char *what) {
     for (int i = 0; i < n; ++i) {
         CKC_REQUIRE(in[i].d, CKC_EINVAL, std::string(what) + ": null input");
@@ -309,6 +390,16 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
             }
             og_off.push_back(int32_t(g_c.size()));
         }
+    // byte indices for the direct form, [tap][input][output padded to 32]
+    if (n_centroids <= kMaxCentLds) {
+        L->Opad = (out_ch + kOutPerWg - 1) / kOutPerWg * kOutPerWg;
+        std::vector<uint8_t> ix(size_t(L->ntap) * in_ch * L->Opad, 0);
+        for (int o = 0; o < out_ch; ++o)
+            for (int i = 0; i < in_ch; ++i)
+                for (int t = 0; t < L->ntap; ++t)
+                    ix[(size_t(t) * in_ch + i) * L->Opad + o] = uint8_t(idx[(size_t(o) * in_ch + i) * L->ntap + t]);
+        CKC_TRY(L->idx8.upload(ix.data(), ix.size()));
+    }
     if (g_c.empty()) g_c.push_back(0);
     if (m_i.empty()) m_i.push_back(0);
     CKC_TRY(L->og_off.upload(og_off.data(), 4 * og_off.size()));
@@ -507,11 +598,21 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                 Ptrs op;
                 for (int j = 0; j < oc; ++j) op.p[j] = out[size_t(img0 + ii) * L->O + o0 + j].d;
                 const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
-                CKC_PROF(PK_CONV_CONTRACT, s, 8.0 * N * nl * 2 * (double(I) * ntap + oc), 0.0);
-                hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups), dim3(256),
-                                   lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent, (const int32_t *)L->og_off.p,
-                                   (const int32_t *)L->g_c.p, (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p,
-                                   L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, c->dprimes(), c->logN);
+                CKC_PROF(PK_CONV_CONTRACT, s, 8.0 * N * nl * (2.0 * I * ntap + 2.0 * oc + double(ntap) * L->kcent),
+                         2.0 * N * nl * double(oc) * I * ntap);
+                if (L->idx8.p) {
+                    const size_t lds_mac = size_t(L->kcent + std::min(I, kIChunk)) * kTile * 8;
+                    hipLaunchKernelGGL(k_conv_mac, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups), dim3(256),
+                                       lds_mac, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent,
+                                       (const uint8_t *)L->idx8.p, L->Opad, L->has_bias ? L->bias.u64() : nullptr, op,
+                                       o0, oc, c->dprimes(), c->logN);
+                } else {
+                    hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups),
+                                       dim3(256), lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent,
+                                       (const int32_t *)L->og_off.p, (const int32_t *)L->g_c.p,
+                                       (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p,
+                                       L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, c->dprimes(), c->logN);
+                }
                 CKC_HIP(hipGetLastError());
             }
         }
@@ -605,25 +706,24 @@ __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ 
     const int limb = blockIdx.y, kk = blockIdx.z >> 1, poly = blockIdx.z & 1;
     const size_t N = size_t(1) << logN, pw = size_t(nl) * N;
     const Prime P = primes[limb];
-    const int prod_cap = P.k >= 61 ? (1 << (128 - 2 * P.k)) - 1 : 64;
+    const int pcap = prod_cap(P.k);
     for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        u128v acc[kDenseImg];
-        for (int i = 0; i < kDenseImg; ++i) acc[i] = u128v{0, 0};
+        acc3 acc[kDenseImg];
+        for (int i = 0; i < kDenseImg; ++i) acc[i] = acc3{0, 0, 0};
         int cnt = 0;
         for (int ch = 0; ch < C; ++ch) {
             const uint64_t pv = pts[(size_t(kk) * C + ch) * pw + size_t(limb) * N + k];
 #pragma unroll
             for (int i = 0; i < kDenseImg; ++i)
-                if (i < nimg)
-                    acc[i] = add128(acc[i], mul64x64(Sb[((size_t(i) * C + ch) * 2 + poly) * pw + size_t(limb) * N + k], pv));
-            if (++cnt == prod_cap) {
+                if (i < nimg) mac3(acc[i], Sb[((size_t(i) * C + ch) * 2 + poly) * pw + size_t(limb) * N + k], pv);
+            if (++cnt == pcap) {
 #pragma unroll
-                for (int i = 0; i < kDenseImg; ++i) acc[i] = u128v{reduce128(acc[i], P), 0};
+                for (int i = 0; i < kDenseImg; ++i) acc[i] = acc3{0, 0, reduce128(acc3_value(acc[i]), P)};
                 cnt = 0;
             }
         }
         for (int i = 0; i < nimg; ++i) {
-            uint64_t y = reduce128(acc[i], P);
+            uint64_t y = reduce128(acc3_value(acc[i]), P);
             if (poly == 0 && bias) y = add_mod(y, bias[size_t(kk) * pw + size_t(limb) * N + k], P.q);
             Z[((size_t(i) * K + kk) * 2 + poly) * pw + size_t(limb) * N + k] = y;
         }
