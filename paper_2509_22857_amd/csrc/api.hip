@@ -7,7 +7,7 @@
 #include <algorithm>
 #include <set>
 
-#include "ckc_internal.h"
+#include "batch.h"
 
 static thread_local std::string g_err;
 void ckc_set_error(const std::string &msg) { g_err = msg; }
@@ -27,6 +27,7 @@ int decrypt_impl(ckc_ctx *c, const ckc_sk *sk, const uint64_t *ct, int level, in
                  hipStream_t s);
 int permute_limbs(const ckc_ctx *c, const uint64_t *src, uint64_t *dst, int nlimbs, const uint32_t *perm,
                   hipStream_t s);
+uint64_t galois_inverse(const ckc_ctx *c, uint64_t g);
 
 namespace {
 
@@ -335,9 +336,17 @@ static int add_galois(ckc_ctx *c, const ckc_sk *sk, ckc_evk *evk, const int32_t 
         CKC_TRY(sp.alloc(8 * N * np, s));
         // sigma_g(s) in the NTT domain: a gather through the permutation, every prime
         CKC_TRY(permute_limbs(c, sk->s_ntt.u64(), sp.u64(), np, perm, s));
+        // generate, then store permuted by sigma_g^-1 (the key inner product
+        // reads digits in order and scatters its outputs through pi_g^-1)
+        DevBuf raw;
+        CKC_TRY(raw.alloc(8 * evk->key_words, s));
+        CKC_TRY(switch_key_impl(c, sk, g, sp.u64(), raw.u64(), s));
+        const uint32_t *iperm = (const uint32_t *)galois_table(c, galois_inverse(c, g), &rc);
+        if (!iperm) return rc;
         auto key = std::make_unique<DevMem>();
         CKC_TRY(key->alloc(8 * evk->key_words));
-        CKC_TRY(switch_key_impl(c, sk, g, sp.u64(), key->u64(), s));
+        CKC_TRY(permute_limbs(c, raw.u64(), key->u64(), int(evk->key_words / N), iperm, s));
+        CKC_HIP(hipStreamSynchronize(s));
         evk->galois[g] = std::move(key);
     }
     return CKC_OK;
@@ -524,8 +533,13 @@ extern "C" int ckc_relin(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, ckc_c
     DevBuf digits;
     CKC_TRY(digits.alloc(8 * N * nt * size_t(c->dnum_at(in->level)), s));
     const size_t ps = size_t(nl) * N;
-    CKC_TRY(ks_modup(c, in->d + 2 * ps, in->level, digits.u64(), s));
-    CKC_TRY(ks_apply(c, digits.u64(), in->level, evk->relin->u64(), 1, in->d, in->d + ps, out->d, out->d + ps, s));
+    CKC_TRY(ks_modup_b(c, in->d + 2 * ps, 0, 1, in->level, digits.u64(), s));
+    Ptrs a0{}, a1{}, o0{}, o1{};
+    a0.p[0] = in->d;
+    a1.p[0] = in->d + ps;
+    o0.p[0] = out->d;
+    o1.p[0] = out->d + ps;
+    CKC_TRY(ks_apply_b(c, digits.u64(), 1, in->level, evk->relin->u64(), 1, &a0, &a1, false, o0, o1, s));
     out->level = in->level;
     out->npoly = 2;
     out->scale = in->scale;
@@ -553,15 +567,18 @@ extern "C" int ckc_rotate(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, cons
     DevBuf digits;
     if (need_ks) {
         CKC_TRY(digits.alloc(8 * N * nt * size_t(c->dnum_at(in->level)), s));
-        CKC_TRY(ks_modup(c, in->d + ps, in->level, digits.u64(), s));
+        CKC_TRY(ks_modup_b(c, in->d + ps, 0, 1, in->level, digits.u64(), s));
     }
     for (int i = 0; i < n_steps; ++i) {
         const uint64_t g = galois_element(c, steps[i]);
         if (g == 1) {
             CKC_TRY(copy_limbs(in->d, 0, out[i].d, 0, 2 * ps, 1, s));
         } else {
-            const uint64_t *key = evk->galois.at(g)->u64();
-            CKC_TRY(ks_apply_perm_add(c, digits.u64(), in->level, key, g, in->d, out[i].d, out[i].d + ps, s));
+            Ptrs a0{}, o0{}, o1{};
+            a0.p[0] = in->d;
+            o0.p[0] = out[i].d;
+            o1.p[0] = out[i].d + ps;
+            CKC_TRY(ks_apply_b(c, digits.u64(), 1, in->level, evk->galois.at(g)->u64(), g, &a0, nullptr, true, o0, o1, s));
         }
         out[i].level = in->level;
         out[i].npoly = 2;

@@ -11,6 +11,7 @@
 
 const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc);
 const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc);
+uint64_t galois_inverse(const ckc_ctx *c, uint64_t g);
 
 namespace {
 
@@ -51,11 +52,16 @@ __global__ __launch_bounds__(256) void k_bconv_b(const uint64_t *__restrict__ sr
 
 constexpr int kMaxDnum = 16;
 
-// key inner product with key reuse across the batch
-// acc[b][p][tt][k] = sum_j digits[b][j][tt][perm(k)] * key[j][p][prime(tt)][k]
+// key inner product with key reuse across the batch.  A Galois key is stored
+// permuted by sigma_g^-1 (key'[m] = key[pi_g^-1(m)]), and since sigma_g acts on
+// NTT-form values as a permutation commuting with pointwise products,
+//   sum_j sigma_g(D_j) * key_j = sigma_g(sum_j D_j * key'_j):
+// the digits are read in order and only the two outputs are scattered,
+//   acc[b][p][tt][scat(m)] = sum_j digits[b][j][tt][m] * key'[j][p][prime(tt)][m]
+// with scat = pi_g^-1 (none for relinearisation).
 __global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digits, int nb, int dnum, int nt,
                                                const uint64_t *__restrict__ key, int nprimes, LimbMap map,
-                                               const uint32_t *__restrict__ perm, uint64_t *__restrict__ acc,
+                                               const uint32_t *__restrict__ scat, uint64_t *__restrict__ acc,
                                                const Prime *__restrict__ primes, int logN) {
     const int tt = blockIdx.y;
     const size_t N = size_t(1) << logN;
@@ -71,9 +77,9 @@ __global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digi
                 ka[j] = key[((size_t(j) * 2 + 1) * nprimes + pi) * N + k];
             }
         }
-        const size_t src = perm ? perm[k] : k;
+        const size_t dst = scat ? scat[k] : k;
         for (int b = 0; b < nb; ++b) {
-            const uint64_t *dg = digits + b * dig_bs + size_t(tt) * N + src;
+            const uint64_t *dg = digits + b * dig_bs + size_t(tt) * N + k;
             acc3 a0{0, 0, 0}, a1{0, 0, 0};
 #pragma unroll
             for (int j = 0; j < kMaxDnum; ++j) {
@@ -84,8 +90,8 @@ __global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digi
                 }
             }
             uint64_t *ab = acc + b * acc_bs;
-            ab[size_t(tt) * N + k] = reduce128(acc3_value(a0), P);
-            ab[(size_t(nt) + tt) * N + k] = reduce128(acc3_value(a1), P);
+            ab[size_t(tt) * N + dst] = reduce128(acc3_value(a0), P);
+            ab[(size_t(nt) + tt) * N + dst] = reduce128(acc3_value(a1), P);
         }
     }
 }
@@ -214,11 +220,13 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
                hipStream_t s) {
     const size_t N = c->N;
     const int nl = level + 1, np = c->np, nt = nl + np, dnum = c->dnum_at(level);
-    const uint32_t *perm = nullptr;
+    const uint32_t *perm = nullptr, *scat = nullptr;
     if (g != 1) {
         int rc;
         perm = (const uint32_t *)galois_table(c, g, &rc);
         if (!perm) return rc;
+        scat = (const uint32_t *)galois_table(c, galois_inverse(c, g), &rc);
+        if (!scat) return rc;
     }
     DevBuf acc, pl, conv;
     CKC_TRY(acc.alloc(8 * N * nt * 2 * nb, s));
@@ -230,7 +238,7 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
         const double bytes = 8.0 * N * nt * (double(nb) * dnum + 2.0 * dnum + 2.0 * nb);
         CKC_PROF(PK_KIP, s, bytes, 2.0 * N * nt * dnum * nb);
     hipLaunchKernelGGL(k_kip_b, dim3(tiles(N), unsigned(nt)), dim3(256), 0, s, digits, nb, dnum, nt, key,
-                       c->nprimes(), ext, perm, acc.u64(), c->dprimes(), c->logN);
+                       c->nprimes(), ext, scat, acc.u64(), c->dprimes(), c->logN);
     }
     CKC_HIP(hipGetLastError());
     // P limbs of every accumulator (2 nb of them) -> coefficient form -> convert to Q -> NTT

@@ -117,7 +117,7 @@ struct ckc_ctx {
     DevMem primes_d;                // Prime[nprimes]
     DevMem tw, twp, itw, itwp;      // [nprimes][N] bit-reversed psi powers (+Shoup)
     DevMem ninv;                    // [nprimes][2] N^-1 and its Shoup companion
-    // encoding FFT tables (host-computed with libm, uploaded)
+    // encoding FFT tables (host-computed from a fixed series, uploaded)
     DevMem fft_w;                   // [n/2] double2 (cos, sin) of 2 pi e / n
     DevMem twist;                   // [n]   double2 (cos, sin) of pi k / N
     DevMem slot_idx;                // [n]   uint32  t_j = (5^j mod 2N - 1)/4
@@ -166,16 +166,6 @@ int ew_binary(const ckc_ctx *c, EwOp op, uint64_t *out, const uint64_t *a, const
 const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc);
 const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc);
 uint64_t galois_element(const ckc_ctx *c, int64_t step);
-
-// Key switching pieces.
-// ModUp of d (NTT form, level+1 limbs) into digits [dnum_l][level+1+np][N] (NTT form).
-int ks_modup(ckc_ctx *c, const uint64_t *d, int level, uint64_t *digits, hipStream_t s);
-// Key inner product + ModDown: u_b = ModDown(sum_j sigma_g(digit_j) * key_j[b]),
-// then out0 = u_0 + add0, out1 = u_1 + add1 (add may be null).  NTT form.
-int ks_apply(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g,
-             const uint64_t *add0, const uint64_t *add1, uint64_t *out0, uint64_t *out1, hipStream_t s);
-int ks_apply_perm_add(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g,
-                      const uint64_t *c0_for_perm, uint64_t *out0, uint64_t *out1, hipStream_t s);
 
 int rescale_impl(ckc_ctx *c, const uint64_t *in, int npoly, int level, uint64_t *out, hipStream_t s);
 

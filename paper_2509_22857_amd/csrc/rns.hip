@@ -1,13 +1,7 @@
-// RNS kernels: limb-wise arithmetic, fast basis conversion, hybrid key
-// switching (ModUp, key inner product, ModDown) and rescale.
-//
-// Hybrid key switching (the special modulus P of Section 2.2): a polynomial d
-// at level l is split into digits of alpha primes; ModUp extends each digit to
-// every other prime of Q_l and P by fast basis conversion (no correction);
-// the key inner product sums digit x key over the digits; ModDown divides by
-// P with the floor-type conversion back from P.  For a rotation the Galois
-// automorphism acts on the ModUp output (in the NTT domain it is a
-// permutation of evaluation points), so one ModUp serves every step.
+// RNS kernels shared by the C-ABI entry points: limb-wise arithmetic,
+// permutations, tensor products, constants, the ModUp conversion tables and
+// Galois tables, and rescale of a single ciphertext.  Key switching lives in
+// batch.hip.
 #include <math.h>
 
 #include <algorithm>
@@ -40,83 +34,6 @@ __global__ __launch_bounds__(kEwThreads) void k_ew(int op, uint64_t *__restrict_
             default: r = x; break;
         }
         ol[k] = r;
-    }
-}
-
-// Fast basis conversion: src limbs (coefficient form, consecutive, primes
-// given by src_map starting at src_first) -> target limb tt of dst.
-//   y_i = [x_i * inv_i]_{s_i};  out_t = sum_i y_i * hat[t][i]  (mod t)
-// Targets in [skip_lo, skip_hi) are left untouched.
-__global__ __launch_bounds__(256) void k_bconv(const uint64_t *__restrict__ src, int ns, int src_first,
-                                               LimbMap src_map, uint64_t *__restrict__ dst, LimbMap dst_map,
-                                               int skip_lo, int skip_hi, const uint64_t *__restrict__ inv,
-                                               const uint64_t *__restrict__ invp,
-                                               const uint64_t *__restrict__ hat,
-                                               const Prime *__restrict__ primes, int logN) {
-    const int tt = blockIdx.y;
-    if (tt >= skip_lo && tt < skip_hi) return;
-    const size_t N = size_t(1) << logN;
-    const Prime T = primes[dst_map.prime(tt)];
-    const uint64_t *h = hat + size_t(tt) * ns;
-    uint64_t *o = dst + size_t(tt) * N;
-    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        u128v acc{0, 0};
-        for (int i = 0; i < ns; ++i) {
-            const uint64_t si = primes[src_map.prime(src_first + i)].q;
-            const uint64_t y = mul_shoup(src[size_t(i) * N + k], inv[i], invp[i], si);
-            acc = add128(acc, mul64x64(y, h[i]));
-        }
-        o[k] = reduce128(acc, T);
-    }
-}
-
-// Key inner product over the extended basis of level l (nt = l+1+np limbs):
-//   acc_b[tt][k] = sum_j digit_j[tt][perm(k)] * key_j[b][prime(tt)][k]
-__global__ __launch_bounds__(256) void k_kip(const uint64_t *__restrict__ digits, int dnum, int nt,
-                                             const uint64_t *__restrict__ key, int nprimes, LimbMap map,
-                                             const uint32_t *__restrict__ perm, uint64_t *__restrict__ acc,
-                                             const Prime *__restrict__ primes, int logN) {
-    const int tt = blockIdx.y;
-    const size_t N = size_t(1) << logN;
-    const int pi = map.prime(tt);
-    const Prime P = primes[pi];
-    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        const size_t src = perm ? perm[k] : k;
-        u128v a0{0, 0}, a1{0, 0};
-        for (int j = 0; j < dnum; ++j) {
-            const uint64_t d = digits[(size_t(j) * nt + tt) * N + src];
-            const uint64_t kb = key[((size_t(j) * 2 + 0) * nprimes + pi) * N + k];
-            const uint64_t ka = key[((size_t(j) * 2 + 1) * nprimes + pi) * N + k];
-            a0 = add128(a0, mul64x64(d, kb));
-            a1 = add128(a1, mul64x64(d, ka));
-        }
-        acc[size_t(tt) * N + k] = reduce128(a0, P);
-        acc[(size_t(nt) + tt) * N + k] = reduce128(a1, P);
-    }
-}
-
-// ModDown combine: out_b[i] = (acc_b[i] - conv_b[i]) * P^-1 + add_b[perm(k)] (NTT form)
-__global__ __launch_bounds__(256) void k_moddown_combine(const uint64_t *__restrict__ acc, int nt,
-                                                         const uint64_t *__restrict__ conv, int nl,
-                                                         const uint64_t *__restrict__ pinv,
-                                                         const uint64_t *__restrict__ add0,
-                                                         const uint64_t *__restrict__ add1,
-                                                         const uint32_t *__restrict__ add_perm,
-                                                         uint64_t *__restrict__ out0, uint64_t *__restrict__ out1,
-                                                         const Prime *__restrict__ primes, int logN) {
-    const int i = blockIdx.y, b = blockIdx.z;
-    const size_t N = size_t(1) << logN;
-    const uint64_t q = primes[i].q;
-    const uint64_t pv = pinv[2 * i], pvp = pinv[2 * i + 1];
-    const uint64_t *x = acc + (size_t(b) * nt + i) * N;
-    const uint64_t *cv = conv + (size_t(b) * nl + i) * N;
-    const uint64_t *ad = b == 0 ? add0 : add1;
-    uint64_t *o = (b == 0 ? out0 : out1) + size_t(i) * N;
-    if (ad) ad += size_t(i) * N;
-    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        uint64_t r = mul_shoup(sub_mod(x[k], cv[k], q), pv, pvp, q);
-        if (ad) r = add_mod(r, ad[add_perm ? add_perm[k] : k], q);
-        o[k] = r;
     }
 }
 
@@ -286,6 +203,18 @@ uint64_t galois_element(const ckc_ctx *c, int64_t step) {
     return g;
 }
 
+// g^-1 mod 2N: the odd residues mod 2N form a group of order N, so g^(N-1)
+uint64_t galois_inverse(const ckc_ctx *c, uint64_t g) {
+    const uint64_t M = 2 * c->N;
+    uint64_t r = 1, b = g % M, e = c->N - 1;
+    while (e) {
+        if (e & 1) r = (r * b) % M;
+        b = (b * b) % M;
+        e >>= 1;
+    }
+    return r;
+}
+
 // NTT-domain permutation of sigma_g: index k holds a(psi^(2 brev(k) + 1)),
 // so sigma_g(a) at k is a at the index whose exponent is g (2 brev(k) + 1).
 const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc) {
@@ -311,83 +240,6 @@ const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc) {
     c->galois_perm[g] = std::move(m);
     *rc = CKC_OK;
     return r;
-}
-
-int ks_modup(ckc_ctx *c, const uint64_t *d, int level, uint64_t *digits, hipStream_t s) {
-    const size_t N = c->N;
-    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
-    DevBuf coeff;
-    CKC_TRY(coeff.alloc(8 * N * nl, s));
-    CKC_TRY(copy_limbs(d, 0, coeff.u64(), 0, N * nl, 1, s));
-    CKC_TRY(ntt_inverse(c, coeff.u64(), nl, qmap(), 1, 0, s));
-    const LimbMap ext{nl, c->nq};
-    for (int j = 0; j < dnum; ++j) {
-        int rc;
-        const BconvTable *t = modup_table(c, level, j, &rc);
-        if (!t) return rc;
-        const int lo = j * c->alpha, ns = t->ns;
-        uint64_t *dj = digits + size_t(j) * nt * N;
-        hipLaunchKernelGGL(k_bconv, dim3(tiles_for(N), unsigned(nt)), dim3(256), 0, s, coeff.u64() + size_t(lo) * N,
-                           ns, lo, qmap(), dj, ext, lo, lo + ns, t->inv.u64(), t->invp.u64(), t->hat.u64(),
-                           c->dprimes(), c->logN);
-        CKC_HIP(hipGetLastError());
-        CKC_TRY(ntt_forward(c, dj, nt, ext, 1, 0, s, lo, lo + ns));
-        // the digit's own limbs: the input limbs, already in NTT form
-        CKC_TRY(copy_limbs(d + size_t(lo) * N, 0, dj + size_t(lo) * N, 0, N * ns, 1, s));
-    }
-    return CKC_OK;
-}
-
-// Shared tail of key switching: KIP over digits, ModDown, combine.
-static int ks_core(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g,
-                   const uint64_t *add0, const uint64_t *add1, const uint32_t *add_perm, uint64_t *out0,
-                   uint64_t *out1, hipStream_t s) {
-    const size_t N = c->N;
-    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
-    const uint32_t *perm = nullptr;
-    if (g != 1) {
-        int rc;
-        perm = (const uint32_t *)galois_table(c, g, &rc);
-        if (!perm) return rc;
-    }
-    DevBuf acc, conv;
-    CKC_TRY(acc.alloc(8 * N * nt * 2, s));
-    CKC_TRY(conv.alloc(8 * N * nl * 2, s));
-    const LimbMap ext{nl, c->nq};
-    hipLaunchKernelGGL(k_kip, dim3(tiles_for(N), unsigned(nt)), dim3(256), 0, s, digits, dnum, nt, key,
-                       c->nprimes(), ext, perm, acc.u64(), c->dprimes(), c->logN);
-    CKC_HIP(hipGetLastError());
-    // ModDown: P limbs of both accumulators -> coefficient form -> convert to Q -> NTT
-    DevBuf pl;
-    CKC_TRY(pl.alloc(8 * N * c->np * 2, s));
-    CKC_TRY(copy_limbs(acc.u64() + size_t(nl) * N, size_t(nt) * N, pl.u64(), size_t(c->np) * N, N * c->np, 2, s));
-    const LimbMap pmap{0, c->nq};
-    CKC_TRY(ntt_inverse(c, pl.u64(), c->np, pmap, 2, size_t(c->np) * N, s));
-    for (int b = 0; b < 2; ++b) {
-        hipLaunchKernelGGL(k_bconv, dim3(tiles_for(N), unsigned(nl)), dim3(256), 0, s,
-                           pl.u64() + size_t(b) * c->np * N, c->np, 0, pmap, conv.u64() + size_t(b) * nl * N,
-                           qmap(), -1, -1, c->p_to_q.inv.u64(), c->p_to_q.invp.u64(), c->p_to_q.hat.u64(),
-                           c->dprimes(), c->logN);
-        CKC_HIP(hipGetLastError());
-    }
-    CKC_TRY(ntt_forward(c, conv.u64(), nl, qmap(), 2, size_t(nl) * N, s));
-    hipLaunchKernelGGL(k_moddown_combine, dim3(tiles_for(N), unsigned(nl), 2), dim3(256), 0, s, acc.u64(), nt,
-                       conv.u64(), nl, c->pinv.u64(), add0, add1, add_perm, out0, out1, c->dprimes(), c->logN);
-    CKC_HIP(hipGetLastError());
-    return CKC_OK;
-}
-
-int ks_apply(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g, const uint64_t *add0,
-             const uint64_t *add1, uint64_t *out0, uint64_t *out1, hipStream_t s) {
-    return ks_core(c, digits, level, key, g, add0, add1, nullptr, out0, out1, s);
-}
-
-int ks_apply_perm_add(ckc_ctx *c, const uint64_t *digits, int level, const uint64_t *key, uint64_t g,
-                      const uint64_t *c0_for_perm, uint64_t *out0, uint64_t *out1, hipStream_t s) {
-    int rc;
-    const uint32_t *perm = (const uint32_t *)galois_table(c, g, &rc);
-    if (!perm) return rc;
-    return ks_core(c, digits, level, key, g, c0_for_perm, nullptr, perm, out0, out1, s);
 }
 
 int rescale_impl(ckc_ctx *c, const uint64_t *in, int npoly, int level, uint64_t *out, hipStream_t s) {
