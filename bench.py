@@ -77,7 +77,7 @@ def main():
         sys.exit(2)
     if args.workload == "micro":
         from paper_2509_22857_amd import microbench
-        print(json.dumps(microbench.run(args)))
+        print(json.dumps(microbench.run(batch=args.batch, reps=max(args.steps, 1), log=log)))
         return
 
     import torch

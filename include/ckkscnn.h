@@ -170,6 +170,31 @@ int ckc_mod_drop(ckc_ctx *ctx, const ckc_ct *in, int to_level, ckc_ct *out, void
  * out may alias a or b). */
 int ckc_rescale_many(ckc_ctx *ctx, const ckc_ct *in, int n, ckc_ct *out, void *stream);
 int ckc_add_many(ckc_ctx *ctx, const ckc_ct *a, const ckc_ct *b, int n, ckc_ct *out, void *stream);
+/* Hoisted rotations of a batch (Section 2.2 rotation; the hoisting shares one
+ * ModUp of c1 per input across every step):
+ * out[i * n_steps + j] = left rotation of in[i] by steps[j] (0 = copy).
+ * Inputs: 2-polynomial ciphertexts at one level with equal scales.  Every
+ * Galois key is read once per 64 inputs.  out must not alias any input.
+ * Errors: CKC_EINVAL, CKC_ELEVEL, CKC_ESHAPE, CKC_ESCALE, CKC_ENOKEY,
+ * CKC_ENOMEM, CKC_EDEVICE. */
+int ckc_rotate_many(ckc_ctx *ctx, const ckc_evk *evk, const ckc_ct *in, int n, const int32_t *steps, int n_steps,
+                    ckc_ct *out, void *stream);
+/* Ciphertext multiplication with relinearisation (Section 2.2; with a == b
+ * the squaring of the quadratic activation, Section 2.3):
+ * out[i] = Relin(a[i] (x) b[i]), scale a.scale * b.scale, level unchanged.
+ * a and b: 2-polynomial ciphertexts at one level (scales may differ
+ * between pairs); out[i] may alias a[i] or b[i].  CKC_ENOKEY without a
+ * relinearisation key. */
+int ckc_mul_relin_many(ckc_ctx *ctx, const ckc_evk *evk, const ckc_ct *a, const ckc_ct *b, int n, ckc_ct *out,
+                       void *stream);
+/* Plaintext multiply-accumulate (the ct x pt MAC of packed convolution and
+ * dense layers, Section 5.1):
+ * out[o] = sum_{t < n_terms} in[o * n_terms + t] * pt[t],  o < n_out,
+ * 1 <= n_terms <= 64; inputs 2-polynomial at one level with equal scales,
+ * plaintexts at that level or above (extra limbs ignored) with equal scales;
+ * result scale = in.scale * pt.scale.  out must not alias any input. */
+int ckc_mac_plain_many(ckc_ctx *ctx, const ckc_ct *in, const ckc_pt *pt, int n_terms, int n_out, ckc_ct *out,
+                       void *stream);
 
 /* ------------------------------------------------------------------ layers
  * HW layout (Section 5.1, Data Layout): every channel is its own

@@ -80,6 +80,11 @@ _SIGS = [
     ("ckc_mod_drop", C.c_int, [_vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
     ("ckc_rescale_many", C.c_int, [_vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
     ("ckc_add_many", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_rotate_many", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), C.c_int, _i32p, C.c_int, C.POINTER(ckc_ct), _vp]),
+    ("ckc_mul_relin_many", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct),
+                                     _vp]),
+    ("ckc_mac_plain_many", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_pt), C.c_int, C.c_int,
+                                     C.POINTER(ckc_ct), _vp]),
     ("ckc_layer_create_conv", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                         _dblp, C.POINTER(C.c_uint16), _dblp, C.c_int, C.c_double, C.c_double,
                                         C.POINTER(_vp), _vp]),
@@ -512,6 +517,42 @@ def add_many(ctx, a, b, outs, stream=None):
     return outs
 
 
+def rotate_many(ctx, keys, ins, steps, outs=None, stream=None):
+    """outs[i * len(steps) + j] = Rot_{steps[j]}(ins[i]) (hoisted, batched)."""
+    steps = list(steps)
+    if outs is None:
+        outs = [ctx.new_ct(c.level, 2, c.scale) for c in ins for _ in steps]
+    ia, oa = _ct_array(ins), _ct_array(outs)
+    st = (C.c_int32 * max(len(steps), 1))(*steps)
+    _check("ckc_rotate_many", lib().ckc_rotate_many(ctx.h, keys.evk, ia, len(ins), st, len(steps), oa,
+                                                    _stream(stream)))
+    _update_all(outs, oa)
+    return outs
+
+
+def mul_relin_many(ctx, keys, a, b, outs=None, stream=None):
+    """outs[i] = Relin(a[i] * b[i])."""
+    if outs is None:
+        outs = [ctx.new_ct(x.level, 2, x.scale) for x in a]
+    aa, ba, oa = _ct_array(a), _ct_array(b), _ct_array(outs)
+    _check("ckc_mul_relin_many", lib().ckc_mul_relin_many(ctx.h, keys.evk, aa, ba, len(a), oa, _stream(stream)))
+    _update_all(outs, oa)
+    return outs
+
+
+def mac_plain_many(ctx, ins, pts, outs=None, stream=None):
+    """outs[o] = sum_t ins[o * len(pts) + t] * pts[t]."""
+    T = len(pts)
+    n_out = len(ins) // T
+    if outs is None:
+        outs = [ctx.new_ct(ins[0].level, 2, ins[0].scale) for _ in range(n_out)]
+    ia, oa = _ct_array(ins), _ct_array(outs)
+    pa = (ckc_pt * T)(*[p.c() for p in pts])
+    _check("ckc_mac_plain_many", lib().ckc_mac_plain_many(ctx.h, ia, pa, T, n_out, oa, _stream(stream)))
+    _update_all(outs, oa)
+    return outs
+
+
 def prof_enable(on: bool = True):
     _check("ckc_prof_enable", lib().ckc_prof_enable(int(on)))
 
@@ -523,4 +564,5 @@ def prof_query(name: str) -> dict:
     return {"launches": int(n.value), "ms": ms.value, "bytes": by.value, "work": wk.value}
 
 
-PROF_KERNELS = ("ntt_fwd", "ntt_inv", "bconv", "kip", "moddown", "conv_contract", "act_tensor", "dense_mac", "ew")
+PROF_KERNELS = ("ntt_fwd", "ntt_inv", "bconv", "kip", "moddown", "conv_contract", "act_tensor", "rescale",
+                "dense_mac", "ew", "mac_plain", "tensor")

@@ -35,3 +35,10 @@ int rescale_b(ckc_ctx *c, const Ptrs &in, const Ptrs &out, int nb, int npoly, in
 // Batched limb-wise op over whole ciphertexts: out.p[b] = a.p[b] op b.p[b] (npoly polys, nl limbs)
 int ew_b(ckc_ctx *c, EwOp op, const Ptrs &out, const Ptrs &a, const Ptrs *b, int nb, int npoly, int nl,
          hipStream_t s);
+
+// Hoisted rotations of nb 2-polynomial ciphertexts in.p[b] (NTT form, `level`):
+// one ModUp per input shared by every step, then one batched key inner
+// product + ModDown per nonzero step (the Galois key is read once for the
+// batch).  dst[i].p[b] receives Rot_{steps[i]}(in.p[b]); step 0 is a copy.
+int hoisted_group(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int level, const std::vector<int32_t> &steps,
+                  const std::vector<Ptrs> &dst, hipStream_t s);

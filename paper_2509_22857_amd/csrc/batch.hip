@@ -25,6 +25,14 @@ __global__ void k_gather(Ptrs src, size_t src_off, uint64_t *__restrict__ dst, s
         d[k] = s[k];
 }
 
+__global__ void k_copy_pp(Ptrs src, Ptrs dst, size_t words) {
+    const int b = blockIdx.y;
+    const uint64_t *sp = src.p[b];
+    uint64_t *d = dst.p[b];
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += size_t(gridDim.x) * blockDim.x)
+        d[k] = sp[k];
+}
+
 // batched fast basis conversion (coefficient form), grid (tiles, targets, batch)
 __global__ __launch_bounds__(256) void k_bconv_b(const uint64_t *__restrict__ src, size_t src_bs, int ns,
                                                  int src_first, LimbMap src_map, uint64_t *__restrict__ dst,
@@ -57,47 +65,81 @@ constexpr int kMaxDnum = 16;
 // NTT-form values as a permutation commuting with pointwise products,
 //   sum_j sigma_g(D_j) * key_j = sigma_g(sum_j D_j * key'_j):
 // the digits are read in order and only the two outputs are scattered,
-//   acc[b][p][tt][scat(m)] = sum_j digits[b][j][tt][m] * key'[j][p][prime(tt)][m]
-// with scat = pi_g^-1 (none for relinearisation).
-__global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digits, int nb, int dnum, int nt,
-                                               const uint64_t *__restrict__ key, int nprimes, LimbMap map,
-                                               const uint32_t *__restrict__ scat, uint64_t *__restrict__ acc,
-                                               const Prime *__restrict__ primes, int logN) {
+//   u[b][p][tt][scat(m)] = sum_j digits[b][j][tt][m] * key'[j][p][prime(tt)][m]
+// with scat = pi_g^-1 (none for relinearisation).  Q limbs (tt < nl) go to
+// accq [b][2][nl][N], P limbs to accp [b][2][np][N].  One thread per
+// coefficient keeps its 2 DNUM key words in registers for the whole batch;
+// the digit loads of one ciphertext are issued together (DNUM is a template
+// parameter, so the loop is straight-line code).
+template <int DNUM>
+__global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digits, int nb, int dnum_rt, int nt,
+                                               int nl, const uint64_t *__restrict__ key, int nprimes, LimbMap map,
+                                               const uint32_t *__restrict__ scat, uint64_t *__restrict__ accq,
+                                               uint64_t *__restrict__ accp, const Prime *__restrict__ primes,
+                                               int logN) {
     const int tt = blockIdx.y;
     const size_t N = size_t(1) << logN;
+    const int dnum = DNUM > 0 ? DNUM : dnum_rt;
     const int pi = map.prime(tt);
     const Prime P = primes[pi];
-    const size_t dig_bs = size_t(dnum) * nt * N, acc_bs = size_t(2) * nt * N;
+    const int np = nt - nl;
+    const size_t dig_bs = size_t(dnum) * nt * N;
+    const bool lowq = tt < nl;
+    uint64_t *obase = lowq ? accq + size_t(tt) * N : accp + size_t(tt - nl) * N;
+    const size_t o_bs = lowq ? size_t(2) * nl * N : size_t(2) * np * N;
+    const size_t o_ps = lowq ? size_t(nl) * N : size_t(np) * N;
+    constexpr int KD = DNUM > 0 ? DNUM : kMaxDnum;
     for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        uint64_t kb[kMaxDnum], ka[kMaxDnum];
+        uint64_t kb[KD], ka[KD];
 #pragma unroll
-        for (int j = 0; j < kMaxDnum; ++j) {
-            if (j < dnum) {
+        for (int j = 0; j < KD; ++j) {
+            if (DNUM > 0 || j < dnum) {
                 kb[j] = key[((size_t(j) * 2 + 0) * nprimes + pi) * N + k];
                 ka[j] = key[((size_t(j) * 2 + 1) * nprimes + pi) * N + k];
             }
         }
         const size_t dst = scat ? scat[k] : k;
+        const uint64_t *dg = digits + size_t(tt) * N + k;
+        uint64_t *ob = obase + dst;
         for (int b = 0; b < nb; ++b) {
-            const uint64_t *dg = digits + b * dig_bs + size_t(tt) * N + k;
+            uint64_t d[KD];
+#pragma unroll
+            for (int j = 0; j < KD; ++j)
+                if (DNUM > 0 || j < dnum) d[j] = dg[size_t(j) * nt * N];
             acc3 a0{0, 0, 0}, a1{0, 0, 0};
 #pragma unroll
-            for (int j = 0; j < kMaxDnum; ++j) {
-                if (j < dnum) {
-                    const uint64_t d = dg[size_t(j) * nt * N];
-                    mac3(a0, d, kb[j]);
-                    mac3(a1, d, ka[j]);
+            for (int j = 0; j < KD; ++j) {
+                if (DNUM > 0 || j < dnum) {
+                    mac3(a0, d[j], kb[j]);
+                    mac3(a1, d[j], ka[j]);
                 }
             }
-            uint64_t *ab = acc + b * acc_bs;
-            ab[size_t(tt) * N + dst] = reduce128(acc3_value(a0), P);
-            ab[(size_t(nt) + tt) * N + dst] = reduce128(acc3_value(a1), P);
+            ob[0] = reduce128(acc3_value(a0), P);
+            ob[o_ps] = reduce128(acc3_value(a1), P);
+            dg += dig_bs;
+            ob += o_bs;
         }
     }
 }
 
+using KipFn = void (*)(const uint64_t *, int, int, int, int, const uint64_t *, int, LimbMap, const uint32_t *,
+                       uint64_t *, uint64_t *, const Prime *, int);
+KipFn kip_kernel(int dnum) {
+    switch (dnum) {
+        case 1: return k_kip_b<1>;
+        case 2: return k_kip_b<2>;
+        case 3: return k_kip_b<3>;
+        case 4: return k_kip_b<4>;
+        case 5: return k_kip_b<5>;
+        case 6: return k_kip_b<6>;
+        case 7: return k_kip_b<7>;
+        case 8: return k_kip_b<8>;
+        default: return k_kip_b<0>;
+    }
+}
+
 // out_p[b][i] = (acc[b][p][i] - conv[b][p][i]) * P^-1 + add_p[b][perm?(k)]
-__global__ __launch_bounds__(256) void k_moddown_combine_b(const uint64_t *__restrict__ acc, int nt,
+__global__ __launch_bounds__(256) void k_moddown_combine_b(const uint64_t *__restrict__ acc,
                                                            const uint64_t *__restrict__ conv, int nl,
                                                            const uint64_t *__restrict__ pinv, Ptrs add0, Ptrs add1,
                                                            int has_add0, int has_add1,
@@ -107,7 +149,7 @@ __global__ __launch_bounds__(256) void k_moddown_combine_b(const uint64_t *__res
     const size_t N = size_t(1) << logN;
     const uint64_t q = primes[i].q;
     const uint64_t pv = pinv[2 * i], pvp = pinv[2 * i + 1];
-    const uint64_t *x = acc + (size_t(b) * 2 + p) * nt * N + size_t(i) * N;
+    const uint64_t *x = acc + (size_t(b) * 2 + p) * nl * N + size_t(i) * N;
     const uint64_t *cv = conv + (size_t(b) * 2 + p) * nl * N + size_t(i) * N;
     const bool has = p == 0 ? has_add0 : has_add1;
     const uint64_t *ad = has ? (p == 0 ? add0.p[b] : add1.p[b]) + size_t(i) * N : nullptr;
@@ -229,20 +271,19 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
         if (!scat) return rc;
     }
     DevBuf acc, pl, conv;
-    CKC_TRY(acc.alloc(8 * N * nt * 2 * nb, s));
+    CKC_TRY(acc.alloc(8 * N * nl * 2 * nb, s));
     CKC_TRY(pl.alloc(8 * N * np * 2 * nb, s));
     CKC_TRY(conv.alloc(8 * N * nl * 2 * nb, s));
     const LimbMap ext{nl, c->nq};
     {
-        // algorithmic bytes: every digit word, every key word and every accumulator word once
+        // algorithmic bytes: every digit word, every key word and every output word once
         const double bytes = 8.0 * N * nt * (double(nb) * dnum + 2.0 * dnum + 2.0 * nb);
         CKC_PROF(PK_KIP, s, bytes, 2.0 * N * nt * dnum * nb);
-    hipLaunchKernelGGL(k_kip_b, dim3(tiles(N), unsigned(nt)), dim3(256), 0, s, digits, nb, dnum, nt, key,
-                       c->nprimes(), ext, scat, acc.u64(), c->dprimes(), c->logN);
+        hipLaunchKernelGGL(kip_kernel(dnum), dim3(unsigned(N / 256), unsigned(nt)), dim3(256), 0, s, digits, nb, dnum,
+                           nt, nl, key, c->nprimes(), ext, scat, acc.u64(), pl.u64(), c->dprimes(), c->logN);
     }
     CKC_HIP(hipGetLastError());
-    // P limbs of every accumulator (2 nb of them) -> coefficient form -> convert to Q -> NTT
-    CKC_TRY(copy_limbs(acc.u64() + size_t(nl) * N, size_t(nt) * N, pl.u64(), size_t(np) * N, N * np, 2 * nb, s));
+    // P limbs of every output (2 nb of them) -> coefficient form -> convert to Q -> NTT
     const LimbMap pmap{0, c->nq};
     CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * nb, size_t(np) * N, s));
     hipLaunchKernelGGL(k_bconv_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s, pl.u64(),
@@ -253,7 +294,7 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
     Ptrs none{};
     CKC_PROF(PK_MODDOWN, s, 8.0 * N * nl * 2 * nb * (3.0 + (add0 ? 0.5 : 0) + (add1 ? 0.5 : 0)), 0.0);
     hipLaunchKernelGGL(k_moddown_combine_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s,
-                       acc.u64(), nt, conv.u64(), nl, c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none,
+                       acc.u64(), conv.u64(), nl, c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none,
                        add0 ? 1 : 0, add1 ? 1 : 0, perm_add0 ? perm : nullptr, out0, out1, c->dprimes(), c->logN);
     CKC_HIP(hipGetLastError());
     return CKC_OK;
@@ -288,5 +329,37 @@ int ew_b(ckc_ctx *c, EwOp op, const Ptrs &out, const Ptrs &a, const Ptrs *b, int
     hipLaunchKernelGGL(k_ew_b, dim3(tiles(c->N), unsigned(nl * npoly), unsigned(nb)), dim3(256), 0, s, int(op), out, a,
                        b ? *b : none, b ? 1 : 0, nl, c->dprimes(), c->logN);
     CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+// Hoisted rotations of nb inputs (pointer table) for every nonzero step;
+// results to dst(b, step index) pointers.  The identity step is a copy.
+int hoisted_group(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int level, const std::vector<int32_t> &steps,
+                  const std::vector<Ptrs> &dst, hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
+    const size_t pw = size_t(nl) * N;
+    bool any = false;
+    for (int32_t st : steps) any |= galois_element(c, st) != 1;
+    DevBuf x1, digits;
+    if (any) {
+        CKC_TRY(x1.alloc(8 * pw * nb, s));
+        CKC_TRY(gather(in, pw, x1.u64(), pw, pw, nb, s));
+        CKC_TRY(digits.alloc(8 * N * nt * dnum * nb, s));
+        CKC_TRY(ks_modup_b(c, x1.u64(), pw, nb, level, digits.u64(), s));
+    }
+    for (size_t si = 0; si < steps.size(); ++si) {
+        const uint64_t g = galois_element(c, steps[si]);
+        if (g == 1) {
+            hipLaunchKernelGGL(k_copy_pp, dim3(1024, unsigned(nb)), dim3(256), 0, s, in, dst[si], 2 * pw);
+            CKC_HIP(hipGetLastError());
+            continue;
+        }
+        auto it = evk->galois.find(g);
+        CKC_REQUIRE(it != evk->galois.end(), CKC_ENOKEY, "missing Galois key for step " + std::to_string(steps[si]));
+        Ptrs o1;
+        for (int b = 0; b < nb; ++b) o1.p[b] = dst[si].p[b] + pw;
+        CKC_TRY(ks_apply_b(c, digits.u64(), nb, level, it->second->u64(), g, &in, nullptr, true, dst[si], o1, s));
+    }
     return CKC_OK;
 }

@@ -117,14 +117,6 @@ int fill_const_pt(ckc_ctx *c, uint64_t *d, double value, double scale, int nl, h
     return CKC_OK;
 }
 
-__global__ void k_copy_pp(Ptrs src, Ptrs dst, size_t words) {
-    const int b = blockIdx.y;
-    const uint64_t *sp = src.p[b];
-    uint64_t *d = dst.p[b];
-    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += size_t(gridDim.x) * blockDim.x)
-        d[k] = sp[k];
-}
-
 __global__ void k_scatter(const uint64_t *__restrict__ src, size_t src_bs, Ptrs dst, size_t words) {
     const int b = blockIdx.y;
     const uint64_t *sp = src + b * src_bs;
@@ -522,38 +514,6 @@ extern "C" int ckc_layer_destroy(ckc_layer *L) {
 }
 
 // ============================================================= evaluation
-// Hoisted rotations of nb inputs (pointer table) for every nonzero step;
-// results to dst(b, step index) pointers.  The identity step is a copy.
-static int hoisted_group(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int level,
-                         const std::vector<int32_t> &steps, const std::vector<Ptrs> &dst, hipStream_t s) {
-    const size_t N = c->N;
-    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
-    const size_t pw = size_t(nl) * N;
-    bool any = false;
-    for (int32_t st : steps) any |= galois_element(c, st) != 1;
-    DevBuf x1, digits;
-    if (any) {
-        CKC_TRY(x1.alloc(8 * pw * nb, s));
-        CKC_TRY(gather(in, pw, x1.u64(), pw, pw, nb, s));
-        CKC_TRY(digits.alloc(8 * N * nt * dnum * nb, s));
-        CKC_TRY(ks_modup_b(c, x1.u64(), pw, nb, level, digits.u64(), s));
-    }
-    for (size_t si = 0; si < steps.size(); ++si) {
-        const uint64_t g = galois_element(c, steps[si]);
-        if (g == 1) {
-            hipLaunchKernelGGL(k_copy_pp, dim3(1024, unsigned(nb)), dim3(256), 0, s, in, dst[si], 2 * pw);
-            CKC_HIP(hipGetLastError());
-            continue;
-        }
-        auto it = evk->galois.find(g);
-        CKC_REQUIRE(it != evk->galois.end(), CKC_ENOKEY, "missing Galois key for step " + std::to_string(steps[si]));
-        Ptrs o1;
-        for (int b = 0; b < nb; ++b) o1.p[b] = dst[si].p[b] + pw;
-        CKC_TRY(ks_apply_b(c, digits.u64(), nb, level, it->second->u64(), g, &in, nullptr, true, dst[si], o1, s));
-    }
-    return CKC_OK;
-}
-
 extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L, const ckc_ct *in, int n_img,
                              ckc_ct *out, void *stream) {
     CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");

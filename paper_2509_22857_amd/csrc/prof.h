@@ -15,6 +15,8 @@ enum ProfKernel {
     PK_RESCALE,
     PK_DENSE_MAC,
     PK_EW,
+    PK_MAC,
+    PK_TENSOR,
     PK_COUNT
 };
 
