@@ -565,4 +565,4 @@ def prof_query(name: str) -> dict:
 
 
 PROF_KERNELS = ("ntt_fwd", "ntt_inv", "bconv", "kip", "moddown", "conv_contract", "act_tensor", "rescale",
-                "dense_mac", "ew", "mac_plain", "tensor")
+                "dense_mac", "ew", "mac_plain", "tensor", "copy")

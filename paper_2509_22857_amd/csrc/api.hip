@@ -298,6 +298,7 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
 
 extern "C" int ckc_ctx_destroy(ckc_ctx *c) {
     delete c;
+    arena_trim();
     return CKC_OK;
 }
 extern "C" size_t ckc_ct_words(const ckc_ctx *c, int level, int npoly) { return words_ct(c, level, npoly); }

@@ -106,16 +106,16 @@ __global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digi
 #pragma unroll
             for (int j = 0; j < KD; ++j)
                 if (DNUM > 0 || j < dnum) d[j] = dg[size_t(j) * nt * N];
-            acc3 a0{0, 0, 0}, a1{0, 0, 0};
+            accc a0{0, 0, 0, 0, 0}, a1{0, 0, 0, 0, 0};
 #pragma unroll
             for (int j = 0; j < KD; ++j) {
                 if (DNUM > 0 || j < dnum) {
-                    mac3(a0, d[j], kb[j]);
-                    mac3(a1, d[j], ka[j]);
+                    macc(a0, d[j], kb[j]);
+                    macc(a1, d[j], ka[j]);
                 }
             }
-            ob[0] = reduce128(acc3_value(a0), P);
-            ob[o_ps] = reduce128(acc3_value(a1), P);
+            ob[0] = reduce128(accc_value(a0), P);
+            ob[o_ps] = reduce128(accc_value(a1), P);
             dg += dig_bs;
             ob += o_bs;
         }
@@ -222,6 +222,7 @@ __global__ __launch_bounds__(256) void k_ew_b(int op, Ptrs out, Ptrs a, Ptrs bb,
 
 int gather(const Ptrs &src, size_t src_off, uint64_t *dst, size_t dst_bs, size_t words, int nb, hipStream_t s) {
     if (nb <= 0) return CKC_OK;
+    CKC_PROF(PK_COPY, s, 16.0 * double(words) * nb, 0.0);
     hipLaunchKernelGGL(k_gather, dim3(unsigned(std::min<size_t>((words + 255) / 256, 1024)), unsigned(nb)), dim3(256),
                        0, s, src, src_off, dst, dst_bs, words);
     CKC_HIP(hipGetLastError());
@@ -286,9 +287,12 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
     // P limbs of every output (2 nb of them) -> coefficient form -> convert to Q -> NTT
     const LimbMap pmap{0, c->nq};
     CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * nb, size_t(np) * N, s));
-    hipLaunchKernelGGL(k_bconv_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s, pl.u64(),
-                       size_t(np) * N, np, 0, pmap, conv.u64(), size_t(nl) * N, qmap(), -1, -1, c->p_to_q.inv.u64(),
-                       c->p_to_q.invp.u64(), c->p_to_q.hat.u64(), c->dprimes(), c->logN);
+    {
+        CKC_PROF(PK_BCONV, s, 8.0 * N * (np + nl) * 2 * nb, 0.0);
+        hipLaunchKernelGGL(k_bconv_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s, pl.u64(),
+                           size_t(np) * N, np, 0, pmap, conv.u64(), size_t(nl) * N, qmap(), -1, -1,
+                           c->p_to_q.inv.u64(), c->p_to_q.invp.u64(), c->p_to_q.hat.u64(), c->dprimes(), c->logN);
+    }
     CKC_HIP(hipGetLastError());
     CKC_TRY(ntt_forward(c, conv.u64(), nl, qmap(), 2 * nb, size_t(nl) * N, s));
     Ptrs none{};
@@ -311,12 +315,18 @@ int rescale_b(ckc_ctx *c, const Ptrs &in, const Ptrs &out, int nb, int npoly, in
         CKC_TRY(gather(in, (size_t(p) * nl + level) * N, top.u64() + size_t(p) * N, size_t(npoly) * N, N, nb, s));
     const LimbMap one{0, level};
     CKC_TRY(ntt_inverse(c, top.u64(), 1, one, nbp, N, s));
-    hipLaunchKernelGGL(k_rescale_lift_b, dim3(tiles(N), unsigned(level), unsigned(nbp)), dim3(256), 0, s, top.u64(),
-                       npoly, lift.u64(), level, c->dprimes(), c->logN);
+    {
+        CKC_PROF(PK_RESCALE, s, 8.0 * N * nbp * (1.0 + level), 0.0);
+        hipLaunchKernelGGL(k_rescale_lift_b, dim3(tiles(N), unsigned(level), unsigned(nbp)), dim3(256), 0, s,
+                           top.u64(), npoly, lift.u64(), level, c->dprimes(), c->logN);
+    }
     CKC_HIP(hipGetLastError());
     CKC_TRY(ntt_forward(c, lift.u64(), level, qmap(), nbp, size_t(level) * N, s));
-    hipLaunchKernelGGL(k_rescale_combine_b, dim3(tiles(N), unsigned(level), unsigned(nbp)), dim3(256), 0, s, in,
-                       npoly, lift.u64(), out, level, c->rescale_inv.u64(), c->dprimes(), c->logN, c->nq);
+    {
+        CKC_PROF(PK_RESCALE, s, 8.0 * N * nbp * 3.0 * level, 0.0);
+        hipLaunchKernelGGL(k_rescale_combine_b, dim3(tiles(N), unsigned(level), unsigned(nbp)), dim3(256), 0, s, in,
+                           npoly, lift.u64(), out, level, c->rescale_inv.u64(), c->dprimes(), c->logN, c->nq);
+    }
     CKC_HIP(hipGetLastError());
     return CKC_OK;
 }
@@ -351,6 +361,7 @@ int hoisted_group(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int le
     for (size_t si = 0; si < steps.size(); ++si) {
         const uint64_t g = galois_element(c, steps[si]);
         if (g == 1) {
+            CKC_PROF(PK_COPY, s, 16.0 * 2 * pw * nb, 0.0);
             hipLaunchKernelGGL(k_copy_pp, dim3(1024, unsigned(nb)), dim3(256), 0, s, in, dst[si], 2 * pw);
             CKC_HIP(hipGetLastError());
             continue;

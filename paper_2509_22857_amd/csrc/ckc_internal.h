@@ -49,26 +49,37 @@ struct LimbMap {
 };
 static inline LimbMap qmap() { return LimbMap{0x7fffffff, 0}; }
 
-// RAII device buffer from the stream-ordered allocator.
+// Per-stream scratch arena.  Every call takes its temporary buffers from the
+// arena of the stream it runs on, stack-wise; the arena keeps one device
+// buffer that grows to the most scratch any call has held at once and is
+// reused by every later call on that stream (work on one stream runs in
+// order, so a later call may reuse what an earlier one released while its
+// kernels are still queued).  Steady-state calls therefore make no
+// allocation API calls.  When a request does not fit while other buffers are
+// live, it is served from the stream-ordered allocator and the arena grows to
+// cover it the next time it is empty.
+struct Arena;
+int arena_alloc(hipStream_t s, size_t bytes, void **p, Arena **a, size_t *off);
+void arena_release(Arena *a, size_t off, void *p, hipStream_t s);
+// release the unused arenas of the current device (their streams idle)
+void arena_trim();
+
+// RAII scratch buffer from the stream's arena.
 struct DevBuf {
     void *p = nullptr;
     hipStream_t s = nullptr;
+    Arena *a = nullptr;
+    size_t off = 0;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() {
-        if (p) (void)hipFreeAsync(p, s);
+        if (p) arena_release(a, off, p, s);
     }
     int alloc(size_t bytes, hipStream_t st) {
         s = st;
         if (bytes == 0) bytes = 256;
-        hipError_t e = hipMallocAsync(&p, bytes, st);
-        if (e != hipSuccess) {
-            p = nullptr;
-            ckc_set_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
-            return CKC_ENOMEM;
-        }
-        return CKC_OK;
+        return arena_alloc(st, bytes, &p, &a, &off);
     }
     uint64_t *u64() const { return (uint64_t *)p; }
 };

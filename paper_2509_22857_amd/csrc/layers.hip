@@ -11,6 +11,7 @@
 // product, which is exact ring arithmetic (the same residues as multiplying
 // every weight separately).
 #include <math.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <vector>
@@ -127,8 +128,8 @@ __global__ void k_scatter(const uint64_t *__restrict__ src, size_t src_bs, Ptrs 
 
 // ----------------------------------------------------------------------- conv
 constexpr int kTile = 64;        // coefficients per workgroup
-constexpr int kOutPerWave = 8;   // outputs accumulated per wave
-constexpr int kOutPerWg = 4 * kOutPerWave;
+constexpr int kGrpOut = 8;       // outputs per wave of the grouped form
+constexpr int kOutPerWg = 4 * kGrpOut;
 
 // One workgroup: 64 coefficients of one limb of one polynomial, 32 outputs.
 // R_img: [I][ntap][2][nl][N]; pts: [ntap][kcent][nl][N]; bias: [O][nl][N].
@@ -149,10 +150,10 @@ __global__ __launch_bounds__(256) void k_conv_contract(
     // prod_cap <= 2^(128 - 2k) - 1 (k = bit length of q)
     const uint64_t add_cap = P.onep - 1;
     const int prod_cap = P.k >= 61 ? (1 << (128 - 2 * P.k)) - 1 : 64;
-    u128v acc[kOutPerWave];
-    int cnt[kOutPerWave];
+    u128v acc[kGrpOut];
+    int cnt[kGrpOut];
 #pragma unroll
-    for (int j = 0; j < kOutPerWave; ++j) {
+    for (int j = 0; j < kGrpOut; ++j) {
         acc[j] = u128v{0, 0};
         cnt[j] = 0;
     }
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256) void k_conv_contract(
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < kOutPerWave; ++j) {
+        for (int j = 0; j < kGrpOut; ++j) {
             const int ol = ogrp * kOutPerWg + wave + 4 * j;  // local output index
             if (ol >= o_count) continue;
             const int o = o_base + ol;
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256) void k_conv_contract(
         }
     }
 #pragma unroll
-    for (int j = 0; j < kOutPerWave; ++j) {
+    for (int j = 0; j < kGrpOut; ++j) {
         const int ol = ogrp * kOutPerWg + wave + 4 * j;
         if (ol >= o_count) continue;
         const int o = o_base + ol;
@@ -202,83 +203,112 @@ __global__ __launch_bounds__(256) void k_conv_contract(
     }
 }
 
-// Direct form of the same contraction for codebooks of at most kMaxCentLds
-// centroids: y_o = sum_t sum_i PT[t][idx[o][i][t]] * R[i][t] + bias_o.
-// Per tap the workgroup stages the tap's whole plaintext codebook tile
-// (kcent x 64 words) and up to 64 rotated inputs (64 x 64 words) in LDS; the
-// centroid index is wave-uniform (a scalar load), so every lane does one LDS
-// read of R, one of the codebook and a 64x64->128 multiply-accumulate.
-// Wave w owns the 8 consecutive outputs 32*group + 8w .. +7.
-// idx8: [ntap][I][Opad] uint8.
-constexpr int kMaxCentLds = 64;
-constexpr int kIChunk = 64;
-__global__ __launch_bounds__(256) void k_conv_mac(const uint64_t *__restrict__ R, int I, int ntap, int nl,
-                                                  const uint64_t *__restrict__ pts, int kcent,
-                                                  const uint8_t *__restrict__ idx8, int Opad,
-                                                  const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
-                                                  int o_count, const Prime *__restrict__ primes, int logN) {
-    extern __shared__ uint64_t lds[];
-    uint64_t *sP = lds;                   // [kcent][kTile]
-    uint64_t *sR = lds + kcent * kTile;   // [kIChunk][kTile]
+// Direct form of the same contraction, batched over images, for codebooks of
+// at most kMaxCentLds centroids:
+//   y[m][o] = sum_t sum_i PT[t][idx[o][i][t]] * R[m][i][t] + bias_o
+// for up to kImgPerWg images m and kOutPerWave consecutive outputs o.  One
+// workgroup = one 64-coefficient column tile of one limb; wave w handles image
+// w >> 1 and polynomial w & 1 and keeps one accumulator per output.  Per tap
+// the tap's whole codebook tile (kcent x 64 words) is staged in LDS once and
+// read by every wave, so the codebook crosses HBM once per group of images and
+// outputs rather than once per image and polynomial.  The centroid index is
+// wave-uniform (scalar loads of 8 packed byte indices); R is read straight
+// from HBM, each element by exactly one wave, for all its outputs.
+// idx8: [ntap][I][Opad] uint8, Opad a multiple of kOutPerWave.
+constexpr int kMaxCentLds = 128;
+constexpr int kImgPerWg = 4;
+template <int OUTS, int IMGS>
+__global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restrict__ R, size_t r_img_words,
+                                                           int n_img, int I, int ntap, int nl,
+                                                           const uint64_t *__restrict__ pts, int kcent,
+                                                           const uint8_t *__restrict__ idx8, int Opad,
+                                                           const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
+                                                           int o_count, const Prime *__restrict__ primes, int logN) {
+    static_assert(OUTS % 8 == 0, "outputs per wave come in packed words of 8 indices");
+    constexpr int NW = OUTS / 8;
+    extern __shared__ uint64_t sP[];  // [kcent][kTile]
     const size_t N = size_t(1) << logN;
     const int limb = blockIdx.y;
-    const int poly = blockIdx.z & 1, ogrp = blockIdx.z >> 1;
     const int lane = threadIdx.x & 63;
     // wave index as a wave-uniform (scalar) value, so per-wave control flow and
     // index loads stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int img = wave >> 1, poly = wave & 1;
+    const bool active = img < n_img;
     const size_t col0 = size_t(blockIdx.x) * kTile;
+    const size_t pw = size_t(nl) * N, ctw = 2 * pw;
     const Prime P = primes[limb];
     const int pcap = prod_cap(P.k);
-    const int ol0 = ogrp * kOutPerWg + wave * kOutPerWave;  // first local output of this wave
-    const int my_out = min(kOutPerWave, o_count - ol0);      // outputs this wave owns (may be <= 0)
-    const int ostride = Opad / 8;                             // idx rows in 8-byte words
-    acc3 acc[kOutPerWave];
+    const int ostride = Opad / 8;  // idx rows in 8-byte words
+    const size_t rstride = size_t(ntap) * ctw;  // R words between consecutive inputs
+    const uint64_t *Rb = R + size_t(active ? img : 0) * r_img_words + size_t(poly) * pw + size_t(limb) * N + col0 + lane;
+    accc acc[OUTS];
 #pragma unroll
-    for (int j = 0; j < kOutPerWave; ++j) acc[j] = acc3{0, 0, 0};
+    for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, 0, 0, 0};
     int cnt = 0;
     for (int t = 0; t < ntap; ++t) {
         __syncthreads();
-        for (int e = threadIdx.x; e < kcent * kTile; e += 256) {
+        for (int e = threadIdx.x; e < kcent * kTile; e += 128 * IMGS) {
             const int c = e / kTile, l = e - c * kTile;
             sP[e] = pts[((size_t(t) * kcent + c) * nl + limb) * N + col0 + l];
         }
-        for (int i0 = 0; i0 < I; i0 += kIChunk) {
-            const int ni = min(kIChunk, I - i0);
-            if (i0 > 0) __syncthreads();
-            for (int e = threadIdx.x; e < ni * kTile; e += 256) {
-                const int i = e / kTile, l = e - i * kTile;
-                sR[e] = R[(((size_t(i0 + i) * ntap + t) * 2 + poly) * nl + limb) * N + col0 + l];
-            }
-            __syncthreads();
-            if (my_out > 0) {
-                // 8 consecutive output indices of this wave, one 8-byte scalar load per input
-                const uint64_t *ix = (const uint64_t *)(idx8 + (size_t(t) * I + i0) * Opad + o_base + ol0);
-                for (int ii = 0; ii < ni; ++ii) {
-                    const uint64_t r = sR[ii * kTile + lane];
-                    const uint64_t packed = ix[size_t(ii) * ostride];
+        __syncthreads();
+        if (!active) continue;
+        const uint64_t *ix = (const uint64_t *)(idx8 + size_t(t) * I * Opad + o_base);
+        const uint64_t *rp = Rb + size_t(t) * ctw;
+        uint64_t r = rp[0], kw[NW];
 #pragma unroll
-                    for (int j = 0; j < kOutPerWave; ++j) {
-                        const int c = int((packed >> (8 * j)) & 0xff);
-                        mac3(acc[j], r, sP[c * kTile + lane]);
-                    }
-                    if (++cnt == pcap) {
+        for (int w = 0; w < NW; ++w) kw[w] = ix[w];
+        for (int i = 0; i < I; ++i) {
+            // prefetch the next input's coefficient and index words
+            const int nx = i + 1 < I ? i + 1 : i;
+            const uint64_t rn = rp[size_t(nx) * rstride];
+            uint64_t kn[NW];
 #pragma unroll
-                        for (int j = 0; j < kOutPerWave; ++j) acc[j] = acc3{0, 0, reduce128(acc3_value(acc[j]), P)};
-                        cnt = 0;
-                    }
-                }
+            for (int w = 0; w < NW; ++w) kn[w] = ix[size_t(nx) * ostride + w];
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) macc(acc[8 * w + j], r, sP[int((kw[w] >> (8 * j)) & 0xff) * kTile + lane]);
+            if (++cnt == pcap) {
+#pragma unroll
+                for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, reduce128(accc_value(acc[j]), P), 0, 0};
+                cnt = 0;
             }
+            r = rn;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) kw[w] = kn[w];
         }
     }
+    if (!active) return;
 #pragma unroll
-    for (int j = 0; j < kOutPerWave; ++j) {
-        if (j >= my_out) continue;
-        const int ol = ol0 + j, o = o_base + ol;
-        uint64_t y = reduce128(acc3_value(acc[j]), P);
+    for (int j = 0; j < OUTS; ++j) {
+        if (j >= o_count) continue;
+        const int o = o_base + j;
+        uint64_t y = reduce128(accc_value(acc[j]), P);
         if (poly == 0 && bias) y = add_mod(y, bias[(size_t(o) * nl + limb) * N + col0 + lane], P.q);
-        outs.p[ol][(size_t(poly) * nl + limb) * N + col0 + lane] = y;
+        outs.p[img * OUTS + j][size_t(poly) * pw + size_t(limb) * N + col0 + lane] = y;
     }
+}
+
+// outputs per wave of the direct form (8 or 16): a tuning choice between
+// accumulator registers (occupancy) and codebook re-reads per output group
+static int conv_outs_per_wave() {
+    static const int v = [] {
+        const char *e = getenv("CKC_CONV_OUTS");
+        const int x = e ? atoi(e) : 8;
+        return x == 16 ? 16 : 8;
+    }();
+    return v;
+}
+
+using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, const uint64_t *, int, const uint8_t *, int,
+                        const uint64_t *, Ptrs, int, int, const Prime *, int);
+// kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images) that holds them
+static ConvFn conv_kernel(int outs, int gi, int *imgs) {
+    *imgs = gi <= 1 ? 1 : gi <= 2 ? 2 : 4;
+    if (outs == 16) return *imgs == 1 ? k_conv_mac<16, 1> : *imgs == 2 ? k_conv_mac<16, 2> : k_conv_mac<16, 4>;
+    return *imgs == 1 ? k_conv_mac<8, 1> : *imgs == 2 ? k_conv_mac<8, 2> : k_conv_mac<8, 4>;
 }
 
 int check_inputs(const ckc_ct *in, int n, int level, const char *what) {
@@ -529,10 +559,12 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
     const size_t N = c->N;
     const int nl = L->level + 1, I = L->I, ntap = L->ntap;
     const size_t pw = size_t(nl) * N, ctw = 2 * pw;
-    // images per chunk: KS batches of at most kMaxBatch ciphertexts
-    const int chunk = std::max(1, kMaxBatch / I);
+    // images per chunk: at least one contraction group, and enough for a full
+    // key-switching batch of kMaxBatch rotated inputs
+    const int chunk = std::max(kImgPerWg, kMaxBatch / I);
+    const size_t r_img = size_t(I) * ntap * ctw;  // R words per image
     DevBuf R;
-    CKC_TRY(R.alloc(8 * ctw * ntap * I * std::min(chunk, n_img), s));
+    CKC_TRY(R.alloc(8 * r_img * std::min(chunk, n_img), s));
     const size_t lds = size_t(I) * kTile * 8;
     for (int img0 = 0; img0 < n_img; img0 += chunk) {
         const int ni = std::min(chunk, n_img - img0);
@@ -550,9 +582,35 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
             }
             CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
         }
-        // contraction per image, outputs in groups of kMaxBatch
+        if (L->idx8.p) {
+            // contraction: groups of kImgPerWg images x `outs` outputs
+            const size_t lds_mac = size_t(L->kcent) * kTile * 8;
+            const int outs = conv_outs_per_wave();
+            for (int g0 = 0; g0 < ni; g0 += kImgPerWg) {
+                const int gi = std::min(kImgPerWg, ni - g0);
+                for (int o0 = 0; o0 < L->O; o0 += outs) {
+                    const int oc = std::min(outs, L->O - o0);
+                    Ptrs op{};
+                    for (int m = 0; m < gi; ++m)
+                        for (int j = 0; j < oc; ++j)
+                            op.p[m * outs + j] = out[size_t(img0 + g0 + m) * L->O + o0 + j].d;
+                    CKC_PROF(PK_CONV_CONTRACT, s,
+                             8.0 * N * nl * (2.0 * gi * I * ntap + 2.0 * gi * oc + double(ntap) * L->kcent),
+                             2.0 * N * nl * double(gi) * oc * I * ntap);
+                    int wg_imgs = 1;
+                    const ConvFn fn = conv_kernel(outs, gi, &wg_imgs);
+                    hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nl)), dim3(128 * wg_imgs), lds_mac, s,
+                                       R.u64() + size_t(g0) * r_img, r_img, gi, I, ntap,
+                                       nl, L->pts.u64(), L->kcent, (const uint8_t *)L->idx8.p, L->Opad,
+                                       L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, c->dprimes(), c->logN);
+                    CKC_HIP(hipGetLastError());
+                }
+            }
+            continue;
+        }
+        // grouped form (codebooks beyond kMaxCentLds centroids): per image, outputs in groups of kMaxBatch
         for (int ii = 0; ii < ni; ++ii) {
-            const uint64_t *Rimg = R.u64() + size_t(ii) * I * ntap * ctw;
+            const uint64_t *Rimg = R.u64() + size_t(ii) * r_img;
             for (int o0 = 0; o0 < L->O; o0 += kMaxBatch) {
                 const int oc = std::min(kMaxBatch, L->O - o0);
                 Ptrs op;
@@ -560,19 +618,11 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                 const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
                 CKC_PROF(PK_CONV_CONTRACT, s, 8.0 * N * nl * (2.0 * I * ntap + 2.0 * oc + double(ntap) * L->kcent),
                          2.0 * N * nl * double(oc) * I * ntap);
-                if (L->idx8.p) {
-                    const size_t lds_mac = size_t(L->kcent + std::min(I, kIChunk)) * kTile * 8;
-                    hipLaunchKernelGGL(k_conv_mac, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups), dim3(256),
-                                       lds_mac, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent,
-                                       (const uint8_t *)L->idx8.p, L->Opad, L->has_bias ? L->bias.u64() : nullptr, op,
-                                       o0, oc, c->dprimes(), c->logN);
-                } else {
-                    hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups),
-                                       dim3(256), lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent,
-                                       (const int32_t *)L->og_off.p, (const int32_t *)L->g_c.p,
-                                       (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p,
-                                       L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, c->dprimes(), c->logN);
-                }
+                hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups), dim3(256),
+                                   lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent, (const int32_t *)L->og_off.p,
+                                   (const int32_t *)L->g_c.p, (const int32_t *)L->g_moff.p,
+                                   (const int32_t *)L->m_i.p, L->has_bias ? L->bias.u64() : nullptr, op, o0, oc,
+                                   c->dprimes(), c->logN);
                 CKC_HIP(hipGetLastError());
             }
         }
@@ -668,22 +718,24 @@ __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ 
     const Prime P = primes[limb];
     const int pcap = prod_cap(P.k);
     for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        acc3 acc[kDenseImg];
-        for (int i = 0; i < kDenseImg; ++i) acc[i] = acc3{0, 0, 0};
+        accc acc[kDenseImg];
+        for (int i = 0; i < kDenseImg; ++i) acc[i] = accc{0, 0, 0, 0, 0};
         int cnt = 0;
         for (int ch = 0; ch < C; ++ch) {
             const uint64_t pv = pts[(size_t(kk) * C + ch) * pw + size_t(limb) * N + k];
 #pragma unroll
             for (int i = 0; i < kDenseImg; ++i)
-                if (i < nimg) mac3(acc[i], Sb[((size_t(i) * C + ch) * 2 + poly) * pw + size_t(limb) * N + k], pv);
+                if (i < nimg) macc(acc[i], Sb[((size_t(i) * C + ch) * 2 + poly) * pw + size_t(limb) * N + k], pv);
             if (++cnt == pcap) {
 #pragma unroll
-                for (int i = 0; i < kDenseImg; ++i) acc[i] = acc3{0, 0, reduce128(acc3_value(acc[i]), P)};
+                for (int i = 0; i < kDenseImg; ++i) acc[i] = accc{0, 0, reduce128(accc_value(acc[i]), P), 0, 0};
                 cnt = 0;
             }
         }
-        for (int i = 0; i < nimg; ++i) {
-            uint64_t y = reduce128(acc3_value(acc[i]), P);
+#pragma unroll
+        for (int i = 0; i < kDenseImg; ++i) {
+            if (i >= nimg) continue;
+            uint64_t y = reduce128(accc_value(acc[i]), P);
             if (poly == 0 && bias) y = add_mod(y, bias[size_t(kk) * pw + size_t(limb) * N + k], P.q);
             Z[((size_t(i) * K + kk) * 2 + poly) * pw + size_t(limb) * N + k] = y;
         }
@@ -736,7 +788,8 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
             }
         }
         {
-            CKC_PROF(PK_DENSE_MAC, s, 8.0 * N * nl * (2.0 * ni * C + double(K) * C + 2.0 * ni * K), 0.0);
+            CKC_PROF(PK_DENSE_MAC, s, 8.0 * N * nl * (2.0 * ni * C + double(K) * C + 2.0 * ni * K),
+                     2.0 * N * nl * double(ni) * K * C);
         hipLaunchKernelGGL(k_dense_mac, dim3(tiles(N), unsigned(nl), unsigned(2 * K)), dim3(256), 0, s, Sb.u64(), ni, C,
                            nl, L->pts.u64(), L->has_bias ? L->bias.u64() : nullptr, Z.u64(), K, c->dprimes(), c->logN);
         }

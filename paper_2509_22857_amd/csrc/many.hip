@@ -61,16 +61,16 @@ __global__ __launch_bounds__(256) void k_mac_plain_b(Ptrs in, int T, Ptrs pt, Pt
     const int pcap = prod_cap(P.k);
     const size_t off = (size_t(poly) * nl + limb) * N;
     for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        acc3 acc{0, 0, 0};
+        accc acc{0, 0, 0, 0, 0};
         int cnt = 0;
         for (int t = 0; t < T; ++t) {
-            mac3(acc, in.p[o * T + t][off + k], pt.p[t][size_t(limb) * N + k]);
+            macc(acc, in.p[o * T + t][off + k], pt.p[t][size_t(limb) * N + k]);
             if (++cnt == pcap) {
-                acc = acc3{0, 0, reduce128(acc3_value(acc), P)};
+                acc = accc{0, 0, reduce128(accc_value(acc), P), 0, 0};
                 cnt = 0;
             }
         }
-        out.p[o][off + k] = reduce128(acc3_value(acc), P);
+        out.p[o][off + k] = reduce128(accc_value(acc), P);
     }
 }
 

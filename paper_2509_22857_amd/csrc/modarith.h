@@ -35,45 +35,40 @@ CKC_HD u128v add128(u128v x, u128v y) {
     return r;
 }
 
-// acc += a * b for residues a, b < 2^62.  With 32-bit halves a = a1 2^32 + a0
-// (a1, b1 < 2^30) the middle sum a0 b1 + a1 b0 + (a0 b0 >> 32) < 2^63 cannot
-// overflow, so the 128-bit product takes four 32x32->64 multiply-adds and no
-// carry handling; one carry chain adds it to the accumulator.
-CKC_HD void mac62(u128v &acc, uint64_t a, uint64_t b) {
-    const uint32_t a0 = uint32_t(a), a1 = uint32_t(a >> 32), b0 = uint32_t(b), b1 = uint32_t(b >> 32);
-    const uint64_t p00 = uint64_t(a0) * b0;
-    uint64_t mid = uint64_t(a0) * b1 + (p00 >> 32);
-    mid = uint64_t(a1) * b0 + mid;
-    const uint64_t hi = uint64_t(a1) * b1 + (mid >> 32);
-    const uint64_t lo = (mid << 32) | (p00 & 0xffffffffull);
-    acc.lo += lo;
-    acc.hi += hi + (acc.lo < lo ? 1ull : 0ull);
-}
-
-// Carry-free accumulator of products of residues < 2^62: value =
-// h 2^64 + m 2^32 + l, where l and m collect 32-bit halves (no overflow for
-// 2^32 terms) and h the high words (< 2^(2k-64) + 2^32 each for k-bit
-// residues, so up to prod_cap(k) terms fit).  One carry chain at the end.
-struct acc3 {
+// Carry-counted accumulator of products of residues < 2^62 (device only):
+//   value = l + cl 2^64 + (m + cm 2^64) 2^32 + h 2^64.
+// A product a b with a = a1 2^32 + a0, b = b1 2^32 + b0 (a1, b1 < 2^30) adds
+// a0 b0 into l, a0 b1 and a1 b0 into m and a1 b1 into h, each with one
+// 32x32+64 multiply-add; the carry out of every multiply-add into l or m is
+// added to cl or cm (the multiply-add's own carry output feeds an add-with-
+// carry), so one product costs four multiply-adds and three adds.  With
+// k-bit residues every product is below 2^(2k), so up to prod_cap(k)
+// products plus one reduced residue keep the value below 2^128.
+struct accc {
     uint64_t h, m, l;
+    uint32_t cm, cl;
 };
-CKC_HD void mac3(acc3 &acc, uint64_t a, uint64_t b) {
+__device__ __forceinline__ void macc(accc &acc, uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
     const uint32_t a0 = uint32_t(a), a1 = uint32_t(a >> 32), b0 = uint32_t(b), b1 = uint32_t(b >> 32);
-    const uint64_t p00 = uint64_t(a0) * b0;
-    uint64_t mid = uint64_t(a0) * b1 + (p00 >> 32);
-    mid = uint64_t(a1) * b0 + mid;
-    acc.h = uint64_t(a1) * b1 + acc.h + (mid >> 32);
-    acc.m += mid & 0xffffffffull;
-    acc.l += p00 & 0xffffffffull;
+    uint64_t c, d;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc.l), "=s"(c) : "v"(a0), "v"(b0));
+    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc.cl), "=s"(d) : "s"(c));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc.m), "=s"(c) : "v"(a0), "v"(b1));
+    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc.cm), "=s"(d) : "s"(c));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc.m), "=s"(c) : "v"(a1), "v"(b0));
+    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc.cm), "=s"(d) : "s"(c));
+    acc.h = uint64_t(a1) * b1 + acc.h;
+#endif
 }
-CKC_HD u128v acc3_value(const acc3 &a) {
-    // l + m 2^32 + h 2^64
+__device__ __forceinline__ u128v accc_value(const accc &a) {
+    const uint64_t ml = a.m << 32;
     u128v r;
-    const uint64_t ml = a.m << 32, mh = a.m >> 32;
     r.lo = a.l + ml;
-    r.hi = a.h + mh + (r.lo < ml ? 1ull : 0ull);
+    r.hi = a.h + a.cl + (a.m >> 32) + (uint64_t(a.cm) << 32) + (r.lo < ml ? 1ull : 0ull);
     return r;
 }
+
 // largest number of products (plus one reduced residue) an accumulator may
 // take for a k-bit modulus
 CKC_HD int prod_cap(int k) { return k >= 61 ? (1 << (128 - 2 * k)) - 1 : 64; }

@@ -17,6 +17,7 @@ enum ProfKernel {
     PK_EW,
     PK_MAC,
     PK_TENSOR,
+    PK_COPY,
     PK_COUNT
 };
 

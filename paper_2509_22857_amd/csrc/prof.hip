@@ -32,7 +32,7 @@ hipEvent_t get_event() {
 }
 
 const char *kNames[PK_COUNT] = {"ntt_fwd", "ntt_inv", "bconv", "kip", "moddown", "conv_contract",
-                                "act_tensor", "rescale", "dense_mac", "ew", "mac_plain", "tensor"};
+                                "act_tensor", "rescale", "dense_mac", "ew", "mac_plain", "tensor", "copy"};
 }  // namespace
 
 ProfScope::ProfScope(int kid_, hipStream_t s_, double bytes_, double work_) : kid(kid_), bytes(bytes_), work(work_), s(s_) {

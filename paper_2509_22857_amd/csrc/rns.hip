@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "ckc_internal.h"
+#include "prof.h"
 
 namespace {
 
@@ -137,6 +138,7 @@ uint64_t h_shoup(uint64_t w, uint64_t q) { return (uint64_t)(((unsigned __int128
 int copy_limbs(const uint64_t *src, size_t src_ps, uint64_t *dst, size_t dst_ps, size_t words, int npoly,
                hipStream_t s) {
     if (words == 0 || npoly == 0) return CKC_OK;
+    CKC_PROF(PK_COPY, s, 16.0 * double(words) * npoly, 0.0);
     hipLaunchKernelGGL(k_copy_limbs, dim3(unsigned(std::min<size_t>((words + 255) / 256, 2048)), unsigned(npoly)),
                        dim3(256), 0, s, src, src_ps, dst, dst_ps, words);
     CKC_HIP(hipGetLastError());

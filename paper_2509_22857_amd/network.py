@@ -186,9 +186,20 @@ class GpuNetwork:
         return out
 
     # --------------------------------------------------------- server side
-    def run(self, keys: ckks.KeyPair, inputs, stream=None, keep=False, hook=None):
-        """inputs: [n_img][C] ciphertexts -> {"out": [n_img][K or C] ciphertexts}.
-        Every tensor of the network is evaluated for all images per call."""
+    def run(self, keys: ckks.KeyPair, inputs, stream=None, keep=False, hook=None, images_per_pass=None):
+        """inputs: [n_img][C] ciphertexts -> ([n_img][K or C] ciphertexts, tensors).
+
+        Every tensor of the network is evaluated for all images of a pass
+        before the next layer starts; images_per_pass bounds the live
+        ciphertexts (a pass of 16 ResNet-20 images already fills every key
+        switching launch with 64 ciphertexts).  With several passes the
+        returned tensors are those of the last pass."""
+        if images_per_pass and len(inputs) > images_per_pass:
+            outs, tensors = [], None
+            for i in range(0, len(inputs), images_per_pass):
+                o, tensors = self.run(keys, inputs[i:i + images_per_pass], stream, keep, hook)
+                outs.extend(o)
+            return outs, tensors
         ctx = self.ctx
         n_img = len(inputs)
         tensors = {"x": [c for row in inputs for c in row]}
