@@ -150,7 +150,8 @@ def main():
         torch.cuda.synchronize()
         t_plain += time.time() - a
     plain_ips = nplain / t_plain if nplain else None
-    log(f"plain: {plain_ips:.3f} images/s")
+    if plain_ips:
+        log(f"plain: {plain_ips:.3f} images/s")
 
     # accuracy of the timed outputs against the FP64 forward
     from oracle.forward import forward

@@ -164,6 +164,8 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
     CKC_REQUIRE(log_n >= 12 && log_n <= 16, CKC_EUNSUPPORTED, "log_n must be in [12, 16]");
     CKC_REQUIRE(n_q >= 1 && n_p >= 1 && n_q + n_p <= 96, CKC_EINVAL, "bad prime counts");
     CKC_REQUIRE(alpha >= 1 && alpha <= n_q, CKC_EINVAL, "bad alpha");
+    CKC_REQUIRE(alpha <= kMaxBconv && n_p <= kMaxBconv, CKC_EUNSUPPORTED,
+                "at most 8 primes per key-switching digit and 8 special primes");
     const size_t N = size_t(1) << log_n;
     std::set<uint64_t> seen;
     for (int i = 0; i < n_q + n_p; ++i) {
@@ -278,6 +280,7 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
             hat[size_t(i) * n_p + a] = h;
         }
     }
+    c->p_to_q.iscale_h.resize(2 * size_t(n_p));
     for (int a = 0; a < n_p; ++a) {
         const uint64_t pa = p[a];
         uint64_t h = 1 % pa;
@@ -285,7 +288,10 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
             if (b != a) h = hmul(h, p[b] % pa, pa);
         inv[a] = hinv(h, pa);
         invp[a] = hshoup(inv[a], pa);
+        c->p_to_q.iscale_h[2 * a] = hmul(hinv(N % pa, pa), inv[a], pa);
+        c->p_to_q.iscale_h[2 * a + 1] = hshoup(c->p_to_q.iscale_h[2 * a], pa);
     }
+    CKC_TRY(c->p_to_q.iscale.upload(c->p_to_q.iscale_h.data(), 8 * c->p_to_q.iscale_h.size()));
     CKC_TRY(c->pinv.upload(pinv.data(), 8 * pinv.size()));
     c->p_to_q.ns = n_p;
     c->p_to_q.nt = n_q;

@@ -13,6 +13,34 @@ struct Ptrs {
 int copy_limbs(const uint64_t *src, size_t src_ps, uint64_t *dst, size_t dst_ps, size_t words, int npoly,
                hipStream_t s);
 
+// Fast basis conversion computing the input of a forward NTT (see
+// ntt_forward_ex): output limb t, word i = sum_k src[b][k][i] hat[t ns + k]
+// mod q_t, with src pre-scaled by (S/s_k)^-1 in coefficient form.
+constexpr int kMaxBconv = 8;
+struct BconvIn {
+    const uint64_t *src;   // [batch][ns][N]
+    size_t src_bs;
+    int ns;
+    const uint64_t *hat;   // [limbs][ns]
+    const uint64_t *copy;  // limbs [copy_lo, copy_hi) come from here (NTT form), untransformed
+    size_t copy_bs;
+    int copy_lo, copy_hi;
+};
+// ModDown epilogue of a forward NTT over [2 nb][nl][N] (batch z = 2 b + p):
+//   out_p.p[b][i][k] = (acc[z][i][k] - ntt[z][i][k]) P^-1 + add_p.p[b][i][perm0?(k)]
+struct CombineOut {
+    const uint64_t *acc;   // same layout as the transformed buffer
+    const uint64_t *pinv;  // [nl][2]
+    Ptrs add0, add1, out0, out1;
+    int has_add0, has_add1;
+    const uint32_t *perm0;  // applied to add0 only (may be null)
+};
+// Forward NTT of nbatch blocks of nlimbs limbs whose first pass may read a
+// basis conversion (bin) and whose last pass may finish ModDown (cout)
+// instead of storing the transform.
+int ntt_forward_ex(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t bs, hipStream_t s,
+                   int skip_lo, int skip_hi, const BconvIn *bin, const CombineOut *cout);
+
 // dst (contiguous, stride dst_bs words) <- src.p[b] + src_off for b < nb, `words` words each.
 int gather(const Ptrs &src, size_t src_off, uint64_t *dst, size_t dst_bs, size_t words, int nb, hipStream_t s);
 

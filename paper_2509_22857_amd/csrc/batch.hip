@@ -33,31 +33,6 @@ __global__ void k_copy_pp(Ptrs src, Ptrs dst, size_t words) {
         d[k] = sp[k];
 }
 
-// batched fast basis conversion (coefficient form), grid (tiles, targets, batch)
-__global__ __launch_bounds__(256) void k_bconv_b(const uint64_t *__restrict__ src, size_t src_bs, int ns,
-                                                 int src_first, LimbMap src_map, uint64_t *__restrict__ dst,
-                                                 size_t dst_bs, LimbMap dst_map, int skip_lo, int skip_hi,
-                                                 const uint64_t *__restrict__ inv, const uint64_t *__restrict__ invp,
-                                                 const uint64_t *__restrict__ hat, const Prime *__restrict__ primes,
-                                                 int logN) {
-    const int tt = blockIdx.y;
-    if (tt >= skip_lo && tt < skip_hi) return;
-    const size_t N = size_t(1) << logN;
-    const uint64_t *sb = src + blockIdx.z * src_bs;
-    uint64_t *o = dst + blockIdx.z * dst_bs + size_t(tt) * N;
-    const Prime T = primes[dst_map.prime(tt)];
-    const uint64_t *h = hat + size_t(tt) * ns;
-    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        u128v acc{0, 0};
-        for (int i = 0; i < ns; ++i) {
-            const uint64_t si = primes[src_map.prime(src_first + i)].q;
-            const uint64_t y = mul_shoup(sb[size_t(i) * N + k], inv[i], invp[i], si);
-            acc = add128(acc, mul64x64(y, h[i]));
-        }
-        o[k] = reduce128(acc, T);
-    }
-}
-
 constexpr int kMaxDnum = 16;
 
 // key inner product with key reuse across the batch.  A Galois key is stored
@@ -138,30 +113,6 @@ KipFn kip_kernel(int dnum) {
     }
 }
 
-// out_p[b][i] = (acc[b][p][i] - conv[b][p][i]) * P^-1 + add_p[b][perm?(k)]
-__global__ __launch_bounds__(256) void k_moddown_combine_b(const uint64_t *__restrict__ acc,
-                                                           const uint64_t *__restrict__ conv, int nl,
-                                                           const uint64_t *__restrict__ pinv, Ptrs add0, Ptrs add1,
-                                                           int has_add0, int has_add1,
-                                                           const uint32_t *__restrict__ perm0, Ptrs out0, Ptrs out1,
-                                                           const Prime *__restrict__ primes, int logN) {
-    const int i = blockIdx.y, b = blockIdx.z >> 1, p = blockIdx.z & 1;
-    const size_t N = size_t(1) << logN;
-    const uint64_t q = primes[i].q;
-    const uint64_t pv = pinv[2 * i], pvp = pinv[2 * i + 1];
-    const uint64_t *x = acc + (size_t(b) * 2 + p) * nl * N + size_t(i) * N;
-    const uint64_t *cv = conv + (size_t(b) * 2 + p) * nl * N + size_t(i) * N;
-    const bool has = p == 0 ? has_add0 : has_add1;
-    const uint64_t *ad = has ? (p == 0 ? add0.p[b] : add1.p[b]) + size_t(i) * N : nullptr;
-    const uint32_t *pm = p == 0 ? perm0 : nullptr;
-    uint64_t *o = (p == 0 ? out0.p[b] : out1.p[b]) + size_t(i) * N;
-    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        uint64_t r = mul_shoup(sub_mod(x[k], cv[k], q), pv, pvp, q);
-        if (ad) r = add_mod(r, ad[pm ? pm[k] : k], q);
-        o[k] = r;
-    }
-}
-
 // rescale lift for a batch: top[b][p] (coefficient form) -> lift[b][p][i] = centred(top) mod q_i
 __global__ __launch_bounds__(256) void k_rescale_lift_b(const uint64_t *__restrict__ top, int npoly,
                                                         uint64_t *__restrict__ lift, int level,
@@ -234,26 +185,22 @@ int ks_modup_b(ckc_ctx *c, const uint64_t *x, size_t xs, int nb, int level, uint
     const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
     CKC_REQUIRE(dnum <= kMaxDnum, CKC_EUNSUPPORTED, "too many key-switching digits");
     const size_t dig_bs = size_t(dnum) * nt * N;
+    int rc = CKC_OK;
+    const uint64_t *scale = modup_scale(c, level, &rc);
+    if (!scale) return rc;
+    // coefficient form, already multiplied by each limb's (D_j / q_i)^-1
     DevBuf coeff;
     CKC_TRY(coeff.alloc(8 * N * nl * nb, s));
-    CKC_TRY(copy_limbs(x, xs, coeff.u64(), size_t(nl) * N, size_t(nl) * N, nb, s));
-    CKC_TRY(ntt_inverse(c, coeff.u64(), nl, qmap(), nb, size_t(nl) * N, s));
+    CKC_TRY(ntt_inverse(c, coeff.u64(), nl, qmap(), nb, size_t(nl) * N, s, scale, x, xs));
     const LimbMap ext{nl, c->nq};
     for (int j = 0; j < dnum; ++j) {
-        int rc;
         const BconvTable *t = modup_table(c, level, j, &rc);
         if (!t) return rc;
         const int lo = j * c->alpha, ns = t->ns;
-        uint64_t *dj = digits + size_t(j) * nt * N;
-        {
-            CKC_PROF(PK_BCONV, s, 8.0 * N * (ns + nt - ns) * nb, 0.0);
-        hipLaunchKernelGGL(k_bconv_b, dim3(tiles(N), unsigned(nt), unsigned(nb)), dim3(256), 0, s,
-                           coeff.u64() + size_t(lo) * N, size_t(nl) * N, ns, lo, qmap(), dj, dig_bs, ext, lo, lo + ns,
-                           t->inv.u64(), t->invp.u64(), t->hat.u64(), c->dprimes(), c->logN);
-        }
-        CKC_HIP(hipGetLastError());
-        CKC_TRY(ntt_forward(c, dj, nt, ext, nb, dig_bs, s, lo, lo + ns));
-        CKC_TRY(copy_limbs(x + size_t(lo) * N, xs, dj + size_t(lo) * N, dig_bs, N * ns, nb, s));
+        // digit j: its own limbs are those of x; every other limb of Q u P is
+        // the conversion of the digit, transformed
+        const BconvIn in{coeff.u64() + size_t(lo) * N, size_t(nl) * N, ns, t->hat.u64(), x, xs, lo, lo + ns};
+        CKC_TRY(ntt_forward_ex(c, digits + size_t(j) * nt * N, nt, ext, nb, dig_bs, s, -1, -1, &in, nullptr));
     }
     return CKC_OK;
 }
@@ -284,23 +231,16 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
                            nt, nl, key, c->nprimes(), ext, scat, acc.u64(), pl.u64(), c->dprimes(), c->logN);
     }
     CKC_HIP(hipGetLastError());
-    // P limbs of every output (2 nb of them) -> coefficient form -> convert to Q -> NTT
+    // ModDown: P limbs of every output (2 nb of them) to coefficient form,
+    // pre-scaled by (P/p_k)^-1; their conversion to Q feeds the forward NTT,
+    // whose last pass forms (acc - conversion) P^-1 + addend
     const LimbMap pmap{0, c->nq};
-    CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * nb, size_t(np) * N, s));
-    {
-        CKC_PROF(PK_BCONV, s, 8.0 * N * (np + nl) * 2 * nb, 0.0);
-        hipLaunchKernelGGL(k_bconv_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s, pl.u64(),
-                           size_t(np) * N, np, 0, pmap, conv.u64(), size_t(nl) * N, qmap(), -1, -1,
-                           c->p_to_q.inv.u64(), c->p_to_q.invp.u64(), c->p_to_q.hat.u64(), c->dprimes(), c->logN);
-    }
-    CKC_HIP(hipGetLastError());
-    CKC_TRY(ntt_forward(c, conv.u64(), nl, qmap(), 2 * nb, size_t(nl) * N, s));
+    CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * nb, size_t(np) * N, s, c->p_to_q.iscale.u64()));
     Ptrs none{};
-    CKC_PROF(PK_MODDOWN, s, 8.0 * N * nl * 2 * nb * (3.0 + (add0 ? 0.5 : 0) + (add1 ? 0.5 : 0)), 0.0);
-    hipLaunchKernelGGL(k_moddown_combine_b, dim3(tiles(N), unsigned(nl), unsigned(2 * nb)), dim3(256), 0, s,
-                       acc.u64(), conv.u64(), nl, c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none,
-                       add0 ? 1 : 0, add1 ? 1 : 0, perm_add0 ? perm : nullptr, out0, out1, c->dprimes(), c->logN);
-    CKC_HIP(hipGetLastError());
+    const BconvIn in{pl.u64(), size_t(np) * N, np, c->p_to_q.hat.u64(), nullptr, 0, -1, -1};
+    const CombineOut co{acc.u64(), c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none, out0, out1,
+                        add0 ? 1 : 0, add1 ? 1 : 0, perm_add0 ? perm : nullptr};
+    CKC_TRY(ntt_forward_ex(c, conv.u64(), nl, qmap(), 2 * nb, size_t(nl) * N, s, -1, -1, &in, &co));
     return CKC_OK;
 }
 

@@ -113,9 +113,11 @@ struct DevMem {
 //   y_i = [x_i * (S/s_i)^-1]_{s_i};   out_t = sum_i y_i * (S/s_i mod t)  (mod t)
 struct BconvTable {
     int ns = 0, nt = 0;
-    DevMem inv;   // [ns] (S/s_i)^-1 mod s_i
-    DevMem invp;  // [ns] Shoup companions
-    DevMem hat;   // [nt][ns] S/s_i mod t
+    DevMem inv;     // [ns] (S/s_i)^-1 mod s_i
+    DevMem invp;    // [ns] Shoup companions
+    DevMem hat;     // [nt][ns] S/s_i mod t
+    std::vector<uint64_t> iscale_h;  // [ns][2] N^-1 (S/s_i)^-1 mod s_i and its Shoup companion
+    DevMem iscale;  // device copy: the last multiply of an INTT that feeds the conversion
 };
 
 struct ckc_ctx {
@@ -141,6 +143,7 @@ struct ckc_ctx {
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<BconvTable>> modup_tabs;
     std::map<uint64_t, std::unique_ptr<DevMem>> galois_perm;   // NTT-domain permutations
+    std::map<int, std::unique_ptr<DevMem>> modup_scale;        // per level: [l+1][2] INTT scale of ModUp
 
     int nprimes() const { return nq + np; }
     const Prime *dprimes() const { return (const Prime *)primes_d.p; }
@@ -164,8 +167,11 @@ struct ckc_evk {
 // (all asynchronous on the given stream; data pointers are device pointers)
 int ntt_forward(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
                 hipStream_t s, int skip_lo = -1, int skip_hi = -1);
+// inverse transform; scale2 (optional, [nlimbs][2] value + Shoup companion)
+// replaces the final multiply by N^-1 per limb; src (optional) makes it
+// out of place (src batch stride src_bs, same limb layout)
 int ntt_inverse(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
-                hipStream_t s);
+                hipStream_t s, const uint64_t *scale2 = nullptr, const uint64_t *src = nullptr, size_t src_bs = 0);
 
 enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4 };
 // out[p][l] = a[p][l] op b[bp][l] over npoly polys of nlimbs limbs (prime l via map);
@@ -175,6 +181,8 @@ int ew_binary(const ckc_ctx *c, EwOp op, uint64_t *out, const uint64_t *a, const
               hipStream_t s);
 
 const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc);
+// [level+1][2]: for limb i of digit j, N^-1 (D_j/q_i)^-1 mod q_i (+ Shoup)
+const uint64_t *modup_scale(ckc_ctx *c, int level, int *rc);
 const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc);
 uint64_t galois_element(const ckc_ctx *c, int64_t step);
 

@@ -3,7 +3,8 @@
 // Forward: merged-twiddle Cooley-Tukey (the psi twist folded into a
 // bit-reversed table tw[k] = psi^bitrev(k)); natural-order input, output
 // index k holds a(psi^(2 bitrev(k) + 1)).  Inverse: Gentleman-Sande with
-// itw[k] = psi^-bitrev(k), then a multiply by N^-1.
+// itw[k] = psi^-bitrev(k), then a multiply by N^-1 (or by a per-limb
+// constant that already contains N^-1).
 //
 // A limb of N = 2^logN words is split as N1 x N2 with N2 = 256: the stages
 // whose butterfly distance is a multiple of N2 only mix words of one column
@@ -11,7 +12,15 @@
 // contiguous run of N2.  Each pass stages 4096 words (32 KiB) per workgroup
 // through LDS and runs its stages there, so a transform reads and writes the
 // limb twice.
-#include "ckc_internal.h"
+//
+// The passes take their input and give their output through load / store
+// functors, so the key-switching steps around a transform run inside it:
+// the first forward pass can compute its input by fast basis conversion from
+// a few coefficient-form source limbs (ModUp and ModDown), and the last
+// forward pass can finish ModDown ((acc - x) P^-1 + addend) instead of
+// storing x.  The arithmetic of the transform itself is the same in every
+// variant.
+#include "batch.h"
 #include "prof.h"
 
 namespace {
@@ -21,35 +30,23 @@ constexpr int kElems = 4096;
 constexpr int kLogN2 = 8;
 constexpr int kN2 = 1 << kLogN2;
 
-// ---------------------------------------------------------------- columns
-template <bool INVERSE>
-__global__ __launch_bounds__(kThreads) void k_ntt_cols(uint64_t *__restrict__ data, size_t batch_stride,
-                                                       LimbMap map, const Prime *__restrict__ primes,
-                                                       const uint64_t *__restrict__ tw,
-                                                       const uint64_t *__restrict__ twp,
-                                                       const uint64_t *__restrict__ ninv, int logN,
-                                                       int skip_lo, int skip_hi) {
-    __shared__ uint64_t s[kElems];
-    const int limb = blockIdx.y;
-    if (limb >= skip_lo && limb < skip_hi) return;
-    const int pi = map.prime(limb);
-    const uint64_t q = primes[pi].q;
-    const size_t N = size_t(1) << logN;
-    uint64_t *a = data + size_t(blockIdx.z) * batch_stride + size_t(limb) * N;
+// ---------------------------------------------------------------- generic sizes
+// columns pass: stages with distance >= N2.  Loads / stores address words of
+// the limb by index (row * N2 + column).
+template <class Ld, class St>
+__device__ __forceinline__ void cols_generic(Ld ld, St st, bool inverse, uint64_t *s, const uint64_t *W,
+                                             const uint64_t *Wp, uint64_t q, int logN, int col0, uint64_t sc,
+                                             uint64_t scp) {
     const int logN1 = logN - kLogN2;
     const int N1 = 1 << logN1;
     const int logC = 12 - logN1;  // columns per workgroup = kElems / N1
     const int C = 1 << logC;
-    const int col0 = blockIdx.x * C;
-    const uint64_t *W = tw + size_t(pi) * N;
-    const uint64_t *Wp = twp + size_t(pi) * N;
-
     for (int e = threadIdx.x; e < kElems; e += kThreads) {
         const int c = e & (C - 1), r = e >> logC;
-        s[e] = a[size_t(r) * kN2 + col0 + c];
+        s[e] = ld(size_t(r) * kN2 + col0 + c);
     }
     __syncthreads();
-    if (!INVERSE) {
+    if (!inverse) {
         for (int m = 1; m < N1; m <<= 1) {
             const int tr = N1 / (2 * m);
             for (int b = threadIdx.x; b < kElems / 2; b += kThreads) {
@@ -66,7 +63,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt_cols(uint64_t *__restrict__ da
         }
         for (int e = threadIdx.x; e < kElems; e += kThreads) {
             const int c = e & (C - 1), r = e >> logC;
-            a[size_t(r) * kN2 + col0 + c] = s[e];
+            st(size_t(r) * kN2 + col0 + c, s[e]);
         }
     } else {
         for (int tr = 1; tr < N1; tr <<= 1) {
@@ -82,35 +79,21 @@ __global__ __launch_bounds__(kThreads) void k_ntt_cols(uint64_t *__restrict__ da
             }
             __syncthreads();
         }
-        const uint64_t ni = ninv[2 * pi], nip = ninv[2 * pi + 1];
         for (int e = threadIdx.x; e < kElems; e += kThreads) {
             const int c = e & (C - 1), r = e >> logC;
-            a[size_t(r) * kN2 + col0 + c] = mul_shoup(s[e], ni, nip, q);
+            st(size_t(r) * kN2 + col0 + c, mul_shoup(s[e], sc, scp, q));
         }
     }
 }
 
-// ---------------------------------------------------------------- rows
-template <bool INVERSE>
-__global__ __launch_bounds__(kThreads) void k_ntt_rows(uint64_t *__restrict__ data, size_t batch_stride,
-                                                       LimbMap map, const Prime *__restrict__ primes,
-                                                       const uint64_t *__restrict__ tw,
-                                                       const uint64_t *__restrict__ twp, int logN,
-                                                       int skip_lo, int skip_hi) {
-    __shared__ uint64_t s[kElems];
-    const int limb = blockIdx.y;
-    if (limb >= skip_lo && limb < skip_hi) return;
-    const int pi = map.prime(limb);
-    const uint64_t q = primes[pi].q;
-    const size_t N = size_t(1) << logN;
-    const size_t base = size_t(blockIdx.x) * kElems;
-    uint64_t *a = data + size_t(blockIdx.z) * batch_stride + size_t(limb) * N + base;
-    const uint64_t *W = tw + size_t(pi) * N;
-    const uint64_t *Wp = twp + size_t(pi) * N;
-
-    for (int e = threadIdx.x; e < kElems; e += kThreads) s[e] = a[e];
+// rows pass: the last 8 stages inside contiguous runs of 256 words; loads and
+// stores address words of the workgroup's 4096-word tile.
+template <class Ld, class St>
+__device__ __forceinline__ void rows_generic(Ld ld, St st, bool inverse, uint64_t *s, const uint64_t *W,
+                                             const uint64_t *Wp, uint64_t q, size_t N, size_t base) {
+    for (int e = threadIdx.x; e < kElems; e += kThreads) s[e] = ld(e);
     __syncthreads();
-    if (!INVERSE) {
+    if (!inverse) {
         // stages m = N/N2 .. N/2, distance t = N/(2m) = N2/2 .. 1
         for (int t = kN2 / 2; t >= 1; t >>= 1) {
             const size_t m = N / (2 * size_t(t));
@@ -141,9 +124,8 @@ __global__ __launch_bounds__(kThreads) void k_ntt_rows(uint64_t *__restrict__ da
             __syncthreads();
         }
     }
-    for (int e = threadIdx.x; e < kElems; e += kThreads) a[e] = s[e];
+    for (int e = threadIdx.x; e < kElems; e += kThreads) st(e, s[e]);
 }
-
 
 // ---------------------------------------------------------------- radix-16
 // Register-resident variant for N = 2^12 and 2^16.  Every thread holds 16
@@ -200,172 +182,354 @@ __device__ __forceinline__ uint64_t full_reduce4(uint64_t x, uint64_t q, uint64_
     x = x >= q2 ? x - q2 : x;
     return x >= q ? x - q : x;
 }
+__device__ __forceinline__ int lds16(int row, int col) { return row * 16 + col + (row >> 4); }  // N1 = 256, padded
+__device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
 
-// columns pass: the first log2(N1) stages (N1 = N / 256 rows of 256 columns)
-// forward: rows r0 + RS*j (RS = N1/16) then, for N1 = 256, rows 16*r0' + j.
-template <bool INVERSE>
-__global__ __launch_bounds__(kThreads) void k_ntt16_cols(uint64_t *__restrict__ data, size_t batch_stride, LimbMap map,
-                                                         const Prime *__restrict__ primes,
-                                                         const uint64_t *__restrict__ tw,
-                                                         const uint64_t *__restrict__ twp,
-                                                         const uint64_t *__restrict__ ninv, int logN, int skip_lo,
-                                                         int skip_hi) {
-    __shared__ uint64_t s[kElems + 16];
-    const int limb = blockIdx.y;
-    if (limb >= skip_lo && limb < skip_hi) return;
-    const int pi = map.prime(limb);
-    const uint64_t q = primes[pi].q, q2 = 2 * q;
-    const size_t N = size_t(1) << logN;
-    uint64_t *a = data + size_t(blockIdx.z) * batch_stride + size_t(limb) * N;
-    const uint64_t *W = tw + size_t(pi) * N;
-    const uint64_t *Wp = twp + size_t(pi) * N;
+// columns pass, forward: the first log2(N1) stages (N1 = N / 256 rows of 256
+// columns); rows r0 + RS*j (RS = N1/16) then, for N1 = 256, rows 16*r0' + j.
+// Output lazy in [0, 4q).
+template <class Ld, class St>
+__device__ __forceinline__ void cols16_fwd(Ld ld, St st, uint64_t *s, const uint64_t *W, const uint64_t *Wp,
+                                           uint64_t q, size_t N, int col_block) {
+    const uint64_t q2 = 2 * q;
     const int N1 = int(N >> 8);
-    const int RS = N1 >> 4;          // 1 or 16
-    const int C = kElems / N1;       // 256 or 16 columns per workgroup
-    const int col0 = blockIdx.x * C;
+    const int RS = N1 >> 4;     // 1 or 16
+    const int C = kElems / N1;  // 256 or 16 columns per workgroup
+    const int col0 = col_block * C;
     const int tid = threadIdx.x;
     const int c = tid % C, r0 = tid / C;
     uint64_t x[16];
-    auto lds = [](int row, int col) { return row * 16 + col + (row >> 4); };  // N1 = 256 layout, padded
-    if (!INVERSE) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = a[size_t(r0 + RS * j) * kN2 + col0 + c];
-        ct16(x, W, Wp, [](int st, int g) { return size_t((1 << st) + g); }, q, q2);
-        if (N1 == 256) {
+    for (int j = 0; j < 16; ++j) x[j] = ld(size_t(r0 + RS * j) * kN2 + col0 + c);
+    ct16(x, W, Wp, [](int st, int g) { return size_t((1 << st) + g); }, q, q2);
+    if (N1 == 256) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) s[lds(r0 + 16 * j, c)] = x[j];
-            __syncthreads();
+        for (int j = 0; j < 16; ++j) s[lds16(r0 + 16 * j, c)] = x[j];
+        __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 16; ++j) x[j] = s[lds(16 * r0 + j, c)];
-            ct16(x, W, Wp, [r0](int st, int g) { return size_t((16 << st) + (r0 << st) + g); }, q, q2);
+        for (int j = 0; j < 16; ++j) x[j] = s[lds16(16 * r0 + j, c)];
+        ct16(x, W, Wp, [r0](int st, int g) { return size_t((16 << st) + (r0 << st) + g); }, q, q2);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) a[size_t(16 * r0 + j) * kN2 + col0 + c] = x[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) a[size_t(j) * kN2 + col0 + c] = x[j];
-        }
+        for (int j = 0; j < 16; ++j) st(size_t(16 * r0 + j) * kN2 + col0 + c, x[j]);
     } else {
-        const uint64_t ni = ninv[2 * pi], nip = ninv[2 * pi + 1];
-        if (N1 == 256) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) x[j] = a[size_t(16 * r0 + j) * kN2 + col0 + c];
-            gs16(x, W, Wp, [r0](int st, int g) { return size_t((128 >> st) + r0 * (8 >> st) + g); }, q, q2);
-#pragma unroll
-            for (int j = 0; j < 16; ++j) s[lds(16 * r0 + j, c)] = x[j];
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 16; ++j) x[j] = s[lds(r0 + 16 * j, c)];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) x[j] = a[size_t(j) * kN2 + col0 + c];
-        }
-        gs16(x, W, Wp, [](int st, int g) { return size_t((8 >> st) + g); }, q, q2);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) a[size_t(r0 + RS * j) * kN2 + col0 + c] = mul_shoup(x[j], ni, nip, q);
+        for (int j = 0; j < 16; ++j) st(size_t(j) * kN2 + col0 + c, x[j]);
     }
 }
 
-// rows pass: the last 8 stages inside contiguous runs of 256 words.
-// mapping A: element 256 b + x0 + 16 j; mapping B: element 256 b + 16 x0 + j.
-template <bool INVERSE>
-__global__ __launch_bounds__(kThreads) void k_ntt16_rows(uint64_t *__restrict__ data, size_t batch_stride, LimbMap map,
-                                                         const Prime *__restrict__ primes,
-                                                         const uint64_t *__restrict__ tw,
-                                                         const uint64_t *__restrict__ twp, int logN, int skip_lo,
-                                                         int skip_hi) {
+// columns pass, inverse (the last pass of an INTT), output times (sc, scp)
+template <class Ld, class St>
+__device__ __forceinline__ void cols16_inv(Ld ld, St st, uint64_t *s, const uint64_t *W, const uint64_t *Wp,
+                                           uint64_t q, size_t N, int col_block, uint64_t sc, uint64_t scp) {
+    const uint64_t q2 = 2 * q;
+    const int N1 = int(N >> 8);
+    const int RS = N1 >> 4;
+    const int C = kElems / N1;
+    const int col0 = col_block * C;
+    const int tid = threadIdx.x;
+    const int c = tid % C, r0 = tid / C;
+    uint64_t x[16];
+    if (N1 == 256) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = ld(size_t(16 * r0 + j) * kN2 + col0 + c);
+        gs16(x, W, Wp, [r0](int st, int g) { return size_t((128 >> st) + r0 * (8 >> st) + g); }, q, q2);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s[lds16(16 * r0 + j, c)] = x[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = s[lds16(r0 + 16 * j, c)];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = ld(size_t(j) * kN2 + col0 + c);
+    }
+    gs16(x, W, Wp, [](int st, int g) { return size_t((8 >> st) + g); }, q, q2);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) st(size_t(r0 + RS * j) * kN2 + col0 + c, mul_shoup(x[j], sc, scp, q));
+}
+
+// rows pass, forward: the last 8 stages inside runs of 256 words.  mapping A:
+// element 256 b + x0 + 16 j; mapping B: element 256 b + 16 x0 + j.  Output in
+// [0, q), stored through st(tile index, value) from LDS in tile order.
+template <class Ld, class St>
+__device__ __forceinline__ void rows16_fwd(Ld ld, St st, uint64_t *s, const uint64_t *W, const uint64_t *Wp,
+                                           uint64_t q, size_t N, int tile) {
+    const uint64_t q2 = 2 * q;
+    const int tid = threadIdx.x;
+    const int x0 = tid & 15, b = tid >> 4;
+    const size_t G = size_t(tile) * 16 + b;  // global 256-run index
+    const size_t Gp = 16 * G + x0;           // global 16-group index (mapping B)
+    uint64_t x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = ld(256 * b + x0 + 16 * j);
+    const size_t m1 = N >> 8;
+    ct16(x, W, Wp, [m1, G](int st, int g) { return (m1 << st) + (G << st) + g; }, q, q2);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s[pad16(256 * b + x0 + 16 * j)] = x[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = s[pad16(256 * b + 16 * x0 + j)];
+    const size_t m2 = N >> 4;
+    ct16(x, W, Wp, [m2, Gp](int st, int g) { return (m2 << st) + (Gp << st) + g; }, q, q2);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s[pad16(256 * b + 16 * x0 + j)] = full_reduce4(x[j], q, q2);
+    __syncthreads();
+    for (int e = tid; e < kElems; e += kThreads) st(e, s[pad16(e)]);
+}
+
+// rows pass, inverse (the first pass of an INTT); output lazy in [0, 2q)
+template <class Ld, class St>
+__device__ __forceinline__ void rows16_inv(Ld ld, St st, uint64_t *s, const uint64_t *W, const uint64_t *Wp,
+                                           uint64_t q, size_t N, int tile) {
+    const uint64_t q2 = 2 * q;
+    const int tid = threadIdx.x;
+    const int x0 = tid & 15, b = tid >> 4;
+    const size_t G = size_t(tile) * 16 + b;
+    const size_t Gp = 16 * G + x0;
+    uint64_t x[16];
+    for (int e = tid; e < kElems; e += kThreads) s[pad16(e)] = ld(e);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = s[pad16(256 * b + 16 * x0 + j)];
+    const size_t h2 = N >> 1;
+    gs16(x, W, Wp, [h2, Gp](int st, int g) { return (h2 >> st) + Gp * (8 >> st) + g; }, q, q2);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s[pad16(256 * b + 16 * x0 + j)] = x[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = s[pad16(256 * b + x0 + 16 * j)];
+    const size_t h1 = N >> 5;
+    gs16(x, W, Wp, [h1, G](int st, int g) { return (h1 >> st) + G * (8 >> st) + g; }, q, q2);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) st(256 * b + x0 + 16 * j, x[j]);
+}
+
+__device__ __forceinline__ bool radix16(int logN) { return logN == 16 || logN == 12; }
+
+// ---------------------------------------------------------------- kernels
+// grid (N / 4096 tiles, limbs, batch); limbs in [skip_lo, skip_hi) untouched
+__global__ __launch_bounds__(kThreads) void k_fwd_cols(uint64_t *__restrict__ data, size_t bs, LimbMap map,
+                                                       const Prime *__restrict__ primes,
+                                                       const uint64_t *__restrict__ tw,
+                                                       const uint64_t *__restrict__ twp, int logN, int skip_lo,
+                                                       int skip_hi) {
     __shared__ uint64_t s[kElems + kElems / 16];
     const int limb = blockIdx.y;
     if (limb >= skip_lo && limb < skip_hi) return;
     const int pi = map.prime(limb);
-    const uint64_t q = primes[pi].q, q2 = 2 * q;
+    const uint64_t q = primes[pi].q;
+    const size_t N = size_t(1) << logN;
+    uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N;
+    const uint64_t *W = tw + size_t(pi) * N, *Wp = twp + size_t(pi) * N;
+    auto ld = [a](size_t i) { return a[i]; };
+    auto st = [a](size_t i, uint64_t v) { a[i] = v; };
+    if (radix16(logN))
+        cols16_fwd(ld, st, s, W, Wp, q, N, blockIdx.x);
+    else
+        cols_generic(ld, st, false, s, W, Wp, q, logN, blockIdx.x << (12 - (logN - kLogN2)), 0, 0);
+}
+
+// first forward pass fed by fast basis conversion: word i of output limb t is
+//   sum_{k < ns} y_k[i] * hat[t][k]  mod q_t
+// from the pre-scaled coefficient-form source limbs y_k (y = x (S/s_k)^-1 mod
+// s_k); limbs in [copy_lo, copy_hi) are copied from `copy` instead (their NTT
+// form is already known) and left alone by the second pass.
+__global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restrict__ data, size_t bs, LimbMap map,
+                                                             const Prime *__restrict__ primes,
+                                                             const uint64_t *__restrict__ tw,
+                                                             const uint64_t *__restrict__ twp, int logN,
+                                                             BconvIn in) {
+    __shared__ uint64_t s[kElems + kElems / 16];
+    const int limb = blockIdx.y;
+    const size_t N = size_t(1) << logN;
+    uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N;
+    if (limb >= in.copy_lo && limb < in.copy_hi) {
+        // this workgroup's words of the limb, in the same (row, column) tiling
+        const int logN1 = logN - kLogN2;
+        const int logC = 12 - logN1;
+        const int col0 = blockIdx.x << logC;
+        const uint64_t *cp = in.copy + size_t(blockIdx.z) * in.copy_bs + size_t(limb) * N;
+        for (int e = threadIdx.x; e < kElems; e += kThreads) {
+            const size_t i = size_t(e >> logC) * kN2 + col0 + (e & ((1 << logC) - 1));
+            a[i] = cp[i];
+        }
+        return;
+    }
+    const int pi = map.prime(limb);
+    const Prime P = primes[pi];
+    const uint64_t *W = tw + size_t(pi) * N, *Wp = twp + size_t(pi) * N;
+    const uint64_t *src = in.src + size_t(blockIdx.z) * in.src_bs;
+    uint64_t h[kMaxBconv];
+#pragma unroll
+    for (int k = 0; k < kMaxBconv; ++k) h[k] = k < in.ns ? in.hat[size_t(limb) * in.ns + k] : 0;
+    const int ns = in.ns;
+    auto ld = [src, h, ns, N, P](size_t i) {
+        accc acc{0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < kMaxBconv; ++k)
+            if (k < ns) macc(acc, src[size_t(k) * N + i], h[k]);
+        return reduce128(accc_value(acc), P);
+    };
+    auto st = [a](size_t i, uint64_t v) { a[i] = v; };
+    if (radix16(logN))
+        cols16_fwd(ld, st, s, W, Wp, P.q, N, blockIdx.x);
+    else
+        cols_generic(ld, st, false, s, W, Wp, P.q, logN, blockIdx.x << (12 - (logN - kLogN2)), 0, 0);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fwd_rows(uint64_t *__restrict__ data, size_t bs, LimbMap map,
+                                                       const Prime *__restrict__ primes,
+                                                       const uint64_t *__restrict__ tw,
+                                                       const uint64_t *__restrict__ twp, int logN, int skip_lo,
+                                                       int skip_hi) {
+    __shared__ uint64_t s[kElems + kElems / 16];
+    const int limb = blockIdx.y;
+    if (limb >= skip_lo && limb < skip_hi) return;
+    const int pi = map.prime(limb);
+    const uint64_t q = primes[pi].q;
     const size_t N = size_t(1) << logN;
     const size_t base = size_t(blockIdx.x) * kElems;
-    uint64_t *a = data + size_t(blockIdx.z) * batch_stride + size_t(limb) * N + base;
-    const uint64_t *W = tw + size_t(pi) * N;
-    const uint64_t *Wp = twp + size_t(pi) * N;
-    const int tid = threadIdx.x;
-    const int x0 = tid & 15, b = tid >> 4;
-    const size_t G = blockIdx.x * 16 + b;      // global 256-run index
-    const size_t Gp = 16 * G + x0;             // global 16-group index (mapping B)
-    auto pad = [](int e) { return e + (e >> 4); };
-    uint64_t x[16];
-    if (!INVERSE) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = a[256 * b + x0 + 16 * j];
-        const size_t m1 = N >> 8;
-        ct16(x, W, Wp, [m1, G](int st, int g) { return (m1 << st) + (G << st) + g; }, q, q2);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) s[pad(256 * b + x0 + 16 * j)] = x[j];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = s[pad(256 * b + 16 * x0 + j)];
-        const size_t m2 = N >> 4;
-        ct16(x, W, Wp, [m2, Gp](int st, int g) { return (m2 << st) + (Gp << st) + g; }, q, q2);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) s[pad(256 * b + 16 * x0 + j)] = full_reduce4(x[j], q, q2);
-        __syncthreads();
-        for (int e = tid; e < kElems; e += kThreads) a[e] = s[pad(e)];
-    } else {
-        for (int e = tid; e < kElems; e += kThreads) s[pad(e)] = a[e];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = s[pad(256 * b + 16 * x0 + j)];
-        const size_t h2 = N >> 1;
-        gs16(x, W, Wp, [h2, Gp](int st, int g) { return (h2 >> st) + Gp * (8 >> st) + g; }, q, q2);
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) s[pad(256 * b + 16 * x0 + j)] = x[j];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = s[pad(256 * b + x0 + 16 * j)];
-        const size_t h1 = N >> 5;
-        gs16(x, W, Wp, [h1, G](int st, int g) { return (h1 >> st) + G * (8 >> st) + g; }, q, q2);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) a[256 * b + x0 + 16 * j] = x[j];
-    }
+    uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N + base;
+    const uint64_t *W = tw + size_t(pi) * N, *Wp = twp + size_t(pi) * N;
+    auto ld = [a](int e) { return a[e]; };
+    auto st = [a](int e, uint64_t v) { a[e] = v; };
+    if (radix16(logN))
+        rows16_fwd(ld, st, s, W, Wp, q, N, blockIdx.x);
+    else
+        rows_generic(ld, st, false, s, W, Wp, q, N, base);
+}
+
+// last forward pass finishing ModDown: batch index z = 2 b + p, and
+//   out_p[b][i][k] = (acc[z][i][k] - x[k]) P^-1 + add_p[b][i][perm?(k)]
+__global__ __launch_bounds__(kThreads) void k_fwd_rows_combine(const uint64_t *__restrict__ data, size_t bs,
+                                                               const Prime *__restrict__ primes,
+                                                               const uint64_t *__restrict__ tw,
+                                                               const uint64_t *__restrict__ twp, int logN,
+                                                               CombineOut co) {
+    __shared__ uint64_t s[kElems + kElems / 16];
+    const int limb = blockIdx.y;
+    const int b = blockIdx.z >> 1, p = blockIdx.z & 1;
+    const uint64_t q = primes[limb].q;
+    const size_t N = size_t(1) << logN;
+    const size_t base = size_t(blockIdx.x) * kElems;
+    const uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N + base;
+    const uint64_t *W = tw + size_t(limb) * N, *Wp = twp + size_t(limb) * N;
+    const uint64_t *x = co.acc + size_t(blockIdx.z) * bs + size_t(limb) * N + base;
+    const uint64_t pv = co.pinv[2 * limb], pvp = co.pinv[2 * limb + 1];
+    const bool has = p == 0 ? co.has_add0 : co.has_add1;
+    const uint64_t *ad = has ? (p == 0 ? co.add0.p[b] : co.add1.p[b]) + size_t(limb) * N : nullptr;
+    const uint32_t *pm = p == 0 ? co.perm0 : nullptr;
+    uint64_t *o = (p == 0 ? co.out0.p[b] : co.out1.p[b]) + size_t(limb) * N;
+    auto ld = [a](int e) { return a[e]; };
+    auto st = [=](int e, uint64_t v) {
+        const size_t k = base + e;
+        uint64_t r = mul_shoup(sub_mod(x[e], v, q), pv, pvp, q);
+        if (ad) r = add_mod(r, ad[pm ? pm[k] : k], q);
+        o[k] = r;
+    };
+    if (radix16(logN))
+        rows16_fwd(ld, st, s, W, Wp, q, N, blockIdx.x);
+    else
+        rows_generic(ld, st, false, s, W, Wp, q, N, base);
+}
+
+// first inverse pass, reading from src (may equal data: in place)
+__global__ __launch_bounds__(kThreads) void k_inv_rows(uint64_t *__restrict__ data, size_t bs,
+                                                       const uint64_t *src, size_t src_bs, LimbMap map,
+                                                       const Prime *__restrict__ primes,
+                                                       const uint64_t *__restrict__ itw,
+                                                       const uint64_t *__restrict__ itwp, int logN) {
+    __shared__ uint64_t s[kElems + kElems / 16];
+    const int limb = blockIdx.y;
+    const int pi = map.prime(limb);
+    const uint64_t q = primes[pi].q;
+    const size_t N = size_t(1) << logN;
+    const size_t base = size_t(blockIdx.x) * kElems;
+    uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N + base;
+    const uint64_t *in = src + size_t(blockIdx.z) * src_bs + size_t(limb) * N + base;
+    const uint64_t *W = itw + size_t(pi) * N, *Wp = itwp + size_t(pi) * N;
+    auto ld = [in](int e) { return in[e]; };
+    auto st = [a](int e, uint64_t v) { a[e] = v; };
+    if (radix16(logN))
+        rows16_inv(ld, st, s, W, Wp, q, N, blockIdx.x);
+    else
+        rows_generic(ld, st, true, s, W, Wp, q, N, base);
+}
+
+// last inverse pass; output times N^-1, or times scale2[limb] (a pair value,
+// Shoup companion that already contains N^-1)
+__global__ __launch_bounds__(kThreads) void k_inv_cols(uint64_t *__restrict__ data, size_t bs, LimbMap map,
+                                                       const Prime *__restrict__ primes,
+                                                       const uint64_t *__restrict__ itw,
+                                                       const uint64_t *__restrict__ itwp,
+                                                       const uint64_t *__restrict__ ninv,
+                                                       const uint64_t *__restrict__ scale2, int logN) {
+    __shared__ uint64_t s[kElems + kElems / 16];
+    const int limb = blockIdx.y;
+    const int pi = map.prime(limb);
+    const uint64_t q = primes[pi].q;
+    const size_t N = size_t(1) << logN;
+    uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N;
+    const uint64_t *W = itw + size_t(pi) * N, *Wp = itwp + size_t(pi) * N;
+    const uint64_t sc = scale2 ? scale2[2 * limb] : ninv[2 * pi];
+    const uint64_t scp = scale2 ? scale2[2 * limb + 1] : ninv[2 * pi + 1];
+    auto ld = [a](size_t i) { return a[i]; };
+    auto st = [a](size_t i, uint64_t v) { a[i] = v; };
+    if (radix16(logN))
+        cols16_inv(ld, st, s, W, Wp, q, N, blockIdx.x, sc, scp);
+    else
+        cols_generic(ld, st, true, s, W, Wp, q, logN, blockIdx.x << (12 - (logN - kLogN2)), sc, scp);
 }
 
 }  // namespace
 
-int ntt_forward(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
-                hipStream_t s, int skip_lo, int skip_hi) {
+int ntt_forward_ex(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t bs, hipStream_t s,
+                   int skip_lo, int skip_hi, const BconvIn *bin, const CombineOut *cout) {
     if (nlimbs <= 0 || nbatch <= 0) return CKC_OK;
-    CKC_REQUIRE(c->logN >= 12 && c->logN <= 17, CKC_EUNSUPPORTED, "NTT supports 2^12 <= N <= 2^17");
-    dim3 grid(unsigned(c->N / kElems), unsigned(nlimbs), unsigned(nbatch));
-    const int active = nlimbs - ((skip_lo >= 0 && skip_hi > skip_lo) ? (skip_hi - skip_lo) : 0);
-    CKC_PROF(PK_NTT_FWD, s, 16.0 * double(c->N) * active * nbatch, 0.5 * double(c->N) * c->logN * active * nbatch);
-    if (c->logN == 16 || c->logN == 12) {
-        hipLaunchKernelGGL(k_ntt16_cols<false>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
-                           c->tw.u64(), c->twp.u64(), c->ninv.u64(), c->logN, skip_lo, skip_hi);
-        hipLaunchKernelGGL(k_ntt16_rows<false>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
-                           c->tw.u64(), c->twp.u64(), c->logN, skip_lo, skip_hi);
-    } else {
-        hipLaunchKernelGGL(k_ntt_cols<false>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
-                           c->tw.u64(), c->twp.u64(), c->ninv.u64(), c->logN, skip_lo, skip_hi);
-        hipLaunchKernelGGL(k_ntt_rows<false>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
-                           c->tw.u64(), c->twp.u64(), c->logN, skip_lo, skip_hi);
+    CKC_REQUIRE(c->logN >= 12 && c->logN <= 16, CKC_EUNSUPPORTED, "NTT supports 2^12 <= N <= 2^16");
+    CKC_REQUIRE(!bin || (bin->ns >= 1 && bin->ns <= kMaxBconv), CKC_EUNSUPPORTED, "too many basis-conversion sources");
+    const dim3 grid(unsigned(c->N / kElems), unsigned(nlimbs), unsigned(nbatch));
+    const int lo = bin ? bin->copy_lo : skip_lo, hi = bin ? bin->copy_hi : skip_hi;
+    const int active = nlimbs - ((lo >= 0 && hi > lo) ? (hi - lo) : 0);
+    {
+        // algorithmic bytes: the source limbs once (basis conversion) or the
+        // limb, the limb written, and the combine's operands
+        const double W = 8.0 * double(c->N) * nbatch;
+        const double src = bin ? double(bin->ns) + 2.0 * (nlimbs - active) : double(active);
+        const double epi = cout ? 2.5 * active : 1.0 * active;
+        CKC_PROF(PK_NTT_FWD, s, W * (src + epi), 0.5 * double(c->N) * c->logN * active * nbatch);
+        if (bin)
+            hipLaunchKernelGGL(k_fwd_cols_bconv, grid, dim3(kThreads), 0, s, d, bs, map, c->dprimes(), c->tw.u64(),
+                               c->twp.u64(), c->logN, *bin);
+        else
+            hipLaunchKernelGGL(k_fwd_cols, grid, dim3(kThreads), 0, s, d, bs, map, c->dprimes(), c->tw.u64(),
+                               c->twp.u64(), c->logN, skip_lo, skip_hi);
+        if (cout)
+            hipLaunchKernelGGL(k_fwd_rows_combine, grid, dim3(kThreads), 0, s, d, bs, c->dprimes(), c->tw.u64(),
+                               c->twp.u64(), c->logN, *cout);
+        else
+            hipLaunchKernelGGL(k_fwd_rows, grid, dim3(kThreads), 0, s, d, bs, map, c->dprimes(), c->tw.u64(),
+                               c->twp.u64(), c->logN, lo, hi);
     }
     CKC_HIP(hipGetLastError());
     return CKC_OK;
 }
 
+int ntt_forward(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
+                hipStream_t s, int skip_lo, int skip_hi) {
+    return ntt_forward_ex(c, d, nlimbs, map, nbatch, batch_stride, s, skip_lo, skip_hi, nullptr, nullptr);
+}
+
 int ntt_inverse(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
-                hipStream_t s) {
+                hipStream_t s, const uint64_t *scale2, const uint64_t *src, size_t src_bs) {
     if (nlimbs <= 0 || nbatch <= 0) return CKC_OK;
-    CKC_REQUIRE(c->logN >= 12 && c->logN <= 17, CKC_EUNSUPPORTED, "NTT supports 2^12 <= N <= 2^17");
-    dim3 grid(unsigned(c->N / kElems), unsigned(nlimbs), unsigned(nbatch));
+    CKC_REQUIRE(c->logN >= 12 && c->logN <= 16, CKC_EUNSUPPORTED, "NTT supports 2^12 <= N <= 2^16");
+    const dim3 grid(unsigned(c->N / kElems), unsigned(nlimbs), unsigned(nbatch));
     CKC_PROF(PK_NTT_INV, s, 16.0 * double(c->N) * nlimbs * nbatch, 0.5 * double(c->N) * c->logN * nlimbs * nbatch);
-    if (c->logN == 16 || c->logN == 12) {
-        hipLaunchKernelGGL(k_ntt16_rows<true>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
-                           c->itw.u64(), c->itwp.u64(), c->logN, -1, -1);
-        hipLaunchKernelGGL(k_ntt16_cols<true>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
-                           c->itw.u64(), c->itwp.u64(), c->ninv.u64(), c->logN, -1, -1);
-    } else {
-        hipLaunchKernelGGL(k_ntt_rows<true>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
-                           c->itw.u64(), c->itwp.u64(), c->logN, -1, -1);
-        hipLaunchKernelGGL(k_ntt_cols<true>, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(),
-                           c->itw.u64(), c->itwp.u64(), c->ninv.u64(), c->logN, -1, -1);
-    }
+    hipLaunchKernelGGL(k_inv_rows, grid, dim3(kThreads), 0, s, d, batch_stride, src ? src : d,
+                       src ? src_bs : batch_stride, map, c->dprimes(), c->itw.u64(), c->itwp.u64(), c->logN);
+    hipLaunchKernelGGL(k_inv_cols, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(), c->itw.u64(),
+                       c->itwp.u64(), c->ninv.u64(), scale2, c->logN);
     CKC_HIP(hipGetLastError());
     return CKC_OK;
 }

@@ -187,6 +187,13 @@ const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc) {
     }
     t->ns = ns;
     t->nt = nt;
+    t->iscale_h.resize(2 * size_t(ns));
+    for (int i = 0; i < ns; ++i) {
+        const uint64_t qi = c->mods[lo + i];
+        t->iscale_h[2 * i] = h_mulmod(h_inv(c->N % qi, qi), inv[i], qi);
+        t->iscale_h[2 * i + 1] = h_shoup(t->iscale_h[2 * i], qi);
+    }
+    if ((*rc = t->iscale.upload(t->iscale_h.data(), 8 * t->iscale_h.size())) != CKC_OK) return nullptr;
     if ((*rc = t->inv.upload(inv.data(), 8 * ns)) != CKC_OK) return nullptr;
     if ((*rc = t->invp.upload(invp.data(), 8 * ns)) != CKC_OK) return nullptr;
     if ((*rc = t->hat.upload(hat.data(), 8 * hat.size())) != CKC_OK) return nullptr;
@@ -194,6 +201,27 @@ const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc) {
     c->modup_tabs[key] = std::move(t);
     *rc = CKC_OK;
     return r;
+}
+
+const uint64_t *modup_scale(ckc_ctx *c, int level, int *rc) {
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        auto it = c->modup_scale.find(level);
+        if (it != c->modup_scale.end()) return it->second->u64();
+    }
+    std::vector<uint64_t> v;
+    for (int j = 0; j < c->dnum_at(level); ++j) {
+        const BconvTable *t = modup_table(c, level, j, rc);
+        if (!t) return nullptr;
+        v.insert(v.end(), t->iscale_h.begin(), t->iscale_h.end());
+    }
+    auto m = std::make_unique<DevMem>();
+    if ((*rc = m->upload(v.data(), 8 * v.size())) != CKC_OK) return nullptr;
+    std::lock_guard<std::mutex> g(c->mu);
+    auto &slot = c->modup_scale[level];
+    if (!slot) slot = std::move(m);
+    *rc = CKC_OK;
+    return slot->u64();
 }
 
 uint64_t galois_element(const ckc_ctx *c, int64_t step) {

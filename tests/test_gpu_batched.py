@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from workloads import gen
-from workloads.params import ParamSet, balanced_chain, tiny, micro
+from workloads.params import ParamSet, balanced_chain, tiny, mid, micro
 
 pytestmark = pytest.mark.gpu
 
@@ -42,11 +42,12 @@ def _cts(ctx, ps, seeds, level, scale=1.0):
     ("wide", 9, 3, [1, -4]),             # dnum 10: generic digit loop
     ("micro", 23, 3, [-33, 0, 1]),       # dnum 8 at the top level
     ("micro", 19, 2, [1]),               # dnum 7
+    ("mid", 3, 3, [1, -2, 0]),           # N = 2^13: the transforms' generic path
 ])
 def test_rotate_many_bit_exact(which, level, n, steps):
     from oracle.ckks import Ct
     from paper_2509_22857_amd import ckks
-    ps = {"tiny": tiny, "wide": wide_digits, "micro": micro}[which]()
+    ps = {"tiny": tiny, "wide": wide_digits, "micro": micro, "mid": mid}[which]()
     ctx, orc, torch = _setup(ps)
     seed = 31
     keys = ctx.keygen(seed, [s for s in steps if s])
@@ -70,11 +71,11 @@ def test_rotate_many_bit_exact(which, level, n, steps):
             assert np.array_equal(ctx.ct_to_coeff(got), want.data), (i, r)
 
 
-@pytest.mark.parametrize("which,level,n", [("tiny", 2, 66), ("wide", 6, 2), ("micro", 23, 2)])
+@pytest.mark.parametrize("which,level,n", [("tiny", 2, 66), ("wide", 6, 2), ("micro", 23, 2), ("mid", 2, 3)])
 def test_mul_relin_many_bit_exact(which, level, n):
     from oracle.ckks import Ct
     from paper_2509_22857_amd import ckks
-    ps = {"tiny": tiny, "wide": wide_digits, "micro": micro}[which]()
+    ps = {"tiny": tiny, "wide": wide_digits, "micro": micro, "mid": mid}[which]()
     ctx, orc, torch = _setup(ps)
     seed = 77
     keys = ctx.keygen(seed, [])

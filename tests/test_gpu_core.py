@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from workloads import gen
-from workloads.params import tiny, micro
+from workloads.params import tiny, mid, micro
 
 pytestmark = pytest.mark.gpu
 
@@ -28,12 +28,12 @@ def _eval(a, x, q):
     return v
 
 
-@pytest.fixture(scope="module", params=["tiny", "micro"])
+@pytest.fixture(scope="module", params=["tiny", "mid", "micro"])
 def env(request):
     import torch
     from paper_2509_22857_amd.ckks import Context
     from oracle.ckks import Oracle
-    ps = tiny() if request.param == "tiny" else micro()
+    ps = {"tiny": tiny, "mid": mid, "micro": micro}[request.param]()
     print(f"[env] params={ps.name} N={ps.N} nq={len(ps.q)} np={len(ps.p)}", flush=True)
     ctx = Context.from_params(ps)
     orc = Oracle.from_params(ps)
@@ -60,7 +60,7 @@ def test_ntt_evaluation_order_and_roundtrip(env):
 
 def test_mul_plain_matches_oracle_products(env):
     ps, ctx, orc, torch = env
-    level = len(ps.q) - 1 if ps.name == "tiny" else 3
+    level = len(ps.q) - 1 if ps.name == "tiny" else min(3, len(ps.q) - 1)
     ct = gen.random_ct(7, ps.q, level, ps.N)
     pt = gen.random_limbs(8, ps.q[:level + 1], ps.N)
     g = ctx.mul_plain(ctx.ct_from_coeff(ct, level, 1.0), ctx.pt_from_coeff(pt, level, 1.0))
@@ -111,7 +111,7 @@ def test_tensor_relin_rescale_bit_exact(env):
     seed = 99
     keys = ctx.keygen(seed, [])
     sk = orc.secret_key(seed)
-    level = len(ps.q) - 1 if ps.name == "tiny" else 5
+    level = len(ps.q) - 1 if ps.name == "tiny" else min(5, len(ps.q) - 1)
     a = gen.random_ct(11, ps.q, level, ps.N)
     b = gen.random_ct(12, ps.q, level, ps.N)
     ga, gb = ctx.ct_from_coeff(a, level, 2.0 ** 40), ctx.ct_from_coeff(b, level, 2.0 ** 40)
@@ -134,7 +134,7 @@ def test_hoisted_rotations_bit_exact(env):
     steps = [1, -1, 31, 0] if ps.name == "tiny" else [1, -33]
     keys = ctx.keygen(seed, steps)
     sk = orc.secret_key(seed)
-    level = len(ps.q) - 1 if ps.name == "tiny" else 4
+    level = len(ps.q) - 1 if ps.name == "tiny" else min(4, len(ps.q) - 1)
     a = gen.random_ct(13, ps.q, level, ps.N)
     outs = ctx.rotate(keys, ctx.ct_from_coeff(a, level, 1.0), steps)
     for r, o in zip(steps, outs):
@@ -147,7 +147,7 @@ def test_hoisted_rotations_bit_exact(env):
 def test_add_const_mod_drop_add_plain(env):
     ps, ctx, orc, torch = env
     from oracle.ckks import Ct, Pt
-    level = len(ps.q) - 1 if ps.name == "tiny" else 3
+    level = len(ps.q) - 1 if ps.name == "tiny" else min(3, len(ps.q) - 1)
     a = gen.random_ct(21, ps.q, level, ps.N)
     b = gen.random_ct(22, ps.q, level, ps.N)
     s = 2.0 ** 70

@@ -136,6 +136,18 @@ def tiny() -> ParamSet:
 
 
 @lru_cache(maxsize=None)
+def mid() -> ParamSet:
+    """Parity case for ring sizes other than 2^12 and 2^16 (the transforms'
+    generic path): N=2^13, four 45-bit Q primes, two 50-bit P primes, two
+    primes per digit."""
+    two_n = 2 << 13
+    q = balanced_chain([45] * 4, two_n)
+    p = balanced_chain([50] * 2, two_n, exclude=q)
+    return ParamSet("mid", 13, tuple(q), tuple(p), alpha=2, delta_log2=40,
+                    note="test-only, not secure")
+
+
+@lru_cache(maxsize=None)
 def micro() -> ParamSet:
     """Kernel microbenchmark: N=2^16, 24 Q primes of 50 bits, 3 P primes of
     50 bits, three primes per digit (dnum = 8)."""
@@ -178,7 +190,7 @@ def small_tower(logN: int = 12, levels: int = 4, big_bits: int = 60,
 
 
 def by_name(name: str) -> ParamSet:
-    table = {"tiny": tiny, "micro": micro}
+    table = {"tiny": tiny, "mid": mid, "micro": micro}
     if name in table:
         return table[name]()
     raise KeyError(name)
