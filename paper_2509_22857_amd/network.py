@@ -148,6 +148,16 @@ class GpuNetwork:
                     steps.update(e.steps())
             self.layers.append(entry)
         self.steps = sorted(steps)
+        # tensors read by the layers after each layer
+        self._later = {}
+        lys = self.spec["layers"]
+        for i, ly in enumerate(lys):
+            later = set()
+            for l2 in lys[i + 1:]:
+                later.add(l2["inp"])
+                if l2.get("short"):
+                    later.add(l2["short"]["inp"])
+            self._later[ly["name"]] = later
 
     def device_bytes(self) -> int:
         return sum(e.nbytes() for ent in self.layers for e in ent.values() if e is not None)
@@ -200,52 +210,118 @@ class GpuNetwork:
                 o, tensors = self.run(keys, inputs[i:i + images_per_pass], stream, keep, hook)
                 outs.extend(o)
             return outs, tensors
+        it = self.stages(keys, inputs, stream, keep, hook)
+        while True:
+            try:
+                next(it)
+            except StopIteration as stop:
+                return stop.value
+
+    def stages(self, keys: ckks.KeyPair, inputs, stream=None, keep=False, hook=None):
+        """Generator form of run(): each step enqueues one layer (all images)
+        on `stream` and yields the layer's name; the generator's return value
+        is run()'s.  Buffers of a step are allocated on `stream`, so steps of
+        different generators may interleave on different streams."""
+        import torch
         ctx = self.ctx
         n_img = len(inputs)
         tensors = {"x": [c for row in inputs for c in row]}
+        scope = torch.cuda.stream(stream) if stream is not None else _NoScope()
         for ly, p, ent in zip(self.spec["layers"], self.plans, self.layers):
-            xin = tensors[ly["inp"]]
-            op = ly["op"]
-            if op == "conv":
-                O = ly["out_ch"]
-                outs = [ctx.new_ct(p.level) for _ in range(n_img * O)]
-                ckks.eval_conv(ctx, keys, ent["main"], xin, n_img, outs, stream)
-                if ent["short"] is not None:
-                    xs = tensors[ly["short"]["inp"]]
-                    if xs[0].level != p.short_level:
-                        xs = [ctx.mod_drop(c, p.short_level, stream=stream) for c in xs]
-                    souts = [ctx.new_ct(p.short_level) for _ in range(n_img * O)]
-                    ckks.eval_conv(ctx, keys, ent["short"], xs, n_img, souts, stream)
-                    ckks.add_many(ctx, outs, souts, outs, stream)
-            elif op == "act":
-                outs = [ctx.new_ct(p.level) for _ in range(len(xin))]
-                ckks.eval_quad_act(ctx, keys, ent["main"], xin, n_img, outs, stream)
-            elif op == "dense":
-                K = ly["w"].shape[1]
-                outs = [ctx.new_ct(p.level) for _ in range(n_img * K)]
-                ckks.eval_dense(ctx, keys, ent["main"], xin, n_img, outs, stream)
-            elif op == "pool":
-                outs = [ctx.new_ct(p.level) for _ in range(len(xin))]
-                ckks.eval_avgpool2(ctx, keys, self.layouts[ly["inp"]], xin, outs, stream)
-            if p.rescale:
-                r = [ctx.new_ct(p.level - 1) for _ in range(len(outs))]
-                ckks.rescale_many(ctx, outs, r, stream)
-                outs = r
+            with scope:
+                outs = self._layer(keys, ly, p, ent, tensors, n_img, stream)
             tensors[ly["out"]] = outs
             if hook is not None:
                 hook(ly, outs)
             if not keep:
                 # drop tensors no later layer reads
-                later = set()
-                idx = self.spec["layers"].index(ly)
-                for l2 in self.spec["layers"][idx + 1:]:
-                    later.add(l2["inp"])
-                    if l2.get("short"):
-                        later.add(l2["short"]["inp"])
                 for name in list(tensors):
-                    if name not in later and name != ly["out"]:
+                    if name not in self._later[ly["name"]] and name != ly["out"]:
                         del tensors[name]
+            yield ly["name"]
         last = self.spec["layers"][-1]["out"]
         flat = tensors[last]
         per = len(flat) // n_img
         return [flat[i * per:(i + 1) * per] for i in range(n_img)], tensors
+
+    def _layer(self, keys, ly, p, ent, tensors, n_img, stream):
+        ctx = self.ctx
+        xin = tensors[ly["inp"]]
+        op = ly["op"]
+        if op == "conv":
+            O = ly["out_ch"]
+            outs = [ctx.new_ct(p.level) for _ in range(n_img * O)]
+            ckks.eval_conv(ctx, keys, ent["main"], xin, n_img, outs, stream)
+            if ent["short"] is not None:
+                xs = tensors[ly["short"]["inp"]]
+                if xs[0].level != p.short_level:
+                    xs = [ctx.mod_drop(c, p.short_level, stream=stream) for c in xs]
+                souts = [ctx.new_ct(p.short_level) for _ in range(n_img * O)]
+                ckks.eval_conv(ctx, keys, ent["short"], xs, n_img, souts, stream)
+                ckks.add_many(ctx, outs, souts, outs, stream)
+        elif op == "act":
+            outs = [ctx.new_ct(p.level) for _ in range(len(xin))]
+            ckks.eval_quad_act(ctx, keys, ent["main"], xin, n_img, outs, stream)
+        elif op == "dense":
+            K = ly["w"].shape[1]
+            outs = [ctx.new_ct(p.level) for _ in range(n_img * K)]
+            ckks.eval_dense(ctx, keys, ent["main"], xin, n_img, outs, stream)
+        elif op == "pool":
+            outs = [ctx.new_ct(p.level) for _ in range(len(xin))]
+            ckks.eval_avgpool2(ctx, keys, self.layouts[ly["inp"]], xin, outs, stream)
+        else:
+            raise ValueError(f"unknown layer op {op}")
+        if p.rescale:
+            r = [ctx.new_ct(p.level - 1) for _ in range(len(outs))]
+            ckks.rescale_many(ctx, outs, r, stream)
+            outs = r
+        return outs
+
+    def working_set_bytes(self, n_img: int) -> int:
+        """Upper estimate of the device bytes one pass of n_img images holds at
+        once: the live tensors around every layer plus that layer's scratch
+        (rotated inputs, digits and key-switching buffers of one batch of 64)."""
+        N = self.ctx.N
+        np_ = len(self.ctx.p)
+        ct = lambda level, npoly=2: 8 * npoly * (level + 1) * N
+        level_of = {"x": len(self.ctx.q) - 1}
+        count_of = {"x": self.spec["image"][0]}
+        peak = 0
+        live = {"x"}
+        for ly, p in zip(self.spec["layers"], self.plans):
+            lvl = p.level
+            out_lvl = p.level - 1 if p.rescale else p.level
+            if ly["op"] == "conv":
+                cnt = ly["out_ch"]
+            elif ly["op"] == "dense":
+                cnt = ly["w"].shape[1]
+            else:
+                cnt = count_of[ly["inp"]]
+            level_of[ly["out"]], count_of[ly["out"]] = out_lvl, cnt
+            held = sum(n_img * count_of[t] * ct(level_of[t]) for t in live)
+            held += n_img * cnt * ct(lvl) * (2 if p.rescale else 1)
+            nl, nt = lvl + 1, lvl + 1 + np_
+            dnum = -(-nl // self.ctx.alpha)
+            ks = 64 * 8 * N * (dnum * nt + 2 * nl + 2 * np_ + 2 * nl + nl)
+            if ly["op"] == "conv":
+                I, taps = ly["in_ch"], ly["ksize"] ** 2
+                chunk = max(4, 64 // I)
+                scratch = min(chunk, n_img) * I * taps * ct(lvl) + ks
+                if ly.get("short") is not None:
+                    held += n_img * cnt * ct(p.short_level)
+            elif ly["op"] == "act":
+                scratch = 64 * ct(lvl, 3) + ks
+            else:
+                scratch = 2 * n_img * cnt * ct(lvl) + ks
+            peak = max(peak, held + scratch)
+            live = set(self._later[ly["name"]]) | {ly["out"]}
+            live = {t for t in live if t in level_of}
+        return int(peak * 1.1)
+
+
+class _NoScope:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False

@@ -1,0 +1,196 @@
+"""Serving loop: continuous batching of encrypted inference requests.
+
+A request is one client's encrypted image(s) for one of the served networks.
+The server holds every network's layers and every registered client's
+evaluation keys on the device, and runs a single host loop that
+
+  * admits queued requests in arrival order while the HBM budget covers the
+    working set of the batch they would start (keys are already resident);
+  * merges queued requests of the same client and network into one batch
+    (their images share every key-switching and contraction launch);
+  * runs every admitted batch on its own HIP stream, one layer per step, with
+    at most `window` layers enqueued ahead of the GPU, so batches admitted
+    while others are on the device overlap with them;
+  * retires a batch when its last layer's event has completed and releases
+    its memory reservation, which lets the next queued requests in.
+
+Each image's result does not depend on which other requests shared its batch
+or ran beside it (every kernel computes each ciphertext independently), so a
+request gives the same ciphertexts alone and in the mix.  Latency is measured
+from arrival to the moment the host sees the batch's last event complete.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import ckks
+
+
+@dataclass
+class Request:
+    rid: int
+    client: str
+    net: str
+    inputs: list            # [n_img][C] ciphertexts (resident)
+    arrival: float          # seconds on the loop clock
+    admitted: float | None = None
+    done: float | None = None
+    outputs: list | None = None
+    batch_id: int | None = None
+
+
+@dataclass
+class _Batch:
+    bid: int
+    net: str
+    client: str
+    reqs: list
+    stream: object
+    gen: object
+    reserve: int
+    events: collections.deque = field(default_factory=collections.deque)
+    finished: bool = False
+    result: object = None
+
+
+class Server:
+    """networks: name -> GpuNetwork; clients are registered with their keys."""
+
+    def __init__(self, networks: dict, budget_bytes: int, max_images: int = 16, n_streams: int = 4,
+                 window: int = 2):
+        import torch
+        self.torch = torch
+        self.networks = networks
+        self.budget = int(budget_bytes)
+        self.max_images = max_images
+        self.window = window
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.keys = {}          # (client, net) -> KeyPair
+        self.reserved = 0
+        self.key_bytes = 0
+        self.stats = collections.Counter()
+
+    def register_client(self, client: str, net: str, keys: ckks.KeyPair):
+        nbytes = keys.evk_bytes()
+        if self.key_bytes + nbytes > self.budget:
+            raise MemoryError(f"keys of client {client} do not fit the HBM budget")
+        self.keys[(client, net)] = keys
+        self.key_bytes += nbytes
+
+    # ------------------------------------------------------------------ loop
+    def serve(self, requests: list, clock=time.perf_counter) -> dict:
+        """Replay `requests` (sorted by arrival, seconds from the start) in
+        real time and return per-request timing plus aggregate statistics."""
+        torch = self.torch
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue = collections.deque()
+        running: list[_Batch] = []
+        free_streams = list(self.streams)
+        t0 = clock()
+        next_bid = 0
+        max_running = 0
+        waiting = None
+        while pending or queue or running:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            progressed = False
+            # ---- admission: FIFO head, merged with later requests of the same client and network
+            while queue and free_streams:
+                head = queue[0]
+                net = self.networks[head.net]
+                group, n_img = [], 0
+                for r in list(queue):
+                    if r.client == head.client and r.net == head.net and n_img + len(r.inputs) <= self.max_images:
+                        group.append(r)
+                        n_img += len(r.inputs)
+                need = net.working_set_bytes(n_img)
+                if need > self.budget - self.key_bytes:
+                    # can never run: reject the head request
+                    queue.popleft()
+                    head.done = float("nan")
+                    self.stats["rejected"] += 1
+                    continue
+                if self.reserved + need > self.budget - self.key_bytes:
+                    if waiting != head.rid:
+                        self.stats["waits_for_memory"] += 1  # requests that had to wait
+                        waiting = head.rid
+                    break
+                for r in group:
+                    queue.remove(r)
+                    r.admitted = now
+                    r.batch_id = next_bid
+                stream = free_streams.pop()
+                # inputs were written on the submitting stream
+                stream.wait_stream(torch.cuda.current_stream())
+                inputs = [row for r in group for row in r.inputs]
+                b = _Batch(next_bid, head.net, head.client, group, stream,
+                           net.stages(self.keys[(head.client, head.net)], inputs, stream=stream), need)
+                next_bid += 1
+                self.reserved += need
+                running.append(b)
+                max_running = max(max_running, len(running))
+                progressed = True
+            # ---- progress: keep up to `window` layers of every batch enqueued
+            for b in running:
+                while b.events and b.events[0].query():
+                    b.events.popleft()
+                while not b.finished and len(b.events) < self.window:
+                    try:
+                        next(b.gen)
+                    except StopIteration as stop:
+                        b.finished = True
+                        b.result = stop.value
+                    ev = torch.cuda.Event()
+                    ev.record(b.stream)
+                    b.events.append(ev)
+                    progressed = True
+            # ---- retire
+            for b in list(running):
+                if b.finished and all(e.query() for e in b.events):
+                    t_done = clock() - t0
+                    outs = b.result[0]
+                    i = 0
+                    for r in b.reqs:
+                        r.outputs = outs[i:i + len(r.inputs)]
+                        i += len(r.inputs)
+                        r.done = t_done
+                    running.remove(b)
+                    free_streams.append(b.stream)
+                    self.reserved -= b.reserve
+                    progressed = True
+            if not progressed:
+                # nothing to enqueue: wait a little for the GPU or the next arrival
+                wait = 5e-4
+                if pending and not queue and not running:
+                    wait = max(0.0, min(0.05, pending[0].arrival - (clock() - t0)))
+                time.sleep(wait)
+        served = [r for r in requests if r.done is not None and not math.isnan(r.done)]
+        lat = np.array([r.done - r.arrival for r in served]) if served else np.zeros(1)
+        span = (max(r.done for r in served) - min(r.arrival for r in requests)) if served else float("nan")
+        n_images = sum(len(r.inputs) for r in served)
+        return {
+            "requests": len(requests),
+            "served": len(served),
+            "rejected": int(self.stats["rejected"]),
+            "waits_for_memory": int(self.stats["waits_for_memory"]),
+            "batches": next_bid,
+            "max_concurrent_batches": max_running,
+            "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()),
+            "images_per_s": n_images / span if span and span > 0 else float("nan"),
+            "span_s": span,
+        }
+
+
+def poisson_arrivals(rate: float, n: int, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process of `rate` requests/s:
+    cumulative sums of seeded exponential gaps."""
+    g = np.random.default_rng(seed)
+    return np.cumsum(g.exponential(1.0 / rate, n))

@@ -1,0 +1,112 @@
+"""Serving loop on the GPU: continuous batching of requests from several
+clients for two networks, checked against running every request alone.
+
+* every output ciphertext of every request is bit-identical alone and in the
+  mix (merged batches, concurrent streams);
+* decrypted logits stay within 1e-3 of the FP64 forward;
+* a budget that fits one batch at a time still serves everything (requests
+  wait for memory), and a budget below any batch's working set rejects.
+"""
+import numpy as np
+import pytest
+
+from workloads import gen, nets
+from workloads.params import small_tower
+
+pytestmark = pytest.mark.gpu
+
+D = 2.0 ** 30
+
+
+@pytest.fixture(scope="module")
+def world():
+    import torch
+    from paper_2509_22857_amd.ckks import Context
+    from paper_2509_22857_amd.network import GpuNetwork
+    ps = small_tower(logN=12, levels=6)
+    ctx = Context.from_params(ps)
+    specs = {
+        "A": nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8,
+                              calib=4),
+        "B": nets.resnet_spec(seed=2, members=1, widths=(4,), blocks=1, classes=5, image=(3, 16, 16), k=4, calib=4),
+    }
+    networks = {n: GpuNetwork(ctx, s, D, D, D) for n, s in specs.items()}
+    clients = {("c0", "A"): 11, ("c1", "A"): 12, ("c2", "B"): 13, ("c0", "B"): 14}
+    keys = {cn: ctx.keygen(seed, networks[cn[1]].steps) for cn, seed in clients.items()}
+    print(f"[serving] N=2^12, nets {list(specs)}, clients {len(clients)}", flush=True)
+    return torch, ctx, specs, networks, keys
+
+
+def _requests(world, n, rate, seed):
+    from paper_2509_22857_amd.serving import Request, poisson_arrivals
+    torch, ctx, specs, networks, keys = world
+    arr = poisson_arrivals(rate, n, seed)
+    g = np.random.default_rng(seed)
+    combos = sorted(keys)
+    reqs = []
+    for i in range(n):
+        client, net = combos[int(g.integers(len(combos)))]
+        img = gen.images(1000 + seed * 100 + i, 1, *specs[net]["image"])
+        cts = networks[net].encrypt_images(keys[(client, net)], img, stream_base=(seed * 100 + i) << 12)
+        reqs.append((Request(i, client, net, cts, float(arr[i])), img[0]))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def _words(cts):
+    return [c.buf.clone() for c in cts]
+
+
+def test_alone_vs_mix_bit_identical_and_accurate(world):
+    from paper_2509_22857_amd.serving import Server
+    from oracle.forward import forward
+    torch, ctx, specs, networks, keys = world
+    reqs = _requests(world, 12, rate=300.0, seed=1)
+    # alone: one request at a time on the default stream
+    alone = []
+    for r, _ in reqs:
+        out, _ = networks[r.net].run(keys[(r.client, r.net)], r.inputs)
+        torch.cuda.synchronize()
+        alone.append(_words(out[0]))
+    srv = Server(networks, budget_bytes=torch.cuda.mem_get_info()[0] // 2, max_images=4, n_streams=3)
+    for cn, k in keys.items():
+        srv.register_client(cn[0], cn[1], k)
+    stats = srv.serve([r for r, _ in reqs])
+    torch.cuda.synchronize()
+    print(f"[serving] mix stats {stats}", flush=True)
+    assert stats["served"] == 12 and stats["rejected"] == 0
+    assert stats["batches"] < 12  # some requests shared a batch
+    for (r, img), a in zip(reqs, alone):
+        got = _words(r.outputs[0])
+        assert len(got) == len(a)
+        for x, y in zip(got, a):
+            assert torch.equal(x, y), (r.rid, r.client, r.net)
+        assert r.done >= r.arrival
+    for r, img in reqs[:4]:
+        net = networks[r.net]
+        logits = net.decrypt_logits(keys[(r.client, r.net)], r.outputs[0])
+        ref = forward(specs[r.net], img)
+        assert np.max(np.abs(logits - ref)) < 1e-3
+
+
+def test_admission_by_memory(world):
+    from paper_2509_22857_amd.serving import Server
+    torch, ctx, specs, networks, keys = world
+    reqs = _requests(world, 6, rate=500.0, seed=2)
+    one = max(networks[n].working_set_bytes(1) for n in networks)
+    kb = sum(k.evk_bytes() for k in keys.values())
+    # room for the keys and exactly one single-image batch at a time
+    srv = Server(networks, budget_bytes=kb + one + one // 2, max_images=1, n_streams=3)
+    for cn, k in keys.items():
+        srv.register_client(cn[0], cn[1], k)
+    stats = srv.serve([r for r, _ in reqs])
+    torch.cuda.synchronize()
+    assert stats["served"] == 6 and stats["max_concurrent_batches"] == 1
+    assert stats["waits_for_memory"] > 0
+    # budget below any batch: every request is rejected
+    srv2 = Server(networks, budget_bytes=kb + 1024, max_images=1, n_streams=2)
+    for cn, k in keys.items():
+        srv2.register_client(cn[0], cn[1], k)
+    reqs2 = _requests(world, 3, rate=500.0, seed=3)
+    stats2 = srv2.serve([r for r, _ in reqs2])
+    assert stats2["rejected"] == 3 and stats2["served"] == 0
