@@ -73,15 +73,24 @@ def main():
     ap.add_argument("--plain", type=int, default=2, help="images timed one at a time")
     ap.add_argument("--check", type=int, default=4, help="images whose logits are checked against FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="resnet20", choices=["resnet20", "micro"])
+    ap.add_argument("--workload", default="resnet20", choices=["resnet20", "micro", "serving"])
+    ap.add_argument("--clients", type=int, default=8, help="serving: clients with their own keys")
+    ap.add_argument("--serve-rates", default="2,5,10,20", help="serving: Poisson arrival rates (req/s)")
+    ap.add_argument("--serve-requests", type=int, default=16, help="serving: requests per rate")
+    ap.add_argument("--serve-max-images", type=int, default=8, help="serving: images per batch")
+    ap.add_argument("--serve-streams", type=int, default=3, help="serving: concurrent batches")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X; "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print("bench.py measures one GPU only: the evaluator runs on a single MI355X "
+              "(sharding across GPUs is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "micro":
         from paper_2509_22857_amd import microbench
         print(json.dumps(microbench.run(batch=args.batch, reps=max(args.steps, 1), log=log)))
+        return
+    if args.workload == "serving":
+        from paper_2509_22857_amd import serve_bench
+        print(json.dumps(serve_bench.run(args, log)))
         return
 
     import torch

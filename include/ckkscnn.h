@@ -264,7 +264,11 @@ int ckc_eval_quad_act(ckc_ctx *ctx, const ckc_evk *evk, const ckc_layer *layer, 
  * out[k] = sum_c PT[k][c] * S_c + bias_k, where PT[k][c] holds w[m][k][c] in
  * slot m*block of member m.  w: [members][classes][in_ch]; bias:
  * [members][classes] or NULL.  Member m's logit for class k is slot m*block
- * of out[img][k].  Result scale = in scale * pt_scale.
+ * of out[img][k].  Result scale = in scale * pt_scale.  With one member
+ * only slot 0 is read, so PT[k][c] is the encoding of the constant vector
+ * w[0][k][c] (the constant polynomial round(w * pt_scale)) and the bias the
+ * constant round(bias * bias_scale); nothing per (class, channel) is stored
+ * but those residues.
  */
 int ckc_layer_create_dense(ckc_ctx *ctx, const ckc_layout *in, int classes, int in_ch, const double *w,
                            const double *bias, int level, double pt_scale, double bias_scale, ckc_layer **out,

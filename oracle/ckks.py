@@ -329,6 +329,17 @@ class Oracle:
             out[0, l, 0] = np.uint64((int(out[0, l, 0]) + int(r[l])) % q)
         return Ct(out, a.level, a.scale)
 
+    def mul_const(self, a: Ct, value: float, scale: float) -> Ct:
+        """Multiply by the constant round(value * scale) (the encoding of the
+        all-`value` slot vector, Section 2.2): every limb times its residue."""
+        r = self.const_residues(value, scale, a.level + 1)
+        out = np.empty_like(a.data)
+        for k in range(a.npoly):
+            for l in range(a.level + 1):
+                q = self.q[l]
+                out[k, l] = ((a.data[k, l].astype(object) * int(r[l])) % q).astype(np.uint64)
+        return Ct(out, a.level, a.scale * scale)
+
     def mul_plain(self, a: Ct, p: Pt) -> Ct:
         if p.level < a.level:
             raise ValueError("plaintext level too low")

@@ -160,16 +160,27 @@ class OracleNetwork:
         for kk in range(K):
             acc = None
             for c, S in enumerate(sums):
-                v = self._vec()
-                for m in range(self.M):
-                    v[m * self.B] = ly["w"][m, kk, c]
-                term = o.mul_plain(S, self.encode(v, level, pt_scale))
+                if self.M == 1:
+                    # one member: a constant multiplier (only slot 0 is read)
+                    term = o.mul_const(S, ly["w"][0, kk, c], pt_scale)
+                else:
+                    v = self._vec()
+                    for m in range(self.M):
+                        v[m * self.B] = ly["w"][m, kk, c]
+                    term = o.mul_plain(S, self.encode(v, level, pt_scale))
                 acc = term if acc is None else o.add(acc, term)
             if ly.get("bias") is not None:
-                v = self._vec()
-                for m in range(self.M):
-                    v[m * self.B] = ly["bias"][m, kk]
-                acc = o.add_plain(acc, self.encode(v, level, bias_scale))
+                if self.M == 1:
+                    r = o.const_residues(ly["bias"][0, kk], bias_scale, level + 1)
+                    data = acc.data.copy()
+                    for l in range(level + 1):
+                        data[0, l, 0] = np.uint64((int(data[0, l, 0]) + int(r[l])) % o.q[l])
+                    acc = Ct(data, acc.level, acc.scale)
+                else:
+                    v = self._vec()
+                    for m in range(self.M):
+                        v[m * self.B] = ly["bias"][m, kk]
+                    acc = o.add_plain(acc, self.encode(v, level, bias_scale))
             outs.append(acc)
         return outs
 

@@ -46,6 +46,7 @@ struct ckc_layer {
     // dense
     int K = 0;
     std::vector<int32_t> sum_steps;
+    DevMem dconst, bconst;             // dense with one member: [K][C][nl] and [K][nl] constant residues
     size_t bytes = 0;
 };
 
@@ -219,11 +220,12 @@ constexpr int kMaxCentLds = 128;
 constexpr int kImgPerWg = 4;
 template <int OUTS, int IMGS>
 __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restrict__ R, size_t r_img_words,
-                                                           int n_img, int I, int ntap, int nl,
+                                                           int n_img, int ni, int I, int i_base, int ntap, int nl,
                                                            const uint64_t *__restrict__ pts, int kcent,
                                                            const uint8_t *__restrict__ idx8, int Opad,
                                                            const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
-                                                           int o_count, const Prime *__restrict__ primes, int logN) {
+                                                           int o_count, int accumulate,
+                                                           const Prime *__restrict__ primes, int logN) {
     static_assert(OUTS % 8 == 0, "outputs per wave come in packed words of 8 indices");
     constexpr int NW = OUTS / 8;
     extern __shared__ uint64_t sP[];  // [kcent][kTile]
@@ -254,14 +256,14 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
         }
         __syncthreads();
         if (!active) continue;
-        const uint64_t *ix = (const uint64_t *)(idx8 + size_t(t) * I * Opad + o_base);
+        const uint64_t *ix = (const uint64_t *)(idx8 + (size_t(t) * I + i_base) * Opad + o_base);
         const uint64_t *rp = Rb + size_t(t) * ctw;
         uint64_t r = rp[0], kw[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) kw[w] = ix[w];
-        for (int i = 0; i < I; ++i) {
+        for (int i = 0; i < ni; ++i) {
             // prefetch the next input's coefficient and index words
-            const int nx = i + 1 < I ? i + 1 : i;
+            const int nx = i + 1 < ni ? i + 1 : i;
             const uint64_t rn = rp[size_t(nx) * rstride];
             uint64_t kn[NW];
 #pragma unroll
@@ -286,8 +288,10 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
         if (j >= o_count) continue;
         const int o = o_base + j;
         uint64_t y = reduce128(accc_value(acc[j]), P);
-        if (poly == 0 && bias) y = add_mod(y, bias[(size_t(o) * nl + limb) * N + col0 + lane], P.q);
-        outs.p[img * OUTS + j][size_t(poly) * pw + size_t(limb) * N + col0 + lane] = y;
+        uint64_t *dst = outs.p[img * OUTS + j] + size_t(poly) * pw + size_t(limb) * N + col0 + lane;
+        if (accumulate) y = add_mod(y, *dst, P.q);
+        else if (poly == 0 && bias) y = add_mod(y, bias[(size_t(o) * nl + limb) * N + col0 + lane], P.q);
+        *dst = y;
     }
 }
 
@@ -302,8 +306,8 @@ static int conv_outs_per_wave() {
     return v;
 }
 
-using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, const uint64_t *, int, const uint8_t *, int,
-                        const uint64_t *, Ptrs, int, int, const Prime *, int);
+using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, const uint64_t *, int,
+                        const uint8_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int);
 // kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images) that holds them
 static ConvFn conv_kernel(int outs, int gi, int *imgs) {
     *imgs = gi <= 1 ? 1 : gi <= 2 ? 2 : 4;
@@ -332,7 +336,9 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
     CKC_TRY(check_layout(c, in));
     CKC_REQUIRE(ksize == 1 || ksize == 3, CKC_EUNSUPPORTED, "kernel size must be 1 or 3");
     CKC_REQUIRE(stride == 1 || stride == 2, CKC_EUNSUPPORTED, "stride must be 1 or 2");
-    CKC_REQUIRE(out_ch >= 1 && in_ch >= 1 && in_ch <= 128, CKC_EUNSUPPORTED, "1 <= in_ch <= 128 required");
+    CKC_REQUIRE(out_ch >= 1 && in_ch >= 1, CKC_EINVAL, "channel counts must be positive");
+    CKC_REQUIRE(n_centroids <= kMaxCentLds || in_ch <= kMaxBatch, CKC_EUNSUPPORTED,
+                "codebooks above 128 centroids need in_ch <= 64");
     CKC_REQUIRE(n_centroids >= 1 && n_centroids <= 65535, CKC_EINVAL, "bad centroid count");
     CKC_REQUIRE(level >= 0 && level < c->nq, CKC_ELEVEL, "level out of range");
     CKC_REQUIRE(in->height % stride == 0 && in->width % stride == 0, CKC_ESHAPE, "grid not divisible by stride");
@@ -499,22 +505,44 @@ extern "C" int ckc_layer_create_dense(ckc_ctx *c, const ckc_layout *in, int clas
     for (int j = 1; j < in->height; j <<= 1) L->sum_steps.push_back(in->gap * in->row_stride * j);
     const int nl = level + 1, M = in->members;
     const size_t N = c->N, n = N / 2, pw = size_t(nl) * N;
-    CKC_TRY(L->pts.alloc(8 * pw * classes * in_ch));
-    std::vector<double> v(n, 0.0);
-    for (int k = 0; k < classes; ++k)
-        for (int ch = 0; ch < in_ch; ++ch) {
-            for (int m = 0; m < M; ++m) v[size_t(m) * in->block] = w[(size_t(m) * classes + k) * in_ch + ch];
-            CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(k) * in_ch + ch) * pw, s));
+    if (M == 1) {
+        // one member: only slot 0 is read, so every weight is a constant
+        // multiplier (the encoding of the constant slot vector) and the bias a
+        // constant addend
+        std::vector<uint64_t> all(size_t(classes) * in_ch * nl), r;
+        for (int k = 0; k < classes; ++k)
+            for (int ch = 0; ch < in_ch; ++ch) {
+                const_residues(c, w[size_t(k) * in_ch + ch], pt_scale, nl, r);
+                std::copy(r.begin(), r.end(), all.begin() + (size_t(k) * in_ch + ch) * nl);
+            }
+        CKC_TRY(L->dconst.upload(all.data(), 8 * all.size()));
+        if (bias) {
+            L->has_bias = true;
+            std::vector<uint64_t> bc(size_t(classes) * nl);
+            for (int k = 0; k < classes; ++k) {
+                const_residues(c, bias[k], bias_scale, nl, r);
+                std::copy(r.begin(), r.end(), bc.begin() + size_t(k) * nl);
+            }
+            CKC_TRY(L->bconst.upload(bc.data(), 8 * bc.size()));
         }
-    if (bias) {
-        L->has_bias = true;
-        CKC_TRY(L->bias.alloc(8 * pw * classes));
-        for (int k = 0; k < classes; ++k) {
-            for (int m = 0; m < M; ++m) v[size_t(m) * in->block] = bias[size_t(m) * classes + k];
-            CKC_TRY(encode_impl(c, v.data(), n, level, bias_scale, L->bias.u64() + size_t(k) * pw, s));
+    } else {
+        CKC_TRY(L->pts.alloc(8 * pw * classes * in_ch));
+        std::vector<double> v(n, 0.0);
+        for (int k = 0; k < classes; ++k)
+            for (int ch = 0; ch < in_ch; ++ch) {
+                for (int m = 0; m < M; ++m) v[size_t(m) * in->block] = w[(size_t(m) * classes + k) * in_ch + ch];
+                CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(k) * in_ch + ch) * pw, s));
+            }
+        if (bias) {
+            L->has_bias = true;
+            CKC_TRY(L->bias.alloc(8 * pw * classes));
+            for (int k = 0; k < classes; ++k) {
+                for (int m = 0; m < M; ++m) v[size_t(m) * in->block] = bias[size_t(m) * classes + k];
+                CKC_TRY(encode_impl(c, v.data(), n, level, bias_scale, L->bias.u64() + size_t(k) * pw, s));
+            }
         }
     }
-    L->bytes = L->pts.bytes + L->bias.bytes;
+    L->bytes = L->pts.bytes + L->bias.bytes + L->dconst.bytes + L->bconst.bytes;
     *out = L.release();
     return CKC_OK;
 }
@@ -559,71 +587,85 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
     const size_t N = c->N;
     const int nl = L->level + 1, I = L->I, ntap = L->ntap;
     const size_t pw = size_t(nl) * N, ctw = 2 * pw;
-    // images per chunk: at least one contraction group, and enough for a full
-    // key-switching batch of kMaxBatch rotated inputs
-    const int chunk = std::max(kImgPerWg, kMaxBatch / I);
-    const size_t r_img = size_t(I) * ntap * ctw;  // R words per image
+    // Input channels in chunks of at most kMaxBatch (one key-switching batch
+    // per image); the contraction accumulates the chunks' partial sums into
+    // the outputs (exact modular sums, so the result does not depend on the
+    // chunking).  Images per pass: at least one contraction group, and enough
+    // to fill a key-switching batch when the layer has few inputs.
+    const int ichunk = std::min(I, kMaxBatch);
+    const int chunk = std::max(kImgPerWg, kMaxBatch / ichunk);
+    const size_t r_img = size_t(ichunk) * ntap * ctw;  // R words per image
     DevBuf R;
     CKC_TRY(R.alloc(8 * r_img * std::min(chunk, n_img), s));
     const size_t lds = size_t(I) * kTile * 8;
     for (int img0 = 0; img0 < n_img; img0 += chunk) {
-        const int ni = std::min(chunk, n_img - img0);
-        // rotations, in KS batches of <= kMaxBatch inputs
-        const int total = ni * I;
-        for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
-            const int nb = std::min(kMaxBatch, total - b0);
-            Ptrs ip;
-            std::vector<Ptrs> dst(ntap);
-            for (int b = 0; b < nb; ++b) {
-                const int flat = b0 + b;  // (image in chunk, input channel)
-                ip.p[b] = in[size_t(img0) * I + flat].d;
-                for (int t = 0; t < ntap; ++t)
-                    dst[t].p[b] = R.u64() + (size_t(flat) * ntap + t) * ctw;
-            }
-            CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
+        const int ni_img = std::min(chunk, n_img - img0);
+        if (!L->idx8.p) {
+            // grouped form (codebooks beyond kMaxCentLds centroids; I <= 128): per image
+            CKC_REQUIRE(ichunk == I, CKC_EUNSUPPORTED, "grouped contraction needs in_ch <= 64");
         }
-        if (L->idx8.p) {
-            // contraction: groups of kImgPerWg images x `outs` outputs
-            const size_t lds_mac = size_t(L->kcent) * kTile * 8;
-            const int outs = conv_outs_per_wave();
-            for (int g0 = 0; g0 < ni; g0 += kImgPerWg) {
-                const int gi = std::min(kImgPerWg, ni - g0);
-                for (int o0 = 0; o0 < L->O; o0 += outs) {
-                    const int oc = std::min(outs, L->O - o0);
-                    Ptrs op{};
-                    for (int m = 0; m < gi; ++m)
-                        for (int j = 0; j < oc; ++j)
-                            op.p[m * outs + j] = out[size_t(img0 + g0 + m) * L->O + o0 + j].d;
+        for (int ic0 = 0; ic0 < I; ic0 += ichunk) {
+            const int nic = std::min(ichunk, I - ic0);
+            // rotations, in KS batches of <= kMaxBatch inputs: (image in chunk, input channel of the chunk)
+            const int total = ni_img * nic;
+            for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
+                const int nb = std::min(kMaxBatch, total - b0);
+                Ptrs ip;
+                std::vector<Ptrs> dst(ntap);
+                for (int b = 0; b < nb; ++b) {
+                    const int flat = b0 + b, im = flat / nic, ii = flat - im * nic;
+                    ip.p[b] = in[size_t(img0 + im) * I + ic0 + ii].d;
+                    for (int t = 0; t < ntap; ++t)
+                        dst[t].p[b] = R.u64() + size_t(im) * r_img + (size_t(ii) * ntap + t) * ctw;
+                }
+                CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
+            }
+            if (L->idx8.p) {
+                // contraction: groups of kImgPerWg images x `outs` outputs
+                const size_t lds_mac = size_t(L->kcent) * kTile * 8;
+                const int outs = conv_outs_per_wave();
+                for (int g0 = 0; g0 < ni_img; g0 += kImgPerWg) {
+                    const int gi = std::min(kImgPerWg, ni_img - g0);
+                    for (int o0 = 0; o0 < L->O; o0 += outs) {
+                        const int oc = std::min(outs, L->O - o0);
+                        Ptrs op{};
+                        for (int m = 0; m < gi; ++m)
+                            for (int j = 0; j < oc; ++j)
+                                op.p[m * outs + j] = out[size_t(img0 + g0 + m) * L->O + o0 + j].d;
+                        CKC_PROF(PK_CONV_CONTRACT, s,
+                                 8.0 * N * nl * (2.0 * gi * nic * ntap + 2.0 * gi * oc * (ic0 > 0 ? 2 : 1) +
+                                                 double(ntap) * L->kcent),
+                                 2.0 * N * nl * double(gi) * oc * nic * ntap);
+                        int wg_imgs = 1;
+                        const ConvFn fn = conv_kernel(outs, gi, &wg_imgs);
+                        hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nl)), dim3(128 * wg_imgs), lds_mac,
+                                           s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap, nl,
+                                           L->pts.u64(), L->kcent, (const uint8_t *)L->idx8.p, L->Opad,
+                                           L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, ic0 > 0 ? 1 : 0,
+                                           c->dprimes(), c->logN);
+                        CKC_HIP(hipGetLastError());
+                    }
+                }
+                continue;
+            }
+            // grouped form: per image, outputs in groups of kMaxBatch
+            for (int ii = 0; ii < ni_img; ++ii) {
+                const uint64_t *Rimg = R.u64() + size_t(ii) * r_img;
+                for (int o0 = 0; o0 < L->O; o0 += kMaxBatch) {
+                    const int oc = std::min(kMaxBatch, L->O - o0);
+                    Ptrs op;
+                    for (int j = 0; j < oc; ++j) op.p[j] = out[size_t(img0 + ii) * L->O + o0 + j].d;
+                    const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
                     CKC_PROF(PK_CONV_CONTRACT, s,
-                             8.0 * N * nl * (2.0 * gi * I * ntap + 2.0 * gi * oc + double(ntap) * L->kcent),
-                             2.0 * N * nl * double(gi) * oc * I * ntap);
-                    int wg_imgs = 1;
-                    const ConvFn fn = conv_kernel(outs, gi, &wg_imgs);
-                    hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nl)), dim3(128 * wg_imgs), lds_mac, s,
-                                       R.u64() + size_t(g0) * r_img, r_img, gi, I, ntap,
-                                       nl, L->pts.u64(), L->kcent, (const uint8_t *)L->idx8.p, L->Opad,
+                             8.0 * N * nl * (2.0 * I * ntap + 2.0 * oc + double(ntap) * L->kcent),
+                             2.0 * N * nl * double(oc) * I * ntap);
+                    hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups),
+                                       dim3(256), lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent,
+                                       (const int32_t *)L->og_off.p, (const int32_t *)L->g_c.p,
+                                       (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p,
                                        L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, c->dprimes(), c->logN);
                     CKC_HIP(hipGetLastError());
                 }
-            }
-            continue;
-        }
-        // grouped form (codebooks beyond kMaxCentLds centroids): per image, outputs in groups of kMaxBatch
-        for (int ii = 0; ii < ni; ++ii) {
-            const uint64_t *Rimg = R.u64() + size_t(ii) * r_img;
-            for (int o0 = 0; o0 < L->O; o0 += kMaxBatch) {
-                const int oc = std::min(kMaxBatch, L->O - o0);
-                Ptrs op;
-                for (int j = 0; j < oc; ++j) op.p[j] = out[size_t(img0 + ii) * L->O + o0 + j].d;
-                const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
-                CKC_PROF(PK_CONV_CONTRACT, s, 8.0 * N * nl * (2.0 * I * ntap + 2.0 * oc + double(ntap) * L->kcent),
-                         2.0 * N * nl * double(oc) * I * ntap);
-                hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups), dim3(256),
-                                   lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent, (const int32_t *)L->og_off.p,
-                                   (const int32_t *)L->g_c.p, (const int32_t *)L->g_moff.p,
-                                   (const int32_t *)L->m_i.p, L->has_bias ? L->bias.u64() : nullptr, op, o0, oc,
-                                   c->dprimes(), c->logN);
-                CKC_HIP(hipGetLastError());
             }
         }
     }
@@ -709,10 +751,14 @@ extern "C" int ckc_eval_quad_act(ckc_ctx *c, const ckc_evk *evk, const ckc_layer
 namespace {
 // Z[img][k][p] = sum_c PT[k][c] * S[img][c][p] (+ bias[k] on p = 0); images of one launch: up to 8
 constexpr int kDenseImg = 8;
+// With one member the weights and biases are constants (consts [K][C][nl],
+// bconsts [K][nl]): in NTT form a constant polynomial is the same value in
+// every coefficient.
 __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ Sb, int nimg, int C, int nl,
                                                    const uint64_t *__restrict__ pts, const uint64_t *__restrict__ bias,
-                                                   uint64_t *__restrict__ Z, int K, const Prime *__restrict__ primes,
-                                                   int logN) {
+                                                   const uint64_t *__restrict__ consts,
+                                                   const uint64_t *__restrict__ bconsts, uint64_t *__restrict__ Z,
+                                                   int K, const Prime *__restrict__ primes, int logN) {
     const int limb = blockIdx.y, kk = blockIdx.z >> 1, poly = blockIdx.z & 1;
     const size_t N = size_t(1) << logN, pw = size_t(nl) * N;
     const Prime P = primes[limb];
@@ -722,7 +768,8 @@ __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ 
         for (int i = 0; i < kDenseImg; ++i) acc[i] = accc{0, 0, 0, 0, 0};
         int cnt = 0;
         for (int ch = 0; ch < C; ++ch) {
-            const uint64_t pv = pts[(size_t(kk) * C + ch) * pw + size_t(limb) * N + k];
+            const uint64_t pv = consts ? consts[(size_t(kk) * C + ch) * nl + limb]
+                                       : pts[(size_t(kk) * C + ch) * pw + size_t(limb) * N + k];
 #pragma unroll
             for (int i = 0; i < kDenseImg; ++i)
                 if (i < nimg) macc(acc[i], Sb[((size_t(i) * C + ch) * 2 + poly) * pw + size_t(limb) * N + k], pv);
@@ -737,6 +784,7 @@ __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ 
             if (i >= nimg) continue;
             uint64_t y = reduce128(accc_value(acc[i]), P);
             if (poly == 0 && bias) y = add_mod(y, bias[size_t(kk) * pw + size_t(limb) * N + k], P.q);
+            if (poly == 0 && bconsts) y = add_mod(y, bconsts[size_t(kk) * nl + limb], P.q);
             Z[((size_t(i) * K + kk) * 2 + poly) * pw + size_t(limb) * N + k] = y;
         }
     }
@@ -791,7 +839,8 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
             CKC_PROF(PK_DENSE_MAC, s, 8.0 * N * nl * (2.0 * ni * C + double(K) * C + 2.0 * ni * K),
                      2.0 * N * nl * double(ni) * K * C);
         hipLaunchKernelGGL(k_dense_mac, dim3(tiles(N), unsigned(nl), unsigned(2 * K)), dim3(256), 0, s, Sb.u64(), ni, C,
-                           nl, L->pts.u64(), L->has_bias ? L->bias.u64() : nullptr, Z.u64(), K, c->dprimes(), c->logN);
+                           nl, L->pts.u64(), L->bias.u64(), L->dconst.u64(), L->bconst.u64(), Z.u64(), K,
+                           c->dprimes(), c->logN);
         }
         CKC_HIP(hipGetLastError());
         for (int b0 = 0; b0 < ni * K; b0 += kMaxBatch) {

@@ -87,6 +87,7 @@ class Server:
         """Replay `requests` (sorted by arrival, seconds from the start) in
         real time and return per-request timing plus aggregate statistics."""
         torch = self.torch
+        self.stats = collections.Counter()
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue = collections.deque()
         running: list[_Batch] = []
@@ -104,18 +105,22 @@ class Server:
             while queue and free_streams:
                 head = queue[0]
                 net = self.networks[head.net]
-                group, n_img = [], 0
-                for r in list(queue):
-                    if r.client == head.client and r.net == head.net and n_img + len(r.inputs) <= self.max_images:
-                        group.append(r)
-                        n_img += len(r.inputs)
-                need = net.working_set_bytes(n_img)
-                if need > self.budget - self.key_bytes:
+                room = self.budget - self.key_bytes
+                if net.working_set_bytes(len(head.inputs)) > room:
                     # can never run: reject the head request
                     queue.popleft()
                     head.done = float("nan")
                     self.stats["rejected"] += 1
                     continue
+                # the head plus later requests of the same client and network,
+                # as many as the image limit and the whole budget allow
+                group, n_img = [], 0
+                for r in list(queue):
+                    if r.client == head.client and r.net == head.net and n_img + len(r.inputs) <= self.max_images \
+                            and net.working_set_bytes(n_img + len(r.inputs)) <= room:
+                        group.append(r)
+                        n_img += len(r.inputs)
+                need = net.working_set_bytes(n_img)
                 if self.reserved + need > self.budget - self.key_bytes:
                     if waiting != head.rid:
                         self.stats["waits_for_memory"] += 1  # requests that had to wait

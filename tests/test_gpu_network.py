@@ -81,3 +81,56 @@ def test_small_resnet_ensemble_bit_exact_and_batch_independent():
         got = gnet.decrypt_logits(keys, gout[n])
         assert np.max(np.abs(got - ref)) < 1e-3
         assert got.mean(0).argmax() == ref.mean(0).argmax()
+
+
+def test_single_member_network_bit_exact():
+    """One member: the dense layer multiplies by constants (the encoding of the
+    constant slot vector) and the activation adds constants."""
+    spec = nets.resnet_spec(seed=3, members=1, widths=(4,), blocks=1, classes=5, image=(3, 16, 16), k=4, calib=4)
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[single_member] N=2^12 M=1 widths=(4,)", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 21)
+    imgs = gen.images(8, 1, 3, 16, 16)
+    gin = gnet.encrypt_images(keys, imgs, 300)
+    gl = []
+    gout, _ = gnet.run(keys, gin, hook=lambda ly, outs: gl.append((ly["name"], _coeff(ctx, outs[0]))))
+    oin = onet.encrypt_image(sk, imgs[0], 300)
+    ol = []
+    oout, _ = onet.run(sk, oin, rlk, gk, hook=lambda ly, outs: ol.append((ly["name"], outs[0].data)))
+    for (n1, a), (n2, b) in zip(gl, ol):
+        assert n1 == n2
+        assert np.array_equal(a, b), n1
+    for k, (g, c) in enumerate(zip(gout[0], oout)):
+        assert np.array_equal(_coeff(ctx, g), c.data), k
+    from oracle.forward import forward
+    ref = forward(spec, imgs[0])
+    got = gnet.decrypt_logits(keys, gout[0])
+    assert np.max(np.abs(got - ref)) < 1e-3
+
+
+def test_wide_conv_input_chunks_bit_exact():
+    """A convolution with more input channels than one key-switching batch
+    (70 = 64 + 6): the contraction accumulates per input chunk; stride 2 and
+    a bias on top."""
+    g = np.random.default_rng(4)
+    I, O, k = 70, 9, 16
+    codebook = g.uniform(-0.3, 0.3, (3, k, 1))
+    idx = g.integers(0, k, (O, I, 3, 3)).astype(np.uint16)
+    bias = g.uniform(-0.5, 0.5, (1, O))
+    spec = dict(name="wide_conv", members=1, classes=0, image=(I, 8, 8), layout=dict(block=64, row_stride=8),
+                layers=[dict(op="conv", name="conv", inp="x", out="c", out_ch=O, in_ch=I, ksize=3, stride=2,
+                             codebook=codebook, idx=idx, bias=bias)], k=k)
+    ps = small_tower(logN=12, levels=2)
+    D = 2.0 ** 30
+    print("[wide_conv] N=2^12 I=70 O=9 stride 2", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 5)
+    imgs = gen.images(12, 2, I, 8, 8)
+    gin = gnet.encrypt_images(keys, imgs, 700)
+    gout, _ = gnet.run(keys, gin)
+    for n in range(2):
+        oin = onet.encrypt_image(sk, imgs[n], 700 + n * 4096)
+        oout, _ = onet.run(sk, oin, rlk, gk)
+        assert len(oout) == O
+        for j in range(O):
+            assert np.array_equal(_coeff(ctx, gout[n][j]), oout[j].data), (n, j)

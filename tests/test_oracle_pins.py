@@ -347,3 +347,23 @@ def test_keyswitch_noise_bound_tiny():
         rhs = o.polymul(d[l], s2, l).astype(object)
         err = np.array([centred(int(v), q) for v in (lhs - rhs) % q])
         assert np.max(np.abs(err)) < 2 ** 20
+
+
+def test_mul_const_equals_product_with_encoded_constant_vector():
+    """Section 2.2: the encoding of the all-w slot vector is the constant
+    polynomial round(w * scale); multiplying by it limb-wise (mul_const) must
+    equal the negacyclic product with that encoded plaintext."""
+    from oracle.ckks import Oracle, Ct
+    from workloads import gen
+    from workloads.params import tiny
+    ps = tiny()
+    o = Oracle.from_params(ps)
+    level = len(ps.q) - 1
+    a = Ct(gen.random_ct(41, ps.q, level, ps.N), level, 2.0 ** 20)
+    for w, sc in ((0.37, 2.0 ** 30), (-1.25, 2.0 ** 40), (3.0e-3, 2.0 ** 55)):
+        p = o.encode(np.full(ps.N // 2, w), level, sc)
+        assert not p.data[:, 1:].any()
+        want = o.mul_plain(a, p)
+        got = o.mul_const(a, w, sc)
+        assert got.scale == want.scale
+        assert np.array_equal(got.data, want.data)

@@ -39,6 +39,12 @@ def kmeans_rows(X: np.ndarray, k: int, iters: int = 50, seed: int = 0):
     x2 = (X * X).sum(axis=1)[:, None]
 
     def assign(C):
+        if X.shape[1] == 1:
+            # one dimension: the nearest centroid is found between the
+            # midpoints of the sorted centroids
+            order = np.argsort(C[:, 0], kind="stable")
+            cs = C[order, 0]
+            return order[np.searchsorted((cs[1:] + cs[:-1]) / 2.0, X[:, 0])]
         d = x2 - 2.0 * (X @ C.T) + (C * C).sum(axis=1)[None, :]
         return d.argmin(axis=1)
 
@@ -46,8 +52,7 @@ def kmeans_rows(X: np.ndarray, k: int, iters: int = 50, seed: int = 0):
     for _ in range(iters):
         labels = assign(C)
         counts = np.bincount(labels, minlength=k)
-        sums = np.zeros_like(C)
-        np.add.at(sums, labels, X)
+        sums = np.stack([np.bincount(labels, weights=X[:, m], minlength=k) for m in range(X.shape[1])], axis=1)
         nz = counts > 0
         C[nz] = sums[nz] / counts[nz, None]
     labels = assign(C)
@@ -87,7 +92,9 @@ def _conv_fwd(x, W, b, stride):
     for dh in range(k):
         for dw in range(k):
             patch = xp[:, :, :, dh:dh + H:stride, dw:dw + Wd:stride][:, :, :, :Ho, :Wo]
-            y += np.einsum("mbihw,moi->mbohw", patch, W[:, :, :, dh, dw])
+            # [M][B][I][Ho][Wo] x [M][O][I] as one batched matrix product per member
+            pm = np.ascontiguousarray(np.moveaxis(patch, 2, -1)).reshape(M, -1, I)
+            y += np.moveaxis((pm @ np.swapaxes(W[:, :, :, dh, dw], 1, 2)).reshape(M, Bn, Ho, Wo, O), -1, 2)
     if b is not None:
         y += b[:, None, :, None, None]
     return y
