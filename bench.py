@@ -33,6 +33,11 @@ def log(msg):
 def build_workload(args):
     from workloads import nets
     from workloads.params import resnet20_tower
+    if args.workload == "vgg":
+        # VGG-style: 3->64, 64->64, pool, 64->128, 128->128, pool, 128->256, dense to 10; k = 16
+        ps = resnet20_tower(levels=6)
+        spec = nets.vgg_spec(seed=0, calib=8)
+        return ps, spec
     ps = resnet20_tower()
     spec = nets.resnet_spec(seed=0, members=4, widths=(16, 32, 64), blocks=3, classes=100, image=(3, 32, 32),
                             k=64, calib=8)
@@ -73,7 +78,7 @@ def main():
     ap.add_argument("--plain", type=int, default=2, help="images timed one at a time")
     ap.add_argument("--check", type=int, default=4, help="images whose logits are checked against FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="resnet20", choices=["resnet20", "micro", "serving"])
+    ap.add_argument("--workload", default="resnet20", choices=["resnet20", "vgg", "micro", "serving"])
     ap.add_argument("--clients", type=int, default=8, help="serving: clients with their own keys")
     ap.add_argument("--serve-rates", default="2,5,10,20", help="serving: Poisson arrival rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=16, help="serving: requests per rate")
@@ -222,7 +227,8 @@ def main():
         cpu = cpu_baseline(ps, spec, ratio)
 
     res = {
-        "metric": "encrypted images/s (ResNet-20-style ensemble, N=2^16, batched)",
+        "metric": ("encrypted images/s (VGG-style, N=2^16, batched)" if args.workload == "vgg" else
+                   "encrypted images/s (ResNet-20-style ensemble, N=2^16, batched)"),
         "value": round(ips, 4),
         "unit": "images/s",
         "n_gpus": 1,
@@ -234,7 +240,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "resnet20_ensemble_N65536", "images_per_step": B,
+        "config": {"workload": ("vgg_N65536" if args.workload == "vgg" else "resnet20_ensemble_N65536"),
+                   "images_per_step": B,
                    "images_per_pass": min(B, args.images_per_pass), "members": spec["members"],
                    "classes": spec["classes"], "k": spec["k"], "image": list(spec["image"]),
                    "levels": len(ps.q) - 1, "primes_q": len(ps.q), "primes_p": len(ps.p), "alpha": ps.alpha},

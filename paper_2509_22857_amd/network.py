@@ -42,6 +42,9 @@ class LayerPlan:
     short_pt_scale: float = 1.0
 
 
+HEADROOM_BITS = 8
+
+
 def plan_network(spec: dict, q, delta: float, target: float, in_scale: float) -> tuple[list, dict]:
     """Returns (plans per layer, final tensor states {name: (level, scale)})."""
     L = len(q) - 1
@@ -80,6 +83,13 @@ def plan_network(spec: dict, q, delta: float, target: float, in_scale: float) ->
             raise ValueError(op)
         if min(state[ly["out"]][0], lv) < 0:
             raise ValueError("chain too short for this network")
+        # headroom: values up to 2^(HEADROOM_BITS - 1) in magnitude must stay
+        # below half the modulus at the level where the product is formed
+        need = math.log2(p.out_scale) + HEADROOM_BITS
+        have = sum(math.log2(float(x)) for x in q[:lv + 1])
+        if need > have:
+            raise ValueError(f"layer {ly['name']}: scale 2^{math.log2(p.out_scale):.1f} leaves less than "
+                             f"{HEADROOM_BITS} bits below the modulus at level {lv}; the chain is too short")
         plans.append(p)
     return plans, state
 

@@ -134,3 +134,28 @@ def test_wide_conv_input_chunks_bit_exact():
         assert len(oout) == O
         for j in range(O):
             assert np.array_equal(_coeff(ctx, gout[n][j]), oout[j].data), (n, j)
+
+
+def test_small_vgg_bit_exact():
+    """VGG-style network (convolutions, activations, 2x2 sum pooling with the
+    divisor folded forward, one member so the dense layer uses constants)."""
+    spec = nets.vgg_spec(seed=2, widths=(4, 4, 8, 8, 8), classes=5, image=(3, 16, 16), k=6, calib=4)
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[small_vgg] N=2^12 widths=(4,4,8,8,8) two pools", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 31)
+    imgs = gen.images(14, 2, 3, 16, 16)
+    gin = gnet.encrypt_images(keys, imgs, 900)
+    gl = []
+    gout, _ = gnet.run(keys, gin, hook=lambda ly, outs: gl.append((ly["name"], _coeff(ctx, outs[0]))))
+    oin = onet.encrypt_image(sk, imgs[0], 900)
+    ol = []
+    oout, _ = onet.run(sk, oin, rlk, gk, hook=lambda ly, outs: ol.append((ly["name"], outs[0].data)))
+    assert [n for n, _ in gl] == [n for n, _ in ol]
+    for (n1, a), (n2, b) in zip(gl, ol):
+        assert np.array_equal(a, b), n1
+    from oracle.forward import forward
+    for n in range(2):
+        ref = forward(spec, imgs[n])
+        got = gnet.decrypt_logits(keys, gout[n])
+        assert np.max(np.abs(got - ref)) < 1e-3

@@ -119,3 +119,15 @@ def test_standard_chain_rescales_after_every_product():
     plans, state = plan_network(spec, ps.q, 2.0 ** 40, 2.0 ** 34, 2.0 ** 40)
     assert [p.rescale for p in plans] == [True, True]
     assert state["y"][0] == 0
+
+
+def test_planner_rejects_chains_without_headroom():
+    """A chain whose last prime cannot hold the activation's squared scale
+    (Delta^2 ~ q_0) is refused instead of wrapping the message."""
+    from paper_2509_22857_amd.network import plan_network
+    from workloads.params import small_tower
+    spec = nets.vgg_spec(seed=2, widths=(4, 4, 8, 8, 8), classes=5, image=(3, 16, 16), k=6, calib=4)
+    with pytest.raises(ValueError):
+        plan_network(spec, small_tower(logN=12, levels=4).q, 2.0 ** 30, 2.0 ** 30, 2.0 ** 30)
+    plans, state = plan_network(spec, small_tower(logN=12, levels=6).q, 2.0 ** 30, 2.0 ** 30, 2.0 ** 30)
+    assert min(p.level for p in plans) >= 1

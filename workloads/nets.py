@@ -104,6 +104,25 @@ def _rms(x):
     return float(np.sqrt(np.mean(x * x)))
 
 
+def _avgpool2(x):
+    """2x2 average pooling of [M][B][C][H][W]."""
+    M, Bn, C, H, W = x.shape
+    return x.reshape(M, Bn, C, H // 2, 2, W // 2, 2).mean(axis=(4, 6))
+
+
+def _standardise(g, xin, Wc, stride, pre_std):
+    """Scale a convolution per (member, output channel) so its output over the
+    calibration images has zero mean and standard deviation pre_std, plus a
+    small random shift (a folded batch normalisation)."""
+    y = _conv_fwd(xin, Wc, None, stride)  # [M][B][O][H][W]
+    Mm, Bn, O = y.shape[0], y.shape[1], y.shape[2]
+    u = np.moveaxis(y, 2, 1).reshape(Mm, O, -1)
+    shift = g.normal(0.0, 0.1 * pre_std, (Mm, O))
+    mu, sd = u.mean(axis=2), u.std(axis=2) + 1e-12
+    s = pre_std / sd
+    return Wc * s[:, :, None, None, None], -mu * s + shift
+
+
 # ----------------------------------------------------------------- network builders
 def _act_coeffs(g, M, C, b_range=(-0.5, 0.5), c_range=(-0.5, 0.5)):
     a = g.uniform(0.05, 0.2, (M, C))
@@ -140,14 +159,12 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
     # calibration images, as a folded batch normalisation would do: zero mean,
     # unit variance, plus a small random shift (the BN offset).
     def calibrate_conv(xin, Wc, stride, extra=None):
+        if extra is None:
+            return _standardise(g, xin, Wc, stride, pre_std)
         y = _conv_fwd(xin, Wc, None, stride)  # [M][B][O][H][W]
         Mm, Bn, O = y.shape[0], y.shape[1], y.shape[2]
         u = np.moveaxis(y, 2, 1).reshape(Mm, O, -1)
         shift = g.normal(0.0, 0.1 * pre_std, (Mm, O))
-        if extra is None:
-            mu, sd = u.mean(axis=2), u.std(axis=2) + 1e-12
-            s = pre_std / sd
-            return Wc * s[:, :, None, None, None], -mu * s + shift
         v = np.moveaxis(extra, 2, 1).reshape(Mm, O, -1)
         uc = u - u.mean(axis=2, keepdims=True)
         vc = v - v.mean(axis=2, keepdims=True)
@@ -208,6 +225,42 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
                      k, seed, block_slots)
 
 
+def vgg_spec(seed: int = 0, widths=(64, 64, 128, 128, 256), pool_after=(1, 3), classes: int = 10,
+             image=(3, 32, 32), k: int = 16, calib: int = 8, members: int = 1, name: str | None = None,
+             pre_std: float = 0.5) -> dict:
+    """VGG-style network: one 3x3 convolution (stride 1) and one quadratic
+    activation per entry of `widths`, 2x2 average pooling after the layers
+    listed in pool_after, global average pooling folded into the dense layer.
+    Weights N(0, 0.05) standardised per output channel (folded batch
+    normalisation); activation coefficients a ~ U[0.05, 0.2] and
+    b, c ~ U[-0.5, 0.5]; slice clustering with k centroids per layer."""
+    g = rng(seed)
+    M = members
+    Cin, H, W = image
+    x = np.broadcast_to(images(seed + 1000, calib, Cin, H, W)[None], (M, calib, Cin, H, W)).copy()
+    raw = []
+    cur, cur_name, cin = x, "x", Cin
+    for li, width in enumerate(widths):
+        Wc, bc = _standardise(g, cur, g.normal(0.0, 0.05, (M, width, cin, 3, 3)), 1, pre_std)
+        y = _conv_fwd(cur, Wc, bc, 1)
+        a, b, c = _act_coeffs(g, M, width)
+        raw.append(("conv", dict(name=f"conv{li}", inp=cur_name, out=f"c{li}", W=Wc, b=bc, stride=1)))
+        raw.append(("act", dict(name=f"act{li}", inp=f"c{li}", out=f"a{li}", a=a, b=b, c=c)))
+        cur = a[:, None, :, None, None] * y ** 2 + b[:, None, :, None, None] * y + c[:, None, :, None, None]
+        cur_name, cin = f"a{li}", width
+        if li in pool_after:
+            raw.append(("pool", dict(name=f"pool{li}", inp=cur_name, out=f"p{li}")))
+            cur, cur_name = _avgpool2(cur), f"p{li}"
+    Hf, Wf = cur.shape[3], cur.shape[4]
+    pooled = cur.sum(axis=(3, 4))
+    Wd = g.normal(0.0, 0.05, (M, classes, cin)) / (Hf * Wf)
+    bd = g.normal(0.0, 0.1, (M, classes))
+    logits = np.einsum("mbc,mkc->mbk", pooled, Wd) + bd[:, None, :]
+    s = 1.0 / max(_rms(logits), 1e-12)
+    raw.append(("dense", dict(name="fc", inp=cur_name, out="logits", W=Wd * s, b=bd * s)))
+    return _finalise(raw, name or f"vgg_{'-'.join(map(str, widths))}_M{M}_k{k}", M, classes, image, k, seed, None)
+
+
 def _finalise(raw, name, M, classes, image, k, seed, block_slots):
     """Weight redistribution (monic activations, a pushed forward) + clustering."""
     # consumers of each tensor: convs (main or shortcut) and dense
@@ -215,6 +268,9 @@ def _finalise(raw, name, M, classes, image, k, seed, block_slots):
     for kind, d in raw:
         if kind == "act":
             act_scale[d["out"]] = d["a"]
+        elif kind == "pool":
+            # sum pooling: the average's divisor 1/4 moves into the consumers too
+            act_scale[d["out"]] = 0.25 * act_scale[d["inp"]]
     layers = []
     for li, (kind, d) in enumerate(raw):
         if kind == "conv":
