@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--plain", type=int, default=2, help="images timed one at a time")
     ap.add_argument("--check", type=int, default=4, help="images whose logits are checked against FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", default="cached", choices=["cached", "fresh", "off"],
+                    help="autotuner: stored choices for this workload if any (else tune), re-tune, or defaults")
     ap.add_argument("--workload", default="resnet20", choices=["resnet20", "vgg", "micro", "serving"])
     ap.add_argument("--clients", type=int, default=8, help="serving: clients with their own keys")
     ap.add_argument("--serve-rates", default="2,5,10,20", help="serving: Poisson arrival rates (req/s)")
@@ -130,6 +132,19 @@ def main():
     cal.copy_(cts[0][0].buf.repeat((32 << 20) // cts[0][0].buf.numel() + 1)[: 32 << 20])
     torch.cuda.synchronize()
     del cal
+    tuned = None
+    if args.tune != "off":
+        from paper_2509_22857_amd.autotune import tune_network, TUNING_FILE
+        t0 = time.time()
+        sample = cts[: min(B, args.images_per_pass)]
+        key = f"{'vgg_N65536' if args.workload == 'vgg' else 'resnet20_ensemble_N65536'}/{len(sample)}"
+        if args.tune == "fresh":
+            os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+            tuned = tune_network(net, keys, sample, cache=os.path.join(ROOT, "gpurun_out", "tuning.json"), key=key,
+                                 log=log, refresh=True)
+        else:
+            tuned = tune_network(net, keys, sample, cache=TUNING_FILE, key=key, log=log, write=False)
+        log(f"autotune ({args.tune}) in {time.time() - t0:.1f}s: { {k: v for k, v in tuned.items() if k != 'timings'} }")
     for w in range(args.warmup):
         t0 = time.time()
         out, _ = net.run(keys, cts, images_per_pass=args.images_per_pass)
@@ -166,6 +181,19 @@ def main():
     plain_ips = nplain / t_plain if nplain else None
     if plain_ips:
         log(f"plain: {plain_ips:.3f} images/s")
+    # plain, as a captured HIP graph replayed per image
+    graph_ips = None
+    if nplain:
+        from paper_2509_22857_amd.graph import GraphedPass
+        gp = GraphedPass(net, keys, 1)
+        torch.cuda.synchronize()
+        a = time.time()
+        for i in range(nplain):
+            gp.run([cts[i]])
+        torch.cuda.synchronize()
+        graph_ips = nplain / (time.time() - a)
+        log(f"plain, graph replay: {graph_ips:.3f} images/s")
+        del gp
 
     # accuracy of the timed outputs against the FP64 forward
     from oracle.forward import forward
@@ -244,9 +272,11 @@ def main():
                    "images_per_step": B,
                    "images_per_pass": min(B, args.images_per_pass), "members": spec["members"],
                    "classes": spec["classes"], "k": spec["k"], "image": list(spec["image"]),
-                   "levels": len(ps.q) - 1, "primes_q": len(ps.q), "primes_p": len(ps.p), "alpha": ps.alpha},
+                   "levels": len(ps.q) - 1, "primes_q": len(ps.q), "primes_p": len(ps.p), "alpha": ps.alpha,
+                   "tuned": ({k: v for k, v in tuned.items() if k != "timings"} if tuned else None)},
         "plain_images_per_s": round(plain_ips, 4) if plain_ips else None,
         "batched_over_plain": round(ips / plain_ips, 3) if plain_ips else None,
+        "plain_graph_images_per_s": round(graph_ips, 4) if graph_ips else None,
         "key_switch_hbm": {"kernels": list(ks_cls), "achieved_GBs": round(ks_gbs, 1),
                            "frac": round(ks_gbs / HBM_PEAK_GBS, 4),
                            "kip_GBs": round(kip_gbs, 1), "kip_frac": round(kip_gbs / HBM_PEAK_GBS, 4)},

@@ -292,14 +292,27 @@ int ckc_layer_destroy(ckc_layer *layer);
 /* ------------------------------------------------------------------ profiling
  * Opt-in launch timing for measurement: while enabled, the library records a
  * HIP event pair around every launch of the named kernel classes ("ntt_fwd",
- * "ntt_inv", "bconv", "kip", "moddown", "conv_contract", "act_tensor",
- * "dense_mac", "ew") on the stream the kernel runs on, together with the
- * algorithmic bytes (each word read or written once) and work (butterflies
- * for the NTT, 64-bit products for the key inner product) of the launch.
+ * "ntt_inv", "kip", "conv_contract", "act_tensor", "rescale", "dense_mac",
+ * "ew", "mac_plain", "tensor", "copy"; "bconv" and "moddown" run inside the
+ * forward NTT and record nothing of their own) on the stream the kernel runs
+ * on, together with the algorithmic bytes (each word read or written once)
+ * and work (butterflies for the NTT, 64-bit products for the key inner
+ * product and the multiply-accumulates) of the launch.
  * ckc_prof_enable clears the records; ckc_prof_query waits for the recorded
  * events and sums them for one class. */
 int ckc_prof_enable(int on);
 int ckc_prof_query(const char *kernel, int64_t *launches, double *total_ms, double *bytes, double *work);
+
+/* ------------------------------------------------------------------ tuning
+ * Launch choices picked by an autotuner (process-wide; every choice gives
+ * bit-identical results, only the speed differs):
+ *   "conv_outs"  outputs per wave of the convolution contraction: 8 or 16
+ *   "conv_imgs"  most images per contraction workgroup: 1, 2 or 4
+ *   "ks_batch"   rotated inputs per key-switching launch in a convolution,
+ *                8 .. 64
+ * Errors: CKC_EINVAL for an unknown knob or a value it does not allow. */
+int ckc_tune_set(const char *knob, int value);
+int ckc_tune_get(const char *knob, int *value);
 
 #ifdef __cplusplus
 }

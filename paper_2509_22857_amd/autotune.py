@@ -1,0 +1,79 @@
+"""Autotuner for the evaluator's launch choices.
+
+The library exposes process-wide launch knobs (ckc_tune_set): outputs per
+wave and images per workgroup of the convolution contraction, and rotated
+inputs per key-switching launch.  Every value gives bit-identical
+ciphertexts; only the speed differs with the network's shapes and the batch.
+The tuner runs coordinate descent over the knobs: for each knob in turn it
+times one whole pass of the network over a representative batch at every
+allowed value (the other knobs at their best so far), keeps the fastest, and
+checks that the outputs did not change.  The result can be cached in a JSON
+file keyed by the workload name.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import ckks
+
+# choices measured on MI355X by this tuner (key: workload / images per pass)
+TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def _pass_time(torch, net, keys, inputs):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, _ = net.run(keys, inputs)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def tune_network(net, keys, inputs, knobs=None, cache: str | None = None, key: str | None = None, log=None,
+                 refresh: bool = False, write: bool = True) -> dict:
+    """Pick the fastest value of every knob for `net` on the batch `inputs`
+    ([n_img][C] ciphertexts); sets the library's knobs and returns
+    {knob: value, "timings": {...}}.  With a cache file and key, stored
+    choices are applied without timing unless `refresh`; new results are
+    written back if `write`."""
+    import torch
+    knobs = dict(knobs or ckks.TUNE_KNOBS)
+    if cache and key and not refresh and os.path.exists(cache):
+        with open(cache) as f:
+            saved = json.load(f).get(key)
+        if saved:
+            for k in knobs:
+                ckks.tune_set(k, saved[k])
+            return saved
+    best = {k: ckks.tune_get(k) for k in knobs}
+    timings = {}
+    ref = None
+    _pass_time(torch, net, keys, inputs)  # warm the tables and scratch arenas
+    for k, values in knobs.items():
+        scores = {}
+        for v in values:
+            ckks.tune_set(k, v)
+            t, out = _pass_time(torch, net, keys, inputs)
+            words = out[0][0].buf.clone()
+            if ref is None:
+                ref = words
+            elif not torch.equal(ref, words):
+                raise RuntimeError(f"knob {k}={v} changed the result")
+            scores[v] = t
+            if log:
+                log(f"tune {k}={v}: {t:.3f}s")
+        best[k] = min(scores, key=scores.get)
+        ckks.tune_set(k, best[k])
+        timings[k] = {str(v): round(t, 4) for v, t in scores.items()}
+    result = dict(best)
+    result["timings"] = timings
+    if cache and key and write:
+        data = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                data = json.load(f)
+        data[key] = result
+        with open(cache, "w") as f:
+            json.dump(data, f, indent=1)
+    return result

@@ -103,6 +103,8 @@ _SIGS = [
     ("ckc_layer_destroy", C.c_int, [_vp]),
     ("ckc_prof_enable", C.c_int, [C.c_int]),
     ("ckc_prof_query", C.c_int, [C.c_char_p, C.POINTER(C.c_int64), _dblp, _dblp, _dblp]),
+    ("ckc_tune_set", C.c_int, [C.c_char_p, C.c_int]),
+    ("ckc_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
 ]
 
 
@@ -563,6 +565,18 @@ def prof_query(name: str) -> dict:
     _check("ckc_prof_query", lib().ckc_prof_query(name.encode(), C.byref(n), C.byref(ms), C.byref(by), C.byref(wk)))
     return {"launches": int(n.value), "ms": ms.value, "bytes": by.value, "work": wk.value}
 
+
+def tune_set(knob: str, value: int):
+    _check("ckc_tune_set", lib().ckc_tune_set(knob.encode(), int(value)))
+
+
+def tune_get(knob: str) -> int:
+    v = C.c_int()
+    _check("ckc_tune_get", lib().ckc_tune_get(knob.encode(), C.byref(v)))
+    return int(v.value)
+
+
+TUNE_KNOBS = {"conv_outs": (8, 16), "conv_imgs": (1, 2, 4), "ks_batch": (16, 32, 64)}
 
 PROF_KERNELS = ("ntt_fwd", "ntt_inv", "bconv", "kip", "moddown", "conv_contract", "act_tensor", "rescale",
                 "dense_mac", "ew", "mac_plain", "tensor", "copy")

@@ -18,6 +18,7 @@
 
 #include "batch.h"
 #include "prof.h"
+#include "tune.h"
 
 int encode_impl(ckc_ctx *c, const double *slots_h, size_t nslots, int level, double scale, uint64_t *m,
                 hipStream_t s);
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void k_conv_contract(
 // Direct form of the same contraction, batched over images, for codebooks of
 // at most kMaxCentLds centroids:
 //   y[m][o] = sum_t sum_i PT[t][idx[o][i][t]] * R[m][i][t] + bias_o
-// for up to kImgPerWg images m and kOutPerWave consecutive outputs o.  One
+// for up to IMGS images m and OUTS consecutive outputs o.  One
 // workgroup = one 64-coefficient column tile of one limb; wave w handles image
 // w >> 1 and polynomial w & 1 and keeps one accumulator per output.  Per tap
 // the tap's whole codebook tile (kcent x 64 words) is staged in LDS once and
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(256) void k_conv_contract(
 // outputs rather than once per image and polynomial.  The centroid index is
 // wave-uniform (scalar loads of 8 packed byte indices); R is read straight
 // from HBM, each element by exactly one wave, for all its outputs.
-// idx8: [ntap][I][Opad] uint8, Opad a multiple of kOutPerWave.
+// idx8: [ntap][I][Opad] uint8, Opad a multiple of 32.
 constexpr int kMaxCentLds = 128;
 constexpr int kImgPerWg = 4;
 template <int OUTS, int IMGS>
@@ -295,20 +296,11 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     }
 }
 
-// outputs per wave of the direct form (8 or 16): a tuning choice between
-// accumulator registers (occupancy) and codebook re-reads per output group
-static int conv_outs_per_wave() {
-    static const int v = [] {
-        const char *e = getenv("CKC_CONV_OUTS");
-        const int x = e ? atoi(e) : 8;
-        return x == 16 ? 16 : 8;
-    }();
-    return v;
-}
-
 using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, const uint64_t *, int,
                         const uint8_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int);
-// kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images) that holds them
+// kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images)
+// that holds them; outs = outputs per wave (8 or 16), a tuning choice between
+// accumulator registers (occupancy) and codebook re-reads per output group
 static ConvFn conv_kernel(int outs, int gi, int *imgs) {
     *imgs = gi <= 1 ? 1 : gi <= 2 ? 2 : 4;
     if (outs == 16) return *imgs == 1 ? k_conv_mac<16, 1> : *imgs == 2 ? k_conv_mac<16, 2> : k_conv_mac<16, 4>;
@@ -608,8 +600,9 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
             const int nic = std::min(ichunk, I - ic0);
             // rotations, in KS batches of <= kMaxBatch inputs: (image in chunk, input channel of the chunk)
             const int total = ni_img * nic;
-            for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
-                const int nb = std::min(kMaxBatch, total - b0);
+            const int ksb = tune_value(TK_KS_BATCH);
+            for (int b0 = 0; b0 < total; b0 += ksb) {
+                const int nb = std::min(ksb, total - b0);
                 Ptrs ip;
                 std::vector<Ptrs> dst(ntap);
                 for (int b = 0; b < nb; ++b) {
@@ -623,9 +616,9 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
             if (L->idx8.p) {
                 // contraction: groups of kImgPerWg images x `outs` outputs
                 const size_t lds_mac = size_t(L->kcent) * kTile * 8;
-                const int outs = conv_outs_per_wave();
-                for (int g0 = 0; g0 < ni_img; g0 += kImgPerWg) {
-                    const int gi = std::min(kImgPerWg, ni_img - g0);
+                const int outs = tune_value(TK_CONV_OUTS), wg_max = tune_value(TK_CONV_IMGS);
+                for (int g0 = 0; g0 < ni_img; g0 += wg_max) {
+                    const int gi = std::min(wg_max, ni_img - g0);
                     for (int o0 = 0; o0 < L->O; o0 += outs) {
                         const int oc = std::min(outs, L->O - o0);
                         Ptrs op{};

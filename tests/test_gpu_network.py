@@ -159,3 +159,32 @@ def test_small_vgg_bit_exact():
         ref = forward(spec, imgs[n])
         got = gnet.decrypt_logits(keys, gout[n])
         assert np.max(np.abs(got - ref)) < 1e-3
+
+
+def test_graphed_pass_replays_match_eager():
+    """A network pass captured as a HIP graph and replayed for new inputs
+    (eager work and synchronisations in between) gives the eager ciphertexts
+    on every replay."""
+    import torch
+    from paper_2509_22857_amd.ckks import Context
+    from paper_2509_22857_amd.graph import GraphedPass
+    from paper_2509_22857_amd.network import GpuNetwork
+    spec = nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8, calib=4)
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[graph] N=2^12 small resnet, 2 images per pass", flush=True)
+    ctx = Context.from_params(ps)
+    net = GpuNetwork(ctx, spec, D, D, D)
+    keys = ctx.keygen(17, net.steps)
+    gp = GraphedPass(net, keys, 2)
+    for rep in range(3):
+        imgs = gen.images(40 + rep, 2, 3, 16, 16)
+        cts = net.encrypt_images(keys, imgs, 4096 * 8 * (rep + 1))
+        eager, _ = net.run(keys, cts)
+        torch.cuda.synchronize()
+        want = [[c.buf.clone() for c in row] for row in eager]
+        got = gp.run(cts)
+        torch.cuda.synchronize()
+        for wrow, grow in zip(want, got):
+            for w, g in zip(wrow, grow):
+                assert torch.equal(w, g.buf), rep
