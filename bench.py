@@ -30,6 +30,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def calibration_copy(torch):
+    """One device copy of a known size (1 GiB read + 1 GiB written): the
+    reference kernel for scaling hardware byte counters (FETCH_SIZE,
+    WRITE_SIZE) of the evaluator's kernels in the same run."""
+    src = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def build_workload(args):
     from workloads import nets
     from workloads.params import resnet20_tower
@@ -92,7 +103,9 @@ def main():
               "(sharding across GPUs is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "micro":
+        import torch
         from paper_2509_22857_amd import microbench
+        calibration_copy(torch)
         print(json.dumps(microbench.run(batch=args.batch, reps=max(args.steps, 1), log=log)))
         return
     if args.workload == "serving":
@@ -126,12 +139,7 @@ def main():
     log(f"encrypted {B} images in {time.time() - t0:.1f}s")
 
     stream = torch.cuda.current_stream()
-    # calibration copy of a known size (256 MiB read + 256 MiB written): the
-    # reference for scaling hardware byte counters of the evaluator's kernels
-    cal = torch.empty(32 << 20, dtype=torch.int64, device="cuda")
-    cal.copy_(cts[0][0].buf.repeat((32 << 20) // cts[0][0].buf.numel() + 1)[: 32 << 20])
-    torch.cuda.synchronize()
-    del cal
+    calibration_copy(torch)
     tuned = None
     if args.tune != "off":
         from paper_2509_22857_amd.autotune import tune_network, TUNING_FILE

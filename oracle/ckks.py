@@ -56,6 +56,8 @@ def lib():
         L.oc_modup_digit.argtypes = [C.c_void_p, _u64p, C.c_int, C.c_int, C.c_int, _u64p]
         L.oc_moddown.argtypes = [C.c_void_p, _u64p, C.c_int, _u64p]
         L.oc_keyswitch.argtypes = [C.c_void_p, _u64p, C.c_int, C.c_int, C.c_uint64, _u64p, _u64p]
+        L.oc_keyswitch_ext.argtypes = [C.c_void_p, _u64p, C.c_int, C.c_int, C.c_uint64, _u64p, _u64p]
+        L.oc_encode_ext.argtypes = [C.c_void_p, _dblp, _dblp, C.c_size_t, C.c_double, C.c_int, _u64p]
         L.oc_rescale.argtypes = [C.c_void_p, _u64p, C.c_int, C.c_int, _u64p]
         L.oc_encode.argtypes = [C.c_void_p, _dblp, _dblp, C.c_size_t, C.c_double, C.c_int, _u64p, _dblp]
         L.oc_decode.argtypes = [C.c_void_p, _dblp, C.c_double, _dblp, _dblp]
@@ -262,6 +264,25 @@ class Oracle:
         out = np.empty((level + 1, self.N), dtype=np.uint64)
         lib().oc_moddown(self._h, _p(x), level, _p(out))
         return out
+
+    def keyswitch_ext(self, d: np.ndarray, level: int, key: np.ndarray, g: int = 1) -> np.ndarray:
+        """The key switch before ModDown: [2][level+1+np][N] over Q_l then P."""
+        d = np.ascontiguousarray(d, dtype=np.uint64)
+        key = np.ascontiguousarray(key, dtype=np.uint64)
+        acc = np.empty((2, level + 1 + len(self.p), self.N), dtype=np.uint64)
+        lib().oc_keyswitch_ext(self._h, _p(d), level, self.alpha, g, _p(key), _p(acc))
+        return acc
+
+    def encode_ext(self, z, level: int, scale: float) -> np.ndarray:
+        """The encoding of z reduced into q_0..q_level and every P prime:
+        [level+1+np][N] coefficient form."""
+        z = np.asarray(z)
+        zr = np.ascontiguousarray(np.real(z), dtype=np.float64)
+        zi = np.ascontiguousarray(np.imag(z), dtype=np.float64) if np.iscomplexobj(z) else None
+        m = np.empty((level + 1 + len(self.p), self.N), dtype=np.uint64)
+        lib().oc_encode_ext(self._h, _p(zr, _dblp), _p(zi, _dblp) if zi is not None else None,
+                            len(zr), float(scale), level, _p(m))
+        return m
 
     def keyswitch(self, d: np.ndarray, level: int, key: np.ndarray, g: int = 1) -> np.ndarray:
         d = np.ascontiguousarray(d, dtype=np.uint64)

@@ -481,8 +481,13 @@ void oc_moddown(const oc_ctx *c, const uint64_t *x, int level, uint64_t *out) {
  * Returns the two polynomials (u0, u1) over q_0..q_level:
  *   u_b = ModDown( sum_j sigma_g(ModUp_j(d)) * key_j[b] ).
  */
-void oc_keyswitch(const oc_ctx *c, const uint64_t *d, int level, int alpha, uint64_t g,
-                  const uint64_t *key, uint64_t *u /* [2][level+1][N] */) {
+/*
+ * The key switch before its ModDown (the extended-basis product):
+ *   acc_b = sum_j sigma_g(ModUp_j(d)) * key_j[b]   over q_0..q_level then P,
+ * acc: [2][level+1+np][N] (coefficient form).
+ */
+void oc_keyswitch_ext(const oc_ctx *c, const uint64_t *d, int level, int alpha, uint64_t g,
+                      const uint64_t *key, uint64_t *acc) {
     size_t N = c->N;
     int np = c->nprimes;
     int nt = level + 1 + c->np;
@@ -490,7 +495,7 @@ void oc_keyswitch(const oc_ctx *c, const uint64_t *d, int level, int alpha, uint
     uint64_t *digit = (uint64_t *)malloc(8 * N * nt);
     uint64_t *rot = (uint64_t *)malloc(8 * N);
     uint64_t *prod = (uint64_t *)malloc(8 * N);
-    uint64_t *acc = (uint64_t *)calloc((size_t)2 * nt * N, 8);
+    memset(acc, 0, (size_t)2 * nt * N * 8);
     for (int j = 0; j < dnum_l; ++j) {
         oc_modup_digit(c, d, level, alpha, j, digit);
         for (int tt = 0; tt < nt; ++tt) {
@@ -509,10 +514,18 @@ void oc_keyswitch(const oc_ctx *c, const uint64_t *d, int level, int alpha, uint
             }
         }
     }
-    for (int b = 0; b < 2; ++b) oc_moddown(c, acc + (size_t)b * nt * N, level, u + (size_t)b * (level + 1) * N);
     free(digit);
     free(rot);
     free(prod);
+}
+
+void oc_keyswitch(const oc_ctx *c, const uint64_t *d, int level, int alpha, uint64_t g,
+                  const uint64_t *key, uint64_t *u /* [2][level+1][N] */) {
+    size_t N = c->N;
+    int nt = level + 1 + c->np;
+    uint64_t *acc = (uint64_t *)malloc((size_t)2 * nt * N * 8);
+    oc_keyswitch_ext(c, d, level, alpha, g, key, acc);
+    for (int b = 0; b < 2; ++b) oc_moddown(c, acc + (size_t)b * nt * N, level, u + (size_t)b * (level + 1) * N);
     free(acc);
 }
 
@@ -650,9 +663,24 @@ static uint64_t double_int_mod(double v, uint64_t q) {
     return v < 0 ? (r ? q - r : 0) : r;
 }
 
+static void encode_limbs(const oc_ctx *c, const double *z_re, const double *z_im, size_t nslots, double delta,
+                         int level, int with_p, uint64_t *m, double *w_out);
+
 /* rounds half away from zero, then reduces into each of the first nl primes */
 void oc_encode(const oc_ctx *c, const double *z_re, const double *z_im, size_t nslots, double delta,
                int level, uint64_t *m /* [level+1][N] */, double *w_out /* optional [2][n] */) {
+    encode_limbs(c, z_re, z_im, nslots, delta, level, 0, m, w_out);
+}
+
+/* the same integer coefficients reduced into q_0..q_level and then every P
+ * prime: m [level+1+np][N] (a plaintext of the extended basis Q_l u P) */
+void oc_encode_ext(const oc_ctx *c, const double *z_re, const double *z_im, size_t nslots, double delta,
+                   int level, uint64_t *m) {
+    encode_limbs(c, z_re, z_im, nslots, delta, level, 1, m, NULL);
+}
+
+static void encode_limbs(const oc_ctx *c, const double *z_re, const double *z_im, size_t nslots, double delta,
+                         int level, int with_p, uint64_t *m, double *w_out) {
     size_t N = c->N, n = N / 2;
     double *re = (double *)calloc(n, sizeof(double)), *im = (double *)calloc(n, sizeof(double));
     uint64_t g = 1, M2 = 2 * N;
@@ -678,10 +706,11 @@ void oc_encode(const oc_ctx *c, const double *z_re, const double *z_im, size_t n
         memcpy(w_out, re, n * sizeof(double));
         memcpy(w_out + n, im, n * sizeof(double));
     }
+    int nl = level + 1, nt = nl + (with_p ? c->np : 0);
     for (size_t k = 0; k < n; ++k) {
         double a = round(delta * re[k]), b = round(delta * im[k]);
-        for (int t = 0; t <= level; ++t) {
-            uint64_t q = c->mod[t];
+        for (int t = 0; t < nt; ++t) {
+            uint64_t q = c->mod[t < nl ? t : c->nq + (t - nl)];
             m[(size_t)t * N + k] = double_int_mod(a, q);
             m[(size_t)t * N + k + n] = double_int_mod(b, q);
         }

@@ -76,40 +76,88 @@ class OracleNetwork:
         Ho, Wo, go = H // s, W // s, g * s
         level = xs[0].level
         cb, idx = ly["codebook"], ly["idx"]
-        # rotated inputs per tap
-        rot = {}
-        for i, x in enumerate(xs):
-            for dh in range(-half, half + 1):
-                for dw in range(-half, half + 1):
-                    step = g * (dh * self.W0 + dw)
-                    gk = gkeys.get(o.galois_elt(step)) if step else None
-                    rot[(i, dh, dw)] = o.rotate(x, step, gk)
-        # plaintext of a weight vector on a tap's mask
-        cache = {}
 
-        def wpt(dh, dw, wvec):
-            key = (dh, dw, tuple(wvec))
-            if key not in cache:
-                v = self._vec()
-                for m in range(self.M):
-                    for r in range(Ho):
-                        if not 0 <= s * r + dh < H:
-                            continue
-                        for c in range(Wo):
-                            if 0 <= s * c + dw < W:
-                                v[self._slot(m, r, c, go)] = wvec[m]
-                cache[key] = self.encode(v, level, pt_scale)
-            return cache[key]
+        def mask(dh, dw, wvec):
+            # a weight vector on the output slots whose input pixel is inside
+            v = self._vec()
+            for m in range(self.M):
+                for r in range(Ho):
+                    if not 0 <= s * r + dh < H:
+                        continue
+                    for c in range(Wo):
+                        if 0 <= s * c + dw < W:
+                            v[self._slot(m, r, c, go)] = wvec[m]
+            return v
 
+        taps = [(dh, dw) for dh in range(-half, half + 1) for dw in range(-half, half + 1)]
         outs = []
-        for oc in range(ly["out_ch"]):
-            acc = None
-            for i in range(ly["in_ch"]):
-                for dh in range(-half, half + 1):
-                    for dw in range(-half, half + 1):
+        if k == 1:
+            # a single tap of step 0: plain products (no key switching)
+            cache = {}
+            for oc in range(ly["out_ch"]):
+                acc = None
+                for i, x in enumerate(xs):
+                    wvec = cb[0][idx[oc, i, 0, 0]]
+                    key = tuple(wvec)
+                    if key not in cache:
+                        cache[key] = self.encode(mask(0, 0, wvec), level, pt_scale)
+                    term = o.mul_plain(x, cache[key])
+                    acc = term if acc is None else o.add(acc, term)
+                outs.append(acc)
+        else:
+            # double hoisting: every rotated input stays in the extended basis
+            # Q_l u P as P*sigma(c0) + u0 and u1 (the key switch without its
+            # ModDown; the identity tap is P*x), the products with plaintexts
+            # encoded over Q_l u P are summed there, and one ModDown per
+            # output polynomial brings the sum back to Q_l.
+            nl = level + 1
+            nt = nl + o.np_
+            prime = [l if l < nl else o.nq + (l - nl) for l in range(nt)]
+            P_mod = []
+            for l in range(nl):
+                v = 1
+                for pk in o.p:
+                    v = (v * pk) % o.q[l]
+                P_mod.append(v)
+
+            def times_P(a, l):
+                return ((a.astype(object) * P_mod[l]) % o.q[l]).astype(np.uint64)
+
+            ext = {}
+            for i, x in enumerate(xs):
+                for dh, dw in taps:
+                    step = g * (dh * self.W0 + dw)
+                    R = np.zeros((2, nt, o.N), dtype=np.uint64)
+                    if step == 0:
+                        for p in range(2):
+                            for l in range(nl):
+                                R[p, l] = times_P(x.data[p, l], l)
+                    else:
+                        gel = o.galois_elt(step)
+                        R = o.keyswitch_ext(x.data[1], level, gkeys[gel], gel)
+                        for l in range(nl):
+                            sa = times_P(o.automorphism(x.data[0, l], gel, l), l)
+                            R[0, l] = o._add(R[0, l], sa, np.uint64(o.q[l]))
+                    ext[(i, dh, dw)] = R
+            cache = {}
+            for oc in range(ly["out_ch"]):
+                acc = np.zeros((2, nt, o.N), dtype=np.uint64)
+                for i in range(ly["in_ch"]):
+                    for dh, dw in taps:
                         wvec = cb[dw + half][idx[oc, i, dh + half, dw + half]]
-                        term = o.mul_plain(rot[(i, dh, dw)], wpt(dh, dw, wvec))
-                        acc = term if acc is None else o.add(acc, term)
+                        key = (dh, dw, tuple(wvec))
+                        if key not in cache:
+                            cache[key] = o.encode_ext(mask(dh, dw, wvec), level, pt_scale)
+                        pt = cache[key]
+                        R = ext[(i, dh, dw)]
+                        for p in range(2):
+                            for l in range(nt):
+                                prod = o.polymul(R[p, l], pt[l], prime[l])
+                                acc[p, l] = o._add(acc[p, l], prod, np.uint64(o.mod[prime[l]]))
+                y = np.stack([o.moddown(acc[p], level) for p in range(2)])
+                outs.append(Ct(y, level, xs[0].scale * pt_scale))
+        for oc in range(ly["out_ch"]):
+            acc = outs[oc]
             if with_bias and ly.get("bias") is not None:
                 v = self._vec()
                 for m in range(self.M):
@@ -117,7 +165,7 @@ class OracleNetwork:
                         for c in range(Wo):
                             v[self._slot(m, r, c, go)] = ly["bias"][m, oc]
                 acc = o.add_plain(acc, self.encode(v, level, bias_scale))
-            outs.append(acc)
+            outs[oc] = acc
         return outs, dict(gap=go, H=Ho, W=Wo)
 
     def act(self, xs, ly, rlk):

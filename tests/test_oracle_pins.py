@@ -367,3 +367,82 @@ def test_mul_const_equals_product_with_encoded_constant_vector():
         got = o.mul_const(a, w, sc)
         assert got.scale == want.scale
         assert np.array_equal(got.data, want.data)
+
+
+def test_keyswitch_ext_then_moddown_is_the_keyswitch():
+    """Section 2.2 hybrid key switching: the extended-basis product followed
+    by ModDown is the key switch; ModDown of (P x, 0) is x exactly."""
+    from oracle.ckks import Oracle
+    from workloads import gen
+    from workloads.params import small_tower
+    ps = small_tower(logN=12, levels=3)
+    o = Oracle.from_params(ps)
+    sk = o.secret_key(3)
+    level = 2
+    d = gen.random_limbs(5, ps.q[:level + 1], ps.N)
+    g = o.galois_elt(5)
+    key = o.galois_key(sk, g)
+    ext = o.keyswitch_ext(d, level, key, g)
+    want = o.keyswitch(d, level, key, g)
+    for b in range(2):
+        assert np.array_equal(o.moddown(ext[b], level), want[b])
+    nl = level + 1
+    x = gen.random_limbs(6, ps.q[:nl], ps.N)
+    px = np.zeros((nl + len(ps.p), ps.N), dtype=np.uint64)
+    for l in range(nl):
+        P = 1
+        for pk in ps.p:
+            P = P * pk % ps.q[l]
+        px[l] = ((x[l].astype(object) * P) % ps.q[l]).astype(np.uint64)
+    assert np.array_equal(o.moddown(px, level), x)
+
+
+def test_double_hoisted_convolution_decrypts_to_the_convolution():
+    """The convolution summed in the extended basis with one ModDown per
+    output decrypts to the exact (FP64) convolution of the image within the
+    input's encryption noise; rotations that each run their own ModDown
+    before the plaintext products (a different ciphertext) carry the ModDown
+    rounding of every rotation into the result and land further away."""
+    from oracle.ckks import Oracle
+    from oracle.network import OracleNetwork
+    from workloads import gen
+    from workloads.params import small_tower
+    ps = small_tower(logN=12, levels=3, alpha=1)  # one prime per digit: negligible key-switching noise
+    o = Oracle.from_params(ps)
+    g = np.random.default_rng(2)
+    I, O, k = 2, 2, 4
+    cb = g.uniform(-0.5, 0.5, (3, k, 1))
+    idx = g.integers(0, k, (O, I, 3, 3)).astype(np.uint16)
+    spec = dict(name="c", members=1, classes=0, image=(I, 8, 8), layout=dict(block=64, row_stride=8),
+                layers=[dict(op="conv", name="conv", inp="x", out="c", out_ch=O, in_ch=I, ksize=3, stride=1,
+                             codebook=cb, idx=idx, bias=None)], k=k)
+    D = 2.0 ** 30
+    net = OracleNetwork(o, spec, D, D, D)
+    sk = o.secret_key(8)
+    gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in net.steps()}
+    img = gen.images(3, 1, I, 8, 8)[0]
+    xs = net.encrypt_image(sk, img, 10)
+    level = xs[0].level
+    outs, grid = net.conv(xs, dict(gap=1, H=8, W=8), spec["layers"][0], D, 1.0, gk, with_bias=False)
+    for oc in range(O):
+        exact = np.zeros((8, 8))
+        ref = None
+        for i in range(I):
+            for dh in (-1, 0, 1):
+                for dw in (-1, 0, 1):
+                    w = cb[dw + 1][idx[oc, i, dh + 1, dw + 1]][0]
+                    st = dh * 8 + dw
+                    v = np.zeros(ps.N // 2)
+                    for rr in range(8):
+                        for cc in range(8):
+                            if 0 <= rr + dh < 8 and 0 <= cc + dw < 8:
+                                exact[rr, cc] += w * img[i, rr + dh, cc + dw]
+                                v[rr * 8 + cc] = w
+                    r = o.rotate(xs[i], st, gk.get(o.galois_elt(st)))
+                    t = o.mul_plain(r, o.encode(v, level, D))
+                    ref = t if ref is None else o.add(ref, t)
+        got = o.decrypt_decode(outs[oc], sk)[:64].reshape(8, 8)
+        per_rot = o.decrypt_decode(ref, sk)[:64].reshape(8, 8)
+        assert not np.array_equal(outs[oc].data, ref.data)
+        assert np.max(np.abs(got - exact)) < 2e-6
+        assert np.max(np.abs(per_rot - exact)) < 1e-4
