@@ -16,7 +16,7 @@ extern "C" const char *ckc_last_error(void) { return g_err.c_str(); }
 int copy_limbs(const uint64_t *src, size_t src_ps, uint64_t *dst, size_t dst_ps, size_t words, int npoly,
                hipStream_t s);
 int encode_impl(ckc_ctx *c, const double *slots_h, size_t nslots, int level, double scale, uint64_t *m,
-                hipStream_t s);
+                hipStream_t s, bool ext = false);
 int decode_impl(ckc_ctx *c, const uint64_t *m, double scale, double *out_h, size_t nslots, hipStream_t s);
 int secret_impl(ckc_ctx *c, ckc_sk *sk, uint64_t seed, hipStream_t s);
 int switch_key_impl(ckc_ctx *c, const ckc_sk *sk, uint64_t key_id, const uint64_t *sprime, uint64_t *key,
@@ -266,13 +266,15 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
     CKC_TRY(c->rescale_inv.upload(rinv.data(), 8 * rinv.size()));
 
     // ModDown: P^-1 mod q_i, and P -> q_i conversion constants
-    std::vector<uint64_t> pinv(2 * n_q), inv(n_p), invp(n_p), hat(size_t(n_q) * n_p);
+    std::vector<uint64_t> pinv(2 * n_q), pmod(2 * n_q), inv(n_p), invp(n_p), hat(size_t(n_q) * n_p);
     for (int i = 0; i < n_q; ++i) {
         const uint64_t qi = c->mods[i];
         uint64_t P = 1 % qi;
         for (int k = 0; k < n_p; ++k) P = hmul(P, p[k] % qi, qi);
         pinv[2 * i] = hinv(P, qi);
         pinv[2 * i + 1] = hshoup(pinv[2 * i], qi);
+        pmod[2 * i] = P;
+        pmod[2 * i + 1] = hshoup(P, qi);
         for (int a = 0; a < n_p; ++a) {
             uint64_t h = 1 % qi;
             for (int b = 0; b < n_p; ++b)
@@ -293,6 +295,7 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
     }
     CKC_TRY(c->p_to_q.iscale.upload(c->p_to_q.iscale_h.data(), 8 * c->p_to_q.iscale_h.size()));
     CKC_TRY(c->pinv.upload(pinv.data(), 8 * pinv.size()));
+    CKC_TRY(c->pmod.upload(pmod.data(), 8 * pmod.size()));
     c->p_to_q.ns = n_p;
     c->p_to_q.nt = n_q;
     CKC_TRY(c->p_to_q.inv.upload(inv.data(), 8 * n_p));

@@ -29,7 +29,8 @@ struct BconvIn {
 // ModDown epilogue of a forward NTT over [2 nb][nl][N] (batch z = 2 b + p):
 //   out_p.p[b][i][k] = (acc[z][i][k] - ntt[z][i][k]) P^-1 + add_p.p[b][i][perm0?(k)]
 struct CombineOut {
-    const uint64_t *acc;   // same layout as the transformed buffer
+    const uint64_t *acc;   // [z][nl][N] with batch stride acc_bs
+    size_t acc_bs;
     const uint64_t *pinv;  // [nl][2]
     Ptrs add0, add1, out0, out1;
     int has_add0, has_add1;
@@ -70,3 +71,17 @@ int ew_b(ckc_ctx *c, EwOp op, const Ptrs &out, const Ptrs &a, const Ptrs *b, int
 // batch).  dst[i].p[b] receives Rot_{steps[i]}(in.p[b]); step 0 is a copy.
 int hoisted_group(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int level, const std::vector<int32_t> &steps,
                   const std::vector<Ptrs> &dst, hipStream_t s);
+
+// Double hoisting (convolutions): rotations kept in the extended basis Q u P.
+// For every nonzero step i and input b, dst[i].p[b] ([2][l+1+n_P][N]) gets
+//   (P sigma_g(c0) + u0, u1),  u = sum_j sigma_g(ModUp_j(c1)) * key_j,
+// and for step 0 (P c0, P c1) on the Q limbs and zeros on the P limbs; one
+// ModUp per input serves every step.
+int hoisted_group_ext(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int level,
+                      const std::vector<int32_t> &steps, const std::vector<Ptrs> &dst, hipStream_t s);
+
+// ModDown of n extended-basis ciphertexts y ([n][2][l+1+n_P][N], contiguous)
+// into out0.p[b] / out1.p[b] (Q limbs), adding add0.p[b] (Q limbs, NTT form)
+// to polynomial 0 when add0 is given; n <= kMaxBatch.
+int moddown_b(ckc_ctx *c, const uint64_t *y, int n, int level, const Ptrs *add0, const Ptrs &out0, const Ptrs &out1,
+              hipStream_t s);

@@ -113,6 +113,93 @@ KipFn kip_kernel(int dnum) {
     }
 }
 
+// key inner product kept in the extended basis (double hoisting): the same
+// products as k_kip_b, written to dst.p[b] = [2][nt][N] at index scat(m), with
+// P * c0[b][m] added on the Q limbs of polynomial 0 (at the output index
+// scat(m) the rotated c0 is c0[pi_g(scat(m))] = c0[m], so the thread reads
+// its own, coalesced, word of c0).
+template <int DNUM>
+__global__ __launch_bounds__(256) void k_kip_ext(const uint64_t *__restrict__ digits, int nb, int dnum_rt, int nt,
+                                                 int nl, const uint64_t *__restrict__ key, int nprimes, LimbMap map,
+                                                 const uint32_t *__restrict__ scat, Ptrs c0, Ptrs dst,
+                                                 const uint64_t *__restrict__ pmod, const Prime *__restrict__ primes,
+                                                 int logN) {
+    const int tt = blockIdx.y;
+    const size_t N = size_t(1) << logN;
+    const int dnum = DNUM > 0 ? DNUM : dnum_rt;
+    const int pi = map.prime(tt);
+    const Prime P = primes[pi];
+    const size_t dig_bs = size_t(dnum) * nt * N;
+    const bool lowq = tt < nl;
+    const uint64_t pm = lowq ? pmod[2 * tt] : 0, pmp = lowq ? pmod[2 * tt + 1] : 0;
+    constexpr int KD = DNUM > 0 ? DNUM : kMaxDnum;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+        uint64_t kb[KD], ka[KD];
+#pragma unroll
+        for (int j = 0; j < KD; ++j) {
+            if (DNUM > 0 || j < dnum) {
+                kb[j] = key[((size_t(j) * 2 + 0) * nprimes + pi) * N + k];
+                ka[j] = key[((size_t(j) * 2 + 1) * nprimes + pi) * N + k];
+            }
+        }
+        const size_t out = size_t(tt) * N + scat[k];
+        const uint64_t *dg = digits + size_t(tt) * N + k;
+        for (int b = 0; b < nb; ++b) {
+            uint64_t d[KD];
+#pragma unroll
+            for (int j = 0; j < KD; ++j)
+                if (DNUM > 0 || j < dnum) d[j] = dg[size_t(j) * nt * N];
+            accc a0{0, 0, 0, 0, 0}, a1{0, 0, 0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < KD; ++j) {
+                if (DNUM > 0 || j < dnum) {
+                    macc(a0, d[j], kb[j]);
+                    macc(a1, d[j], ka[j]);
+                }
+            }
+            uint64_t u0 = reduce128(accc_value(a0), P);
+            if (lowq) u0 = add_mod(u0, mul_shoup(c0.p[b][size_t(tt) * N + k], pm, pmp, P.q), P.q);
+            uint64_t *o = dst.p[b] + out;
+            o[0] = u0;
+            o[size_t(nt) * N] = reduce128(accc_value(a1), P);
+            dg += dig_bs;
+        }
+    }
+}
+
+using KipExtFn = void (*)(const uint64_t *, int, int, int, int, const uint64_t *, int, LimbMap, const uint32_t *,
+                          Ptrs, Ptrs, const uint64_t *, const Prime *, int);
+KipExtFn kip_ext_kernel(int dnum) {
+    switch (dnum) {
+        case 1: return k_kip_ext<1>;
+        case 2: return k_kip_ext<2>;
+        case 3: return k_kip_ext<3>;
+        case 4: return k_kip_ext<4>;
+        case 5: return k_kip_ext<5>;
+        case 6: return k_kip_ext<6>;
+        case 7: return k_kip_ext<7>;
+        case 8: return k_kip_ext<8>;
+        default: return k_kip_ext<0>;
+    }
+}
+
+// dst.p[b] = [2][nt][N]: P * in.p[b] on the Q limbs, zeros on the P limbs
+__global__ __launch_bounds__(256) void k_lift_P(Ptrs in, Ptrs dst, int nl, int nt, const uint64_t *__restrict__ pmod,
+                                                const Prime *__restrict__ primes, int logN) {
+    const int tt = blockIdx.y, b = blockIdx.z >> 1, p = blockIdx.z & 1;
+    const size_t N = size_t(1) << logN;
+    uint64_t *o = dst.p[b] + (size_t(p) * nt + tt) * N;
+    if (tt >= nl) {
+        for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x)
+            o[k] = 0;
+        return;
+    }
+    const uint64_t q = primes[tt].q, pm = pmod[2 * tt], pmp = pmod[2 * tt + 1];
+    const uint64_t *x = in.p[b] + (size_t(p) * nl + tt) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x)
+        o[k] = mul_shoup(x[k], pm, pmp, q);
+}
+
 // rescale lift for a batch: top[b][p] (coefficient form) -> lift[b][p][i] = centred(top) mod q_i
 __global__ __launch_bounds__(256) void k_rescale_lift_b(const uint64_t *__restrict__ top, int npoly,
                                                         uint64_t *__restrict__ lift, int level,
@@ -238,8 +325,8 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
     CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * nb, size_t(np) * N, s, c->p_to_q.iscale.u64()));
     Ptrs none{};
     const BconvIn in{pl.u64(), size_t(np) * N, np, c->p_to_q.hat.u64(), nullptr, 0, -1, -1};
-    const CombineOut co{acc.u64(), c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none, out0, out1,
-                        add0 ? 1 : 0, add1 ? 1 : 0, perm_add0 ? perm : nullptr};
+    const CombineOut co{acc.u64(), size_t(nl) * N, c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none, out0,
+                        out1, add0 ? 1 : 0, add1 ? 1 : 0, perm_add0 ? perm : nullptr};
     CKC_TRY(ntt_forward_ex(c, conv.u64(), nl, qmap(), 2 * nb, size_t(nl) * N, s, -1, -1, &in, &co));
     return CKC_OK;
 }
@@ -313,4 +400,66 @@ int hoisted_group(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int le
         CKC_TRY(ks_apply_b(c, digits.u64(), nb, level, it->second->u64(), g, &in, nullptr, true, dst[si], o1, s));
     }
     return CKC_OK;
+}
+
+int hoisted_group_ext(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int level,
+                      const std::vector<int32_t> &steps, const std::vector<Ptrs> &dst, hipStream_t s) {
+    const size_t N = c->N;
+    const int nl = level + 1, np = c->np, nt = nl + np, dnum = c->dnum_at(level);
+    const size_t pw = size_t(nl) * N;
+    bool any = false;
+    for (int32_t st : steps) any |= galois_element(c, st) != 1;
+    DevBuf x1, digits;
+    if (any) {
+        CKC_TRY(x1.alloc(8 * pw * nb, s));
+        CKC_TRY(gather(in, pw, x1.u64(), pw, pw, nb, s));
+        CKC_TRY(digits.alloc(8 * N * nt * dnum * nb, s));
+        CKC_TRY(ks_modup_b(c, x1.u64(), pw, nb, level, digits.u64(), s));
+    }
+    const LimbMap ext{nl, c->nq};
+    for (size_t si = 0; si < steps.size(); ++si) {
+        const uint64_t g = galois_element(c, steps[si]);
+        if (g == 1) {
+            CKC_PROF(PK_EW, s, 8.0 * N * nb * 2 * (nl + nt), 0.0);
+            hipLaunchKernelGGL(k_lift_P, dim3(tiles(N), unsigned(nt), unsigned(2 * nb)), dim3(256), 0, s, in, dst[si],
+                               nl, nt, c->pmod.u64(), c->dprimes(), c->logN);
+            CKC_HIP(hipGetLastError());
+            continue;
+        }
+        auto it = evk->galois.find(g);
+        CKC_REQUIRE(it != evk->galois.end(), CKC_ENOKEY, "missing Galois key for step " + std::to_string(steps[si]));
+        int rc;
+        const uint32_t *scat = (const uint32_t *)galois_table(c, galois_inverse(c, g), &rc);
+        if (!scat) return rc;
+        {
+            // algorithmic bytes: digits, key, c0 (Q limbs) and both outputs once
+            const double bytes = 8.0 * N * (nt * (double(nb) * dnum + 2.0 * dnum + 2.0 * nb) + double(nb) * nl);
+            CKC_PROF(PK_KIP, s, bytes, 2.0 * N * nt * dnum * nb);
+            hipLaunchKernelGGL(kip_ext_kernel(dnum), dim3(unsigned(N / 256), unsigned(nt)), dim3(256), 0, s,
+                               digits.u64(), nb, dnum, nt, nl, it->second->u64(), c->nprimes(), ext, scat, in,
+                               dst[si], c->pmod.u64(), c->dprimes(), c->logN);
+        }
+        CKC_HIP(hipGetLastError());
+    }
+    return CKC_OK;
+}
+
+int moddown_b(ckc_ctx *c, const uint64_t *y, int n, int level, const Ptrs *add0, const Ptrs &out0, const Ptrs &out1,
+              hipStream_t s) {
+    if (n <= 0) return CKC_OK;
+    CKC_REQUIRE(n <= kMaxBatch, CKC_EINVAL, "moddown_b: at most 64 ciphertexts per call");
+    const size_t N = c->N;
+    const int nl = level + 1, np = c->np, nt = nl + np;
+    DevBuf pl, conv;
+    CKC_TRY(pl.alloc(8 * N * np * 2 * n, s));
+    CKC_TRY(conv.alloc(8 * N * nl * 2 * n, s));
+    const LimbMap pmap{0, c->nq};
+    // P limbs of every polynomial -> coefficient form, scaled by (P/p_k)^-1
+    CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * n, size_t(np) * N, s, c->p_to_q.iscale.u64(), y + size_t(nl) * N,
+                        size_t(nt) * N));
+    Ptrs none{};
+    const BconvIn in{pl.u64(), size_t(np) * N, np, c->p_to_q.hat.u64(), nullptr, 0, -1, -1};
+    const CombineOut co{y, size_t(nt) * N, c->pinv.u64(), add0 ? *add0 : none, none, out0, out1, add0 ? 1 : 0, 0,
+                        nullptr};
+    return ntt_forward_ex(c, conv.u64(), nl, qmap(), 2 * n, size_t(nl) * N, s, -1, -1, &in, &co);
 }

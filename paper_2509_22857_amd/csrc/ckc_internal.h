@@ -138,6 +138,7 @@ struct ckc_ctx {
     DevMem rescale_inv;             // [nq][nq][2]
     // ModDown P -> Q constants for every Q prime: P^-1 mod q_i (Shoup)
     DevMem pinv;                    // [nq][2]
+    DevMem pmod;                    // [nq][2] P mod q_i (Shoup): lifting into Q u P as P x
     BconvTable p_to_q;              // P -> q_0..q_{nq-1}
     // ModUp tables per (level, digit)
     std::mutex mu;

@@ -179,7 +179,8 @@ __device__ uint64_t dint_mod(double v, const Prime &P) {
 
 // twist by (cos, -sin)(pi k / N) / n, scale, round, reduce into every limb
 __global__ void k_encode_finish(const double2 *__restrict__ Y, const double2 *__restrict__ twist, double delta,
-                                uint64_t *__restrict__ m, int nl, const Prime *__restrict__ primes, int logN) {
+                                uint64_t *__restrict__ m, int nl, LimbMap map, const Prime *__restrict__ primes,
+                                int logN) {
     const size_t N = size_t(1) << logN, n = N / 2;
     const double inv_n = 1.0 / double(n);
     for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
@@ -190,7 +191,7 @@ __global__ void k_encode_finish(const double2 *__restrict__ Y, const double2 *__
         const double wi = y.x * ti + y.y * tr;
         const double a = round(delta * wr), b = round(delta * wi);
         for (int t = 0; t < nl; ++t) {
-            const Prime P = primes[t];
+            const Prime P = primes[map.prime(t)];
             m[size_t(t) * N + k] = dint_mod(a, P);
             m[size_t(t) * N + k + n] = dint_mod(b, P);
         }
@@ -239,7 +240,7 @@ int copy_limbs(const uint64_t *src, size_t src_ps, uint64_t *dst, size_t dst_ps,
 
 // ---------------------------------------------------------------- encode / decode
 int encode_impl(ckc_ctx *c, const double *slots_h, size_t nslots, int level, double scale, uint64_t *m,
-                hipStream_t s) {
+                hipStream_t s, bool ext) {
     const size_t N = c->N, n = N / 2;
     DevBuf zb, yb, tb;
     CKC_TRY(zb.alloc(8 * std::max<size_t>(nslots, 1), s));
@@ -250,10 +251,13 @@ int encode_impl(ckc_ctx *c, const double *slots_h, size_t nslots, int level, dou
     hipLaunchKernelGGL(k_fft_scatter, dim3(tiles(n)), dim3(256), 0, s, (const double *)zb.p, nslots,
                        (const uint32_t *)c->slot_idx.p, (double2 *)yb.p, n);
     CKC_TRY(fft_run(c, (double2 *)yb.p, (double2 *)tb.p, 1, s));
+    // the integer coefficients reduced into q_0..q_level (and, for ext, every P prime)
+    const int nlimbs = level + 1 + (ext ? c->np : 0);
+    const LimbMap map = ext ? LimbMap{level + 1, c->nq} : qmap();
     hipLaunchKernelGGL(k_encode_finish, dim3(tiles(n)), dim3(256), 0, s, (const double2 *)tb.p,
-                       (const double2 *)c->twist.p, scale, m, level + 1, c->dprimes(), c->logN);
+                       (const double2 *)c->twist.p, scale, m, nlimbs, map, c->dprimes(), c->logN);
     CKC_HIP(hipGetLastError());
-    CKC_TRY(ntt_forward(c, m, level + 1, qmap(), 1, 0, s));
+    CKC_TRY(ntt_forward(c, m, nlimbs, map, 1, 0, s));
     // the host array must stay valid until the copy ran
     CKC_HIP(hipStreamSynchronize(s));
     return CKC_OK;

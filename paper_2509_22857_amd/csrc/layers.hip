@@ -21,7 +21,7 @@
 #include "tune.h"
 
 int encode_impl(ckc_ctx *c, const double *slots_h, size_t nslots, int level, double scale, uint64_t *m,
-                hipStream_t s);
+                hipStream_t s, bool ext = false);
 uint64_t galois_element(const ckc_ctx *c, int64_t step);
 
 enum LayerKind { LK_CONV = 0, LK_ACT = 1, LK_DENSE = 2 };
@@ -39,6 +39,7 @@ struct ckc_layer {
     DevMem bias;                       // conv: [O][nl][N]; dense: [K][nl][N]
     DevMem og_off, g_c, g_moff, m_i;   // conv group lists (grouped form, any codebook size)
     DevMem idx8;                       // conv: [ntap][I][Opad] centroid indices (direct form)
+    bool ext = false;                  // conv with rotations: codebook over Q_l u P, one ModDown per output
     int Opad = 0;
     // act
     int C = 0;
@@ -136,7 +137,7 @@ constexpr int kOutPerWg = 4 * kGrpOut;
 // One workgroup: 64 coefficients of one limb of one polynomial, 32 outputs.
 // R_img: [I][ntap][2][nl][N]; pts: [ntap][kcent][nl][N]; bias: [O][nl][N].
 __global__ __launch_bounds__(256) void k_conv_contract(
-    const uint64_t *__restrict__ R, int I, int ntap, int nl, const uint64_t *__restrict__ pts, int kcent,
+    const uint64_t *__restrict__ R, int I, int ntap, int nl, LimbMap map, const uint64_t *__restrict__ pts, int kcent,
     const int32_t *__restrict__ og_off, const int32_t *__restrict__ g_c, const int32_t *__restrict__ g_moff,
     const int32_t *__restrict__ m_i, const uint64_t *__restrict__ bias, Ptrs outs, int o_base, int o_count,
     const Prime *__restrict__ primes, int logN) {
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(256) void k_conv_contract(
     const int poly = blockIdx.z & 1, ogrp = blockIdx.z >> 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const size_t k = size_t(blockIdx.x) * kTile + lane;
-    const Prime P = primes[limb];
+    const Prime P = primes[map.prime(limb)];
     // a sum of n residues stays below 2^64 while (n + 1) q <= 2^64; a sum of
     // products (each < q^2) plus one residue stays below 2^128 for
     // prod_cap <= 2^(128 - 2k) - 1 (k = bit length of q)
@@ -222,7 +223,7 @@ constexpr int kImgPerWg = 4;
 template <int OUTS, int IMGS>
 __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restrict__ R, size_t r_img_words,
                                                            int n_img, int ni, int I, int i_base, int ntap, int nl,
-                                                           const uint64_t *__restrict__ pts, int kcent,
+                                                           LimbMap map, const uint64_t *__restrict__ pts, int kcent,
                                                            const uint8_t *__restrict__ idx8, int Opad,
                                                            const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
                                                            int o_count, int accumulate,
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     const bool active = img < n_img;
     const size_t col0 = size_t(blockIdx.x) * kTile;
     const size_t pw = size_t(nl) * N, ctw = 2 * pw;
-    const Prime P = primes[limb];
+    const Prime P = primes[map.prime(limb)];
     const int pcap = prod_cap(P.k);
     const int ostride = Opad / 8;  // idx rows in 8-byte words
     const size_t rstride = size_t(ntap) * ctw;  // R words between consecutive inputs
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     }
 }
 
-using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, const uint64_t *, int,
+using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, LimbMap, const uint64_t *, int,
                         const uint8_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int);
 // kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images)
 // that holds them; outs = outputs per wave (8 or 16), a tuning choice between
@@ -357,8 +358,12 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
         const int dh = t / ksize - half, dw = t % ksize - half;
         L->tap_step.push_back(in->gap * (dh * in->row_stride + dw));
     }
-    // codebook plaintexts: PT[t][c] = centroid c of column(t), per member, on the tap's mask
-    CKC_TRY(L->pts.alloc(8 * pw * L->ntap * n_centroids));
+    // codebook plaintexts: PT[t][c] = centroid c of column(t), per member, on
+    // the tap's mask.  A layer with rotations sums its products in Q_l u P
+    // (one ModDown per output), so its plaintexts carry the P limbs too.
+    L->ext = ksize > 1;
+    const size_t ppw = L->ext ? size_t(nl + c->np) * N : pw;  // words per codebook plaintext
+    CKC_TRY(L->pts.alloc(8 * ppw * L->ntap * n_centroids));
     std::vector<double> v(n);
     const ckc_layout &Lo = L->lout;
     for (int t = 0; t < L->ntap; ++t) {
@@ -377,7 +382,8 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
                     }
                 }
             }
-            CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(t) * n_centroids + cc) * pw, s));
+            CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(t) * n_centroids + cc) * ppw, s,
+                                L->ext));
         }
     }
     if (bias) {
@@ -577,28 +583,40 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                     "eval_conv: bias scale does not match in.scale * pt_scale");
     hipStream_t s = S(stream);
     const size_t N = c->N;
-    const int nl = L->level + 1, I = L->I, ntap = L->ntap;
-    const size_t pw = size_t(nl) * N, ctw = 2 * pw;
+    const int nl = L->level + 1, I = L->I, ntap = L->ntap, O = L->O;
+    const size_t pw = size_t(nl) * N;
+    // A layer with rotations (ext) keeps every rotated input in Q_l u P and
+    // sums the products there; one ModDown per output polynomial returns to
+    // Q_l and adds the bias.  A 1x1 layer multiplies its inputs directly.
+    const int nlim = L->ext ? nl + c->np : nl;  // limbs of R and of the sums
+    const LimbMap map = L->ext ? LimbMap{nl, c->nq} : qmap();
+    const size_t lpw = size_t(nlim) * N, lctw = 2 * lpw;
     // Input channels in chunks of at most kMaxBatch (one key-switching batch
-    // per image); the contraction accumulates the chunks' partial sums into
-    // the outputs (exact modular sums, so the result does not depend on the
-    // chunking).  Images per pass: at least one contraction group, and enough
-    // to fill a key-switching batch when the layer has few inputs.
+    // per image); the contraction accumulates the chunks' partial sums (exact
+    // modular sums, so the result does not depend on the chunking).  Images
+    // per pass: at least one contraction group, and enough to fill a
+    // key-switching batch when the layer has few inputs.
     const int ichunk = std::min(I, kMaxBatch);
     const int chunk = std::max(kImgPerWg, kMaxBatch / ichunk);
-    const size_t r_img = size_t(ichunk) * ntap * ctw;  // R words per image
-    DevBuf R;
-    CKC_TRY(R.alloc(8 * r_img * std::min(chunk, n_img), s));
+    const int nchunk = std::min(chunk, n_img);
+    const size_t r_img = size_t(ichunk) * ntap * lctw;  // R words per image
+    DevBuf R, Y;
+    CKC_TRY(R.alloc(8 * r_img * nchunk, s));
+    if (L->ext) CKC_TRY(Y.alloc(8 * lctw * O * nchunk, s));
     const size_t lds = size_t(I) * kTile * 8;
     for (int img0 = 0; img0 < n_img; img0 += chunk) {
         const int ni_img = std::min(chunk, n_img - img0);
-        if (!L->idx8.p) {
-            // grouped form (codebooks beyond kMaxCentLds centroids; I <= 128): per image
+        if (!L->idx8.p)
             CKC_REQUIRE(ichunk == I, CKC_EUNSUPPORTED, "grouped contraction needs in_ch <= 64");
-        }
+        // destination of output o of image m of the chunk: its extended-basis
+        // sum (ext) or the caller's ciphertext
+        auto dest = [&](int m, int o) -> uint64_t * {
+            return L->ext ? Y.u64() + (size_t(m) * O + o) * lctw : out[size_t(img0 + m) * O + o].d;
+        };
+        const uint64_t *bias_k = L->ext ? nullptr : (L->has_bias ? L->bias.u64() : nullptr);
         for (int ic0 = 0; ic0 < I; ic0 += ichunk) {
             const int nic = std::min(ichunk, I - ic0);
-            // rotations, in KS batches of <= kMaxBatch inputs: (image in chunk, input channel of the chunk)
+            // rotations, in KS batches: (image in chunk, input channel of the chunk)
             const int total = ni_img * nic;
             const int ksb = tune_value(TK_KS_BATCH);
             for (int b0 = 0; b0 < total; b0 += ksb) {
@@ -609,56 +627,73 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                     const int flat = b0 + b, im = flat / nic, ii = flat - im * nic;
                     ip.p[b] = in[size_t(img0 + im) * I + ic0 + ii].d;
                     for (int t = 0; t < ntap; ++t)
-                        dst[t].p[b] = R.u64() + size_t(im) * r_img + (size_t(ii) * ntap + t) * ctw;
+                        dst[t].p[b] = R.u64() + size_t(im) * r_img + (size_t(ii) * ntap + t) * lctw;
                 }
-                CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
+                if (L->ext)
+                    CKC_TRY(hoisted_group_ext(c, evk, ip, nb, L->level, L->tap_step, dst, s));
+                else
+                    CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
             }
             if (L->idx8.p) {
-                // contraction: groups of kImgPerWg images x `outs` outputs
+                // contraction: groups of up to conv_imgs images x conv_outs outputs
                 const size_t lds_mac = size_t(L->kcent) * kTile * 8;
                 const int outs = tune_value(TK_CONV_OUTS), wg_max = tune_value(TK_CONV_IMGS);
                 for (int g0 = 0; g0 < ni_img; g0 += wg_max) {
                     const int gi = std::min(wg_max, ni_img - g0);
-                    for (int o0 = 0; o0 < L->O; o0 += outs) {
-                        const int oc = std::min(outs, L->O - o0);
+                    for (int o0 = 0; o0 < O; o0 += outs) {
+                        const int oc = std::min(outs, O - o0);
                         Ptrs op{};
                         for (int m = 0; m < gi; ++m)
-                            for (int j = 0; j < oc; ++j)
-                                op.p[m * outs + j] = out[size_t(img0 + g0 + m) * L->O + o0 + j].d;
+                            for (int j = 0; j < oc; ++j) op.p[m * outs + j] = dest(g0 + m, o0 + j);
                         CKC_PROF(PK_CONV_CONTRACT, s,
-                                 8.0 * N * nl * (2.0 * gi * nic * ntap + 2.0 * gi * oc * (ic0 > 0 ? 2 : 1) +
-                                                 double(ntap) * L->kcent),
-                                 2.0 * N * nl * double(gi) * oc * nic * ntap);
+                                 8.0 * N * nlim * (2.0 * gi * nic * ntap + 2.0 * gi * oc * (ic0 > 0 ? 2 : 1) +
+                                                   double(ntap) * L->kcent),
+                                 2.0 * N * nlim * double(gi) * oc * nic * ntap);
                         int wg_imgs = 1;
                         const ConvFn fn = conv_kernel(outs, gi, &wg_imgs);
-                        hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nl)), dim3(128 * wg_imgs), lds_mac,
-                                           s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap, nl,
-                                           L->pts.u64(), L->kcent, (const uint8_t *)L->idx8.p, L->Opad,
-                                           L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, ic0 > 0 ? 1 : 0,
-                                           c->dprimes(), c->logN);
+                        hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
+                                           lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
+                                           nlim, map, L->pts.u64(), L->kcent, (const uint8_t *)L->idx8.p, L->Opad,
+                                           bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN);
                         CKC_HIP(hipGetLastError());
                     }
                 }
-                continue;
-            }
-            // grouped form: per image, outputs in groups of kMaxBatch
-            for (int ii = 0; ii < ni_img; ++ii) {
-                const uint64_t *Rimg = R.u64() + size_t(ii) * r_img;
-                for (int o0 = 0; o0 < L->O; o0 += kMaxBatch) {
-                    const int oc = std::min(kMaxBatch, L->O - o0);
-                    Ptrs op;
-                    for (int j = 0; j < oc; ++j) op.p[j] = out[size_t(img0 + ii) * L->O + o0 + j].d;
-                    const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
-                    CKC_PROF(PK_CONV_CONTRACT, s,
-                             8.0 * N * nl * (2.0 * I * ntap + 2.0 * oc + double(ntap) * L->kcent),
-                             2.0 * N * nl * double(oc) * I * ntap);
-                    hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nl), 2 * ogroups),
-                                       dim3(256), lds, s, Rimg, I, ntap, nl, L->pts.u64(), L->kcent,
-                                       (const int32_t *)L->og_off.p, (const int32_t *)L->g_c.p,
-                                       (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p,
-                                       L->has_bias ? L->bias.u64() : nullptr, op, o0, oc, c->dprimes(), c->logN);
-                    CKC_HIP(hipGetLastError());
+            } else {
+                // grouped form: per image, outputs in groups of kMaxBatch
+                for (int ii = 0; ii < ni_img; ++ii) {
+                    const uint64_t *Rimg = R.u64() + size_t(ii) * r_img;
+                    for (int o0 = 0; o0 < O; o0 += kMaxBatch) {
+                        const int oc = std::min(kMaxBatch, O - o0);
+                        Ptrs op;
+                        for (int j = 0; j < oc; ++j) op.p[j] = dest(ii, o0 + j);
+                        const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
+                        CKC_PROF(PK_CONV_CONTRACT, s,
+                                 8.0 * N * nlim * (2.0 * I * ntap + 2.0 * oc + double(ntap) * L->kcent),
+                                 2.0 * N * nlim * double(oc) * I * ntap);
+                        hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nlim), 2 * ogroups),
+                                           dim3(256), lds, s, Rimg, I, ntap, nlim, map, L->pts.u64(), L->kcent,
+                                           (const int32_t *)L->og_off.p, (const int32_t *)L->g_c.p,
+                                           (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p, bias_k, op, o0,
+                                           oc, c->dprimes(), c->logN);
+                        CKC_HIP(hipGetLastError());
+                    }
                 }
+            }
+        }
+        if (L->ext) {
+            // one ModDown per output polynomial (bias added to polynomial 0)
+            const int total = ni_img * O;
+            for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
+                const int nb = std::min(kMaxBatch, total - b0);
+                Ptrs o0{}, o1{}, bp{};
+                for (int b = 0; b < nb; ++b) {
+                    const int flat = b0 + b, m = flat / O, o = flat - m * O;
+                    o0.p[b] = out[size_t(img0 + m) * O + o].d;
+                    o1.p[b] = o0.p[b] + pw;
+                    if (L->has_bias) bp.p[b] = L->bias.u64() + size_t(o) * pw;
+                }
+                CKC_TRY(moddown_b(c, Y.u64() + size_t(b0) * lctw, nb, L->level, L->has_bias ? &bp : nullptr, o0, o1,
+                                  s));
             }
         }
     }

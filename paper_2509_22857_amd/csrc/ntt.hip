@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows_combine(const uint64_t *_
     const size_t base = size_t(blockIdx.x) * kElems;
     const uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N + base;
     const uint64_t *W = tw + size_t(limb) * N, *Wp = twp + size_t(limb) * N;
-    const uint64_t *x = co.acc + size_t(blockIdx.z) * bs + size_t(limb) * N + base;
+    const uint64_t *x = co.acc + size_t(blockIdx.z) * co.acc_bs + size_t(limb) * N + base;
     const uint64_t pv = co.pinv[2 * limb], pvp = co.pinv[2 * limb + 1];
     const bool has = p == 0 ? co.has_add0 : co.has_add1;
     const uint64_t *ad = has ? (p == 0 ? co.add0.p[b] : co.add1.p[b]) + size_t(limb) * N : nullptr;
