@@ -10,6 +10,7 @@ are already resident in HBM.  The same kernels also run one image at a time
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -30,6 +31,40 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# sources whose change invalidates a kernel class's measured HBM traffic
+TRAFFIC_SOURCES = {"conv_contract": ("paper_2509_22857_amd/csrc/layers.hip", "paper_2509_22857_amd/csrc/modarith.h")}
+
+
+def kernel_source_hash(cls):
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES.get(cls, ()):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cls, workload_key):
+    """HBM bytes per launch of kernel class `cls` from its committed counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    same counter reads for a copy of known size in the same run), or None
+    when there is no summary, it was taken for another workload or launch
+    choice, or the kernel's sources have changed since."""
+    path = os.path.join(ROOT, "profiles", f"{cls}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            k, sep, v = line.partition(": ")
+            if sep and k.strip().replace("_", "").isalnum():
+                rec[k.strip()] = v.strip()
+    if rec.get("sources_sha256_16") != kernel_source_hash(cls) or rec.get("workload_key") != workload_key:
+        return None
+    return {"bytes_per_launch": float(rec["traffic_bytes_per_launch"]),
+            "fetch_bytes_per_launch": float(rec["fetch_bytes_per_launch"]),
+            "write_bytes_per_launch": float(rec["write_bytes_per_launch"])}
+
+
 def calibration_copy(torch):
     """One device copy of a known size (1 GiB read + 1 GiB written): the
     reference kernel for scaling hardware byte counters (FETCH_SIZE,
@@ -39,6 +74,11 @@ def calibration_copy(torch):
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+
+def workload_key(args, tuned):
+    knobs = {k: v for k, v in (tuned or {}).items() if k != "timings"}
+    return f"{args.workload}/batch{args.batch}/pass{args.images_per_pass}/" + json.dumps(knobs, sort_keys=True)
 
 
 def build_workload(args):
@@ -236,7 +276,14 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     roof.update({"avg_launch_ms": round(d["ms"] / launches, 4), "launches": d["launches"],
-                 "hbm_GBs": round(d["bytes"] / (d["ms"] / 1e3) / 1e9, 1) if d["ms"] > 0 else 0.0})
+                 "hbm_GBs": round(d["bytes"] / (d["ms"] / 1e3) / 1e9, 1) if d["ms"] > 0 else 0.0,
+                 "alg_bytes_per_launch": round(d["bytes"] / launches)})
+    wkey = workload_key(args, tuned)
+    tr = measured_traffic(dom, wkey)
+    log(f"traffic key {dom} {kernel_source_hash(dom)} {wkey}: {tr}")
+    if tr is not None:
+        roof["traffic"] = round(tr["bytes_per_launch"])
+        roof["traffic_unit"] = "bytes/launch"
     shares = {k: round(v / max(sum(tot.values()), 1e-9), 3) for k, v in tot.items()}
     busy = sum(tot.values()) / max(ms, 1e-9)
     log(f"profiled kernel time {sum(tot.values()) / 1e3:.2f}s of {ms / 1e3:.2f}s timed ({100 * busy:.1f}%)")

@@ -38,7 +38,7 @@ struct ckc_layer {
     DevMem pts;                        // conv: [ntap][kcent][nl][N]; dense: [K][C][nl][N]
     DevMem bias;                       // conv: [O][nl][N]; dense: [K][nl][N]
     DevMem og_off, g_c, g_moff, m_i;   // conv group lists (grouped form, any codebook size)
-    DevMem idx8;                       // conv: [ntap][I][Opad] centroid indices (direct form)
+    DevMem idx64;                      // conv: [ntap][Opad/8][I] packed byte centroid indices (direct form)
     bool ext = false;                  // conv with rotations: codebook over Q_l u P, one ModDown per output
     int Opad = 0;
     // act
@@ -214,17 +214,20 @@ __global__ __launch_bounds__(256) void k_conv_contract(
 // w >> 1 and polynomial w & 1 and keeps one accumulator per output.  Per tap
 // the tap's whole codebook tile (kcent x 64 words) is staged in LDS once and
 // read by every wave, so the codebook crosses HBM once per group of images and
-// outputs rather than once per image and polynomial.  The centroid index is
-// wave-uniform (scalar loads of 8 packed byte indices); R is read straight
-// from HBM, each element by exactly one wave, for all its outputs.
-// idx8: [ntap][I][Opad] uint8, Opad a multiple of 32.
+// outputs rather than once per image and polynomial.  The centroid indices
+// are wave-uniform: 8 byte indices per 64-bit word, the words of consecutive
+// inputs contiguous so one scalar load brings several; R is read straight
+// from HBM, each element by exactly one wave, for all its outputs, kUnroll
+// inputs ahead of their use.
+// idx64: [ntap][ngrp][I] words, byte j of word (t, g, i) = idx[8 g + j][i][t].
 constexpr int kMaxCentLds = 128;
 constexpr int kImgPerWg = 4;
+constexpr int kUnroll = 4;
 template <int OUTS, int IMGS>
 __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restrict__ R, size_t r_img_words,
                                                            int n_img, int ni, int I, int i_base, int ntap, int nl,
                                                            LimbMap map, const uint64_t *__restrict__ pts, int kcent,
-                                                           const uint8_t *__restrict__ idx8, int Opad,
+                                                           const uint64_t *__restrict__ idx64, int ngrp,
                                                            const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
                                                            int o_count, int accumulate,
                                                            const Prime *__restrict__ primes, int logN) {
@@ -243,9 +246,9 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     const size_t pw = size_t(nl) * N, ctw = 2 * pw;
     const Prime P = primes[map.prime(limb)];
     const int pcap = prod_cap(P.k);
-    const int ostride = Opad / 8;  // idx rows in 8-byte words
     const size_t rstride = size_t(ntap) * ctw;  // R words between consecutive inputs
     const uint64_t *Rb = R + size_t(active ? img : 0) * r_img_words + size_t(poly) * pw + size_t(limb) * N + col0 + lane;
+    const int g0 = o_base / 8;
     accc acc[OUTS];
 #pragma unroll
     for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, 0, 0, 0};
@@ -258,30 +261,41 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
         }
         __syncthreads();
         if (!active) continue;
-        const uint64_t *ix = (const uint64_t *)(idx8 + (size_t(t) * I + i_base) * Opad + o_base);
+        const uint64_t *ixw = idx64 + (size_t(t) * ngrp + g0) * I + i_base;
         const uint64_t *rp = Rb + size_t(t) * ctw;
-        uint64_t r = rp[0], kw[NW];
+        uint64_t rr[kUnroll];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) kw[w] = ix[w];
-        for (int i = 0; i < ni; ++i) {
-            // prefetch the next input's coefficient and index words
-            const int nx = i + 1 < ni ? i + 1 : i;
-            const uint64_t rn = rp[size_t(nx) * rstride];
-            uint64_t kn[NW];
+        for (int u = 0; u < kUnroll; ++u) rr[u] = u < ni ? rp[size_t(u) * rstride] : 0;
+        for (int i = 0; i < ni; i += kUnroll) {
+            // the next block's coefficients, in flight while this block runs
+            uint64_t rn[kUnroll];
 #pragma unroll
-            for (int w = 0; w < NW; ++w) kn[w] = ix[size_t(nx) * ostride + w];
+            for (int u = 0; u < kUnroll; ++u) {
+                const int nx = i + kUnroll + u;
+                rn[u] = nx < ni ? rp[size_t(nx) * rstride] : 0;
+            }
+            uint64_t kw[NW][kUnroll];
 #pragma unroll
             for (int w = 0; w < NW; ++w)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) macc(acc[8 * w + j], r, sP[int((kw[w] >> (8 * j)) & 0xff) * kTile + lane]);
-            if (++cnt == pcap) {
+                for (int u = 0; u < kUnroll; ++u) kw[w][u] = i + u < ni ? ixw[size_t(w) * I + i + u] : 0;
+            if (cnt + kUnroll > pcap) {
 #pragma unroll
                 for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, reduce128(accc_value(acc[j]), P), 0, 0};
                 cnt = 0;
             }
-            r = rn;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) kw[w] = kn[w];
+            for (int u = 0; u < kUnroll; ++u) {
+                if (i + u >= ni) break;
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        macc(acc[8 * w + j], rr[u], sP[int((kw[w][u] >> (8 * j)) & 0xff) * kTile + lane]);
+            }
+            cnt += kUnroll;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) rr[u] = rn[u];
         }
     }
     if (!active) return;
@@ -298,7 +312,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
 }
 
 using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, LimbMap, const uint64_t *, int,
-                        const uint8_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int);
+                        const uint64_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int);
 // kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images)
 // that holds them; outs = outputs per wave (8 or 16), a tuning choice between
 // accumulator registers (occupancy) and codebook re-reads per output group
@@ -419,12 +433,14 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
     // byte indices for the direct form, [tap][input][output padded to 32]
     if (n_centroids <= kMaxCentLds) {
         L->Opad = (out_ch + kOutPerWg - 1) / kOutPerWg * kOutPerWg;
-        std::vector<uint8_t> ix(size_t(L->ntap) * in_ch * L->Opad, 0);
+        const int ngrp = L->Opad / 8;
+        std::vector<uint64_t> ix(size_t(L->ntap) * ngrp * in_ch, 0);
         for (int o = 0; o < out_ch; ++o)
             for (int i = 0; i < in_ch; ++i)
                 for (int t = 0; t < L->ntap; ++t)
-                    ix[(size_t(t) * in_ch + i) * L->Opad + o] = uint8_t(idx[(size_t(o) * in_ch + i) * L->ntap + t]);
-        CKC_TRY(L->idx8.upload(ix.data(), ix.size()));
+                    ix[(size_t(t) * ngrp + o / 8) * in_ch + i] |=
+                        uint64_t(uint8_t(idx[(size_t(o) * in_ch + i) * L->ntap + t])) << (8 * (o % 8));
+        CKC_TRY(L->idx64.upload(ix.data(), 8 * ix.size()));
     }
     if (g_c.empty()) g_c.push_back(0);
     if (m_i.empty()) m_i.push_back(0);
@@ -606,7 +622,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
     const size_t lds = size_t(I) * kTile * 8;
     for (int img0 = 0; img0 < n_img; img0 += chunk) {
         const int ni_img = std::min(chunk, n_img - img0);
-        if (!L->idx8.p)
+        if (!L->idx64.p)
             CKC_REQUIRE(ichunk == I, CKC_EUNSUPPORTED, "grouped contraction needs in_ch <= 64");
         // destination of output o of image m of the chunk: its extended-basis
         // sum (ext) or the caller's ciphertext
@@ -634,7 +650,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                 else
                     CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
             }
-            if (L->idx8.p) {
+            if (L->idx64.p) {
                 // contraction: groups of up to conv_imgs images x conv_outs outputs
                 const size_t lds_mac = size_t(L->kcent) * kTile * 8;
                 const int outs = tune_value(TK_CONV_OUTS), wg_max = tune_value(TK_CONV_IMGS);
@@ -653,7 +669,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                         const ConvFn fn = conv_kernel(outs, gi, &wg_imgs);
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
                                            lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
-                                           nlim, map, L->pts.u64(), L->kcent, (const uint8_t *)L->idx8.p, L->Opad,
+                                           nlim, map, L->pts.u64(), L->kcent, L->idx64.u64(), L->Opad / 8,
                                            bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN);
                         CKC_HIP(hipGetLastError());
                     }

@@ -44,6 +44,12 @@ CKC_HD u128v add128(u128v x, u128v y) {
 // carry), so one product costs four multiply-adds and three adds.  With
 // k-bit residues every product is below 2^(2k), so up to prod_cap(k)
 // products plus one reduced residue keep the value below 2^128.
+// The seven instructions form one block: the four multiply-adds come first,
+// each with its own carry register pair, and every add-with-carry reads its
+// carry at least two instructions after it was written, the distance gfx950
+// requires between a vector write of a scalar register and a vector read of
+// it as carry-in.  Nothing the block writes to a scalar register outlives it,
+// so the compiler has no hazard to pad around it.
 struct accc {
     uint64_t h, m, l;
     uint32_t cm, cl;
@@ -51,14 +57,17 @@ struct accc {
 __device__ __forceinline__ void macc(accc &acc, uint64_t a, uint64_t b) {
 #if defined(__HIP_DEVICE_COMPILE__)
     const uint32_t a0 = uint32_t(a), a1 = uint32_t(a >> 32), b0 = uint32_t(b), b1 = uint32_t(b >> 32);
-    uint64_t c, d;
-    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc.l), "=s"(c) : "v"(a0), "v"(b0));
-    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc.cl), "=s"(d) : "s"(c));
-    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc.m), "=s"(c) : "v"(a0), "v"(b1));
-    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc.cm), "=s"(d) : "s"(c));
-    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc.m), "=s"(c) : "v"(a1), "v"(b0));
-    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc.cm), "=s"(d) : "s"(c));
-    acc.h = uint64_t(a1) * b1 + acc.h;
+    uint64_t c1, c2, c3, j;
+    asm("v_mad_u64_u32 %0, %5, %9, %11, %0\n\t"
+        "v_mad_u64_u32 %1, %6, %9, %12, %1\n\t"
+        "v_mad_u64_u32 %1, %7, %10, %11, %1\n\t"
+        "v_mad_u64_u32 %2, %8, %10, %12, %2\n\t"
+        "v_addc_co_u32_e64 %3, %8, %3, 0, %5\n\t"
+        "v_addc_co_u32_e64 %4, %8, %4, 0, %6\n\t"
+        "v_addc_co_u32_e64 %4, %8, %4, 0, %7"
+        : "+v"(acc.l), "+v"(acc.m), "+v"(acc.h), "+v"(acc.cl), "+v"(acc.cm), "=&s"(c1), "=&s"(c2), "=&s"(c3),
+          "=&s"(j)
+        : "v"(a0), "v"(a1), "v"(b0), "v"(b1));
 #endif
 }
 __device__ __forceinline__ u128v accc_value(const accc &a) {
