@@ -333,7 +333,10 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(uint64_t *__restrict__ da
 //   sum_{k < ns} y_k[i] * hat[t][k]  mod q_t
 // from the pre-scaled coefficient-form source limbs y_k (y = x (S/s_k)^-1 mod
 // s_k); limbs in [copy_lo, copy_hi) are copied from `copy` instead (their NTT
-// form is already known) and left alone by the second pass.
+// form is already known) and left alone by the second pass.  The number of
+// sources NS is a template argument: with a run-time count the compiler
+// executed every one of the kMaxBconv possible products under a mask.
+template <int NS>
 __global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restrict__ data, size_t bs, LimbMap map,
                                                              const Prime *__restrict__ primes,
                                                              const uint64_t *__restrict__ tw,
@@ -359,15 +362,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restric
     const Prime P = primes[pi];
     const uint64_t *W = tw + size_t(pi) * N, *Wp = twp + size_t(pi) * N;
     const uint64_t *src = in.src + size_t(blockIdx.z) * in.src_bs;
-    uint64_t h[kMaxBconv];
+    uint64_t h[NS];
 #pragma unroll
-    for (int k = 0; k < kMaxBconv; ++k) h[k] = k < in.ns ? in.hat[size_t(limb) * in.ns + k] : 0;
-    const int ns = in.ns;
-    auto ld = [src, h, ns, N, P](size_t i) {
+    for (int k = 0; k < NS; ++k) h[k] = in.hat[size_t(limb) * NS + k];
+    auto ld = [src, h, N, P](size_t i) {
         accc acc{0, 0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < kMaxBconv; ++k)
-            if (k < ns) macc(acc, src[size_t(k) * N + i], h[k]);
+        for (int k = 0; k < NS; ++k) macc(acc, src[size_t(k) * N + i], h[k]);
         return reduce128(accc_value(acc), P);
     };
     auto st = [a](size_t i, uint64_t v) { a[i] = v; };
@@ -498,9 +499,15 @@ int ntt_forward_ex(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int n
         const double src = bin ? double(bin->ns) + 2.0 * (nlimbs - active) : double(active);
         const double epi = cout ? 2.5 * active : 1.0 * active;
         CKC_PROF(PK_NTT_FWD, s, W * (src + epi), 0.5 * double(c->N) * c->logN * active * nbatch);
-        if (bin)
-            hipLaunchKernelGGL(k_fwd_cols_bconv, grid, dim3(kThreads), 0, s, d, bs, map, c->dprimes(), c->tw.u64(),
+        if (bin) {
+            using BconvFn = void (*)(uint64_t *, size_t, LimbMap, const Prime *, const uint64_t *, const uint64_t *,
+                                     int, BconvIn);
+            static constexpr BconvFn fns[kMaxBconv] = {k_fwd_cols_bconv<1>, k_fwd_cols_bconv<2>, k_fwd_cols_bconv<3>,
+                                                       k_fwd_cols_bconv<4>, k_fwd_cols_bconv<5>, k_fwd_cols_bconv<6>,
+                                                       k_fwd_cols_bconv<7>, k_fwd_cols_bconv<8>};
+            hipLaunchKernelGGL(fns[bin->ns - 1], grid, dim3(kThreads), 0, s, d, bs, map, c->dprimes(), c->tw.u64(),
                                c->twp.u64(), c->logN, *bin);
+        }
         else
             hipLaunchKernelGGL(k_fwd_cols, grid, dim3(kThreads), 0, s, d, bs, map, c->dprimes(), c->tw.u64(),
                                c->twp.u64(), c->logN, skip_lo, skip_hi);
