@@ -218,7 +218,10 @@ __global__ __launch_bounds__(256) void k_conv_contract(
 // are wave-uniform: 8 byte indices per 64-bit word, the words of consecutive
 // inputs contiguous so one scalar load brings several; R is read straight
 // from HBM, each element by exactly one wave, for all its outputs, kUnroll
-// inputs ahead of their use.
+// inputs ahead of their use (across tap boundaries).  With dbuf the next
+// tap's codebook tile travels from HBM straight into a second LDS buffer
+// (direct-to-LDS loads, two 512-byte rows per wave instruction) while the
+// current tap computes.
 // idx64: [ntap][ngrp][I] words, byte j of word (t, g, i) = idx[8 g + j][i][t].
 constexpr int kMaxCentLds = 128;
 constexpr int kImgPerWg = 4;
@@ -230,10 +233,10 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
                                                            const uint64_t *__restrict__ idx64, int ngrp,
                                                            const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
                                                            int o_count, int accumulate,
-                                                           const Prime *__restrict__ primes, int logN) {
+                                                           const Prime *__restrict__ primes, int logN, int dbuf) {
     static_assert(OUTS % 8 == 0, "outputs per wave come in packed words of 8 indices");
     constexpr int NW = OUTS / 8;
-    extern __shared__ uint64_t sP[];  // [kcent][kTile]
+    extern __shared__ uint64_t sP[];  // [dbuf ? 2 : 1][kcent][kTile]
     const size_t N = size_t(1) << logN;
     const int limb = blockIdx.y;
     const int lane = threadIdx.x & 63;
@@ -253,50 +256,95 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
 #pragma unroll
     for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, 0, 0, 0};
     int cnt = 0;
-    for (int t = 0; t < ntap; ++t) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kcent * kTile; e += 128 * IMGS) {
-            const int c = e / kTile, l = e - c * kTile;
-            sP[e] = pts[((size_t(t) * kcent + c) * nl + limb) * N + col0 + l];
+    // codebook rows 2 pr and 2 pr + 1 of tap t: lane l brings words 2 (l & 31)
+    // and 2 (l & 31) + 1 of row 2 pr + (l >> 5) to LDS address 16 l past the
+    // pair (an odd last row leaves the upper half-wave idle)
+    auto stage = [&](int t, uint64_t *buf) {
+        for (int pr = wave; 2 * pr < kcent; pr += 2 * IMGS) {
+            const int c = 2 * pr + (lane >> 5);
+            if (c < kcent)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(pts + ((size_t(t) * kcent + c) * nl + limb) * N + col0 + 2 * (lane & 31)),
+                    (__attribute__((address_space(3))) void *)(buf + size_t(2 * pr) * kTile), 16, 0, 0);
         }
-        __syncthreads();
-        if (!active) continue;
-        const uint64_t *ixw = idx64 + (size_t(t) * ngrp + g0) * I + i_base;
-        const uint64_t *rp = Rb + size_t(t) * ctw;
-        uint64_t rr[kUnroll];
+    };
+    uint64_t *const buf0 = sP, *const buf1 = dbuf ? sP + size_t(kcent) * kTile : sP;
+    if (dbuf) stage(0, buf0);
+    const uint64_t *ixw0 = idx64 + size_t(g0) * I + i_base;
+    // one block of kUnroll inputs of tap t from codebook tile cb: the products
+    // with the coefficients in cr, while the next block's (this tap's or the
+    // next tap's first) travel into nx.  Indices past the end are clamped to
+    // the last valid input and tap, so every load is unconditional; the two
+    // buffers swap roles block by block, so no coefficient is ever copied
+    // between registers (a copy would wait for its load).
+    auto block = [&](int t, int i, uint64_t(&cr)[kUnroll], uint64_t(&nx)[kUnroll], const uint64_t *cb) {
+        const bool same = i + kUnroll < ni;
+        const int tn = min(same ? t : t + 1, ntap - 1), in0 = same ? i + kUnroll : 0;
+        const uint64_t *rpn = Rb + size_t(tn) * ctw;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) rr[u] = u < ni ? rp[size_t(u) * rstride] : 0;
-        for (int i = 0; i < ni; i += kUnroll) {
-            // the next block's coefficients, in flight while this block runs
-            uint64_t rn[kUnroll];
+        for (int u = 0; u < kUnroll; ++u) nx[u] = rpn[size_t(min(in0 + u, ni - 1)) * rstride];
+        const uint64_t *ixw = ixw0 + size_t(t) * ngrp * I;
+        uint64_t kw[NW][kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int nx = i + kUnroll + u;
-                rn[u] = nx < ni ? rp[size_t(nx) * rstride] : 0;
-            }
-            uint64_t kw[NW][kUnroll];
+        for (int w = 0; w < NW; ++w)
 #pragma unroll
-            for (int w = 0; w < NW; ++w)
+            for (int u = 0; u < kUnroll; ++u) kw[w][u] = ixw[size_t(w) * I + min(i + u, ni - 1)];
+        if (cnt + kUnroll > pcap) {
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) kw[w][u] = i + u < ni ? ixw[size_t(w) * I + i + u] : 0;
-            if (cnt + kUnroll > pcap) {
+            for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, reduce128(accc_value(acc[j]), P), 0, 0};
+            cnt = 0;
+        }
+        // codebook words of the next input are read while this input's
+        // products run
+        uint64_t cv[OUTS];
 #pragma unroll
-                for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, reduce128(accc_value(acc[j]), P), 0, 0};
-                cnt = 0;
-            }
+        for (int w = 0; w < NW; ++w)
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                if (i + u >= ni) break;
+            for (int j = 0; j < 8; ++j) cv[8 * w + j] = cb[int((kw[w][0] >> (8 * j)) & 0xff) * kTile + lane];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (i + u >= ni) break;
+            uint64_t cn[OUTS];
+            if (u + 1 < kUnroll) {
 #pragma unroll
                 for (int w = 0; w < NW; ++w)
 #pragma unroll
                     for (int j = 0; j < 8; ++j)
-                        macc(acc[8 * w + j], rr[u], sP[int((kw[w][u] >> (8 * j)) & 0xff) * kTile + lane]);
+                        cn[8 * w + j] = cb[int((kw[w][u + 1 < kUnroll ? u + 1 : u] >> (8 * j)) & 0xff) * kTile + lane];
             }
-            cnt += kUnroll;
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) rr[u] = rn[u];
+            for (int j = 0; j < OUTS; ++j) macc(acc[j], cr[u], cv[j]);
+            if (u + 1 < kUnroll) {
+#pragma unroll
+                for (int j = 0; j < OUTS; ++j) cv[j] = cn[j];
+            }
         }
+        cnt += kUnroll;
+    };
+    // blocks of the flat (tap, input) stream, two per iteration so that the
+    // buffers swap roles in straight-line code; a tap's first block first
+    // synchronises on its codebook tile and starts the next tap's transfer
+    const int nbt = (ni + kUnroll - 1) / kUnroll, nblk = ntap * nbt;
+    auto step = [&](int b, uint64_t(&cr)[kUnroll], uint64_t(&nx)[kUnroll]) {
+        if (b >= nblk) return;
+        const int t = b / nbt, i = (b - t * nbt) * kUnroll;
+        uint64_t *const cur = (t & 1) ? buf1 : buf0;
+        if (i == 0) {
+            if (!dbuf) {
+                __syncthreads();
+                stage(t, cur);
+            }
+            __syncthreads();
+            if (dbuf && t + 1 < ntap) stage(t + 1, (t & 1) ? buf0 : buf1);
+        }
+        if (active) block(t, i, cr, nx, cur);
+    };
+    uint64_t ra[kUnroll], rb[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) ra[u] = active ? Rb[size_t(min(u, ni - 1)) * rstride] : 0;
+    for (int b = 0; b < nblk; b += 2) {
+        step(b, ra, rb);
+        step(b + 1, rb, ra);
     }
     if (!active) return;
 #pragma unroll
@@ -312,7 +360,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
 }
 
 using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, LimbMap, const uint64_t *, int,
-                        const uint64_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int);
+                        const uint64_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int, int);
 // kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images)
 // that holds them; outs = outputs per wave (8 or 16), a tuning choice between
 // accumulator registers (occupancy) and codebook re-reads per output group
@@ -652,10 +700,17 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
             }
             if (L->idx64.p) {
                 // contraction: groups of up to conv_imgs images x conv_outs outputs
-                const size_t lds_mac = size_t(L->kcent) * kTile * 8;
                 const int outs = tune_value(TK_CONV_OUTS), wg_max = tune_value(TK_CONV_IMGS);
                 for (int g0 = 0; g0 < ni_img; g0 += wg_max) {
                     const int gi = std::min(wg_max, ni_img - g0);
+                    int wg_imgs = 1;
+                    const ConvFn fn = conv_kernel(outs, gi, &wg_imgs);
+                    // two codebook tiles (double buffered) when they fit in
+                    // 64 KiB and the workgroup has four images' waves: with
+                    // fewer waves per workgroup the doubled tile would cut the
+                    // waves a CU can hold
+                    const int dbuf = wg_imgs == kImgPerWg && 2 * size_t(L->kcent) * kTile * 8 <= 65536 ? 1 : 0;
+                    const size_t lds_mac = size_t(1 + dbuf) * L->kcent * kTile * 8;
                     for (int o0 = 0; o0 < O; o0 += outs) {
                         const int oc = std::min(outs, O - o0);
                         Ptrs op{};
@@ -665,12 +720,10 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                                  8.0 * N * nlim * (2.0 * gi * nic * ntap + 2.0 * gi * oc * (ic0 > 0 ? 2 : 1) +
                                                    double(ntap) * L->kcent),
                                  2.0 * N * nlim * double(gi) * oc * nic * ntap);
-                        int wg_imgs = 1;
-                        const ConvFn fn = conv_kernel(outs, gi, &wg_imgs);
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
                                            lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
                                            nlim, map, L->pts.u64(), L->kcent, L->idx64.u64(), L->Opad / 8,
-                                           bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN);
+                                           bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN, dbuf);
                         CKC_HIP(hipGetLastError());
                     }
                 }

