@@ -217,8 +217,8 @@ __global__ __launch_bounds__(256) void k_conv_contract(
 // outputs rather than once per image and polynomial.  The centroid indices
 // are wave-uniform: 8 byte indices per 64-bit word, the words of consecutive
 // inputs contiguous so one scalar load brings several; R is read straight
-// from HBM, each element by exactly one wave, for all its outputs, kUnroll
-// inputs ahead of their use (across tap boundaries).  With dbuf the next
+// from HBM, each element by exactly one wave, for all its outputs, two blocks
+// of kUnroll inputs ahead of their use (across tap boundaries).  With dbuf the next
 // tap's codebook tile travels from HBM straight into a second LDS buffer
 // (direct-to-LDS loads, two 512-byte rows per wave instruction) while the
 // current tap computes.
@@ -271,24 +271,62 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     uint64_t *const buf0 = sP, *const buf1 = dbuf ? sP + size_t(kcent) * kTile : sP;
     if (dbuf) stage(0, buf0);
     const uint64_t *ixw0 = idx64 + size_t(g0) * I + i_base;
-    // one block of kUnroll inputs of tap t from codebook tile cb: the products
-    // with the coefficients in cr, while the next block's (this tap's or the
-    // next tap's first) travel into nx.  Indices past the end are clamped to
-    // the last valid input and tap, so every load is unconditional; the two
-    // buffers swap roles block by block, so no coefficient is ever copied
-    // between registers (a copy would wait for its load).
-    auto block = [&](int t, int i, uint64_t(&cr)[kUnroll], uint64_t(&nx)[kUnroll], const uint64_t *cb) {
-        const bool same = i + kUnroll < ni;
-        const int tn = min(same ? t : t + 1, ntap - 1), in0 = same ? i + kUnroll : 0;
-        const uint64_t *rpn = Rb + size_t(tn) * ctw;
+    // The flat stream of blocks of kUnroll inputs, tap by tap.  Coefficients
+    // travel two blocks ahead of their use in a ring of three register
+    // buffers that swap roles in straight-line code (a register copy would wait
+    // for its load); indices past the end are clamped to the last valid input
+    // and tap, so every load is unconditional.  Positions are kept as
+    // wave-uniform counters (no division).
+    int tc = 0, ic = 0;  // block being computed
+    // next block whose coefficients to fetch: (tp, ip), word offset roff of
+    // its first input from Rb; past the last block the offset stays on the
+    // last valid one
+    int tp = 0, ip = 0;
+    size_t roff = 0;
+    auto load_block = [&](uint64_t(&buf)[kUnroll]) {
+        const uint64_t *rp = Rb + roff;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) nx[u] = rpn[size_t(min(in0 + u, ni - 1)) * rstride];
-        const uint64_t *ixw = ixw0 + size_t(t) * ngrp * I;
-        uint64_t kw[NW][kUnroll];
+        for (int u = 0; u < kUnroll; ++u) {
+            // opaque to the optimiser: a past-the-end offset of 0 must stay a
+            // load of its own (merged with input 0 it becomes a register copy,
+            // and a copy waits for its load)
+            size_t off = ip + u < ni ? size_t(u) * rstride : 0;
+            asm("" : "+s"(off));
+            buf[u] = rp[off];
+        }
+        if (ip + kUnroll < ni) {
+            ip += kUnroll;
+            roff += size_t(kUnroll) * rstride;
+        } else if (tp + 1 < ntap) {
+            ip = 0;
+            ++tp;
+            roff = size_t(tp) * ctw;
+        }
+    };
+    // the index words of a block, one contiguous scalar load per group of 8
+    // outputs (a row's ragged end reads into the next row, the last row into
+    // kUnroll words of zero padding)
+    int tk = 0, ik = 0;
+    size_t koff = 0;
+    auto load_index = [&](uint64_t(&kw)[NW][kUnroll]) {
+        const uint64_t *ixw = ixw0 + koff;
 #pragma unroll
         for (int w = 0; w < NW; ++w)
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) kw[w][u] = ixw[size_t(w) * I + min(i + u, ni - 1)];
+            for (int u = 0; u < kUnroll; ++u) kw[w][u] = ixw[size_t(w) * I + u];
+        if (ik + kUnroll < ni) {
+            ik += kUnroll;
+            koff += kUnroll;
+        } else if (tk + 1 < ntap) {
+            ik = 0;
+            ++tk;
+            koff = size_t(tk) * ngrp * I;
+        }
+    };
+    // the products of the block at (tc, ic): coefficients cr, index words kw,
+    // codebook tile cb
+    auto block = [&](const uint64_t(&cr)[kUnroll], const uint64_t(&kw)[NW][kUnroll], const uint64_t *cb) {
+        const int i = ic;
         if (cnt + kUnroll > pcap) {
 #pragma unroll
             for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, reduce128(accc_value(acc[j]), P), 0, 0};
@@ -321,30 +359,49 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
         }
         cnt += kUnroll;
     };
-    // blocks of the flat (tap, input) stream, two per iteration so that the
-    // buffers swap roles in straight-line code; a tap's first block first
-    // synchronises on its codebook tile and starts the next tap's transfer
-    const int nbt = (ni + kUnroll - 1) / kUnroll, nblk = ntap * nbt;
-    auto step = [&](int b, uint64_t(&cr)[kUnroll], uint64_t(&nx)[kUnroll]) {
-        if (b >= nblk) return;
-        const int t = b / nbt, i = (b - t * nbt) * kUnroll;
-        uint64_t *const cur = (t & 1) ? buf1 : buf0;
-        if (i == 0) {
+    // one block: a tap's first block first synchronises on its codebook tile
+    // (and starts the next tap's transfer); the coefficients two blocks ahead
+    // are fetched before the products, the next block's index words after
+    // them (a wait on a scalar load also waits for every LDS read in flight)
+    auto step = [&](const uint64_t(&cr)[kUnroll], uint64_t(&nx)[kUnroll], const uint64_t(&kc)[NW][kUnroll],
+                    uint64_t(&kn)[NW][kUnroll]) {
+        if (tc >= ntap) return;
+        uint64_t *const cur = (tc & 1) ? buf1 : buf0;
+        if (ic == 0) {
             if (!dbuf) {
                 __syncthreads();
-                stage(t, cur);
+                stage(tc, cur);
             }
             __syncthreads();
-            if (dbuf && t + 1 < ntap) stage(t + 1, (t & 1) ? buf0 : buf1);
+            if (dbuf && tc + 1 < ntap) stage(tc + 1, (tc & 1) ? buf0 : buf1);
         }
-        if (active) block(t, i, cr, nx, cur);
+        if (active) {
+            load_block(nx);
+            block(cr, kc, cur);
+            load_index(kn);
+        }
+        ic += kUnroll;
+        if (ic >= ni) {
+            ic = 0;
+            ++tc;
+        }
     };
-    uint64_t ra[kUnroll], rb[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) ra[u] = active ? Rb[size_t(min(u, ni - 1)) * rstride] : 0;
-    for (int b = 0; b < nblk; b += 2) {
-        step(b, ra, rb);
-        step(b + 1, rb, ra);
+    uint64_t ra[kUnroll], rb[kUnroll], rc[kUnroll];
+    uint64_t ka[NW][kUnroll], kb[NW][kUnroll];
+    if (active) {
+        load_block(ra);
+        load_block(rb);
+        load_index(ka);
+    }
+    // three blocks per iteration: coefficients rotate through three buffers,
+    // index words through two
+    while (tc < ntap) {
+        step(ra, rc, ka, kb);
+        step(rb, ra, kb, ka);
+        step(rc, rb, ka, kb);
+        step(ra, rc, kb, ka);
+        step(rb, ra, ka, kb);
+        step(rc, rb, kb, ka);
     }
     if (!active) return;
 #pragma unroll
@@ -482,7 +539,8 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
     if (n_centroids <= kMaxCentLds) {
         L->Opad = (out_ch + kOutPerWg - 1) / kOutPerWg * kOutPerWg;
         const int ngrp = L->Opad / 8;
-        std::vector<uint64_t> ix(size_t(L->ntap) * ngrp * in_ch, 0);
+        // kUnroll zero words past the end: the kernel reads whole blocks
+        std::vector<uint64_t> ix(size_t(L->ntap) * ngrp * in_ch + kUnroll, 0);
         for (int o = 0; o < out_ch; ++o)
             for (int i = 0; i < in_ch; ++i)
                 for (int t = 0; t < L->ntap; ++t)
