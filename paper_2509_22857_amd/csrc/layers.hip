@@ -38,7 +38,7 @@ struct ckc_layer {
     DevMem pts;                        // conv: [ntap][kcent][nl][N]; dense: [K][C][nl][N]
     DevMem bias;                       // conv: [O][nl][N]; dense: [K][nl][N]
     DevMem og_off, g_c, g_moff, m_i;   // conv group lists (grouped form, any codebook size)
-    DevMem idx64;                      // conv: [ntap][Opad/8][I] packed byte centroid indices (direct form)
+    DevMem ioff;                       // conv: [ntap][Opad/4][I] codebook row byte offsets, 16 bits each (direct form)
     bool ext = false;                  // conv with rotations: codebook over Q_l u P, one ModDown per output
     int Opad = 0;
     // act
@@ -214,15 +214,18 @@ __global__ __launch_bounds__(256) void k_conv_contract(
 // w >> 1 and polynomial w & 1 and keeps one accumulator per output.  Per tap
 // the tap's whole codebook tile (kcent x 64 words) is staged in LDS once and
 // read by every wave, so the codebook crosses HBM once per group of images and
-// outputs rather than once per image and polynomial.  The centroid indices
-// are wave-uniform: 8 byte indices per 64-bit word, the words of consecutive
-// inputs contiguous so one scalar load brings several; R is read straight
+// outputs rather than once per image and polynomial.  The centroid choices
+// are wave-uniform: each is stored as the byte offset of its codebook row in
+// the LDS tile (c * 512, 16 bits), four per 64-bit word, so a product's LDS
+// address costs one scalar field extraction and one vector add; the words of
+// consecutive inputs are contiguous so one scalar load brings several; R is read straight
 // from HBM, each element by exactly one wave, for all its outputs, two blocks
 // of kUnroll inputs ahead of their use (across tap boundaries).  With dbuf the next
 // tap's codebook tile travels from HBM straight into a second LDS buffer
 // (direct-to-LDS loads, two 512-byte rows per wave instruction) while the
 // current tap computes.
-// idx64: [ntap][ngrp][I] words, byte j of word (t, g, i) = idx[8 g + j][i][t].
+// ioff: [ntap][ngrp][I] words, bits 16 j .. 16 j + 15 of word (t, g, i) =
+// 512 * idx[4 g + j][i][t].
 constexpr int kMaxCentLds = 128;
 constexpr int kImgPerWg = 4;
 constexpr int kUnroll = 4;
@@ -230,12 +233,12 @@ template <int OUTS, int IMGS>
 __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restrict__ R, size_t r_img_words,
                                                            int n_img, int ni, int I, int i_base, int ntap, int nl,
                                                            LimbMap map, const uint64_t *__restrict__ pts, int kcent,
-                                                           const uint64_t *__restrict__ idx64, int ngrp,
+                                                           const uint64_t *__restrict__ ioff, int ngrp,
                                                            const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
                                                            int o_count, int accumulate,
                                                            const Prime *__restrict__ primes, int logN, int dbuf) {
-    static_assert(OUTS % 8 == 0, "outputs per wave come in packed words of 8 indices");
-    constexpr int NW = OUTS / 8;
+    static_assert(OUTS % 4 == 0, "outputs per wave come in packed words of 4 offsets");
+    constexpr int NW = OUTS / 4;
     extern __shared__ uint64_t sP[];  // [dbuf ? 2 : 1][kcent][kTile]
     const size_t N = size_t(1) << logN;
     const int limb = blockIdx.y;
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     const int pcap = prod_cap(P.k);
     const size_t rstride = size_t(ntap) * ctw;  // R words between consecutive inputs
     const uint64_t *Rb = R + size_t(active ? img : 0) * r_img_words + size_t(poly) * pw + size_t(limb) * N + col0 + lane;
-    const int g0 = o_base / 8;
+    const int g0 = o_base / 4;
     accc acc[OUTS];
 #pragma unroll
     for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, 0, 0, 0};
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     };
     uint64_t *const buf0 = sP, *const buf1 = dbuf ? sP + size_t(kcent) * kTile : sP;
     if (dbuf) stage(0, buf0);
-    const uint64_t *ixw0 = idx64 + size_t(g0) * I + i_base;
+    const uint64_t *ixw0 = ioff + size_t(g0) * I + i_base;
     // The flat stream of blocks of kUnroll inputs, tap by tap.  Coefficients
     // travel two blocks ahead of their use in a ring of three register
     // buffers that swap roles in straight-line code (a register copy would wait
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
             roff = size_t(tp) * ctw;
         }
     };
-    // the index words of a block, one contiguous scalar load per group of 8
+    // the offset words of a block, one contiguous scalar load per group of 4
     // outputs (a row's ragged end reads into the next row, the last row into
     // kUnroll words of zero padding)
     int tk = 0, ik = 0;
@@ -334,11 +337,15 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
         }
         // codebook words of the next input are read while this input's
         // products run
+        const char *cbl = (const char *)(cb + lane);
+        auto word = [&](uint64_t k, int j) {
+            return *(const uint64_t *)(cbl + uint32_t(k >> (16 * j)) % 65536u);
+        };
         uint64_t cv[OUTS];
 #pragma unroll
         for (int w = 0; w < NW; ++w)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) cv[8 * w + j] = cb[int((kw[w][0] >> (8 * j)) & 0xff) * kTile + lane];
+            for (int j = 0; j < 4; ++j) cv[4 * w + j] = word(kw[w][0], j);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (i + u >= ni) break;
@@ -347,8 +354,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
 #pragma unroll
                 for (int w = 0; w < NW; ++w)
 #pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        cn[8 * w + j] = cb[int((kw[w][u + 1 < kUnroll ? u + 1 : u] >> (8 * j)) & 0xff) * kTile + lane];
+                    for (int j = 0; j < 4; ++j) cn[4 * w + j] = word(kw[w][u + 1 < kUnroll ? u + 1 : u], j);
             }
 #pragma unroll
             for (int j = 0; j < OUTS; ++j) macc(acc[j], cr[u], cv[j]);
@@ -535,18 +541,19 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
             }
             og_off.push_back(int32_t(g_c.size()));
         }
-    // byte indices for the direct form, [tap][input][output padded to 32]
+    // codebook row byte offsets for the direct form, [tap][output group of
+    // 4][input], outputs padded to a multiple of 32
     if (n_centroids <= kMaxCentLds) {
         L->Opad = (out_ch + kOutPerWg - 1) / kOutPerWg * kOutPerWg;
-        const int ngrp = L->Opad / 8;
+        const int ngrp = L->Opad / 4;
         // kUnroll zero words past the end: the kernel reads whole blocks
         std::vector<uint64_t> ix(size_t(L->ntap) * ngrp * in_ch + kUnroll, 0);
         for (int o = 0; o < out_ch; ++o)
             for (int i = 0; i < in_ch; ++i)
                 for (int t = 0; t < L->ntap; ++t)
-                    ix[(size_t(t) * ngrp + o / 8) * in_ch + i] |=
-                        uint64_t(uint8_t(idx[(size_t(o) * in_ch + i) * L->ntap + t])) << (8 * (o % 8));
-        CKC_TRY(L->idx64.upload(ix.data(), 8 * ix.size()));
+                    ix[(size_t(t) * ngrp + o / 4) * in_ch + i] |=
+                        uint64_t(uint32_t(idx[(size_t(o) * in_ch + i) * L->ntap + t]) * kTile * 8) << (16 * (o % 4));
+        CKC_TRY(L->ioff.upload(ix.data(), 8 * ix.size()));
     }
     if (g_c.empty()) g_c.push_back(0);
     if (m_i.empty()) m_i.push_back(0);
@@ -728,7 +735,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
     const size_t lds = size_t(I) * kTile * 8;
     for (int img0 = 0; img0 < n_img; img0 += chunk) {
         const int ni_img = std::min(chunk, n_img - img0);
-        if (!L->idx64.p)
+        if (!L->ioff.p)
             CKC_REQUIRE(ichunk == I, CKC_EUNSUPPORTED, "grouped contraction needs in_ch <= 64");
         // destination of output o of image m of the chunk: its extended-basis
         // sum (ext) or the caller's ciphertext
@@ -756,7 +763,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                 else
                     CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
             }
-            if (L->idx64.p) {
+            if (L->ioff.p) {
                 // contraction: groups of up to conv_imgs images x conv_outs outputs
                 const int outs = tune_value(TK_CONV_OUTS), wg_max = tune_value(TK_CONV_IMGS);
                 for (int g0 = 0; g0 < ni_img; g0 += wg_max) {
@@ -780,7 +787,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                                  2.0 * N * nlim * double(gi) * oc * nic * ntap);
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
                                            lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
-                                           nlim, map, L->pts.u64(), L->kcent, L->idx64.u64(), L->Opad / 8,
+                                           nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(), L->Opad / 4,
                                            bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN, dbuf);
                         CKC_HIP(hipGetLastError());
                     }
