@@ -133,18 +133,95 @@ __device__ __forceinline__ void rows_generic(Ld ld, St st, bool inverse, uint64_
 // 256-point pass is two such blocks with one LDS exchange between them.
 // Harvey's lazy reduction keeps values in [0, 4q) (forward) or [0, 2q)
 // (inverse) between stages; the last stage reduces into [0, q).
+//
+// Each butterfly is one block of instructions over four fixed scratch pairs
+// v56..v63 (clobbered, so the compiler keeps nothing there across it):
+//  * the Shoup quotient qh = hi64(Y w') exactly: A = y1 p0 + hi32(y0 p0)
+//    (no overflow), A' = y0 p1 + A with its carry k out of 2^64, then
+//    qh = y1 p1 + (hi32(A') + k 2^32) as one multiply-add whose addend pair
+//    is {hi32(A'), k};
+//  * t = Y w - qh q mod 2^64 as Y w + qh (2^64 - q): multiply-adds and
+//    low-word products only, no 64-bit subtraction;
+//  * conditional subtractions of 2q through a mask-selected pair added with
+//    one 64-bit add, and x - t + 2q as x + (2q + 1) + ~t.
+// gfx950 needs two instructions between a vector write of a scalar register
+// and its read (carry-in or mask); the orders below keep that distance.  The
+// compiler's own code for the same formulas spends ~30 instructions per
+// butterfly (half a dozen of them register moves building multiply-add
+// addend pairs), these 24 and 25.
+#define CKC_BFLY_CLOBBERS "v56", "v57", "v58", "v59", "v60", "v61", "v62", "v63"
 __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp, uint64_t q, uint64_t q2) {
-    const uint64_t x = X >= q2 ? X - q2 : X;
-    const uint64_t t = mul_shoup_lazy(Y, w, wp, q);
-    X = x + t;
-    Y = x - t + q2;
+    const uint64_t qn = 0 - q, nq2 = 0 - q2, q2p1 = q2 + 1;
+    uint64_t xo, yo, m, k, j;
+    asm("v_cmp_ge_u64_e64 %[m], %[X], %[q2]\n\t"
+        "v_mul_hi_u32 v56, %[y0], %[p0]\n\t"
+        "v_mov_b32 v57, 0\n\t"
+        "v_mad_u64_u32 v[56:57], %[j], %[y1], %[p0], v[56:57]\n\t"
+        "v_mad_u64_u32 v[58:59], %[j], %[y0], %[w0], 0\n\t"
+        "v_mad_u64_u32 v[56:57], %[k], %[y0], %[p1], v[56:57]\n\t"
+        "v_mul_lo_u32 v60, %[y0], %[w1]\n\t"
+        "v_mul_lo_u32 v61, %[y1], %[w0]\n\t"
+        "v_mov_b32 v56, v57\n\t"
+        "v_addc_co_u32_e64 v57, %[j], 0, 0, %[k]\n\t"
+        "v_mad_u64_u32 v[56:57], %[j], %[y1], %[p1], v[56:57]\n\t"
+        "v_add3_u32 v59, v59, v60, v61\n\t"
+        "v_mad_u64_u32 v[58:59], %[j], v56, %[qn0], v[58:59]\n\t"
+        "v_mul_lo_u32 v60, v56, %[qn1]\n\t"
+        "v_mul_lo_u32 v61, v57, %[qn0]\n\t"
+        "v_cndmask_b32_e64 v62, 0, %[nq2lo], %[m]\n\t"
+        "v_cndmask_b32_e64 v63, 0, %[nq2hi], %[m]\n\t"
+        "v_add3_u32 v59, v59, v60, v61\n\t"
+        "v_lshl_add_u64 v[62:63], %[X], 0, v[62:63]\n\t"
+        "v_lshl_add_u64 %[xo], v[62:63], 0, v[58:59]\n\t"
+        "v_not_b32 v60, v58\n\t"
+        "v_not_b32 v61, v59\n\t"
+        "v_lshl_add_u64 v[62:63], v[62:63], 0, %[q2p1]\n\t"
+        "v_lshl_add_u64 %[yo], v[62:63], 0, v[60:61]"
+        : [xo] "=&v"(xo), [yo] "=&v"(yo), [m] "=&s"(m), [k] "=&s"(k), [j] "=&s"(j)
+        : [X] "v"(X), [q2] "v"(q2), [y0] "v"(uint32_t(Y)), [y1] "v"(uint32_t(Y >> 32)), [w0] "v"(uint32_t(w)),
+          [w1] "v"(uint32_t(w >> 32)), [p0] "v"(uint32_t(wp)), [p1] "v"(uint32_t(wp >> 32)),
+          [qn0] "v"(uint32_t(qn)), [qn1] "v"(uint32_t(qn >> 32)), [nq2lo] "v"(uint32_t(nq2)),
+          [nq2hi] "v"(uint32_t(nq2 >> 32)), [q2p1] "v"(q2p1)
+        : CKC_BFLY_CLOBBERS);
+    X = xo;
+    Y = yo;
 }
 __device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp, uint64_t q, uint64_t q2) {
-    uint64_t s = X + Y;
-    s = s >= q2 ? s - q2 : s;
-    const uint64_t d = X - Y + q2;
-    X = s;
-    Y = mul_shoup_lazy(d, w, wp, q);
+    const uint64_t qn = 0 - q, nq2 = 0 - q2, q2p1 = q2 + 1;
+    uint64_t xo, yo, m, k, j;
+    asm("v_lshl_add_u64 v[62:63], %[X], 0, %[Y]\n\t"
+        "v_not_b32 v60, %[y0]\n\t"
+        "v_not_b32 v61, %[y1]\n\t"
+        "v_cmp_ge_u64_e64 %[m], v[62:63], %[q2]\n\t"
+        "v_lshl_add_u64 v[58:59], %[X], 0, %[q2p1]\n\t"
+        "v_lshl_add_u64 v[58:59], v[58:59], 0, v[60:61]\n\t"
+        "v_mul_hi_u32 v56, v58, %[p0]\n\t"
+        "v_mov_b32 v57, 0\n\t"
+        "v_mad_u64_u32 v[56:57], %[j], v59, %[p0], v[56:57]\n\t"
+        "v_cndmask_b32_e64 v60, 0, %[nq2lo], %[m]\n\t"
+        "v_mad_u64_u32 v[56:57], %[k], v58, %[p1], v[56:57]\n\t"
+        "v_cndmask_b32_e64 v61, 0, %[nq2hi], %[m]\n\t"
+        "v_lshl_add_u64 %[xo], v[62:63], 0, v[60:61]\n\t"
+        "v_mov_b32 v56, v57\n\t"
+        "v_addc_co_u32_e64 v57, %[j], 0, 0, %[k]\n\t"
+        "v_mad_u64_u32 v[56:57], %[j], v59, %[p1], v[56:57]\n\t"
+        "v_mul_lo_u32 v60, v58, %[w1]\n\t"
+        "v_mul_lo_u32 v61, v59, %[w0]\n\t"
+        "v_mul_lo_u32 v62, v56, %[qn1]\n\t"
+        "v_mul_lo_u32 v63, v57, %[qn0]\n\t"
+        "v_add3_u32 v61, v60, v61, v62\n\t"
+        "v_add_u32 v61, v61, v63\n\t"
+        "v_mov_b32 v60, 0\n\t"
+        "v_mad_u64_u32 %[yo], %[j], v58, %[w0], v[60:61]\n\t"
+        "v_mad_u64_u32 %[yo], %[j], v56, %[qn0], %[yo]"
+        : [xo] "=&v"(xo), [yo] "=&v"(yo), [m] "=&s"(m), [k] "=&s"(k), [j] "=&s"(j)
+        : [X] "v"(X), [Y] "v"(Y), [q2] "v"(q2), [y0] "v"(uint32_t(Y)), [y1] "v"(uint32_t(Y >> 32)),
+          [w0] "v"(uint32_t(w)), [w1] "v"(uint32_t(w >> 32)), [p0] "v"(uint32_t(wp)), [p1] "v"(uint32_t(wp >> 32)),
+          [qn0] "v"(uint32_t(qn)), [qn1] "v"(uint32_t(qn >> 32)), [nq2lo] "v"(uint32_t(nq2)),
+          [nq2hi] "v"(uint32_t(nq2 >> 32)), [q2p1] "v"(q2p1)
+        : CKC_BFLY_CLOBBERS);
+    X = xo;
+    Y = yo;
 }
 // stage s pairs j, j + (8 >> s) inside groups g of 2 (8 >> s); twiddle index idx(s, g)
 template <class F>
