@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--tune", default="cached", choices=["cached", "fresh", "off"],
                     help="autotuner: stored choices for this workload if any (else tune), re-tune, or defaults")
     ap.add_argument("--workload", default="resnet20", choices=["resnet20", "vgg", "micro", "serving"])
-    ap.add_argument("--clients", type=int, default=8, help="serving: clients with their own keys")
+    ap.add_argument("--clients", type=int, default=4, help="serving: clients with their own keys")
     ap.add_argument("--serve-rates", default="2,5,10,20", help="serving: Poisson arrival rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=16, help="serving: requests per rate")
     ap.add_argument("--serve-max-images", type=int, default=8, help="serving: images per batch")

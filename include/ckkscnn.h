@@ -314,6 +314,25 @@ int ckc_prof_query(const char *kernel, int64_t *launches, double *total_ms, doub
 int ckc_tune_set(const char *knob, int value);
 int ckc_tune_get(const char *knob, int *value);
 
+/* ------------------------------------------------------------------ memory
+ * Scratch memory (rotated inputs, digits, key-switching buffers) comes from
+ * one growable arena per (device, stream) that keeps its largest size so that
+ * steady-state calls allocate nothing.  ckc_stream_release frees the arena of
+ * `stream` (a hipStream_t; NULL = the default stream) on the current device
+ * after waiting for the work queued on it, and returns what the device's
+ * default memory pool caches (overflow buffers) to the device; the next call
+ * on the stream grows a new arena.  For callers that bound device memory per stream, such as a
+ * serving loop releasing a finished batch's stream.  ckc_stream_reserve
+ * grows the stream's arena to at least `bytes` now (one allocation), so that
+ * the calls of a batch whose scratch peak the caller knows allocate nothing
+ * while it runs.  Neither is to be called while another thread has a call
+ * running on the same stream.
+ * Errors: CKC_EINVAL if a call on the stream still holds scratch;
+ * CKC_ENOMEM if the reservation cannot be allocated; CKC_EDEVICE on a HIP
+ * error. */
+int ckc_stream_release(void *stream);
+int ckc_stream_reserve(void *stream, size_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -105,6 +105,8 @@ _SIGS = [
     ("ckc_prof_query", C.c_int, [C.c_char_p, C.POINTER(C.c_int64), _dblp, _dblp, _dblp]),
     ("ckc_tune_set", C.c_int, [C.c_char_p, C.c_int]),
     ("ckc_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
+    ("ckc_stream_release", C.c_int, [C.c_void_p]),
+    ("ckc_stream_reserve", C.c_int, [C.c_void_p, C.c_size_t]),
 ]
 
 
@@ -577,6 +579,17 @@ def tune_get(knob: str) -> int:
 
 
 TUNE_KNOBS = {"conv_outs": (8, 16), "conv_imgs": (1, 2, 4), "ks_batch": (16, 32, 64)}
+
+
+def stream_release(stream=None):
+    """Free the library's scratch arena of `stream` (after its queued work);
+    the next call on the stream grows a new one."""
+    _check("ckc_stream_release", lib().ckc_stream_release(_stream(stream)))
+
+
+def stream_reserve(nbytes: int, stream=None):
+    """Grow the library's scratch arena of `stream` to at least nbytes now."""
+    _check("ckc_stream_reserve", lib().ckc_stream_reserve(_stream(stream), C.c_size_t(int(nbytes))))
 
 PROF_KERNELS = ("ntt_fwd", "ntt_inv", "bconv", "kip", "moddown", "conv_contract", "act_tensor", "rescale",
                 "dense_mac", "ew", "mac_plain", "tensor", "copy")

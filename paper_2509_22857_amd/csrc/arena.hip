@@ -67,6 +67,13 @@ int arena_alloc(hipStream_t s, size_t bytes, void **p, Arena **out, size_t *off)
                 a->base = nullptr;
                 a->cap = 0;
             }
+            // overflow buffers of earlier calls went back to the device's
+            // default pool, which keeps them: return them to the device first
+            hipMemPool_t pool;
+            if (a->high > 0 && hipDeviceGetDefaultMemPool(&pool, a->dev) == hipSuccess) {
+                CKC_HIP(hipStreamSynchronize(s));
+                (void)hipMemPoolTrimTo(pool, 0);
+            }
             hipError_t e = hipMalloc((void **)&a->base, want);
             if (e != hipSuccess) {
                 a->base = nullptr;
@@ -140,4 +147,75 @@ void arena_trim() {
             ++it;
         }
     }
+}
+
+int arena_trim_stream(hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        ckc_set_error(std::string("hipGetDevice: ") + hipGetErrorString(e));
+        return CKC_EDEVICE;
+    }
+    Arena *a = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_arenas.find({dev, s});
+        if (it == g_arenas.end()) return CKC_OK;
+        a = it->second;
+        {
+            std::lock_guard<std::mutex> la(a->mu);
+            if (a->top != 0 || a->overflow_live != 0) {
+                ckc_set_error("ckc_stream_release: a call on the stream still holds scratch");
+                return CKC_EINVAL;
+            }
+        }
+        g_arenas.erase(it);
+    }
+    // the stream's queued work may still use the buffer
+    e = hipStreamSynchronize(s);
+    if (a->base) (void)hipFree(a->base);
+    delete a;
+    // overflow buffers went back to the device's default pool: return what
+    // it caches to the device so that later hipMalloc calls can use it
+    hipMemPool_t pool;
+    if (e == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    if (e != hipSuccess) {
+        ckc_set_error(std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+        return CKC_EDEVICE;
+    }
+    return CKC_OK;
+}
+
+int arena_reserve_stream(hipStream_t s, size_t bytes) {
+    int rc = CKC_OK;
+    Arena *a = arena_for(s, &rc);
+    if (!a) return rc;
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    std::lock_guard<std::mutex> lk(a->mu);
+    CKC_REQUIRE(a->top == 0 && a->overflow_live == 0, CKC_EINVAL,
+                "ckc_stream_reserve: a call on the stream still holds scratch");
+    if (bytes > a->cap) {
+        CKC_HIP(hipStreamSynchronize(s));
+        if (a->base) {
+            CKC_HIP(hipFree(a->base));
+            a->base = nullptr;
+            a->cap = 0;
+        }
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, a->dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+        hipError_t e = hipMalloc((void **)&a->base, bytes);
+        if (e != hipSuccess) {
+            a->base = nullptr;
+            ckc_set_error(std::string("ckc_stream_reserve hipMalloc: ") + hipGetErrorString(e));
+            return CKC_ENOMEM;
+        }
+        a->cap = bytes;
+    }
+    a->high = std::max(a->high, bytes);
+    return CKC_OK;
+}
+
+extern "C" int ckc_stream_release(void *stream) { return arena_trim_stream((hipStream_t)stream); }
+extern "C" int ckc_stream_reserve(void *stream, size_t bytes) {
+    return arena_reserve_stream((hipStream_t)stream, bytes);
 }

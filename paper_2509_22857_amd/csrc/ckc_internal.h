@@ -63,6 +63,10 @@ int arena_alloc(hipStream_t s, size_t bytes, void **p, Arena **a, size_t *off);
 void arena_release(Arena *a, size_t off, void *p, hipStream_t s);
 // release the unused arenas of the current device (their streams idle)
 void arena_trim();
+// frees the arena of (current device, s) once the stream is idle
+int arena_trim_stream(hipStream_t s);
+// grows the (idle) arena of (current device, s) to at least `bytes`
+int arena_reserve_stream(hipStream_t s, size_t bytes);
 
 // RAII scratch buffer from the stream's arena.
 struct DevBuf {

@@ -288,15 +288,26 @@ class GpuNetwork:
         return outs
 
     def working_set_bytes(self, n_img: int) -> int:
-        """Upper estimate of the device bytes one pass of n_img images holds at
-        once: the live tensors around every layer plus that layer's scratch
-        (rotated inputs, digits and key-switching buffers of one batch of 64)."""
+        """Upper estimate of the device bytes one pass of n_img images holds:
+        the most live tensors around any layer plus the largest scratch of any
+        layer (rotated inputs, a 3x3 layer's outputs over Q_l and P, digits
+        and key-switching buffers of one batch of 64), which the stream's
+        scratch arena keeps for the whole pass."""
+        held, scratch = self._memory(n_img)
+        return int(1.1 * (held + scratch))
+
+    def scratch_bytes(self, n_img: int) -> int:
+        """Upper estimate of the largest scratch one call of a pass of n_img
+        images takes (the size to reserve for the stream's arena)."""
+        return int(1.1 * self._memory(n_img)[1])
+
+    def _memory(self, n_img: int):
         N = self.ctx.N
         np_ = len(self.ctx.p)
         ct = lambda level, npoly=2: 8 * npoly * (level + 1) * N
         level_of = {"x": len(self.ctx.q) - 1}
         count_of = {"x": self.spec["image"][0]}
-        peak = 0
+        max_held = max_scratch = 0
         live = {"x"}
         for ly, p in zip(self.spec["layers"], self.plans):
             lvl = p.level
@@ -314,19 +325,25 @@ class GpuNetwork:
             dnum = -(-nl // self.ctx.alpha)
             ks = 64 * 8 * N * (dnum * nt + 2 * nl + 2 * np_ + 2 * nl + nl)
             if ly["op"] == "conv":
+                # rotated inputs of one input-channel chunk (at most 64) for a
+                # group of images; a 3x3 layer keeps them, and its outputs
+                # before ModDown, over Q_l and P
                 I, taps = ly["in_ch"], ly["ksize"] ** 2
-                chunk = max(4, 64 // I)
-                scratch = min(chunk, n_img) * I * taps * ct(lvl) + ks
+                ich = min(I, 64)
+                nimg = min(max(4, 64 // ich), n_img)
+                ext = ly["ksize"] > 1
+                cte = 8 * 2 * (nt if ext else nl) * N
+                scratch = nimg * ich * taps * cte + (nimg * cnt * cte if ext else 0) + ks
                 if ly.get("short") is not None:
                     held += n_img * cnt * ct(p.short_level)
             elif ly["op"] == "act":
                 scratch = 64 * ct(lvl, 3) + ks
             else:
                 scratch = 2 * n_img * cnt * ct(lvl) + ks
-            peak = max(peak, held + scratch)
+            max_held, max_scratch = max(max_held, held), max(max_scratch, scratch)
             live = set(self._later[ly["name"]]) | {ly["out"]}
             live = {t for t in live if t in level_of}
-        return int(peak * 1.1)
+        return max_held, max_scratch
 
 
 class _NoScope:

@@ -64,7 +64,7 @@ def run(args, log) -> dict:
     kb = sum(k.evk_bytes() for k in keys.values())
     log(f"{len(keys)} clients' keys: {kb / 2**30:.1f} GiB in {time.time() - t0:.1f}s")
     free, total = torch.cuda.mem_get_info()
-    budget = int(0.9 * free) + kb
+    budget = int(0.8 * free) + kb
     srv = Server(networks, budget, max_images=args.serve_max_images, n_streams=args.serve_streams)
     for (c, net), k in keys.items():
         srv.register_client(c, net, k)

@@ -5,14 +5,17 @@ The server holds every network's layers and every registered client's
 evaluation keys on the device, and runs a single host loop that
 
   * admits queued requests in arrival order while the HBM budget covers the
-    working set of the batch they would start (keys are already resident);
+    working set of the batch they would start (keys are already resident),
+    and sizes the scratch arena of the batch's stream for its largest call;
   * merges queued requests of the same client and network into one batch
     (their images share every key-switching and contraction launch);
   * runs every admitted batch on its own HIP stream, one layer per step, with
     at most `window` layers enqueued ahead of the GPU, so batches admitted
     while others are on the device overlap with them;
-  * retires a batch when its last layer's event has completed and releases
-    its memory reservation, which lets the next queued requests in.
+  * retires a batch when its last layer's event has completed, frees its
+    stream's scratch arena (the library keeps one per stream at its largest
+    size otherwise) and the blocks torch keeps cached, and releases its memory
+    reservation, which lets the next queued requests in.
 
 Each image's result does not depend on which other requests shared its batch
 or ran beside it (every kernel computes each ciphertext independently), so a
@@ -131,6 +134,9 @@ class Server:
                     r.admitted = now
                     r.batch_id = next_bid
                 stream = free_streams.pop()
+                # the batch's largest scratch is allocated now, so its calls
+                # allocate nothing while it runs (part of the reservation)
+                ckks.stream_reserve(net.scratch_bytes(n_img), stream)
                 # inputs were written on the submitting stream
                 stream.wait_stream(torch.cuda.current_stream())
                 inputs = [row for r in group for row in r.inputs]
@@ -166,6 +172,10 @@ class Server:
                         i += len(r.inputs)
                         r.done = t_done
                     running.remove(b)
+                    # the stream's scratch arena and the blocks torch keeps
+                    # cached go with the reservation
+                    ckks.stream_release(b.stream)
+                    torch.cuda.empty_cache()
                     free_streams.append(b.stream)
                     self.reserved -= b.reserve
                     progressed = True
