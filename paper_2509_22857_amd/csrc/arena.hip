@@ -78,6 +78,7 @@ int arena_alloc(hipStream_t s, size_t bytes, void **p, Arena **out, size_t *off)
             if (e != hipSuccess) {
                 a->base = nullptr;
                 ckc_set_error(std::string("scratch arena hipMalloc: ") + hipGetErrorString(e));
+                (void)hipGetLastError();  // the failure is reported here, not by the next launch check
                 return CKC_ENOMEM;
             }
             a->cap = want;
@@ -93,6 +94,7 @@ int arena_alloc(hipStream_t s, size_t bytes, void **p, Arena **out, size_t *off)
         if (e != hipSuccess) {
             *p = nullptr;
             ckc_set_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
+            (void)hipGetLastError();  // reported here, not by the next launch check
             return CKC_ENOMEM;
         }
         *off = SIZE_MAX;
@@ -207,6 +209,7 @@ int arena_reserve_stream(hipStream_t s, size_t bytes) {
         if (e != hipSuccess) {
             a->base = nullptr;
             ckc_set_error(std::string("ckc_stream_reserve hipMalloc: ") + hipGetErrorString(e));
+            (void)hipGetLastError();  // reported here, not by the next launch check
             return CKC_ENOMEM;
         }
         a->cap = bytes;

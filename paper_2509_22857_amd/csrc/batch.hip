@@ -167,6 +167,85 @@ __global__ __launch_bounds__(256) void k_kip_ext(const uint64_t *__restrict__ di
     }
 }
 
+// The same for up to kMaxRot rotations of the batch in one launch: block id
+// -> (rotation r, tile-limb pair) with the pair's low 3 bits equal to id mod
+// 8, so the r blocks of one 256-coefficient tile of one limb are dispatched
+// within 8 nrot consecutive ids to the same XCD (workgroups go round-robin
+// over the 8 XCDs) and all but the first find the tile's digits in that XCD's
+// L2: the digits cross HBM about once instead of once per rotation.  Output
+// of rotation r for input b at dst.p[b] + off[r] (the same layout as above).
+constexpr int kMaxRot = 8;
+struct KipRot {
+    const uint64_t *key[kMaxRot];
+    const uint32_t *scat[kMaxRot];
+    int64_t off[kMaxRot];
+};
+template <int DNUM>
+__global__ __launch_bounds__(256) void k_kip_ext_rot(const uint64_t *__restrict__ digits, int nb, int dnum_rt, int nt,
+                                                     int nl, int nrot, KipRot kr, int nprimes, LimbMap map, Ptrs c0,
+                                                     Ptrs dst, const uint64_t *__restrict__ pmod,
+                                                     const Prime *__restrict__ primes, int logN) {
+    const size_t N = size_t(1) << logN;
+    const unsigned ntile = unsigned(N >> 8);
+    const unsigned id = blockIdx.x, r = (id >> 3) % unsigned(nrot);
+    const unsigned tl = (id / (8u * unsigned(nrot))) * 8u + (id & 7u);
+    const int tt = int(tl / ntile);
+    const size_t k = size_t(tl % ntile) * 256 + threadIdx.x;
+    const int dnum = DNUM > 0 ? DNUM : dnum_rt;
+    const int pi = map.prime(tt);
+    const Prime P = primes[pi];
+    const size_t dig_bs = size_t(dnum) * nt * N;
+    const bool lowq = tt < nl;
+    const uint64_t pm = lowq ? pmod[2 * tt] : 0, pmp = lowq ? pmod[2 * tt + 1] : 0;
+    const uint64_t *key = kr.key[r];
+    constexpr int KD = DNUM > 0 ? DNUM : kMaxDnum;
+    uint64_t kb[KD], ka[KD];
+#pragma unroll
+    for (int j = 0; j < KD; ++j) {
+        if (DNUM > 0 || j < dnum) {
+            kb[j] = key[((size_t(j) * 2 + 0) * nprimes + pi) * N + k];
+            ka[j] = key[((size_t(j) * 2 + 1) * nprimes + pi) * N + k];
+        }
+    }
+    const int64_t out = kr.off[r] + int64_t(tt) * int64_t(N) + int64_t(kr.scat[r][k]);
+    const uint64_t *dg = digits + size_t(tt) * N + k;
+    for (int b = 0; b < nb; ++b) {
+        uint64_t d[KD];
+#pragma unroll
+        for (int j = 0; j < KD; ++j)
+            if (DNUM > 0 || j < dnum) d[j] = dg[size_t(j) * nt * N];
+        accc a0{0, 0, 0, 0, 0}, a1{0, 0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < KD; ++j) {
+            if (DNUM > 0 || j < dnum) {
+                macc(a0, d[j], kb[j]);
+                macc(a1, d[j], ka[j]);
+            }
+        }
+        uint64_t u0 = reduce128(accc_value(a0), P);
+        if (lowq) u0 = add_mod(u0, mul_shoup(c0.p[b][size_t(tt) * N + k], pm, pmp, P.q), P.q);
+        uint64_t *o = dst.p[b] + out;
+        o[0] = u0;
+        o[size_t(nt) * N] = reduce128(accc_value(a1), P);
+        dg += dig_bs;
+    }
+}
+using KipRotFn = void (*)(const uint64_t *, int, int, int, int, int, KipRot, int, LimbMap, Ptrs, Ptrs,
+                          const uint64_t *, const Prime *, int);
+KipRotFn kip_rot_kernel(int dnum) {
+    switch (dnum) {
+        case 1: return k_kip_ext_rot<1>;
+        case 2: return k_kip_ext_rot<2>;
+        case 3: return k_kip_ext_rot<3>;
+        case 4: return k_kip_ext_rot<4>;
+        case 5: return k_kip_ext_rot<5>;
+        case 6: return k_kip_ext_rot<6>;
+        case 7: return k_kip_ext_rot<7>;
+        case 8: return k_kip_ext_rot<8>;
+        default: return k_kip_ext_rot<0>;
+    }
+}
+
 using KipExtFn = void (*)(const uint64_t *, int, int, int, int, const uint64_t *, int, LimbMap, const uint32_t *,
                           Ptrs, Ptrs, const uint64_t *, const Prime *, int);
 KipExtFn kip_ext_kernel(int dnum) {
@@ -417,7 +496,44 @@ int hoisted_group_ext(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, in
         CKC_TRY(ks_modup_b(c, x1.u64(), pw, nb, level, digits.u64(), s));
     }
     const LimbMap ext{nl, c->nq};
+    // rotations whose outputs sit at one offset from the first step's for
+    // every input (the convolution's layout) share one launch
+    std::vector<size_t> fused;
+    const bool tiles8 = ((N >> 8) * size_t(nt)) % 8 == 0 && (N >> 8) > 0;
     for (size_t si = 0; si < steps.size(); ++si) {
+        if (galois_element(c, steps[si]) == 1 || !tiles8 || fused.size() == size_t(kMaxRot)) continue;
+        const ptrdiff_t d0 = dst[si].p[0] - dst[0].p[0];
+        bool same = true;
+        for (int b = 1; b < nb && same; ++b) same = dst[si].p[b] - dst[0].p[b] == d0;
+        if (same) fused.push_back(si);
+    }
+    if (fused.size() < 2) fused.clear();
+    if (!fused.empty()) {
+        KipRot kr{};
+        for (size_t r = 0; r < fused.size(); ++r) {
+            const uint64_t g = galois_element(c, steps[fused[r]]);
+            auto it = evk->galois.find(g);
+            CKC_REQUIRE(it != evk->galois.end(), CKC_ENOKEY,
+                        "missing Galois key for step " + std::to_string(steps[fused[r]]));
+            int rc;
+            kr.scat[r] = (const uint32_t *)galois_table(c, galois_inverse(c, g), &rc);
+            if (!kr.scat[r]) return rc;
+            kr.key[r] = it->second->u64();
+            kr.off[r] = int64_t(dst[fused[r]].p[0] - dst[0].p[0]);
+        }
+        const int nrot = int(fused.size());
+        // algorithmic bytes: digits once, every key, c0 (Q limbs) and both
+        // outputs of every rotation once
+        const double bytes =
+            8.0 * N * (nt * (double(nb) * dnum + nrot * (2.0 * dnum + 2.0 * nb)) + double(nb) * nl);
+        CKC_PROF(PK_KIP, s, bytes, 2.0 * N * nt * dnum * nb * nrot);
+        const unsigned blocks = unsigned((N >> 8) * size_t(nt) * size_t(nrot));
+        hipLaunchKernelGGL(kip_rot_kernel(dnum), dim3(blocks), dim3(256), 0, s, digits.u64(), nb, dnum, nt, nl, nrot,
+                           kr, c->nprimes(), ext, in, dst[0], c->pmod.u64(), c->dprimes(), c->logN);
+        CKC_HIP(hipGetLastError());
+    }
+    for (size_t si = 0; si < steps.size(); ++si) {
+        if (std::find(fused.begin(), fused.end(), si) != fused.end()) continue;
         const uint64_t g = galois_element(c, steps[si]);
         if (g == 1) {
             CKC_PROF(PK_EW, s, 8.0 * N * nb * 2 * (nl + nt), 0.0);

@@ -101,6 +101,7 @@ struct DevMem {
         if (e != hipSuccess) {
             p = nullptr;
             ckc_set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+            (void)hipGetLastError();  // reported here, not by the next launch check
             return CKC_ENOMEM;
         }
         return CKC_OK;

@@ -139,3 +139,30 @@ def test_batched_errors_and_empty():
     with pytest.raises(CkcError) as e:
         ckks.mac_plain_many(ctx, cts[:1], [lowpt])
     assert e.value.code == -2
+
+
+def test_stream_reserve_and_release_keep_results():
+    """A stream whose arena was reserved up front, or freed between calls,
+    gives the same bits as the default stream; a reservation the device
+    cannot hold is refused with CKC_ENOMEM and leaves the stream usable."""
+    from paper_2509_22857_amd import ckks
+    ps = tiny()
+    ctx, orc, torch = _setup(ps)
+    keys = ctx.keygen(5, [1, -3])
+    _, cts = _cts(ctx, ps, range(300, 306), 2)
+    ref = [o.buf.clone() for o in ckks.rotate_many(ctx, keys, cts, [1, -3])]
+    s = torch.cuda.Stream()
+    ckks.stream_reserve(1 << 26, s)
+    for rnd in range(2):
+        with torch.cuda.stream(s):
+            got = ckks.rotate_many(ctx, keys, cts, [1, -3], stream=s)
+        s.synchronize()
+        assert all(torch.equal(g.buf, r) for g, r in zip(got, ref)), rnd
+        ckks.stream_release(s)
+    with pytest.raises(ckks.CkcError, match="CKC_ENOMEM"):
+        ckks.stream_reserve(1 << 52, s)
+    with torch.cuda.stream(s):
+        got = ckks.rotate_many(ctx, keys, cts, [1, -3], stream=s)
+    s.synchronize()
+    assert all(torch.equal(g.buf, r) for g, r in zip(got, ref))
+    ckks.stream_release(s)
