@@ -310,6 +310,9 @@ int ckc_prof_query(const char *kernel, int64_t *launches, double *total_ms, doub
  *   "conv_imgs"  most images per contraction workgroup: 1, 2 or 4
  *   "ks_batch"   rotated inputs per key-switching launch in a convolution,
  *                8 .. 64
+ *   "conv_fuse"  1: one contraction launch covers every output group of a 3x3
+ *                layer (the groups of one coefficient tile share an XCD's
+ *                L2); 0: one launch per output group
  * Errors: CKC_EINVAL for an unknown knob or a value it does not allow. */
 int ckc_tune_set(const char *knob, int value);
 int ckc_tune_get(const char *knob, int *value);

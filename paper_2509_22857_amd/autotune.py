@@ -43,8 +43,10 @@ def tune_network(net, keys, inputs, knobs=None, cache: str | None = None, key: s
         with open(cache) as f:
             saved = json.load(f).get(key)
         if saved:
+            # knobs the stored choice predates keep the library's default
             for k in knobs:
-                ckks.tune_set(k, saved[k])
+                if k in saved:
+                    ckks.tune_set(k, saved[k])
             return saved
     best = {k: ckks.tune_get(k) for k in knobs}
     timings = {}

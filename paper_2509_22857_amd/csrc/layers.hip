@@ -229,6 +229,20 @@ __global__ __launch_bounds__(256) void k_conv_contract(
 constexpr int kMaxCentLds = 128;
 constexpr int kImgPerWg = 4;
 constexpr int kUnroll = 4;
+// With ybase set, one launch covers every group of OUTS outputs: block id ->
+// (output group, column tile, limb) with the tile-limb pair's low 3 bits equal
+// to id mod 8, so all output groups of one tile of one limb run on the same
+// XCD (workgroups go round-robin over the 8 XCDs) within 8 ngroups
+// consecutive ids and read the tile's rotated inputs from that XCD's L2 after
+// the first; outputs at ybase + img * y_img + o * 2 nl N.  Otherwise blockIdx
+// = (tile, limb) and the outputs of the o_count outputs from o_base are at
+// outs.p[img * OUTS + j].
+struct ConvOut {
+    uint64_t *ybase;
+    size_t y_img;
+    int ngroups;
+    int O;
+};
 template <int OUTS, int IMGS>
 __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restrict__ R, size_t r_img_words,
                                                            int n_img, int ni, int I, int i_base, int ntap, int nl,
@@ -236,19 +250,31 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
                                                            const uint64_t *__restrict__ ioff, int ngrp,
                                                            const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
                                                            int o_count, int accumulate,
-                                                           const Prime *__restrict__ primes, int logN, int dbuf) {
+                                                           const Prime *__restrict__ primes, int logN, int dbuf,
+                                                           ConvOut yo) {
     static_assert(OUTS % 4 == 0, "outputs per wave come in packed words of 4 offsets");
     constexpr int NW = OUTS / 4;
     extern __shared__ uint64_t sP[];  // [dbuf ? 2 : 1][kcent][kTile]
     const size_t N = size_t(1) << logN;
-    const int limb = blockIdx.y;
+    int limb, tile;
+    if (yo.ybase) {
+        const unsigned id = blockIdx.x, ng = unsigned(yo.ngroups);
+        const unsigned tl = (id / (8u * ng)) * 8u + (id & 7u), ntiles = unsigned(N / kTile);
+        tile = int(tl % ntiles);
+        limb = int(tl / ntiles);
+        o_base = int((id >> 3) % ng) * OUTS;
+        o_count = min(OUTS, yo.O - o_base);
+    } else {
+        tile = blockIdx.x;
+        limb = blockIdx.y;
+    }
     const int lane = threadIdx.x & 63;
     // wave index as a wave-uniform (scalar) value, so per-wave control flow and
     // index loads stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int img = wave >> 1, poly = wave & 1;
     const bool active = img < n_img;
-    const size_t col0 = size_t(blockIdx.x) * kTile;
+    const size_t col0 = size_t(tile) * kTile;
     const size_t pw = size_t(nl) * N, ctw = 2 * pw;
     const Prime P = primes[map.prime(limb)];
     const int pcap = prod_cap(P.k);
@@ -415,7 +441,8 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
         if (j >= o_count) continue;
         const int o = o_base + j;
         uint64_t y = reduce128(accc_value(acc[j]), P);
-        uint64_t *dst = outs.p[img * OUTS + j] + size_t(poly) * pw + size_t(limb) * N + col0 + lane;
+        uint64_t *dst = (yo.ybase ? yo.ybase + size_t(img) * yo.y_img + size_t(o) * ctw : outs.p[img * OUTS + j]) +
+                        size_t(poly) * pw + size_t(limb) * N + col0 + lane;
         if (accumulate) y = add_mod(y, *dst, P.q);
         else if (poly == 0 && bias) y = add_mod(y, bias[(size_t(o) * nl + limb) * N + col0 + lane], P.q);
         *dst = y;
@@ -423,7 +450,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
 }
 
 using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, LimbMap, const uint64_t *, int,
-                        const uint64_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int, int);
+                        const uint64_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int, int, ConvOut);
 // kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images)
 // that holds them; outs = outputs per wave (8 or 16), a tuning choice between
 // accumulator registers (occupancy) and codebook re-reads per output group
@@ -776,6 +803,22 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                     // waves a CU can hold
                     const int dbuf = wg_imgs == kImgPerWg && 2 * size_t(L->kcent) * kTile * 8 <= 65536 ? 1 : 0;
                     const size_t lds_mac = size_t(1 + dbuf) * L->kcent * kTile * 8;
+                    if (L->ext && tune_value(TK_CONV_FUSE)) {
+                        // every output group in one launch (outputs in Y)
+                        const int ngroups = (O + outs - 1) / outs;
+                        const ConvOut yo{Y.u64() + size_t(g0) * O * lctw, size_t(O) * lctw, ngroups, O};
+                        CKC_PROF(PK_CONV_CONTRACT, s,
+                                 8.0 * N * nlim * (2.0 * gi * nic * ntap + 2.0 * gi * O * (ic0 > 0 ? 2 : 1) +
+                                                   double(ntap) * L->kcent),
+                                 2.0 * N * nlim * double(gi) * O * nic * ntap);
+                        hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile) * unsigned(nlim) * unsigned(ngroups)),
+                                           dim3(128 * wg_imgs), lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi,
+                                           nic, I, ic0, ntap, nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(),
+                                           L->Opad / 4, bias_k, Ptrs{}, 0, 0, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN,
+                                           dbuf, yo);
+                        CKC_HIP(hipGetLastError());
+                        continue;
+                    }
                     for (int o0 = 0; o0 < O; o0 += outs) {
                         const int oc = std::min(outs, O - o0);
                         Ptrs op{};
@@ -788,7 +831,8 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
                                            lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
                                            nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(), L->Opad / 4,
-                                           bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN, dbuf);
+                                           bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN, dbuf,
+                                           ConvOut{nullptr, 0, 0, 0});
                         CKC_HIP(hipGetLastError());
                     }
                 }

@@ -16,8 +16,9 @@ constexpr KnobDef kDefs[TK_COUNT] = {
     {"conv_outs", 8, 8, 16},
     {"conv_imgs", 4, 1, 4},
     {"ks_batch", 64, 8, 64},
+    {"conv_fuse", 1, 0, 1},
 };
-std::atomic<int> g_val[TK_COUNT] = {{8}, {4}, {64}};
+std::atomic<int> g_val[TK_COUNT] = {{8}, {4}, {64}, {1}};
 
 bool allowed(int k, int v) {
     if (v < kDefs[k].lo || v > kDefs[k].hi) return false;

@@ -124,16 +124,31 @@ def test_wide_conv_input_chunks_bit_exact():
     ps = small_tower(logN=12, levels=2)
     D = 2.0 ** 30
     print("[wide_conv] N=2^12 I=70 O=9 stride 2", flush=True)
+    from paper_2509_22857_amd import ckks
     ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 5)
     imgs = gen.images(12, 2, I, 8, 8)
     gin = gnet.encrypt_images(keys, imgs, 700)
-    gout, _ = gnet.run(keys, gin)
+    want = []
     for n in range(2):
         oin = onet.encrypt_image(sk, imgs[n], 700 + n * 4096)
         oout, _ = onet.run(sk, oin, rlk, gk)
         assert len(oout) == O
-        for j in range(O):
-            assert np.array_equal(_coeff(ctx, gout[n][j]), oout[j].data), (n, j)
+        want.append([c.data for c in oout])
+    # every launch form of the contraction: all output groups in one launch or
+    # one launch per group, 8 or 16 outputs per wave
+    saved = {k: ckks.tune_get(k) for k in ("conv_fuse", "conv_outs")}
+    try:
+        for fuse, outs in ((1, 8), (0, 8), (1, 16), (0, 16)):
+            ckks.tune_set("conv_fuse", fuse)
+            ckks.tune_set("conv_outs", outs)
+            print(f"[wide_conv] conv_fuse={fuse} conv_outs={outs}", flush=True)
+            gout, _ = gnet.run(keys, gin)
+            for n in range(2):
+                for j in range(O):
+                    assert np.array_equal(_coeff(ctx, gout[n][j]), want[n][j]), (fuse, outs, n, j)
+    finally:
+        for k, v in saved.items():
+            ckks.tune_set(k, v)
 
 
 def test_small_vgg_bit_exact():
