@@ -31,15 +31,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# sources whose change invalidates a kernel class's measured HBM traffic
-TRAFFIC_SOURCES = {"conv_contract": ("paper_2509_22857_amd/csrc/layers.hip", "paper_2509_22857_amd/csrc/modarith.h")}
+# device code whose change invalidates a kernel class's measured HBM traffic:
+# (file, first line of the region, text that ends it) — None: the whole file
+TRAFFIC_SOURCES = {"conv_contract": (("paper_2509_22857_amd/csrc/layers.hip", "constexpr int kMaxCentLds",
+                                      "using ConvFn"),
+                                     ("paper_2509_22857_amd/csrc/modarith.h", None, None))}
 
 
 def kernel_source_hash(cls):
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES.get(cls, ()):
+    for rel, start, end in TRAFFIC_SOURCES.get(cls, ()):
         with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+            text = f.read()
+        if start is not None:
+            a = text.index(start.encode())
+            text = text[a:text.index(end.encode(), a)]
+        h.update(text)
     return h.hexdigest()[:16]
 
 
