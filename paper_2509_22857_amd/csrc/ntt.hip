@@ -150,81 +150,109 @@ __device__ __forceinline__ void rows_generic(Ld ld, St st, bool inverse, uint64_
 // butterfly (half a dozen of them register moves building multiply-add
 // addend pairs), these 24 and 25.
 #define CKC_BFLY_CLOBBERS "v56", "v57", "v58", "v59", "v60", "v61", "v62", "v63"
+// The modulus' constants are wave-uniform and stay in scalar registers (every
+// instruction below reads at most one); twiddles are scalar too where the
+// whole wave uses the same ones (UT), else per lane.  The forward block reads
+// no input after writing an output, so outputs may reuse input registers.
+#define CKC_CT_BODY                                         \
+    "v_cmp_ge_u64_e64 %[m], %[X], %[q2]\n\t"                \
+    "v_mul_hi_u32 v56, %[y0], %[p0]\n\t"                    \
+    "v_mov_b32 v57, 0\n\t"                                  \
+    "v_mad_u64_u32 v[56:57], %[j], %[y1], %[p0], v[56:57]\n\t" \
+    "v_mad_u64_u32 v[58:59], %[j], %[y0], %[w0], 0\n\t"     \
+    "v_mad_u64_u32 v[56:57], %[k], %[y0], %[p1], v[56:57]\n\t" \
+    "v_mul_lo_u32 v60, %[y0], %[w1]\n\t"                    \
+    "v_mul_lo_u32 v61, %[y1], %[w0]\n\t"                    \
+    "v_mov_b32 v56, v57\n\t"                                \
+    "v_addc_co_u32_e64 v57, %[j], 0, 0, %[k]\n\t"           \
+    "v_mad_u64_u32 v[56:57], %[j], %[y1], %[p1], v[56:57]\n\t" \
+    "v_add3_u32 v59, v59, v60, v61\n\t"                     \
+    "v_mad_u64_u32 v[58:59], %[j], v56, %[qn0], v[58:59]\n\t" \
+    "v_mul_lo_u32 v60, v56, %[qn1]\n\t"                     \
+    "v_mul_lo_u32 v61, v57, %[qn0]\n\t"                     \
+    "v_cndmask_b32_e64 v62, 0, %[nq2lo], %[m]\n\t"          \
+    "v_cndmask_b32_e64 v63, 0, %[nq2hi], %[m]\n\t"          \
+    "v_add3_u32 v59, v59, v60, v61\n\t"                     \
+    "v_lshl_add_u64 v[62:63], %[X], 0, v[62:63]\n\t"        \
+    "v_lshl_add_u64 %[xo], v[62:63], 0, v[58:59]\n\t"       \
+    "v_not_b32 v60, v58\n\t"                                \
+    "v_not_b32 v61, v59\n\t"                                \
+    "v_lshl_add_u64 v[62:63], v[62:63], 0, %[q2p1]\n\t"     \
+    "v_lshl_add_u64 %[yo], v[62:63], 0, v[60:61]"
+#define CKC_GS_BODY                                         \
+    "v_lshl_add_u64 v[62:63], %[X], 0, %[Y]\n\t"            \
+    "v_not_b32 v60, %[y0]\n\t"                              \
+    "v_not_b32 v61, %[y1]\n\t"                              \
+    "v_cmp_ge_u64_e64 %[m], v[62:63], %[q2]\n\t"            \
+    "v_lshl_add_u64 v[58:59], %[X], 0, %[q2p1]\n\t"         \
+    "v_lshl_add_u64 v[58:59], v[58:59], 0, v[60:61]\n\t"    \
+    "v_mul_hi_u32 v56, v58, %[p0]\n\t"                      \
+    "v_mov_b32 v57, 0\n\t"                                  \
+    "v_mad_u64_u32 v[56:57], %[j], v59, %[p0], v[56:57]\n\t" \
+    "v_cndmask_b32_e64 v60, 0, %[nq2lo], %[m]\n\t"          \
+    "v_mad_u64_u32 v[56:57], %[k], v58, %[p1], v[56:57]\n\t" \
+    "v_cndmask_b32_e64 v61, 0, %[nq2hi], %[m]\n\t"          \
+    "v_lshl_add_u64 %[xo], v[62:63], 0, v[60:61]\n\t"       \
+    "v_mov_b32 v56, v57\n\t"                                \
+    "v_addc_co_u32_e64 v57, %[j], 0, 0, %[k]\n\t"           \
+    "v_mad_u64_u32 v[56:57], %[j], v59, %[p1], v[56:57]\n\t" \
+    "v_mul_lo_u32 v60, v58, %[w1]\n\t"                      \
+    "v_mul_lo_u32 v61, v59, %[w0]\n\t"                      \
+    "v_mul_lo_u32 v62, v56, %[qn1]\n\t"                     \
+    "v_mul_lo_u32 v63, v57, %[qn0]\n\t"                     \
+    "v_add3_u32 v61, v60, v61, v62\n\t"                     \
+    "v_add_u32 v61, v61, v63\n\t"                           \
+    "v_mov_b32 v60, 0\n\t"                                  \
+    "v_mad_u64_u32 %[yo], %[j], v58, %[w0], v[60:61]\n\t"   \
+    "v_mad_u64_u32 %[yo], %[j], v56, %[qn0], %[yo]"
+template <bool UT>
 __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp, uint64_t q, uint64_t q2) {
     const uint64_t qn = 0 - q, nq2 = 0 - q2, q2p1 = q2 + 1;
     uint64_t xo, yo, m, k, j;
-    asm("v_cmp_ge_u64_e64 %[m], %[X], %[q2]\n\t"
-        "v_mul_hi_u32 v56, %[y0], %[p0]\n\t"
-        "v_mov_b32 v57, 0\n\t"
-        "v_mad_u64_u32 v[56:57], %[j], %[y1], %[p0], v[56:57]\n\t"
-        "v_mad_u64_u32 v[58:59], %[j], %[y0], %[w0], 0\n\t"
-        "v_mad_u64_u32 v[56:57], %[k], %[y0], %[p1], v[56:57]\n\t"
-        "v_mul_lo_u32 v60, %[y0], %[w1]\n\t"
-        "v_mul_lo_u32 v61, %[y1], %[w0]\n\t"
-        "v_mov_b32 v56, v57\n\t"
-        "v_addc_co_u32_e64 v57, %[j], 0, 0, %[k]\n\t"
-        "v_mad_u64_u32 v[56:57], %[j], %[y1], %[p1], v[56:57]\n\t"
-        "v_add3_u32 v59, v59, v60, v61\n\t"
-        "v_mad_u64_u32 v[58:59], %[j], v56, %[qn0], v[58:59]\n\t"
-        "v_mul_lo_u32 v60, v56, %[qn1]\n\t"
-        "v_mul_lo_u32 v61, v57, %[qn0]\n\t"
-        "v_cndmask_b32_e64 v62, 0, %[nq2lo], %[m]\n\t"
-        "v_cndmask_b32_e64 v63, 0, %[nq2hi], %[m]\n\t"
-        "v_add3_u32 v59, v59, v60, v61\n\t"
-        "v_lshl_add_u64 v[62:63], %[X], 0, v[62:63]\n\t"
-        "v_lshl_add_u64 %[xo], v[62:63], 0, v[58:59]\n\t"
-        "v_not_b32 v60, v58\n\t"
-        "v_not_b32 v61, v59\n\t"
-        "v_lshl_add_u64 v[62:63], v[62:63], 0, %[q2p1]\n\t"
-        "v_lshl_add_u64 %[yo], v[62:63], 0, v[60:61]"
-        : [xo] "=&v"(xo), [yo] "=&v"(yo), [m] "=&s"(m), [k] "=&s"(k), [j] "=&s"(j)
-        : [X] "v"(X), [q2] "v"(q2), [y0] "v"(uint32_t(Y)), [y1] "v"(uint32_t(Y >> 32)), [w0] "v"(uint32_t(w)),
-          [w1] "v"(uint32_t(w >> 32)), [p0] "v"(uint32_t(wp)), [p1] "v"(uint32_t(wp >> 32)),
-          [qn0] "v"(uint32_t(qn)), [qn1] "v"(uint32_t(qn >> 32)), [nq2lo] "v"(uint32_t(nq2)),
-          [nq2hi] "v"(uint32_t(nq2 >> 32)), [q2p1] "v"(q2p1)
-        : CKC_BFLY_CLOBBERS);
+    if constexpr (UT)
+        asm(CKC_CT_BODY
+            : [xo] "=v"(xo), [yo] "=v"(yo), [m] "=&s"(m), [k] "=&s"(k), [j] "=&s"(j)
+            : [X] "v"(X), [q2] "s"(q2), [y0] "v"(uint32_t(Y)), [y1] "v"(uint32_t(Y >> 32)), [w0] "s"(uint32_t(w)),
+              [w1] "s"(uint32_t(w >> 32)), [p0] "s"(uint32_t(wp)), [p1] "s"(uint32_t(wp >> 32)),
+              [qn0] "s"(uint32_t(qn)), [qn1] "s"(uint32_t(qn >> 32)), [nq2lo] "v"(uint32_t(nq2)),
+              [nq2hi] "v"(uint32_t(nq2 >> 32)), [q2p1] "s"(q2p1)
+            : CKC_BFLY_CLOBBERS);
+    else
+        asm(CKC_CT_BODY
+            : [xo] "=v"(xo), [yo] "=v"(yo), [m] "=&s"(m), [k] "=&s"(k), [j] "=&s"(j)
+            : [X] "v"(X), [q2] "s"(q2), [y0] "v"(uint32_t(Y)), [y1] "v"(uint32_t(Y >> 32)), [w0] "v"(uint32_t(w)),
+              [w1] "v"(uint32_t(w >> 32)), [p0] "v"(uint32_t(wp)), [p1] "v"(uint32_t(wp >> 32)),
+              [qn0] "s"(uint32_t(qn)), [qn1] "s"(uint32_t(qn >> 32)), [nq2lo] "v"(uint32_t(nq2)),
+              [nq2hi] "v"(uint32_t(nq2 >> 32)), [q2p1] "s"(q2p1)
+            : CKC_BFLY_CLOBBERS);
     X = xo;
     Y = yo;
 }
+template <bool UT>
 __device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp, uint64_t q, uint64_t q2) {
     const uint64_t qn = 0 - q, nq2 = 0 - q2, q2p1 = q2 + 1;
     uint64_t xo, yo, m, k, j;
-    asm("v_lshl_add_u64 v[62:63], %[X], 0, %[Y]\n\t"
-        "v_not_b32 v60, %[y0]\n\t"
-        "v_not_b32 v61, %[y1]\n\t"
-        "v_cmp_ge_u64_e64 %[m], v[62:63], %[q2]\n\t"
-        "v_lshl_add_u64 v[58:59], %[X], 0, %[q2p1]\n\t"
-        "v_lshl_add_u64 v[58:59], v[58:59], 0, v[60:61]\n\t"
-        "v_mul_hi_u32 v56, v58, %[p0]\n\t"
-        "v_mov_b32 v57, 0\n\t"
-        "v_mad_u64_u32 v[56:57], %[j], v59, %[p0], v[56:57]\n\t"
-        "v_cndmask_b32_e64 v60, 0, %[nq2lo], %[m]\n\t"
-        "v_mad_u64_u32 v[56:57], %[k], v58, %[p1], v[56:57]\n\t"
-        "v_cndmask_b32_e64 v61, 0, %[nq2hi], %[m]\n\t"
-        "v_lshl_add_u64 %[xo], v[62:63], 0, v[60:61]\n\t"
-        "v_mov_b32 v56, v57\n\t"
-        "v_addc_co_u32_e64 v57, %[j], 0, 0, %[k]\n\t"
-        "v_mad_u64_u32 v[56:57], %[j], v59, %[p1], v[56:57]\n\t"
-        "v_mul_lo_u32 v60, v58, %[w1]\n\t"
-        "v_mul_lo_u32 v61, v59, %[w0]\n\t"
-        "v_mul_lo_u32 v62, v56, %[qn1]\n\t"
-        "v_mul_lo_u32 v63, v57, %[qn0]\n\t"
-        "v_add3_u32 v61, v60, v61, v62\n\t"
-        "v_add_u32 v61, v61, v63\n\t"
-        "v_mov_b32 v60, 0\n\t"
-        "v_mad_u64_u32 %[yo], %[j], v58, %[w0], v[60:61]\n\t"
-        "v_mad_u64_u32 %[yo], %[j], v56, %[qn0], %[yo]"
-        : [xo] "=&v"(xo), [yo] "=&v"(yo), [m] "=&s"(m), [k] "=&s"(k), [j] "=&s"(j)
-        : [X] "v"(X), [Y] "v"(Y), [q2] "v"(q2), [y0] "v"(uint32_t(Y)), [y1] "v"(uint32_t(Y >> 32)),
-          [w0] "v"(uint32_t(w)), [w1] "v"(uint32_t(w >> 32)), [p0] "v"(uint32_t(wp)), [p1] "v"(uint32_t(wp >> 32)),
-          [qn0] "v"(uint32_t(qn)), [qn1] "v"(uint32_t(qn >> 32)), [nq2lo] "v"(uint32_t(nq2)),
-          [nq2hi] "v"(uint32_t(nq2 >> 32)), [q2p1] "v"(q2p1)
-        : CKC_BFLY_CLOBBERS);
+    if constexpr (UT)
+        asm(CKC_GS_BODY
+            : [xo] "=&v"(xo), [yo] "=&v"(yo), [m] "=&s"(m), [k] "=&s"(k), [j] "=&s"(j)
+            : [X] "v"(X), [Y] "v"(Y), [q2] "s"(q2), [y0] "v"(uint32_t(Y)), [y1] "v"(uint32_t(Y >> 32)),
+              [w0] "s"(uint32_t(w)), [w1] "s"(uint32_t(w >> 32)), [p0] "s"(uint32_t(wp)), [p1] "s"(uint32_t(wp >> 32)),
+              [qn0] "s"(uint32_t(qn)), [qn1] "s"(uint32_t(qn >> 32)), [nq2lo] "v"(uint32_t(nq2)),
+              [nq2hi] "v"(uint32_t(nq2 >> 32)), [q2p1] "s"(q2p1)
+            : CKC_BFLY_CLOBBERS);
+    else
+        asm(CKC_GS_BODY
+            : [xo] "=&v"(xo), [yo] "=&v"(yo), [m] "=&s"(m), [k] "=&s"(k), [j] "=&s"(j)
+            : [X] "v"(X), [Y] "v"(Y), [q2] "s"(q2), [y0] "v"(uint32_t(Y)), [y1] "v"(uint32_t(Y >> 32)),
+              [w0] "v"(uint32_t(w)), [w1] "v"(uint32_t(w >> 32)), [p0] "v"(uint32_t(wp)), [p1] "v"(uint32_t(wp >> 32)),
+              [qn0] "s"(uint32_t(qn)), [qn1] "s"(uint32_t(qn >> 32)), [nq2lo] "v"(uint32_t(nq2)),
+              [nq2hi] "v"(uint32_t(nq2 >> 32)), [q2p1] "s"(q2p1)
+            : CKC_BFLY_CLOBBERS);
     X = xo;
     Y = yo;
 }
 // stage s pairs j, j + (8 >> s) inside groups g of 2 (8 >> s); twiddle index idx(s, g)
-template <class F>
+template <bool UT = false, class F>
 __device__ __forceinline__ void ct16(uint64_t (&x)[16], const uint64_t *W, const uint64_t *Wp, F idx, uint64_t q,
                                      uint64_t q2) {
 #pragma unroll
@@ -235,12 +263,12 @@ __device__ __forceinline__ void ct16(uint64_t (&x)[16], const uint64_t *W, const
             const size_t i = idx(s, g);
             const uint64_t w = W[i], wp = Wp[i];
 #pragma unroll
-            for (int k = 0; k < d; ++k) ct_bfly(x[g * 2 * d + k], x[g * 2 * d + k + d], w, wp, q, q2);
+            for (int k = 0; k < d; ++k) ct_bfly<UT>(x[g * 2 * d + k], x[g * 2 * d + k + d], w, wp, q, q2);
         }
     }
 }
 // stage s pairs j, j + (1 << s) inside groups g of 2 (1 << s)
-template <class F>
+template <bool UT = false, class F>
 __device__ __forceinline__ void gs16(uint64_t (&x)[16], const uint64_t *W, const uint64_t *Wp, F idx, uint64_t q,
                                      uint64_t q2) {
 #pragma unroll
@@ -251,7 +279,7 @@ __device__ __forceinline__ void gs16(uint64_t (&x)[16], const uint64_t *W, const
             const size_t i = idx(s, g);
             const uint64_t w = W[i], wp = Wp[i];
 #pragma unroll
-            for (int k = 0; k < d; ++k) gs_bfly(x[g * 2 * d + k], x[g * 2 * d + k + d], w, wp, q, q2);
+            for (int k = 0; k < d; ++k) gs_bfly<UT>(x[g * 2 * d + k], x[g * 2 * d + k + d], w, wp, q, q2);
         }
     }
 }
@@ -278,7 +306,7 @@ __device__ __forceinline__ void cols16_fwd(Ld ld, St st, uint64_t *s, const uint
     uint64_t x[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) x[j] = ld(size_t(r0 + RS * j) * kN2 + col0 + c);
-    ct16(x, W, Wp, [](int st, int g) { return size_t((1 << st) + g); }, q, q2);
+    ct16<true>(x, W, Wp, [](int st, int g) { return size_t((1 << st) + g); }, q, q2);
     if (N1 == 256) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) s[lds16(r0 + 16 * j, c)] = x[j];
@@ -319,7 +347,7 @@ __device__ __forceinline__ void cols16_inv(Ld ld, St st, uint64_t *s, const uint
 #pragma unroll
         for (int j = 0; j < 16; ++j) x[j] = ld(size_t(j) * kN2 + col0 + c);
     }
-    gs16(x, W, Wp, [](int st, int g) { return size_t((8 >> st) + g); }, q, q2);
+    gs16<true>(x, W, Wp, [](int st, int g) { return size_t((8 >> st) + g); }, q, q2);
 #pragma unroll
     for (int j = 0; j < 16; ++j) st(size_t(r0 + RS * j) * kN2 + col0 + c, mul_shoup(x[j], sc, scp, q));
 }
