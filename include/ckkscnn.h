@@ -85,6 +85,8 @@ int ckc_ctx_destroy(ckc_ctx *ctx);
 /* words (uint64) of a ciphertext at `level` with `npoly` polynomials */
 size_t ckc_ct_words(const ckc_ctx *ctx, int level, int npoly);
 size_t ckc_pt_words(const ckc_ctx *ctx, int level);
+/* the same ciphertext size in bytes (8 ckc_ct_words) */
+size_t ckc_ct_bytes(const ckc_ctx *ctx, int level, int npoly);
 /* the primitive 2N-th root of unity the library uses for prime index t
  * (Q primes first, then P), and its NTT order: output index k of a forward
  * transform holds a(psi^(2*bitrev(k)+1)). */
@@ -128,6 +130,19 @@ int ckc_encode(ckc_ctx *ctx, const double *slots, size_t n, int level, double sc
  * be unique per ciphertext under one key. */
 int ckc_encrypt(ckc_ctx *ctx, const ckc_sk *sk, const ckc_pt *pt, uint64_t stream_id, ckc_ct *out,
                 void *stream);
+/* Client-side HW-layout packing and encryption of one image (Sections 5.1
+ * and 5.3): chw is [C][H][W] (host, FP64); channel c becomes the ciphertext
+ * out[c] at `level` and `scale`, with member mm's copy of the image in the
+ * slot block [mm block, (mm + 1) block) and pixel (r, x) at slot
+ * mm block + r row_stride + x (all ensemble members share the input
+ * ciphertexts); every other slot is zero.  Channel c uses PRNG stream
+ * stream_id + c.  The same as ckc_encode then ckc_encrypt per channel.
+ * out[c].d must each hold ckc_ct_words(level, 2).
+ * Errors: CKC_EINVAL if (H - 1) row_stride + W > block, row_stride < W or
+ * members block > N/2; CKC_ELEVEL for a level out of range. */
+int ckc_encode_encrypt_image(ckc_ctx *ctx, const ckc_sk *sk, const double *chw, int C, int H, int W, int members,
+                             int block, int row_stride, int level, double scale, uint64_t stream_id, ckc_ct *out,
+                             void *stream);
 /* m = c0 + c1 s (+ c2 s^2 for 3-polynomial ciphertexts) at the ciphertext's level. */
 int ckc_decrypt(ckc_ctx *ctx, const ckc_sk *sk, const ckc_ct *ct, ckc_pt *out, void *stream);
 /* Decoding: limb q_0 of pt, centred, mapped to n real slot values divided by
@@ -335,6 +350,16 @@ int ckc_tune_get(const char *knob, int *value);
  * error. */
 int ckc_stream_release(void *stream);
 int ckc_stream_reserve(void *stream, size_t bytes);
+
+/* ------------------------------------------------------------------ testing
+ * Test-only fault injection, for callers' failure handling (a serving loop
+ * that must retire a failed batch and go on): the call_index-th following
+ * call of a layer evaluation entry point (ckc_eval_conv, ckc_eval_quad_act,
+ * ckc_eval_dense, ckc_eval_avgpool2; counted process-wide from 1) returns
+ * `code` (a negative CKC_ error) at once, before touching any buffer or
+ * launching anything; once.  call_index 0 disarms.
+ * Errors: CKC_EINVAL for a negative index or a non-negative code. */
+int ckc_set_test_fault(int call_index, int code);
 
 #ifdef __cplusplus
 }

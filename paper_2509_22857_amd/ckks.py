@@ -107,6 +107,11 @@ _SIGS = [
     ("ckc_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
     ("ckc_stream_release", C.c_int, [C.c_void_p]),
     ("ckc_stream_reserve", C.c_int, [C.c_void_p, C.c_size_t]),
+    ("ckc_ct_bytes", C.c_size_t, [C.c_void_p, C.c_int, C.c_int]),
+    ("ckc_encode_encrypt_image", C.c_int, [C.c_void_p, C.c_void_p, _dblp, C.c_int, C.c_int, C.c_int, C.c_int,
+                                           C.c_int, C.c_int, C.c_int, C.c_double, C.c_uint64, C.c_void_p,
+                                           C.c_void_p]),
+    ("ckc_set_test_fault", C.c_int, [C.c_int, C.c_int]),
 ]
 
 
@@ -264,6 +269,25 @@ class Context:
                                               C.byref(s), _stream(stream)))
         pt.level, pt.scale = int(s.level), float(s.scale)
         return pt
+
+    def ct_bytes(self, level: int, npoly: int = 2) -> int:
+        return int(lib().ckc_ct_bytes(self.h, level, npoly))
+
+    def encode_encrypt_image(self, keys: "KeyPair", chw, members: int, block: int, row_stride: int, level: int,
+                             scale: float, stream_id: int, stream=None) -> list:
+        """HW-layout packing and encryption of one image [C][H][W] in one call:
+        ciphertext c uses PRNG stream stream_id + c."""
+        x = np.ascontiguousarray(np.asarray(chw, dtype=np.float64))
+        Cn, H, W = x.shape
+        outs = [self.new_ct(level, 2, scale) for _ in range(Cn)]
+        arr = (ckc_ct * Cn)(*[o.c() for o in outs])
+        _check("ckc_encode_encrypt_image",
+               lib().ckc_encode_encrypt_image(self.h, keys.sk, x.ctypes.data_as(_dblp), Cn, H, W, members, block,
+                                              row_stride, level, float(scale), int(stream_id), arr,
+                                              _stream(stream)))
+        for o, a in zip(outs, arr):
+            o.update(a)
+        return outs
 
     def encrypt(self, keys: "KeyPair", pt: Plaintext, stream_id: int, out: Ciphertext | None = None,
                 stream=None) -> Ciphertext:
@@ -585,6 +609,12 @@ def stream_release(stream=None):
     """Free the library's scratch arena of `stream` (after its queued work);
     the next call on the stream grows a new one."""
     _check("ckc_stream_release", lib().ckc_stream_release(_stream(stream)))
+
+
+def set_test_fault(call_index: int, code: int = -6):
+    """Test-only: the call_index-th following layer evaluation call fails
+    with `code` (CKC_EDEVICE by default); 0 disarms."""
+    _check("ckc_set_test_fault", lib().ckc_set_test_fault(int(call_index), int(code)))
 
 
 def stream_reserve(nbytes: int, stream=None):

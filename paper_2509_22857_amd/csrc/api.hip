@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <set>
 
 #include "batch.h"
@@ -312,6 +313,22 @@ extern "C" int ckc_ctx_destroy(ckc_ctx *c) {
 }
 extern "C" size_t ckc_ct_words(const ckc_ctx *c, int level, int npoly) { return words_ct(c, level, npoly); }
 extern "C" size_t ckc_pt_words(const ckc_ctx *c, int level) { return size_t(level + 1) * c->N; }
+extern "C" size_t ckc_ct_bytes(const ckc_ctx *c, int level, int npoly) { return 8 * words_ct(c, level, npoly); }
+
+namespace {
+std::atomic<int> g_fault_after{0}, g_fault_code{0};
+}
+int test_fault_take() {
+    if (g_fault_after.load(std::memory_order_relaxed) <= 0) return 0;
+    if (g_fault_after.fetch_sub(1) != 1) return 0;
+    return g_fault_code.load();
+}
+extern "C" int ckc_set_test_fault(int call_index, int code) {
+    CKC_REQUIRE(call_index >= 0 && (call_index == 0 || code < 0), CKC_EINVAL, "fault needs a negative error code");
+    g_fault_code.store(code);
+    g_fault_after.store(call_index);
+    return CKC_OK;
+}
 extern "C" uint64_t ckc_ctx_root(const ckc_ctx *c, int t) {
     return (t >= 0 && t < c->nprimes()) ? c->psi_h[t] : 0;
 }
@@ -431,6 +448,36 @@ extern "C" int ckc_encrypt(ckc_ctx *c, const ckc_sk *sk, const ckc_pt *pt, uint6
     out->level = pt->level;
     out->npoly = 2;
     out->scale = pt->scale;
+    return CKC_OK;
+}
+
+extern "C" int ckc_encode_encrypt_image(ckc_ctx *c, const ckc_sk *sk, const double *chw, int C, int H, int W,
+                                        int members, int block, int row_stride, int level, double scale,
+                                        uint64_t stream_id, ckc_ct *out, void *stream) {
+    CKC_REQUIRE(c && sk && chw && out, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(C > 0 && H > 0 && W > 0 && members > 0 && block > 0 && row_stride >= W, CKC_EINVAL, "bad image shape");
+    CKC_REQUIRE(size_t(H - 1) * row_stride + W <= size_t(block) && size_t(members) * block <= c->N / 2, CKC_EINVAL,
+                "image does not fit the slot layout");
+    CKC_REQUIRE(level >= 0 && level < c->nq, CKC_ELEVEL, "level out of range");
+    CKC_REQUIRE(scale > 0 && isfinite(scale), CKC_EINVAL, "bad scale");
+    for (int ch = 0; ch < C; ++ch) CKC_REQUIRE(out[ch].d, CKC_EINVAL, "null output buffer");
+    const hipStream_t s = S(stream);
+    DevBuf m;
+    CKC_TRY(m.alloc(8 * size_t(level + 1) * c->N, s));
+    std::vector<double> v(size_t(members) * block);
+    for (int ch = 0; ch < C; ++ch) {
+        // member mm's copy of channel ch: pixel (r, x) at slot mm block + r row_stride + x
+        std::fill(v.begin(), v.end(), 0.0);
+        for (int mm = 0; mm < members; ++mm)
+            for (int r = 0; r < H; ++r)
+                std::copy(chw + (size_t(ch) * H + r) * W, chw + (size_t(ch) * H + r) * W + W,
+                          v.begin() + size_t(mm) * block + size_t(r) * row_stride);
+        CKC_TRY(encode_impl(c, v.data(), v.size(), level, scale, m.u64(), s, false));
+        CKC_TRY(encrypt_impl(c, sk, m.u64(), level, stream_id + uint64_t(ch), out[ch].d, s));
+        out[ch].level = level;
+        out[ch].npoly = 2;
+        out[ch].scale = scale;
+    }
     return CKC_OK;
 }
 

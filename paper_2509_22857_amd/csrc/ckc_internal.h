@@ -14,6 +14,17 @@
 
 // ---------------------------------------------------------------- errors
 void ckc_set_error(const std::string &msg);
+// test-only fault injection (ckc_set_test_fault): nonzero = the code this
+// call must return instead of running
+int test_fault_take();
+#define CKC_FAULT_POINT()                          \
+    do {                                           \
+        const int _f = test_fault_take();          \
+        if (_f != 0) {                             \
+            ckc_set_error("injected test fault");  \
+            return _f;                             \
+        }                                          \
+    } while (0)
 
 #define CKC_HIP(call)                                                        \
     do {                                                                     \

@@ -728,6 +728,7 @@ extern "C" int ckc_layer_destroy(ckc_layer *L) {
 // ============================================================= evaluation
 extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L, const ckc_ct *in, int n_img,
                              ckc_ct *out, void *stream) {
+    CKC_FAULT_POINT();
     CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
     CKC_REQUIRE(L->kind == LK_CONV, CKC_EINVAL, "not a convolution layer");
     if (n_img == 0) return CKC_OK;
@@ -905,6 +906,7 @@ __global__ __launch_bounds__(256) void k_act_tensor(Ptrs x, Ptrs bp, uint64_t *_
 
 extern "C" int ckc_eval_quad_act(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L, const ckc_ct *in, int n_img,
                                  ckc_ct *out, void *stream) {
+    CKC_FAULT_POINT();
     CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
     CKC_REQUIRE(L->kind == LK_ACT, CKC_EINVAL, "not an activation layer");
     CKC_REQUIRE(evk->relin, CKC_ENOKEY, "no relinearisation key");
@@ -999,6 +1001,7 @@ __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ 
 
 extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L, const ckc_ct *in, int n_img,
                               ckc_ct *out, void *stream) {
+    CKC_FAULT_POINT();
     CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
     CKC_REQUIRE(L->kind == LK_DENSE, CKC_EINVAL, "not a dense layer");
     if (n_img == 0) return CKC_OK;
@@ -1068,6 +1071,7 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
 
 extern "C" int ckc_eval_avgpool2(ckc_ctx *c, const ckc_evk *evk, const ckc_layout *layout, const ckc_ct *in, int n,
                                  ckc_ct *out, void *stream) {
+    CKC_FAULT_POINT();
     CKC_REQUIRE(c && evk && layout && in && out && n >= 0, CKC_EINVAL, "null argument");
     CKC_TRY(check_layout(c, layout));
     CKC_REQUIRE(layout->height % 2 == 0 && layout->width % 2 == 0, CKC_ESHAPE, "pool: odd grid");

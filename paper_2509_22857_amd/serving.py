@@ -12,7 +12,9 @@ evaluation keys on the device, and runs a single host loop that
   * runs every admitted batch on its own HIP stream, one layer per step, with
     at most `window` layers enqueued ahead of the GPU, so batches admitted
     while others are on the device overlap with them;
-  * retires a batch when its last layer's event has completed, frees its
+  * retires a batch when its last layer's event has completed (or, when a
+    library call of the batch failed, once its enqueued work has drained,
+    marking its requests failed with the error), frees its
     stream's scratch arena (the library keeps one per stream at its largest
     size otherwise) and the blocks torch keeps cached, and releases its memory
     reservation, which lets the next queued requests in.
@@ -45,6 +47,7 @@ class Request:
     done: float | None = None
     outputs: list | None = None
     batch_id: int | None = None
+    error: str | None = None   # set when the request's batch failed
 
 
 @dataclass
@@ -59,6 +62,7 @@ class _Batch:
     events: collections.deque = field(default_factory=collections.deque)
     finished: bool = False
     result: object = None
+    error: str | None = None
 
 
 class Server:
@@ -157,6 +161,11 @@ class Server:
                     except StopIteration as stop:
                         b.finished = True
                         b.result = stop.value
+                    except ckks.CkcError as err:
+                        # the batch cannot complete: its requests fail once
+                        # its enqueued work has drained; the loop goes on
+                        b.finished = True
+                        b.error = str(err)
                     ev = torch.cuda.Event()
                     ev.record(b.stream)
                     b.events.append(ev)
@@ -165,12 +174,18 @@ class Server:
             for b in list(running):
                 if b.finished and all(e.query() for e in b.events):
                     t_done = clock() - t0
-                    outs = b.result[0]
-                    i = 0
-                    for r in b.reqs:
-                        r.outputs = outs[i:i + len(r.inputs)]
-                        i += len(r.inputs)
-                        r.done = t_done
+                    if b.error is not None:
+                        for r in b.reqs:
+                            r.error = b.error
+                            r.done = float("nan")
+                        self.stats["failed"] += len(b.reqs)
+                    else:
+                        outs = b.result[0]
+                        i = 0
+                        for r in b.reqs:
+                            r.outputs = outs[i:i + len(r.inputs)]
+                            i += len(r.inputs)
+                            r.done = t_done
                     running.remove(b)
                     # the stream's scratch arena and the blocks torch keeps
                     # cached go with the reservation
@@ -193,6 +208,7 @@ class Server:
             "requests": len(requests),
             "served": len(served),
             "rejected": int(self.stats["rejected"]),
+            "failed": int(self.stats["failed"]),
             "waits_for_memory": int(self.stats["waits_for_memory"]),
             "batches": next_bid,
             "max_concurrent_batches": max_running,

@@ -37,3 +37,14 @@ def test_binding_covers_the_header():
 def test_last_error_callable_without_gpu():
     lib = ckks.lib()
     assert lib.ckc_last_error() is not None
+
+
+def test_test_fault_hook_argument_checks_without_gpu():
+    """The fault hook only sets host-side state: a non-negative code or a
+    negative index is refused, index 0 disarms."""
+    import pytest
+    with pytest.raises(ckks.CkcError, match="CKC_EINVAL"):
+        ckks.set_test_fault(1, 5)
+    with pytest.raises(ckks.CkcError, match="CKC_EINVAL"):
+        ckks.set_test_fault(-1, -6)
+    ckks.set_test_fault(0, 0)

@@ -90,6 +90,34 @@ def test_secret_encode_encrypt_bit_exact(env):
     assert np.max(np.abs(zz - orc.decode(orc.decrypt(oct_, sk), oct_.scale))) < 1e-9
 
 
+def test_encode_encrypt_image_matches_oracle(env):
+    """One-call HW packing + encryption of an image: channel c equals the
+    oracle's encryption (stream stream_id + c) of the slot vector with every
+    member block holding the image at row stride W0."""
+    ps, ctx, orc, torch = env
+    if ps.N < 2 ** 12 or ps.name == "micro":
+        pytest.skip("one small and one mid parameter set suffice")
+    seed = 99
+    keys = ctx.keygen(seed, [])
+    sk = orc.secret_key(seed)
+    level = len(ps.q) - 1
+    Cn, H, W, M, B, W0 = 3, 6, 5, 2, 64, 8
+    img = gen.images(3, 1, Cn, H, W)[0]
+    cts = ctx.encode_encrypt_image(keys, img, M, B, W0, level, 2.0 ** 30, 5000)
+    assert len(cts) == Cn
+    for c in range(Cn):
+        z = np.zeros(M * B)
+        for m in range(M):
+            for r in range(H):
+                z[m * B + r * W0: m * B + r * W0 + W] = img[c, r]
+        want = orc.encrypt(orc.encode(z, level, 2.0 ** 30), sk, 5000 + c)
+        assert cts[c].level == level and cts[c].scale == 2.0 ** 30
+        assert np.array_equal(ctx.ct_to_coeff(cts[c]), want.data), c
+    from paper_2509_22857_amd.ckks import CkcError
+    with pytest.raises(CkcError, match="CKC_EINVAL"):
+        ctx.encode_encrypt_image(keys, img, M, 16, W0, level, 2.0 ** 30, 5000)  # rows overflow the block
+
+
 def test_encode_bit_exact_at_large_scales(env):
     """Encodings at scales where the FFT's last bits decide the integers."""
     ps, ctx, orc, torch = env

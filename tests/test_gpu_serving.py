@@ -112,3 +112,43 @@ def test_admission_by_memory(world):
     reqs2 = _requests(world, 3, rate=500.0, seed=3)
     stats2 = srv2.serve([r for r, _ in reqs2])
     assert stats2["rejected"] == 3 and stats2["served"] == 0
+
+
+def test_failed_batch_is_retired_and_the_rest_served(world):
+    """A library call that fails inside one batch (fault injected into the
+    first layer call) fails exactly that batch's requests with the error; the
+    loop goes on and every other request gives the same ciphertexts as alone."""
+    from paper_2509_22857_amd import ckks
+    from paper_2509_22857_amd.serving import Server, Request
+    torch, ctx, specs, networks, keys = world
+    combos = sorted(keys)  # four (client, network) pairs: four batches, no merging
+    reqs = []
+    for i, (client, net) in enumerate(combos):
+        img = gen.images(5000 + i, 1, *specs[net]["image"])
+        cts = networks[net].encrypt_images(keys[(client, net)], img, stream_base=(900 + i) << 12)
+        reqs.append(Request(i, client, net, cts, 0.0))
+    torch.cuda.synchronize()
+    alone = []
+    for r in reqs:
+        out, _ = networks[r.net].run(keys[(r.client, r.net)], r.inputs)
+        torch.cuda.synchronize()
+        alone.append(_words(out[0]))
+    srv = Server(networks, budget_bytes=torch.cuda.mem_get_info()[0] // 2, max_images=4, n_streams=1)
+    for cn, k in keys.items():
+        srv.register_client(cn[0], cn[1], k)
+    ckks.set_test_fault(1, -6)
+    try:
+        stats = srv.serve(reqs)
+    finally:
+        ckks.set_test_fault(0, 0)
+    torch.cuda.synchronize()
+    print(f"[serving] fault stats {stats}", flush=True)
+    assert stats["failed"] == 1 and stats["served"] == 3 and stats["rejected"] == 0
+    first = min(reqs, key=lambda r: r.batch_id)
+    assert first.error is not None and "CKC_EDEVICE" in first.error and first.outputs is None
+    for r, a in zip(reqs, alone):
+        if r is first:
+            continue
+        assert r.error is None
+        got = _words(r.outputs[0])
+        assert all(torch.equal(x, y) for x, y in zip(got, a)), r.rid
