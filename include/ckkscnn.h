@@ -52,6 +52,7 @@ typedef struct ckc_ctx ckc_ctx;     /* parameters and device tables */
 typedef struct ckc_sk ckc_sk;       /* client secret key (ternary, host + device copy) */
 typedef struct ckc_evk ckc_evk;     /* device-resident relinearisation + Galois keys */
 typedef struct ckc_layer ckc_layer; /* device-resident conv / dense layer */
+typedef struct ckc_plan ckc_plan;   /* a network's layer program (native runner) */
 
 /* Ciphertext: d = device [npoly][level+1][N]; scale is the CKKS scale. */
 typedef struct {
@@ -331,6 +332,41 @@ int ckc_prof_query(const char *kernel, int64_t *launches, double *total_ms, doub
  * Errors: CKC_EINVAL for an unknown knob or a value it does not allow. */
 int ckc_tune_set(const char *knob, int value);
 int ckc_tune_get(const char *knob, int *value);
+
+/* ------------------------------------------------------------------ runner
+ * Native execution of a whole network.  ckc_batch_plan parses the network's
+ * layer program (JSON) once, over the layer handles it names by index:
+ *   {"input": {"name": "x", "count": C, "level": L},
+ *    "output": "<tensor>",
+ *    "steps": [{"op": "conv" | "act" | "dense" | "pool", "in": "<tensor>",
+ *               "out": "<new tensor>", "count": <ciphertexts per image>,
+ *               "level": <level the layer runs at>, "layer": <index>,
+ *               "rescale": 0 | 1,
+ *               "short": {"layer": <1x1 conv index>, "in": "<tensor>",
+ *                         "level": <its level>},          (conv, optional)
+ *               "layout": {"block", "row_stride", "gap", "height", "width",
+ *                          "members"}},                   (pool)
+ *              ...]}
+ * A step evaluates its layer on every image (ckc_eval_conv / _quad_act /
+ * _dense / _avgpool2); a shortcut's input is mod-dropped to its level, taken
+ * through its 1x1 convolution and added to the step's output (residual,
+ * Section 4.3); "rescale" rescales the result once.  Tensors are written once
+ * and freed after their last reader.  The plan keeps the layer handles (the
+ * caller keeps them alive) and the ctx.
+ * ckc_batch_run evaluates the plan for n_requests images: inputs[r] holds
+ * request r's `count` input ciphertexts at the input level, outputs[r] the
+ * caller's buffers for the output tensor (ckc_batch_plan_info gives its count
+ * and level); consecutive requests with the same key set run as one batched
+ * pass.  Intermediate ciphertexts are allocated on `stream`.
+ * Errors: CKC_EINVAL for a malformed program or null arguments; CKC_ELEVEL
+ * for inconsistent levels; any error of the layer calls, after which the
+ * outputs are unspecified. */
+int ckc_batch_plan(ckc_ctx *ctx, const char *network_json, ckc_layer *const *layers, int n_layers,
+                   ckc_plan **plan_out);
+int ckc_batch_plan_info(const ckc_plan *plan, int *in_count, int *in_level, int *out_count, int *out_level);
+int ckc_batch_plan_destroy(ckc_plan *plan);
+int ckc_batch_run(ckc_plan *plan, const ckc_evk *const *evks, ckc_ct *const *inputs, int n_requests,
+                  ckc_ct *const *outputs, void *stream);
 
 /* ------------------------------------------------------------------ memory
  * Scratch memory (rotated inputs, digits, key-switching buffers) comes from

@@ -112,6 +112,12 @@ _SIGS = [
                                            C.c_int, C.c_int, C.c_int, C.c_double, C.c_uint64, C.c_void_p,
                                            C.c_void_p]),
     ("ckc_set_test_fault", C.c_int, [C.c_int, C.c_int]),
+    ("ckc_batch_plan", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]),
+    ("ckc_batch_plan_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]),
+    ("ckc_batch_plan_destroy", C.c_int, [C.c_void_p]),
+    ("ckc_batch_run", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
+                                C.POINTER(C.c_void_p), C.c_void_p]),
 ]
 
 
@@ -609,6 +615,42 @@ def stream_release(stream=None):
     """Free the library's scratch arena of `stream` (after its queued work);
     the next call on the stream grows a new one."""
     _check("ckc_stream_release", lib().ckc_stream_release(_stream(stream)))
+
+
+class Plan:
+    """A network's layer program parsed by the native runner."""
+
+    def __init__(self, ctx, program_json: str, layers: list):
+        self.ctx, self.layers = ctx, list(layers)  # the handles must outlive the plan
+        arr = (C.c_void_p * max(len(layers), 1))(*[l.h for l in layers])
+        h = C.c_void_p()
+        _check("ckc_batch_plan", lib().ckc_batch_plan(ctx.h, program_json.encode(), arr, len(layers), C.byref(h)))
+        self.h = h
+        v = [C.c_int() for _ in range(4)]
+        _check("ckc_batch_plan_info", lib().ckc_batch_plan_info(self.h, *[C.byref(x) for x in v]))
+        self.in_count, self.in_level, self.out_count, self.out_level = (int(x.value) for x in v)
+
+    def run(self, evks: list, inputs: list, stream=None) -> list:
+        """inputs[r]: request r's input ciphertexts; evks[r]: its KeyPair.
+        Returns [r][out_count] output ciphertexts."""
+        n = len(inputs)
+        outs = [[self.ctx.new_ct(self.out_level) for _ in range(self.out_count)] for _ in range(n)]
+        in_arrs = [_ct_array(row) for row in inputs]
+        out_arrs = [_ct_array(row) for row in outs]
+        pin = (C.c_void_p * max(n, 1))(*[C.cast(a, C.c_void_p) for a in in_arrs])
+        pout = (C.c_void_p * max(n, 1))(*[C.cast(a, C.c_void_p) for a in out_arrs])
+        pev = (C.c_void_p * max(n, 1))(*[k.evk for k in evks])
+        _check("ckc_batch_run", lib().ckc_batch_run(self.h, pev, pin, n, pout, _stream(stream)))
+        for row, a in zip(outs, out_arrs):
+            _update_all(row, a)
+        return outs
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().ckc_batch_plan_destroy(self.h)
+        except Exception:
+            pass
 
 
 def set_test_fault(call_index: int, code: int = -6):

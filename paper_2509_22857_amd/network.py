@@ -287,6 +287,42 @@ class GpuNetwork:
             outs = r
         return outs
 
+    def native_plan(self) -> "ckks.Plan":
+        """The network as a program for the library's native runner (the same
+        layer calls, rescales and residual additions as stages())."""
+        import json
+        handles = []
+
+        def idx(layer):
+            handles.append(layer)
+            return len(handles) - 1
+
+        count_of = {"x": self.spec["image"][0]}
+        steps = []
+        for ly, p, ent in zip(self.spec["layers"], self.plans, self.layers):
+            op = ly["op"]
+            st = {"op": op, "in": ly["inp"], "out": ly["out"], "level": p.level, "rescale": int(bool(p.rescale))}
+            if op == "conv":
+                st["count"], st["layer"] = ly["out_ch"], idx(ent["main"])
+                if ent["short"] is not None:
+                    st["short"] = {"layer": idx(ent["short"]), "in": ly["short"]["inp"], "level": p.short_level}
+            elif op == "act":
+                st["count"], st["layer"] = count_of[ly["inp"]], idx(ent["main"])
+            elif op == "dense":
+                st["count"], st["layer"] = ly["w"].shape[1], idx(ent["main"])
+            elif op == "pool":
+                lay = self.layouts[ly["inp"]]
+                st["count"] = count_of[ly["inp"]]
+                st["layout"] = {k: int(getattr(lay, k)) for k in ("block", "row_stride", "gap", "height", "width",
+                                                                   "members")}
+            else:
+                raise ValueError(f"unknown layer op {op}")
+            count_of[ly["out"]] = st["count"]
+            steps.append(st)
+        program = {"input": {"name": "x", "count": self.spec["image"][0], "level": len(self.ctx.q) - 1},
+                   "output": self.spec["layers"][-1]["out"], "steps": steps}
+        return ckks.Plan(self.ctx, json.dumps(program), handles)
+
     def working_set_bytes(self, n_img: int) -> int:
         """Upper estimate of the device bytes one pass of n_img images holds:
         the most live tensors around any layer plus the largest scratch of any

@@ -203,3 +203,40 @@ def test_graphed_pass_replays_match_eager():
         for wrow, grow in zip(want, got):
             for w, g in zip(wrow, grow):
                 assert torch.equal(w, g.buf), rep
+
+
+def test_native_runner_matches_python_orchestration():
+    """The library's native runner (ckc_batch_plan / ckc_batch_run) executes
+    the same layer program as the Python orchestration, bit for bit: a small
+    ResNet ensemble (residual shortcuts, stride 2) and a small VGG (pooling),
+    two requests under one key set batched together, a third under another
+    key set in its own pass."""
+    from paper_2509_22857_amd import ckks
+    D = 2.0 ** 30
+    cases = [
+        ("resnet", nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8,
+                                    calib=4), small_tower(logN=12, levels=6)),
+        ("vgg", nets.vgg_spec(seed=2, widths=(4, 4, 8, 8, 8), classes=5, image=(3, 16, 16), k=6, calib=4),
+         small_tower(logN=12, levels=6)),
+    ]
+    from paper_2509_22857_amd.ckks import Context
+    from paper_2509_22857_amd.network import GpuNetwork
+    for name, spec, ps in cases:
+        print(f"[native] {name}", flush=True)
+        ctx = Context.from_params(ps)
+        gnet = GpuNetwork(ctx, spec, D, D, D)
+        k1 = ctx.keygen(31, gnet.steps)
+        k2 = ctx.keygen(32, gnet.steps)
+        imgs = gen.images(77, 3, *spec["image"])
+        ins = [gnet.encrypt_images(k, imgs[i:i + 1], 9000 + 64 * i)[0] for i, k in enumerate((k1, k1, k2))]
+        want = [gnet.run(k, [row])[0][0] for k, row in zip((k1, k1, k2), ins)]
+        plan = gnet.native_plan()
+        assert plan.in_count == spec["image"][0] and plan.out_count == len(want[0])
+        got = plan.run([k1, k1, k2], ins)
+        for r in range(3):
+            assert len(got[r]) == len(want[r])
+            for a, b in zip(got[r], want[r]):
+                assert a.level == b.level and a.scale == b.scale
+                assert np.array_equal(_coeff(ctx, a), _coeff(ctx, b)), (name, r)
+        with pytest.raises(ckks.CkcError, match="CKC_EINVAL"):
+            ckks.Plan(ctx, '{"input": {"name": "x", "count": 3, "level": 0}, "output": "y", "steps": []}', [])
