@@ -83,6 +83,74 @@ def calibration_copy(torch):
     del src, dst
 
 
+def run_packed(args):
+    """Slot packing, a separate labelled row (not the headline): args.pack
+    images share every ciphertext (image p in member blocks p M .. p M + M - 1
+    of the same network), so one pass over the ciphertexts serves pack images.
+    Prints its own JSON line."""
+    import torch
+    from paper_2509_22857_amd.autotune import tune_network, TUNING_FILE
+    from paper_2509_22857_amd.ckks import Context
+    from paper_2509_22857_amd.network import GpuNetwork
+    from oracle.forward import forward
+    from workloads import gen, nets
+    P = args.pack
+    t0 = time.time()
+    ps, spec = build_workload(args)
+    pspec = nets.pack_spec(spec, P)
+    M, B = spec["members"], spec["layout"]["block"]
+    if M * P * B > (1 << ps.logN) // 2:
+        log(f"{P} images x {M} members x {B} slots do not fit N/2 slots")
+        sys.exit(2)
+    ctx = Context.from_params(ps)
+    delta = 2.0 ** ps.delta_log2
+    net = GpuNetwork(ctx, pspec, delta, delta, delta)
+    keys = ctx.keygen(12345, net.steps)
+    torch.cuda.synchronize()
+    log(f"packed: {P} images x {M} members per ciphertext, set-up {time.time() - t0:.1f}s")
+    n_img = args.batch
+    imgs = gen.images(777, n_img, *spec["image"])
+    groups = net.encrypt_packed(keys, imgs, stream_base=1 << 20)
+    torch.cuda.synchronize()
+    if args.tune != "off":
+        tune_network(net, keys, groups[: min(len(groups), args.images_per_pass)], cache=TUNING_FILE,
+                     key=f"resnet20_ensemble_N65536/{min(len(groups), args.images_per_pass)}", write=False)
+    for _ in range(args.warmup):
+        net.run(keys, groups, images_per_pass=args.images_per_pass)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        out, _ = net.run(keys, groups, images_per_pass=args.images_per_pass)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3 / args.steps
+    ips = n_img / sec
+    log(f"packed batched: {sec:.2f}s per step of {n_img} images ({len(groups)} ciphertext groups) -> {ips:.3f} images/s")
+    max_err, agree, nchk = 0.0, 0, 0
+    for g in range(min(len(groups), max(1, args.check // P))):
+        got = net.decrypt_logits(keys, out[g]).reshape(P, M, -1)
+        for p in range(P):
+            i = g * P + p
+            if i >= n_img:
+                break
+            ref = forward(spec, imgs[i])
+            max_err = max(max_err, float(np.max(np.abs(got[p] - ref))))
+            agree += int(got[p].mean(0).argmax() == ref.mean(0).argmax())
+            nchk += 1
+    log(f"packed logits vs FP64: max abs err {max_err:.2e}, top-1 agree {agree}/{nchk}")
+    print(json.dumps({
+        "metric": "encrypted images/s (ResNet-20-style ensemble, N=2^16, slot-packed row, not the headline)",
+        "value": round(ips, 4), "unit": "images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "resnet20_ensemble_N65536_slot_packed", "images_per_ciphertext": P,
+                   "members": M, "images_per_step": n_img, "ciphertext_groups_per_pass": args.images_per_pass},
+        "accuracy": {"max_abs_logit_err": max_err, "top1_agree": f"{agree}/{nchk}"},
+        "roofline": None, "cpu_baseline": None}))
+
+
 def workload_key(args, tuned):
     knobs = {k: v for k, v in (tuned or {}).items() if k != "timings"}
     return f"{args.workload}/batch{args.batch}/pass{args.images_per_pass}/" + json.dumps(knobs, sort_keys=True)
@@ -139,6 +207,8 @@ def main():
     ap.add_argument("--tune", default="cached", choices=["cached", "fresh", "off"],
                     help="autotuner: stored choices for this workload if any (else tune), re-tune, or defaults")
     ap.add_argument("--workload", default="resnet20", choices=["resnet20", "vgg", "micro", "serving"])
+    ap.add_argument("--pack", type=int, default=1,
+                    help="images per ciphertext (slot packing, a separate labelled row; resnet20 only)")
     ap.add_argument("--clients", type=int, default=4, help="serving: clients with their own keys")
     ap.add_argument("--serve-rates", default="2,5,10,20", help="serving: Poisson arrival rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=16, help="serving: requests per rate")
@@ -158,6 +228,10 @@ def main():
     if args.workload == "serving":
         from paper_2509_22857_amd import serve_bench
         print(json.dumps(serve_bench.run(args, log)))
+        return
+
+    if args.pack > 1:
+        run_packed(args)
         return
 
     import torch

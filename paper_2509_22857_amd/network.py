@@ -115,6 +115,26 @@ def image_slots(spec: dict, img: np.ndarray, N: int) -> list[np.ndarray]:
     return out
 
 
+def packed_image_slots(spec: dict, imgs: np.ndarray, N: int) -> list[np.ndarray]:
+    """Client-side packing of len(imgs) images into one set of ciphertexts
+    (a spec from workloads.nets.pack_spec): image p in the member blocks
+    p M .. p M + M - 1."""
+    C, H, W = spec["image"]
+    B, W0 = spec["layout"]["block"], spec["layout"]["row_stride"]
+    M, P = spec["packed"]["members"], spec["packed"]["images"]
+    assert len(imgs) <= P and M * P * B <= N // 2
+    out = []
+    for c in range(C):
+        v = np.zeros(M * P * B)
+        for p, img in enumerate(imgs):
+            for m in range(M):
+                base = (p * M + m) * B
+                for r in range(H):
+                    v[base + r * W0: base + r * W0 + W] = img[c, r]
+        out.append(v)
+    return out
+
+
 class GpuNetwork:
     """Device-resident layers of one network under one parameter set."""
 
@@ -182,6 +202,19 @@ class GpuNetwork:
             for c, v in enumerate(image_slots(self.spec, img, self.ctx.N)):
                 pt = self.ctx.encode(v, L, self.in_scale)
                 row.append(self.ctx.encrypt(keys, pt, stream_base + n * 4096 + c))
+            out.append(row)
+        return out
+
+    def encrypt_packed(self, keys: ckks.KeyPair, imgs: np.ndarray, stream_base: int = 0):
+        """Packed spec: groups of `images` images -> [n_groups][C] ciphertexts."""
+        P = self.spec["packed"]["images"]
+        L = len(self.ctx.q) - 1
+        out = []
+        for g0 in range(0, len(imgs), P):
+            row = []
+            for c, v in enumerate(packed_image_slots(self.spec, imgs[g0:g0 + P], self.ctx.N)):
+                pt = self.ctx.encode(v, L, self.in_scale)
+                row.append(self.ctx.encrypt(keys, pt, stream_base + (g0 // P) * 4096 + c))
             out.append(row)
         return out
 

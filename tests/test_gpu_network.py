@@ -240,3 +240,41 @@ def test_native_runner_matches_python_orchestration():
                 assert np.array_equal(_coeff(ctx, a), _coeff(ctx, b)), (name, r)
         with pytest.raises(ckks.CkcError, match="CKC_EINVAL"):
             ckks.Plan(ctx, '{"input": {"name": "x", "count": 3, "level": 0}, "output": "y", "steps": []}', [])
+
+
+def test_slot_packed_images_bit_exact_and_accurate():
+    """Two images packed into one set of ciphertexts (image p in member blocks
+    p M .. p M + M - 1): every output ciphertext equals the oracle's on the
+    same packed slots, and each image's logits match its own FP64 forward."""
+    from oracle.ckks import Oracle
+    from oracle.network import OracleNetwork
+    from paper_2509_22857_amd.ckks import Context
+    from paper_2509_22857_amd.network import GpuNetwork, packed_image_slots
+    from oracle.forward import forward
+    spec = nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8, calib=4)
+    P, M = 2, 2
+    pspec = nets.pack_spec(spec, P)
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[packed] 2 images x 2 members, N=2^12", flush=True)
+    ctx = Context.from_params(ps)
+    gnet = GpuNetwork(ctx, pspec, D, D, D)
+    keys = ctx.keygen(41, gnet.steps)
+    imgs = gen.images(88, P, *spec["image"])
+    groups = gnet.encrypt_packed(keys, imgs, stream_base=3000)
+    gout, _ = gnet.run(keys, groups)
+    o = Oracle.from_params(ps)
+    onet = OracleNetwork(o, pspec, D, D, D)
+    sk = o.secret_key(41)
+    rlk = o.relin_key(sk)
+    gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in onet.steps()}
+    L = len(ps.q) - 1
+    oin = [o.encrypt(o.encode(v, L, D), sk, 3000 + c) for c, v in enumerate(packed_image_slots(pspec, imgs, ps.N))]
+    oout, _ = onet.run(sk, oin, rlk, gk)
+    assert len(oout) == len(gout[0])
+    for j, (g, w) in enumerate(zip(gout[0], oout)):
+        assert np.array_equal(_coeff(ctx, g), w.data), j
+    logits = gnet.decrypt_logits(keys, gout[0]).reshape(P, M, -1)
+    for p in range(P):
+        ref = forward(spec, imgs[p])
+        assert np.max(np.abs(logits[p] - ref)) < 1e-3

@@ -131,3 +131,14 @@ def test_planner_rejects_chains_without_headroom():
         plan_network(spec, small_tower(logN=12, levels=4).q, 2.0 ** 30, 2.0 ** 30, 2.0 ** 30)
     plans, state = plan_network(spec, small_tower(logN=12, levels=6).q, 2.0 ** 30, 2.0 ** 30, 2.0 ** 30)
     assert min(p.level for p in plans) >= 1
+
+
+def test_pack_spec_repeats_members_per_image():
+    """Slot packing changes no arithmetic: with the same image in every group
+    of member blocks, the packed network's logits are the original network's
+    logits repeated once per packed image."""
+    spec = nets.resnet_spec(seed=6, members=2, widths=(4, 8), blocks=1, classes=5, image=(3, 8, 8), k=6, calib=2)
+    packed = nets.pack_spec(spec, 3)
+    assert packed["members"] == 6 and packed["packed"] == {"images": 3, "members": 2}
+    img = gen.images(21, 1, 3, 8, 8)[0]
+    assert np.allclose(forward(packed, img), np.tile(forward(spec, img), (3, 1)), rtol=1e-12, atol=1e-12)

@@ -326,3 +326,41 @@ def tiny_spec(seed: int = 0) -> dict:
     ]
     return dict(name="tiny_conv_act", members=1, classes=0, image=(1, 8, 8), layout=dict(block=64, row_stride=8),
                 layers=layers, k=3)
+
+
+def pack_spec(spec: dict, images: int) -> dict:
+    """Slot packing of several images per ciphertext: the same network with
+    members * images member blocks, block p * M + m running member m on image
+    p.  Every per-member array (codebook centroids, biases, activation
+    coefficients, dense weights) is repeated once per packed image, so the
+    evaluator computes, block by block, exactly what it computes for one image
+    per ciphertext; only the client's packing puts a different image into each
+    group of M blocks."""
+    M, P = spec["members"], int(images)
+    assert P >= 1
+
+    def tile0(a):
+        return None if a is None else np.tile(np.asarray(a), (P,) + (1,) * (np.ndim(a) - 1))
+
+    def conv(d):
+        d = dict(d)
+        d["codebook"] = np.tile(d["codebook"], (1, 1, P))
+        if d.get("bias") is not None:
+            d["bias"] = tile0(d["bias"])
+        if d.get("short") is not None:
+            d["short"] = conv(d["short"])
+        return d
+
+    layers = []
+    for ly in spec["layers"]:
+        if ly["op"] == "conv":
+            layers.append(conv(ly))
+        elif ly["op"] == "act":
+            layers.append(dict(ly, b=tile0(ly["b"]), c=tile0(ly["c"])))
+        elif ly["op"] == "dense":
+            layers.append(dict(ly, w=tile0(ly["w"]), bias=tile0(ly["bias"])))
+        else:
+            layers.append(dict(ly))
+    out = dict(spec, members=M * P, layers=layers)
+    out["packed"] = dict(images=P, members=M)
+    return out
