@@ -52,25 +52,42 @@ __global__ __launch_bounds__(256) void k_tensor_b(Ptrs a, Ptrs b, uint64_t *__re
 }
 
 // out[o] = sum_{t < T} in[o T + t] * pt[t] for the no outputs of one launch
-// (no T <= kMaxBatch); grid (tiles, limbs, 2 no): z = 2 o + polynomial
-__global__ __launch_bounds__(256) void k_mac_plain_b(Ptrs in, int T, Ptrs pt, Ptrs out, int nl,
+// (no T <= kMaxBatch); grid (N / 256, limbs), one coefficient per thread.
+// Each thread reads its T plaintext words once and reuses them for both
+// polynomials of every output, so a launch reads each plaintext from HBM once
+// (with a grid dimension per output and polynomial every block re-read them:
+// 1.8x the algorithmic bytes).  Up to kMacRegTerms terms sit in registers;
+// more are re-read per output, from cache.
+constexpr int kMacRegTerms = 16;
+__global__ __launch_bounds__(256) void k_mac_plain_b(Ptrs in, int T, Ptrs pt, Ptrs out, int no, int nl,
                                                      const Prime *__restrict__ primes, int logN) {
-    const int limb = blockIdx.y, o = blockIdx.z >> 1, poly = blockIdx.z & 1;
+    const int limb = blockIdx.y;
     const size_t N = size_t(1) << logN;
+    const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const Prime P = primes[limb];
     const int pcap = prod_cap(P.k);
-    const size_t off = (size_t(poly) * nl + limb) * N;
-    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
-        accc acc{0, 0, 0, 0, 0};
-        int cnt = 0;
-        for (int t = 0; t < T; ++t) {
-            macc(acc, in.p[o * T + t][off + k], pt.p[t][size_t(limb) * N + k]);
-            if (++cnt == pcap) {
-                acc = accc{0, 0, reduce128(accc_value(acc), P), 0, 0};
-                cnt = 0;
-            }
+    const size_t lo = size_t(limb) * N + k;
+    uint64_t pv[kMacRegTerms];
+#pragma unroll
+    for (int t = 0; t < kMacRegTerms; ++t) pv[t] = t < T ? pt.p[t][lo] : 0;
+    for (int o = 0; o < no; ++o) {
+        for (int poly = 0; poly < 2; ++poly) {
+            const size_t off = size_t(poly) * nl * N + lo;
+            accc acc{0, 0, 0, 0, 0};
+            int cnt = 0;
+            auto step = [&](uint64_t x, uint64_t w) {
+                macc(acc, x, w);
+                if (++cnt == pcap) {
+                    acc = accc{0, 0, reduce128(accc_value(acc), P), 0, 0};
+                    cnt = 0;
+                }
+            };
+#pragma unroll
+            for (int t = 0; t < kMacRegTerms; ++t)
+                if (t < T) step(in.p[o * T + t][off], pv[t]);
+            for (int t = kMacRegTerms; t < T; ++t) step(in.p[o * T + t][off], pt.p[t][lo]);
+            out.p[o][off] = reduce128(accc_value(acc), P);
         }
-        out.p[o][off + k] = reduce128(accc_value(acc), P);
     }
 }
 
@@ -189,8 +206,8 @@ extern "C" int ckc_mac_plain_many(ckc_ctx *c, const ckc_ct *in, const ckc_pt *pt
             for (int t = 0; t < n_terms; ++t) ip.p[o * n_terms + t] = in[size_t(o0 + o) * n_terms + t].d;
         }
         CKC_PROF(PK_MAC, s, 8.0 * N * nl * (2.0 * no * n_terms + n_terms + 2.0 * no), 2.0 * N * nl * no * n_terms);
-        hipLaunchKernelGGL(k_mac_plain_b, dim3(tiles(N), unsigned(nl), unsigned(2 * no)), dim3(256), 0, s, ip,
-                           n_terms, pp, op, nl, c->dprimes(), c->logN);
+        hipLaunchKernelGGL(k_mac_plain_b, dim3(unsigned(N / 256), unsigned(nl)), dim3(256), 0, s, ip, n_terms, pp,
+                           op, no, nl, c->dprimes(), c->logN);
         CKC_HIP(hipGetLastError());
     }
     for (int o = 0; o < n_out; ++o) {
