@@ -278,3 +278,29 @@ def test_slot_packed_images_bit_exact_and_accurate():
     for p in range(P):
         ref = forward(spec, imgs[p])
         assert np.max(np.abs(logits[p] - ref)) < 1e-3
+
+
+def test_compiled_batch_normalised_network_bit_exact():
+    """A trained-form network (batch normalisations, non-monic activations,
+    projection and identity shortcuts, global average pooling) through the
+    post-training compiler, then the evaluator: bit-exact with the oracle on
+    the compiled description, logits within 1e-3 of its FP64 forward."""
+    from oracle.forward import forward
+    from paper_2509_22857_amd import compiler as cc
+    from workloads.graphs import bn_resnet_graph
+    g = bn_resnet_graph(seed=5, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16))
+    spec, log = cc.compile_network(g, k=64, order="poly_first", direction="backward")
+    assert {"case1", "case3", "case4"} <= {e[0] for e in log}
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[compiled_bn_resnet] N=2^12 M=2 widths=(4,8)", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 31)
+    imgs = gen.images(60, 1, 3, 16, 16)
+    gin = gnet.encrypt_images(keys, imgs, 700)
+    gout, _ = gnet.run(keys, gin)
+    oin = onet.encrypt_image(sk, imgs[0], 700)
+    oout, _ = onet.run(sk, oin, rlk, gk)
+    for k, (a, b) in enumerate(zip(gout[0], oout)):
+        assert np.array_equal(_coeff(ctx, a), b.data), k
+    got = gnet.decrypt_logits(keys, gout[0])
+    assert np.max(np.abs(got - forward(spec, imgs[0]))) < 1e-3
