@@ -220,3 +220,18 @@ def test_compile_errors():
     _close(spec_forward(spec, img)[0], og.forward(g, img)[0], 1e-11)
     with pytest.raises(cc.CompileError, match="unique"):
         cc.shapes(dict(members=1, image=(1, 4, 4), nodes=[dict(op="add", name="a", inp=["x", "x"], out="x")]))
+
+
+def test_fixed_fitted_activation_becomes_per_channel():
+    """A network trained with one quantisation-aware fitted activation
+    (d = 2, b = 10, c = 2): Case 1 fusing gives every channel its own
+    coefficients, and the compiled network still equals the trained one."""
+    from paper_2509_22857_amd import qafit
+    act = qafit.coefficients(2, 10, 2.0)
+    g = bn_resnet_graph(8, members=2, act=act)
+    assert all(np.array_equal(n["c"][0, 0], act) for n in g["nodes"] if n["op"] == "poly")
+    spec, log = cc.compile_network(g, k=4096, order="poly_first")
+    acts = [L for L in spec["layers"] if L["op"] == "act"]
+    assert all(np.unique(L["b"]).size > 1 for L in acts)
+    img = gen.images(70, 1, 3, 16, 16)[0]
+    _close(spec_forward(spec, img), og.forward(g, img), 1e-10)

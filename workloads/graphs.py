@@ -53,7 +53,8 @@ def _calib(n, t):
 
 
 class _Builder:
-    def __init__(self, seed, members, image, calib, pre_std):
+    def __init__(self, seed, members, image, calib, pre_std, act=None):
+        self.act_poly = None if act is None else np.asarray(act, dtype=np.float64)
         self.g = rng(seed)
         self.M = members
         self.pre_std = pre_std
@@ -85,6 +86,9 @@ class _Builder:
 
     def act(self, name, inp, degree=2):
         C = self.t[inp].shape[2]
+        if self.act_poly is not None:  # one fixed activation polynomial everywhere
+            c = np.broadcast_to(self.act_poly, (self.M, C, len(self.act_poly))).copy()
+            return self.add(dict(op="poly", name=name, inp=[inp], out=name, c=c))
         c = np.zeros((self.M, C, degree + 1))
         c[..., 0] = self.g.uniform(-0.1, 0.1, (self.M, C))
         c[..., 1] = self.g.uniform(0.4, 0.6, (self.M, C))
@@ -106,12 +110,14 @@ class _Builder:
 
 
 def bn_resnet_graph(seed: int = 0, members: int = 2, widths=(4, 8), blocks: int = 1, classes: int = 10,
-                    image=(3, 16, 16), calib: int = 4, pre_std: float = 0.5) -> dict:
+                    image=(3, 16, 16), calib: int = 4, pre_std: float = 0.5, act=None) -> dict:
     """ResNet-style: conv-BN-act, then per stage `blocks` basic blocks
     (conv-BN-act-conv-BN, plus the shortcut -- identity, or a 1x1 stride-2
     projection conv-BN at a new stage -- then the activation of the sum),
-    global average pooling and a dense layer."""
-    b = _Builder(seed, members, image, calib, pre_std)
+    global average pooling and a dense layer.  act = (c0, c1, c2, ...) puts
+    that one polynomial at every activation (a network trained with a fixed
+    fitted activation); otherwise coefficients are drawn per channel."""
+    b = _Builder(seed, members, image, calib, pre_std, act)
     cur = b.act("act1", b.bn("bn1", b.conv("conv1", "x", widths[0], 3, bias=False)))
     ch = widths[0]
     for si, w in enumerate(widths):
