@@ -209,11 +209,17 @@ __global__ __launch_bounds__(256) void k_kip_ext_rot(const uint64_t *__restrict_
     }
     const int64_t out = kr.off[r] + int64_t(tt) * int64_t(N) + int64_t(kr.scat[r][k]);
     const uint64_t *dg = digits + size_t(tt) * N + k;
-    for (int b = 0; b < nb; ++b) {
-        uint64_t d[KD];
+    // the digits (and c0 word) of input b + 1 are loaded while input b's
+    // products run; two buffers swap roles (a register copy would wait for
+    // its load)
+    auto load = [&](uint64_t(&d)[KD + 1], int b) {
+        if (b >= nb) return;
 #pragma unroll
         for (int j = 0; j < KD; ++j)
-            if (DNUM > 0 || j < dnum) d[j] = dg[size_t(j) * nt * N];
+            if (DNUM > 0 || j < dnum) d[j] = dg[size_t(b) * dig_bs + size_t(j) * nt * N];
+        if (lowq) d[KD] = c0.p[b][size_t(tt) * N + k];
+    };
+    auto body = [&](const uint64_t(&d)[KD + 1], int b) {
         accc a0{0, 0, 0, 0, 0}, a1{0, 0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < KD; ++j) {
@@ -223,11 +229,18 @@ __global__ __launch_bounds__(256) void k_kip_ext_rot(const uint64_t *__restrict_
             }
         }
         uint64_t u0 = reduce128(accc_value(a0), P);
-        if (lowq) u0 = add_mod(u0, mul_shoup(c0.p[b][size_t(tt) * N + k], pm, pmp, P.q), P.q);
+        if (lowq) u0 = add_mod(u0, mul_shoup(d[KD], pm, pmp, P.q), P.q);
         uint64_t *o = dst.p[b] + out;
         o[0] = u0;
         o[size_t(nt) * N] = reduce128(accc_value(a1), P);
-        dg += dig_bs;
+    };
+    uint64_t da[KD + 1], db[KD + 1];
+    load(da, 0);
+    for (int b = 0; b < nb; b += 2) {
+        load(db, b + 1);
+        body(da, b);
+        load(da, b + 2);
+        if (b + 1 < nb) body(db, b + 1);
     }
 }
 using KipRotFn = void (*)(const uint64_t *, int, int, int, int, int, KipRot, int, LimbMap, Ptrs, Ptrs,
