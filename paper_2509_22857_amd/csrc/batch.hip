@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_kip_ext(const uint64_t *__restrict__ di
     const Prime P = primes[pi];
     const size_t dig_bs = size_t(dnum) * nt * N;
     const bool lowq = tt < nl;
-    const uint64_t pm = lowq ? pmod[2 * tt] : 0, pmp = lowq ? pmod[2 * tt + 1] : 0;
+    const uint64_t pm = lowq ? pmod[2 * tt] : 0;
     constexpr int KD = DNUM > 0 ? DNUM : kMaxDnum;
     for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
         uint64_t kb[KD], ka[KD];
@@ -157,10 +157,10 @@ __global__ __launch_bounds__(256) void k_kip_ext(const uint64_t *__restrict__ di
                     macc(a1, d[j], ka[j]);
                 }
             }
-            uint64_t u0 = reduce128(accc_value(a0), P);
-            if (lowq) u0 = add_mod(u0, mul_shoup(c0.p[b][size_t(tt) * N + k], pm, pmp, P.q), P.q);
+            // P c0 joins the sum as one more product (P mod q < q, c0 < q)
+            if (lowq) macc(a0, c0.p[b][size_t(tt) * N + k], pm);
             uint64_t *o = dst.p[b] + out;
-            o[0] = u0;
+            o[0] = reduce128(accc_value(a0), P);
             o[size_t(nt) * N] = reduce128(accc_value(a1), P);
             dg += dig_bs;
         }
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void k_kip_ext_rot(const uint64_t *__restrict_
     const Prime P = primes[pi];
     const size_t dig_bs = size_t(dnum) * nt * N;
     const bool lowq = tt < nl;
-    const uint64_t pm = lowq ? pmod[2 * tt] : 0, pmp = lowq ? pmod[2 * tt + 1] : 0;
+    const uint64_t pm = lowq ? pmod[2 * tt] : 0;
     const uint64_t *key = kr.key[r];
     constexpr int KD = DNUM > 0 ? DNUM : kMaxDnum;
     uint64_t kb[KD], ka[KD];
@@ -228,10 +228,10 @@ __global__ __launch_bounds__(256) void k_kip_ext_rot(const uint64_t *__restrict_
                 macc(a1, d[j], ka[j]);
             }
         }
-        uint64_t u0 = reduce128(accc_value(a0), P);
-        if (lowq) u0 = add_mod(u0, mul_shoup(d[KD], pm, pmp, P.q), P.q);
+        // P c0 joins the sum as one more product (P mod q < q, c0 < q)
+        if (lowq) macc(a0, d[KD], pm);
         uint64_t *o = dst.p[b] + out;
-        o[0] = u0;
+        o[0] = reduce128(accc_value(a0), P);
         o[size_t(nt) * N] = reduce128(accc_value(a1), P);
     };
     uint64_t da[KD + 1], db[KD + 1];
