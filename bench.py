@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--plain", type=int, default=2, help="images timed one at a time")
     ap.add_argument("--check", type=int, default=4, help="images whose logits are checked against FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-out", default=os.path.join(ROOT, "tuning_fresh.json"),
+                    help="where --tune fresh writes the choices it measured")
     ap.add_argument("--tune", default="cached", choices=["cached", "fresh", "off"],
                     help="autotuner: stored choices for this workload if any (else tune), re-tune, or defaults")
     ap.add_argument("--workload", default="resnet20", choices=["resnet20", "vgg", "micro", "serving"])
@@ -268,9 +270,9 @@ def main():
         sample = cts[: min(B, args.images_per_pass)]
         key = f"{'vgg_N65536' if args.workload == 'vgg' else 'resnet20_ensemble_N65536'}/{len(sample)}"
         if args.tune == "fresh":
-            os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-            tuned = tune_network(net, keys, sample, cache=os.path.join(ROOT, "gpurun_out", "tuning.json"), key=key,
-                                 log=log, refresh=True)
+            # a fresh search writes its own cache file (--tune-out), never the committed choices
+            os.makedirs(os.path.dirname(os.path.abspath(args.tune_out)), exist_ok=True)
+            tuned = tune_network(net, keys, sample, cache=args.tune_out, key=key, log=log, refresh=True)
         else:
             tuned = tune_network(net, keys, sample, cache=TUNING_FILE, key=key, log=log, write=False)
         log(f"autotune ({args.tune}) in {time.time() - t0:.1f}s: { {k: v for k, v in tuned.items() if k != 'timings'} }")
