@@ -83,6 +83,11 @@ Prime make_prime(uint64_t q) {
     P.r2 = (uint64_t)(((u128)1 << 64) % q);
     P.r2p = hshoup(P.r2, q);
     P.onep = (uint64_t)(((u128)1 << 64) / q);
+    // q^-1 mod 2^64 by Newton's iteration (each step doubles the correct
+    // low bits; q odd, so q is its own inverse mod 8)
+    uint64_t inv = q;
+    for (int i = 0; i < 5; ++i) inv *= 2 - q * inv;
+    P.qinv = 0 - inv;
     return P;
 }
 

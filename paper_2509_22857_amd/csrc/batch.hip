@@ -45,7 +45,9 @@ constexpr int kMaxDnum = 16;
 // accq [b][2][nl][N], P limbs to accp [b][2][np][N].  One thread per
 // coefficient keeps its 2 DNUM key words in registers for the whole batch;
 // the digit loads of one ciphertext are issued together (DNUM is a template
-// parameter, so the loop is straight-line code).
+// parameter, so the loop is straight-line code).  Keys are stored times 2^64
+// mod q, so each output's sum ends in one Montgomery reduction (redc_accc),
+// which removes that factor, instead of a general 128-bit reduction.
 template <int DNUM>
 __global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digits, int nb, int dnum_rt, int nt,
                                                int nl, const uint64_t *__restrict__ key, int nprimes, LimbMap map,
@@ -89,8 +91,8 @@ __global__ __launch_bounds__(256) void k_kip_b(const uint64_t *__restrict__ digi
                     macc(a1, d[j], ka[j]);
                 }
             }
-            ob[0] = reduce128(accc_value(a0), P);
-            ob[o_ps] = reduce128(accc_value(a1), P);
+            ob[0] = redc_accc<KD>(a0, P);
+            ob[o_ps] = redc_accc<KD>(a1, P);
             dg += dig_bs;
             ob += o_bs;
         }
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(256) void k_kip_ext(const uint64_t *__restrict__ di
     const Prime P = primes[pi];
     const size_t dig_bs = size_t(dnum) * nt * N;
     const bool lowq = tt < nl;
-    const uint64_t pm = lowq ? pmod[2 * tt] : 0;
+    const uint64_t pm = lowq ? mul_shoup(pmod[2 * tt], P.r2, P.r2p, P.q) : 0;  // P 2^64 mod q
     constexpr int KD = DNUM > 0 ? DNUM : kMaxDnum;
     for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
         uint64_t kb[KD], ka[KD];
@@ -157,11 +159,11 @@ __global__ __launch_bounds__(256) void k_kip_ext(const uint64_t *__restrict__ di
                     macc(a1, d[j], ka[j]);
                 }
             }
-            // P c0 joins the sum as one more product (P mod q < q, c0 < q)
+            // P c0 joins the sum as one more product (pm = P 2^64 mod q, c0 < q)
             if (lowq) macc(a0, c0.p[b][size_t(tt) * N + k], pm);
             uint64_t *o = dst.p[b] + out;
-            o[0] = reduce128(accc_value(a0), P);
-            o[size_t(nt) * N] = reduce128(accc_value(a1), P);
+            o[0] = redc_accc<KD + 1>(a0, P);
+            o[size_t(nt) * N] = redc_accc<KD>(a1, P);
             dg += dig_bs;
         }
     }
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(256) void k_kip_ext_rot(const uint64_t *__restrict_
     const Prime P = primes[pi];
     const size_t dig_bs = size_t(dnum) * nt * N;
     const bool lowq = tt < nl;
-    const uint64_t pm = lowq ? pmod[2 * tt] : 0;
+    const uint64_t pm = lowq ? mul_shoup(pmod[2 * tt], P.r2, P.r2p, P.q) : 0;  // P 2^64 mod q
     const uint64_t *key = kr.key[r];
     constexpr int KD = DNUM > 0 ? DNUM : kMaxDnum;
     uint64_t kb[KD], ka[KD];
@@ -228,11 +230,11 @@ __global__ __launch_bounds__(256) void k_kip_ext_rot(const uint64_t *__restrict_
                 macc(a1, d[j], ka[j]);
             }
         }
-        // P c0 joins the sum as one more product (P mod q < q, c0 < q)
+        // P c0 joins the sum as one more product (pm = P 2^64 mod q, c0 < q)
         if (lowq) macc(a0, d[KD], pm);
         uint64_t *o = dst.p[b] + out;
-        o[0] = reduce128(accc_value(a0), P);
-        o[size_t(nt) * N] = reduce128(accc_value(a1), P);
+        o[0] = redc_accc<KD + 1>(a0, P);
+        o[size_t(nt) * N] = redc_accc<KD>(a1, P);
     };
     uint64_t da[KD + 1], db[KD + 1];
     load(da, 0);

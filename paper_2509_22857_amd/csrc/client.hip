@@ -93,6 +93,19 @@ __global__ void k_keygen_combine(uint64_t *__restrict__ b, const uint64_t *__res
     }
 }
 
+// evaluation keys are kept times 2^64 mod q (Montgomery form): the key inner
+// products end in one Montgomery reduction per output instead of a 128-bit
+// reduction (x -> x 2^64 mod q is a Shoup product by r2 = 2^64 mod q)
+__global__ void k_to_montgomery(uint64_t *__restrict__ x, int nlimbs_per_row, const Prime *__restrict__ primes,
+                                int logN) {
+    const size_t N = size_t(1) << logN;
+    const int row = blockIdx.y;
+    const Prime P = primes[row % nlimbs_per_row];
+    uint64_t *r = x + size_t(row) * N;
+    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x)
+        r[k] = mul_shoup(r[k], P.r2, P.r2p, P.q);
+}
+
 // c0 = m - a s + e over the Q limbs (NTT form)
 __global__ void k_encrypt_combine(uint64_t *__restrict__ c0, const uint64_t *__restrict__ m,
                                   const uint64_t *__restrict__ a, const uint64_t *__restrict__ e,
@@ -303,7 +316,8 @@ int secret_impl(ckc_ctx *c, ckc_sk *sk, uint64_t seed, hipStream_t s) {
     return CKC_OK;
 }
 
-// key[j][2][nprimes][N] switching s' (NTT form, every prime) -> s
+// key[j][2][nprimes][N] switching s' (NTT form, every prime) -> s, stored
+// times 2^64 mod q
 int switch_key_impl(ckc_ctx *c, const ckc_sk *sk, uint64_t key_id, const uint64_t *sprime, uint64_t *key,
                     hipStream_t s) {
     const size_t N = c->N;
@@ -335,6 +349,10 @@ int switch_key_impl(ckc_ctx *c, const ckc_sk *sk, uint64_t key_id, const uint64_
                            sk->s_ntt.u64(), sprime, (const uint64_t *)pmd.p, dlo, dhi, c->dprimes(), c->logN);
         CKC_HIP(hipGetLastError());
     }
+    // rows [dnum][2][np], row r over prime r mod np
+    hipLaunchKernelGGL(k_to_montgomery, dim3(tiles(N), unsigned(dnum * 2 * np)), dim3(256), 0, s, key, np,
+                       c->dprimes(), c->logN);
+    CKC_HIP(hipGetLastError());
     CKC_HIP(hipStreamSynchronize(s));
     return CKC_OK;
 }

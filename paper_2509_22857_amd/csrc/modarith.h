@@ -91,6 +91,7 @@ struct Prime {
     uint64_t r2;    // 2^64 mod q
     uint64_t r2p;   // floor(r2 * 2^64 / q)   (Shoup companion of r2)
     uint64_t onep;  // floor(2^64 / q)        (Shoup companion of 1)
+    uint64_t qinv;  // -q^-1 mod 2^64         (Montgomery reduction)
     int32_t k;      // bit length of q
     int32_t pad;
 };
@@ -141,6 +142,23 @@ CKC_HD uint64_t reduce128(u128v x, const Prime &P) {
     uint64_t a = mul_shoup(x.hi, P.r2, P.r2p, P.q);
     uint64_t b = mul_shoup(x.lo, 1, P.onep, P.q);
     return add_mod(a, b, P.q);
+}
+
+// Montgomery reduction of a carry-counted sum: the representative in [0, q)
+// of value * 2^-64 mod q, for a sum of at most NPROD products of residues
+// (each below q^2 < q 2^62).  With m = lo * qinv mod 2^64, value + m q is a
+// multiple of 2^64 whose quotient hi + mulhi(m, q) + [lo != 0] lies below
+// value / 2^64 + q < (NPROD / 4 + 1) q, so ceil(NPROD / 4) conditional
+// subtractions of q finish it.  Used where the sum's operands carry a factor
+// 2^64 (evaluation keys are stored times 2^64 mod q).
+template <int NPROD>
+__device__ __forceinline__ uint64_t redc_accc(const accc &a, const Prime &P) {
+    const u128v v = accc_value(a);
+    const uint64_t m = v.lo * P.qinv;
+    uint64_t t = v.hi + mulhi64(m, P.q) + (v.lo != 0 ? 1ull : 0ull);
+#pragma unroll
+    for (int i = 0; i < (NPROD + 3) / 4; ++i) t = t >= P.q ? t - P.q : t;
+    return t;
 }
 
 // Reduce an arbitrary 64-bit word into [0, q) (Shoup multiplication by 1).
