@@ -285,7 +285,7 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
             uint64_t h = 1 % qi;
             for (int b = 0; b < n_p; ++b)
                 if (b != a) h = hmul(h, p[b] % qi, qi);
-            hat[size_t(i) * n_p + a] = h;
+            hat[size_t(i) * n_p + a] = hmul(h, (uint64_t)(((u128)1 << 64) % qi), qi);  // times 2^64 mod q_i
         }
     }
     c->p_to_q.iscale_h.resize(2 * size_t(n_p));

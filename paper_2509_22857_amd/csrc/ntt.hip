@@ -436,6 +436,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(uint64_t *__restrict__ da
 
 // first forward pass fed by fast basis conversion: word i of output limb t is
 //   sum_{k < ns} y_k[i] * hat[t][k]  mod q_t
+// (the table holds hat times 2^64 mod q_t, and the sum ends in one
+// Montgomery reduction, which removes the factor)
 // from the pre-scaled coefficient-form source limbs y_k (y = x (S/s_k)^-1 mod
 // s_k); limbs in [copy_lo, copy_hi) are copied from `copy` instead (their NTT
 // form is already known) and left alone by the second pass.  The number of
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restric
         accc acc{0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < NS; ++k) macc(acc, src[size_t(k) * N + i], h[k]);
-        return reduce128(accc_value(acc), P);
+        return redc_accc<NS>(acc, P);
     };
     auto st = [a](size_t i, uint64_t v) { a[i] = v; };
     if (radix16(logN))

@@ -182,7 +182,8 @@ const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc) {
             uint64_t prod = 1 % qt;
             for (int j = 0; j < ns; ++j)
                 if (j != i) prod = h_mulmod(prod, c->mods[lo + j] % qt, qt);
-            hat[size_t(tt) * ns + i] = prod;
+            // times 2^64 mod q_t: the conversion ends in a Montgomery reduction
+            hat[size_t(tt) * ns + i] = h_mulmod(prod, uint64_t(((unsigned __int128)1 << 64) % qt), qt);
         }
     }
     t->ns = ns;
