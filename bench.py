@@ -419,6 +419,13 @@ def main():
                            "frac": round(ks_gbs / HBM_PEAK_GBS, 4),
                            "kip_GBs": round(kip_gbs, 1), "kip_frac": round(kip_gbs / HBM_PEAK_GBS, 4)},
         "kernel_rates": rates,
+        # whole-step HBM roofline fraction: the algorithmic bytes of every
+        # profiled launch of the timed steps (inputs, keys and codebook tiles
+        # counted once per launch that reads them) at 8 TB/s, over the
+        # measured step time
+        "throughput_hbm": {"alg_bytes_per_image": round(sum(v["bytes"] for v in prof.values()) / (B * args.steps)),
+                           "frac": round(sum(v["bytes"] for v in prof.values()) / (HBM_PEAK_GBS * 1e9)
+                                         / (ms / 1e3), 4)},
         "accuracy": {"max_abs_logit_err": max_err, "top1_agree": f"{agree}/{nchk}"},
         "kernel_time_share": shares,
         "profiled_kernel_busy": round(busy, 4),
