@@ -156,13 +156,20 @@ def workload_key(args, tuned):
     return f"{args.workload}/batch{args.batch}/pass{args.images_per_pass}/" + json.dumps(knobs, sort_keys=True)
 
 
+VGG_HOISTING = ["single", "double", "double", "double", "single"]
+
+
 def build_workload(args):
     from workloads import nets
     from workloads.params import resnet20_tower
     if args.workload == "vgg":
-        # VGG-style: 3->64, 64->64, pool, 64->128, 128->128, pool, 128->256, dense to 10; k = 16
+        # VGG-style: 3->64, 64->64, pool, 64->128, 128->128, pool, 128->256, dense to 10; k = 16.
+        # Per-layer key-switching form: what network.choose_hoisting picks for
+        # this network and chain (a test keeps the two in step): the first
+        # layer (3 inputs, 64 outputs) and the last (level 2: three Q limbs,
+        # to which the three P limbs would add as many again) single-hoisted
         ps = resnet20_tower(levels=6)
-        spec = nets.vgg_spec(seed=0, calib=8)
+        spec = nets.vgg_spec(seed=0, calib=8, hoist=VGG_HOISTING)
         return ps, spec
     ps = resnet20_tower()
     spec = nets.resnet_spec(seed=0, members=4, widths=(16, 32, 64), blocks=3, classes=100, image=(3, 32, 32),

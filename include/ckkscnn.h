@@ -247,6 +247,33 @@ typedef struct {
 int ckc_layer_create_conv(ckc_ctx *ctx, const ckc_layout *in, int out_ch, int in_ch, int ksize, int stride,
                           int n_centroids, const double *codebook, const uint16_t *idx, const double *bias,
                           int level, double pt_scale, double bias_scale, ckc_layer **out, void *stream);
+
+/*
+ * Key-switching form of a layer's rotations (Section 2.2 hybrid key
+ * switching behind the Section 5.1 rotations of a convolution).  Both share
+ * one decomposition (ModUp) per input ciphertext; they differ in where the
+ * ModDown happens, so their ciphertexts differ in the low bits while
+ * decrypting to the same values within the key-switching noise:
+ *   CKC_HOIST_DOUBLE: every rotated input stays in Q_l u P and the products
+ *     with the codebook (encoded over Q_l u P) are summed there; one ModDown
+ *     per output polynomial.  Fewer ModDowns; the contraction runs over
+ *     l + 1 + n_P limbs.
+ *   CKC_HOIST_SINGLE: every rotated input is brought back to Q_l (one ModDown
+ *     per input and tap), then summed over l + 1 limbs.  Cheaper where the
+ *     P limbs are a large share of the limbs (low levels).
+ * 1x1 layers have no rotations and ignore the choice.
+ */
+enum { CKC_HOIST_SINGLE = 1, CKC_HOIST_DOUBLE = 2 };
+
+/*
+ * ckc_layer_create_conv with the key-switching form chosen explicitly
+ * (ckc_layer_create_conv is this with CKC_HOIST_DOUBLE).  Errors as
+ * ckc_layer_create_conv, and CKC_EINVAL for another hoisting value.
+ */
+int ckc_layer_create_conv_ex(ckc_ctx *ctx, const ckc_layout *in, int out_ch, int in_ch, int ksize, int stride,
+                             int n_centroids, const double *codebook, const uint16_t *idx, const double *bias,
+                             int level, double pt_scale, double bias_scale, int hoisting, ckc_layer **out,
+                             void *stream);
 /*
  * out[img][o] = sum_t sum_c PT[t][c] * (sum_{i : idx[o][i][t] = c} Rot_{step(t)}(in[img][i])) + bias_o
  * with step(t) = gap*(dh*row_stride + dw) for tap t = (dh, dw); one hoisted

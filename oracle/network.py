@@ -8,7 +8,10 @@ Written independently of the GPU runner from the paper's method:
     slots whose input pixel lies inside the image, and multiplies the input
     rotated by gap*(dh*row_stride + dw); all products are summed, plus the
     bias on the output grid.  This is the unclustered sum; grouping equal
-    centroids first gives the same ring element;
+    centroids first gives the same ring element.  A 3x3 layer's rotated
+    inputs stay in Q_l u P and are summed there with one ModDown per output
+    (double hoisting), or, for a layer marked single-hoisted, each is a
+    complete rotation back in Q_l before the sum;
   * activation x^2 + b x + c: t = x + b, y = Relin(x * t) + c (Section 4.2
     makes it monic), scale s^2 / a_absorb;
   * dense: rotation sums over the grid, then per class the weighted sum of
@@ -103,6 +106,28 @@ class OracleNetwork:
                         cache[key] = self.encode(mask(0, 0, wvec), level, pt_scale)
                     term = o.mul_plain(x, cache[key])
                     acc = term if acc is None else o.add(acc, term)
+                outs.append(acc)
+        elif ly.get("hoist", "double") == "single":
+            # single hoisting: every rotated input is a complete rotation
+            # (key switch with its own ModDown, back in Q_l), the products
+            # with plaintexts encoded over Q_l are summed there
+            rot = {}
+            for i, x in enumerate(xs):
+                for dh, dw in taps:
+                    step = g * (dh * self.W0 + dw)
+                    gk = gkeys[o.galois_elt(step)] if step else None
+                    rot[(i, dh, dw)] = o.rotate(x, step, gk)
+            cache = {}
+            for oc in range(ly["out_ch"]):
+                acc = None
+                for i in range(ly["in_ch"]):
+                    for dh, dw in taps:
+                        wvec = cb[dw + half][idx[oc, i, dh + half, dw + half]]
+                        key = (dh, dw, tuple(wvec))
+                        if key not in cache:
+                            cache[key] = self.encode(mask(dh, dw, wvec), level, pt_scale)
+                        term = o.mul_plain(rot[(i, dh, dw)], cache[key])
+                        acc = term if acc is None else o.add(acc, term)
                 outs.append(acc)
         else:
             # double hoisting: every rotated input stays in the extended basis

@@ -88,6 +88,9 @@ _SIGS = [
     ("ckc_layer_create_conv", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                         _dblp, C.POINTER(C.c_uint16), _dblp, C.c_int, C.c_double, C.c_double,
                                         C.POINTER(_vp), _vp]),
+    ("ckc_layer_create_conv_ex", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, C.c_int, C.c_int, C.c_int,
+                                           C.c_int, _dblp, C.POINTER(C.c_uint16), _dblp, C.c_int, C.c_double,
+                                           C.c_double, C.c_int, C.POINTER(_vp), _vp]),
     ("ckc_eval_conv", C.c_int, [_vp, _vp, _vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
     ("ckc_layer_create_act", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, _dblp, _dblp, C.c_double, C.c_int,
                                        C.c_double, C.POINTER(_vp), _vp]),
@@ -469,8 +472,13 @@ def make_layout(block, row_stride, gap, height, width, members) -> ckc_layout:
     return ckc_layout(int(block), int(row_stride), int(gap), int(height), int(width), int(members))
 
 
+HOIST = {"single": 1, "double": 2}  # CKC_HOIST_SINGLE, CKC_HOIST_DOUBLE
+
+
 def layer_create_conv(ctx: Context, layout: ckc_layout, out_ch, in_ch, ksize, stride, codebook, idx, bias,
-                      level, pt_scale, bias_scale, stream=None) -> Layer:
+                      level, pt_scale, bias_scale, stream=None, hoisting: str = "double") -> Layer:
+    """hoisting: "double" (one ModDown per output) or "single" (one per
+    rotated input); see ckc_layer_create_conv_ex."""
     cb, cbp = _dbl(codebook)
     ix = np.ascontiguousarray(np.asarray(idx, dtype=np.uint16))
     if bias is not None:
@@ -479,9 +487,9 @@ def layer_create_conv(ctx: Context, layout: ckc_layout, out_ch, in_ch, ksize, st
         bbp = None
     k = int(cb.shape[1])
     h = _vp()
-    _check("ckc_layer_create_conv", lib().ckc_layer_create_conv(
+    _check("ckc_layer_create_conv_ex", lib().ckc_layer_create_conv_ex(
         ctx.h, C.byref(layout), out_ch, in_ch, ksize, stride, k, cbp, ix.ctypes.data_as(C.POINTER(C.c_uint16)),
-        bbp, level, float(pt_scale), float(bias_scale), C.byref(h), _stream(stream)))
+        bbp, level, float(pt_scale), float(bias_scale), HOIST[hoisting], C.byref(h), _stream(stream)))
     return Layer(ctx, h, "conv")
 
 

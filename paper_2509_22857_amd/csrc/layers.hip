@@ -474,10 +474,12 @@ int check_inputs(const ckc_ct *in, int n, int level, const char *what) {
 }  // namespace
 
 // ============================================================= layer creation
-extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_ch, int in_ch, int ksize, int stride,
-                                     int n_centroids, const double *codebook, const uint16_t *idx, const double *bias,
-                                     int level, double pt_scale, double bias_scale, ckc_layer **out, void *stream) {
+extern "C" int ckc_layer_create_conv_ex(ckc_ctx *c, const ckc_layout *in, int out_ch, int in_ch, int ksize,
+                                        int stride, int n_centroids, const double *codebook, const uint16_t *idx,
+                                        const double *bias, int level, double pt_scale, double bias_scale,
+                                        int hoisting, ckc_layer **out, void *stream) {
     CKC_REQUIRE(c && out && codebook && idx, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(hoisting == CKC_HOIST_DOUBLE || hoisting == CKC_HOIST_SINGLE, CKC_EINVAL, "bad hoisting mode");
     CKC_TRY(check_layout(c, in));
     CKC_REQUIRE(ksize == 1 || ksize == 3, CKC_EUNSUPPORTED, "kernel size must be 1 or 3");
     CKC_REQUIRE(stride == 1 || stride == 2, CKC_EUNSUPPORTED, "stride must be 1 or 2");
@@ -512,8 +514,9 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
     }
     // codebook plaintexts: PT[t][c] = centroid c of column(t), per member, on
     // the tap's mask.  A layer with rotations sums its products in Q_l u P
-    // (one ModDown per output), so its plaintexts carry the P limbs too.
-    L->ext = ksize > 1;
+    // (one ModDown per output) unless it is single-hoisted (one ModDown per
+    // rotated input), so its plaintexts carry the P limbs too.
+    L->ext = ksize > 1 && hoisting == CKC_HOIST_DOUBLE;
     const size_t ppw = L->ext ? size_t(nl + c->np) * N : pw;  // words per codebook plaintext
     CKC_TRY(L->pts.alloc(8 * ppw * L->ntap * n_centroids));
     std::vector<double> v(n);
@@ -592,6 +595,13 @@ extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_c
     CKC_HIP(hipStreamSynchronize(s));
     *out = L.release();
     return CKC_OK;
+}
+
+extern "C" int ckc_layer_create_conv(ckc_ctx *c, const ckc_layout *in, int out_ch, int in_ch, int ksize, int stride,
+                                     int n_centroids, const double *codebook, const uint16_t *idx, const double *bias,
+                                     int level, double pt_scale, double bias_scale, ckc_layer **out, void *stream) {
+    return ckc_layer_create_conv_ex(c, in, out_ch, in_ch, ksize, stride, n_centroids, codebook, idx, bias, level,
+                                    pt_scale, bias_scale, CKC_HOIST_DOUBLE, out, stream);
 }
 
 extern "C" int ckc_layer_create_act(ckc_ctx *c, const ckc_layout *layout, int channels, const double *b,

@@ -94,6 +94,33 @@ def plan_network(spec: dict, q, delta: float, target: float, in_scale: float) ->
     return plans, state
 
 
+def choose_hoisting(spec: dict, q, n_p: int, delta: float, target: float, in_scale: float,
+                     ntt_cost: float = 80.0) -> list[str]:
+    """Key-switching form per 3x3 convolution by an operation count, at the
+    level the planner gives each layer: double hoisting adds the n_P special
+    limbs to every product of the contraction (2 taps O I n_P limb-products),
+    single hoisting adds one ModDown per rotated input instead of one per
+    output (2 ((taps - 1) I - O) ModDowns of n_P + l + 1 limb transforms,
+    each weighed as ntt_cost limb-products; 80 matches per-layer timings of
+    both forms on MI355X).  Returns one "single"/"double" per convolution, in
+    order (1x1 layers have no rotations: "double", which they ignore); pass
+    it to workloads.nets.set_hoisting to mark the network description."""
+    plans, _ = plan_network(spec, q, delta, target, in_scale)
+    out = []
+    for ly, p in zip(spec["layers"], plans):
+        if ly["op"] != "conv":
+            continue
+        taps, I, O = ly["ksize"] ** 2, ly["in_ch"], ly["out_ch"]
+        if taps == 1:
+            out.append("double")
+            continue
+        nl = p.level + 1
+        extra_products = 2 * taps * O * I * n_p
+        saved_moddowns = 2 * ((taps - 1) * I - O) * (n_p + nl) * ntt_cost
+        out.append("double" if extra_products < saved_moddowns else "single")
+    return out
+
+
 def input_layout(spec: dict) -> ckks.ckc_layout:
     C, H, W = spec["image"]
     lay = spec["layout"]
@@ -151,7 +178,7 @@ class GpuNetwork:
             if ly["op"] == "conv":
                 entry["main"] = ckks.layer_create_conv(ctx, lay, ly["out_ch"], ly["in_ch"], ly["ksize"], ly["stride"],
                                                        ly["codebook"], ly["idx"], ly["bias"], p.level, p.pt_scale,
-                                                       p.bias_scale)
+                                                       p.bias_scale, hoisting=ly.get("hoist", "double"))
                 if ly.get("short") is not None:
                     sh = ly["short"]
                     slay = self.layouts[sh["inp"]]
@@ -400,7 +427,7 @@ class GpuNetwork:
                 I, taps = ly["in_ch"], ly["ksize"] ** 2
                 ich = min(I, 64)
                 nimg = min(max(4, 64 // ich), n_img)
-                ext = ly["ksize"] > 1
+                ext = ly["ksize"] > 1 and ly.get("hoist", "double") == "double"
                 cte = 8 * 2 * (nt if ext else nl) * N
                 scratch = nimg * ich * taps * cte + (nimg * cnt * cte if ext else 0) + ks
                 if ly.get("short") is not None:

@@ -151,13 +151,16 @@ def test_wide_conv_input_chunks_bit_exact():
             ckks.tune_set(k, v)
 
 
-def test_small_vgg_bit_exact():
+@pytest.mark.parametrize("hoist", [None, ["double", "single", "double", "single", "single"]])
+def test_small_vgg_bit_exact(hoist):
     """VGG-style network (convolutions, activations, 2x2 sum pooling with the
-    divisor folded forward, one member so the dense layer uses constants)."""
-    spec = nets.vgg_spec(seed=2, widths=(4, 4, 8, 8, 8), classes=5, image=(3, 16, 16), k=6, calib=4)
+    divisor folded forward, one member so the dense layer uses constants);
+    with every 3x3 layer double-hoisted, and with a per-layer mix of single
+    and double hoisting."""
+    spec = nets.vgg_spec(seed=2, widths=(4, 4, 8, 8, 8), classes=5, image=(3, 16, 16), k=6, calib=4, hoist=hoist)
     ps = small_tower(logN=12, levels=6)
     D = 2.0 ** 30
-    print("[small_vgg] N=2^12 widths=(4,4,8,8,8) two pools", flush=True)
+    print(f"[small_vgg] N=2^12 widths=(4,4,8,8,8) two pools hoist={hoist}", flush=True)
     ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 31)
     imgs = gen.images(14, 2, 3, 16, 16)
     gin = gnet.encrypt_images(keys, imgs, 900)

@@ -142,3 +142,48 @@ def test_pack_spec_repeats_members_per_image():
     assert packed["members"] == 6 and packed["packed"] == {"images": 3, "members": 2}
     img = gen.images(21, 1, 3, 8, 8)[0]
     assert np.allclose(forward(packed, img), np.tile(forward(spec, img), (3, 1)), rtol=1e-12, atol=1e-12)
+
+
+def test_single_hoisted_convolutions_decrypt_to_forward():
+    """Both key-switching forms of a 3x3 layer (one ModDown per output, or
+    one per rotated input) decrypt to the FP64 forward; their ciphertexts
+    differ in the low bits (the ModDowns round at different places)."""
+    ps = small_tower(logN=12, levels=4)
+    o = Oracle.from_params(ps)
+    D = 2.0 ** 30
+    img = gen.images(4, 1, 3, 8, 8)[0]
+    sk = o.secret_key(13)
+    rlk = o.relin_key(sk)
+    got = {}
+    for mode in ("single", "double"):
+        spec = nets.vgg_spec(seed=2, widths=(4, 4), pool_after=(0,), classes=3, image=(3, 8, 8), k=4, calib=2,
+                             hoist=mode)
+        net = OracleNetwork(o, spec, delta=D, target=D, in_scale=D)
+        gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in net.steps()}
+        outs, _ = net.run(sk, net.encrypt_image(sk, img, 100), rlk, gk)
+        got[mode] = outs
+        vals = np.array([o.decrypt_decode(c, sk)[0] for c in outs])
+        assert np.max(np.abs(vals - forward(spec, img)[0])) < 1e-3
+    assert any(not np.array_equal(a.data, b.data) for a, b in zip(got["single"], got["double"]))
+    with pytest.raises(ValueError):
+        nets.vgg_spec(seed=2, widths=(4, 4), pool_after=(0,), classes=3, image=(3, 8, 8), k=4, calib=2,
+                      hoist=["single"])
+
+
+def test_hoisting_choice_of_the_benchmarked_networks():
+    """The operation-count choice of key-switching form: every ResNet-20 3x3
+    layer double-hoisted; the VGG-style network single-hoisted at its first
+    layer (3 inputs, 64 outputs: more outputs than rotated inputs) and at
+    its last (level 2: three Q limbs plus three P limbs), as bench.py runs
+    it."""
+    import bench
+    from paper_2509_22857_amd.network import choose_hoisting
+    ps = resnet20_tower(levels=6)
+    D = 2.0 ** ps.delta_log2
+    spec = nets.vgg_spec(seed=0, calib=2)
+    assert choose_hoisting(spec, ps.q, len(ps.p), D, D, D) == bench.VGG_HOISTING
+    ps = resnet20_tower()
+    D = 2.0 ** ps.delta_log2
+    spec = nets.resnet_spec(seed=0, members=4, widths=(16, 32, 64), blocks=3, classes=100, image=(3, 32, 32),
+                            k=64, calib=2)
+    assert set(choose_hoisting(spec, ps.q, len(ps.p), D, D, D)) == {"double"}

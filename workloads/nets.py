@@ -227,7 +227,7 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
 
 def vgg_spec(seed: int = 0, widths=(64, 64, 128, 128, 256), pool_after=(1, 3), classes: int = 10,
              image=(3, 32, 32), k: int = 16, calib: int = 8, members: int = 1, name: str | None = None,
-             pre_std: float = 0.5) -> dict:
+             pre_std: float = 0.5, hoist=None) -> dict:
     """VGG-style network: one 3x3 convolution (stride 1) and one quadratic
     activation per entry of `widths`, 2x2 average pooling after the layers
     listed in pool_after, global average pooling folded into the dense layer.
@@ -258,7 +258,24 @@ def vgg_spec(seed: int = 0, widths=(64, 64, 128, 128, 256), pool_after=(1, 3), c
     logits = np.einsum("mbc,mkc->mbk", pooled, Wd) + bd[:, None, :]
     s = 1.0 / max(_rms(logits), 1e-12)
     raw.append(("dense", dict(name="fc", inp=cur_name, out="logits", W=Wd * s, b=bd * s)))
-    return _finalise(raw, name or f"vgg_{'-'.join(map(str, widths))}_M{M}_k{k}", M, classes, image, k, seed, None)
+    spec = _finalise(raw, name or f"vgg_{'-'.join(map(str, widths))}_M{M}_k{k}", M, classes, image, k, seed, None)
+    return set_hoisting(spec, hoist)
+
+
+def set_hoisting(spec: dict, hoist) -> dict:
+    """Mark the key-switching form of every 3x3 convolution: hoist is None
+    (the default, double hoisting), "single"/"double" for all, or one entry
+    per convolution in order.  The mark is part of the network description,
+    read by both evaluators."""
+    if hoist is None:
+        return spec
+    convs = [ly for ly in spec["layers"] if ly["op"] == "conv"]
+    modes = [hoist] * len(convs) if isinstance(hoist, str) else list(hoist)
+    if len(modes) != len(convs) or any(m not in ("single", "double") for m in modes):
+        raise ValueError("hoist: 'single', 'double', or one of them per convolution")
+    for ly, m in zip(convs, modes):
+        ly["hoist"] = m
+    return spec
 
 
 def _finalise(raw, name, M, classes, image, k, seed, block_slots):
