@@ -25,7 +25,7 @@ import numpy as np
 def build(log, r18_calib: int = 4):
     import torch
     from . import ckks
-    from .network import GpuNetwork
+    from .network import GpuNetwork, choose_hoisting
     from workloads import nets
     from workloads.params import resnet20_tower
     t0 = time.time()
@@ -42,6 +42,9 @@ def build(log, r18_calib: int = 4):
         ps = chains[name]
         ctx = ckks.Context.from_params(ps)
         d = 2.0 ** ps.delta_log2
+        # per-layer key-switching form (ResNet-18's wide low-level layers single-hoisted)
+        nets.set_hoisting(spec, choose_hoisting(spec, ps.q, len(ps.p), d, d, d))
+        log(f"{name}: hoisting {[ly.get('hoist', 'double') for ly in spec['layers'] if ly['op'] == 'conv']}")
         t0 = time.time()
         nets_on_gpu[name] = GpuNetwork(ctx, spec, d, d, d)
         torch.cuda.synchronize()

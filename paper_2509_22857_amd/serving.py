@@ -103,13 +103,14 @@ class Server:
         next_bid = 0
         max_running = 0
         waiting = None
+        blocked = False  # a scratch reservation failed: admit again after a retirement
         while pending or queue or running:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             progressed = False
             # ---- admission: FIFO head, merged with later requests of the same client and network
-            while queue and free_streams:
+            while queue and free_streams and not blocked:
                 head = queue[0]
                 net = self.networks[head.net]
                 room = self.budget - self.key_bytes
@@ -133,14 +134,40 @@ class Server:
                         self.stats["waits_for_memory"] += 1  # requests that had to wait
                         waiting = head.rid
                     break
+                stream = free_streams[-1]
+                # the batch's largest scratch is allocated now, so its calls
+                # allocate nothing while it runs (part of the reservation).
+                # The budget counts bytes, not contiguous blocks: when the
+                # device cannot hand out the block after all, the group stays
+                # queued and admission resumes after the next retirement (or,
+                # with nothing running, after the cached blocks are returned)
+                try:
+                    ckks.stream_reserve(net.scratch_bytes(n_img), stream)
+                except ckks.CkcError as err:
+                    if "CKC_ENOMEM" not in str(err):
+                        raise
+                    self.stats["reserve_retries"] += 1
+                    ckks.stream_release(stream)
+                    torch.cuda.empty_cache()
+                    if running:
+                        blocked = True
+                        break
+                    if self.stats["reserve_retries_idle"] >= 1:
+                        # nothing else holds memory and it still does not fit
+                        queue.popleft()
+                        head.done = float("nan")
+                        head.error = str(err)
+                        self.stats["rejected"] += 1
+                        self.stats["reserve_retries_idle"] = 0
+                        continue
+                    self.stats["reserve_retries_idle"] += 1
+                    continue
+                self.stats["reserve_retries_idle"] = 0
+                free_streams.pop()
                 for r in group:
                     queue.remove(r)
                     r.admitted = now
                     r.batch_id = next_bid
-                stream = free_streams.pop()
-                # the batch's largest scratch is allocated now, so its calls
-                # allocate nothing while it runs (part of the reservation)
-                ckks.stream_reserve(net.scratch_bytes(n_img), stream)
                 # inputs were written on the submitting stream
                 stream.wait_stream(torch.cuda.current_stream())
                 inputs = [row for r in group for row in r.inputs]
@@ -193,6 +220,7 @@ class Server:
                     torch.cuda.empty_cache()
                     free_streams.append(b.stream)
                     self.reserved -= b.reserve
+                    blocked = False
                     progressed = True
             if not progressed:
                 # nothing to enqueue: wait a little for the GPU or the next arrival
@@ -210,6 +238,7 @@ class Server:
             "rejected": int(self.stats["rejected"]),
             "failed": int(self.stats["failed"]),
             "waits_for_memory": int(self.stats["waits_for_memory"]),
+            "reserve_retries": int(self.stats["reserve_retries"]),
             "batches": next_bid,
             "max_concurrent_batches": max_running,
             "p50_s": float(np.percentile(lat, 50)),

@@ -152,3 +152,47 @@ def test_failed_batch_is_retired_and_the_rest_served(world):
         assert r.error is None
         got = _words(r.outputs[0])
         assert all(torch.equal(x, y) for x, y in zip(got, a)), r.rid
+
+
+def test_failed_scratch_reservation_waits_for_a_retirement(world, monkeypatch):
+    """When the device cannot hand out a batch's scratch block although the
+    byte budget allows it (a failure injected into the second reservation,
+    while the first batch runs), the batch stays queued and is admitted after
+    a retirement; every request is served with the same ciphertexts as alone."""
+    from paper_2509_22857_amd import ckks
+    from paper_2509_22857_amd.serving import Server, Request
+    torch, ctx, specs, networks, keys = world
+    combos = sorted(keys)
+    reqs = []
+    for i, (client, net) in enumerate(combos):
+        img = gen.images(6000 + i, 1, *specs[net]["image"])
+        cts = networks[net].encrypt_images(keys[(client, net)], img, stream_base=(950 + i) << 12)
+        reqs.append(Request(i, client, net, cts, 0.0))
+    torch.cuda.synchronize()
+    alone = []
+    for r in reqs:
+        out, _ = networks[r.net].run(keys[(r.client, r.net)], r.inputs)
+        torch.cuda.synchronize()
+        alone.append(_words(out[0]))
+    real = ckks.stream_reserve
+    calls = []
+
+    def flaky(nbytes, stream):
+        calls.append(nbytes)
+        if len(calls) == 2:
+            raise ckks.CkcError("ckc_stream_reserve", -5, "injected: no block of that size")
+        return real(nbytes, stream)
+
+    monkeypatch.setattr(ckks, "stream_reserve", flaky)
+    srv = Server(networks, budget_bytes=torch.cuda.mem_get_info()[0] // 2, max_images=4, n_streams=2)
+    for cn, k in keys.items():
+        srv.register_client(cn[0], cn[1], k)
+    stats = srv.serve(reqs)
+    torch.cuda.synchronize()
+    print(f"[serving] reserve-failure stats {stats}", flush=True)
+    assert stats["reserve_retries"] == 1 and stats["served"] == len(reqs) and stats["rejected"] == 0
+    assert len(calls) == len(reqs) + 1
+    for r, a in zip(reqs, alone):
+        assert r.error is None
+        got = _words(r.outputs[0])
+        assert all(torch.equal(x, y) for x, y in zip(got, a)), r.rid
