@@ -977,11 +977,22 @@ __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ 
                                                    const uint64_t *__restrict__ consts,
                                                    const uint64_t *__restrict__ bconsts, uint64_t *__restrict__ Z,
                                                    int K, const Prime *__restrict__ primes, int logN) {
-    const int limb = blockIdx.y, kk = blockIdx.z >> 1, poly = blockIdx.z & 1;
+    // one 256-coefficient chunk of one (limb, polynomial) per block, block id
+    // -> (class kk, group) with the group's low 3 bits equal to id mod 8: the
+    // K class blocks of a group are dispatched within 8 K consecutive ids to
+    // the same XCD (workgroups go round-robin over the 8 XCDs), so all but
+    // the first read the group's inputs S from that XCD's L2 (without this
+    // every class re-read S from HBM)
+    const unsigned id = blockIdx.x;
+    const unsigned j = id >> 3, kk = j % unsigned(K), grp = (j / unsigned(K)) * 8u + (id & 7u);
+    const unsigned nchunk = unsigned(size_t(1) << logN) / 256u;
+    const int chunk = int(grp % nchunk), limb = int((grp / nchunk) % unsigned(nl)),
+              poly = int(grp / (nchunk * unsigned(nl)));
     const size_t N = size_t(1) << logN, pw = size_t(nl) * N;
     const Prime P = primes[limb];
     const int pcap = prod_cap(P.k);
-    for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N; k += size_t(gridDim.x) * blockDim.x) {
+    {
+        const size_t k = size_t(chunk) * 256 + threadIdx.x;
         accc acc[kDenseImg];
         for (int i = 0; i < kDenseImg; ++i) acc[i] = accc{0, 0, 0, 0, 0};
         int cnt = 0;
@@ -1057,9 +1068,11 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
         {
             CKC_PROF(PK_DENSE_MAC, s, 8.0 * N * nl * (2.0 * ni * C + double(K) * C + 2.0 * ni * K),
                      2.0 * N * nl * double(ni) * K * C);
-        hipLaunchKernelGGL(k_dense_mac, dim3(tiles(N), unsigned(nl), unsigned(2 * K)), dim3(256), 0, s, Sb.u64(), ni, C,
-                           nl, L->pts.u64(), L->bias.u64(), L->dconst.u64(), L->bconst.u64(), Z.u64(), K,
-                           c->dprimes(), c->logN);
+        // groups (chunk, limb, polynomial): N / 256 chunks, a multiple of 8 for N >= 2^11
+        const size_t groups = (N / 256) * size_t(nl) * 2;
+        hipLaunchKernelGGL(k_dense_mac, dim3(unsigned(groups * K)), dim3(256), 0, s, Sb.u64(), ni, C, nl,
+                           L->pts.u64(), L->bias.u64(), L->dconst.u64(), L->bconst.u64(), Z.u64(), K, c->dprimes(),
+                           c->logN);
         }
         CKC_HIP(hipGetLastError());
         for (int b0 = 0; b0 < ni * K; b0 += kMaxBatch) {
