@@ -479,6 +479,8 @@ def layer_create_conv(ctx: Context, layout: ckc_layout, out_ch, in_ch, ksize, st
                       level, pt_scale, bias_scale, stream=None, hoisting: str = "double") -> Layer:
     """hoisting: "double" (one ModDown per output) or "single" (one per
     rotated input); see ckc_layer_create_conv_ex."""
+    if hoisting not in HOIST:
+        raise ValueError(f"hoisting must be one of {sorted(HOIST)}, not {hoisting!r}")
     cb, cbp = _dbl(codebook)
     ix = np.ascontiguousarray(np.asarray(idx, dtype=np.uint16))
     if bias is not None:
