@@ -235,3 +235,34 @@ def test_fixed_fitted_activation_becomes_per_channel():
     assert all(np.unique(L["b"]).size > 1 for L in acts)
     img = gen.images(70, 1, 3, 16, 16)[0]
     _close(spec_forward(spec, img), og.forward(g, img), 1e-10)
+
+
+def test_batch_norm_after_dense_and_after_pooling():
+    """Case 2 folds a BN that reads a dense layer; a BN after average pooling
+    (not fusable) stays and receives the pooling's update as a polynomial of
+    degree 1 -- until lowering, which refuses an unfused BN."""
+    r = np.random.default_rng(9)
+    M, C, K = 2, 3, 4
+
+    def bn(name, inp, out, n):
+        return dict(op="bn", name=name, inp=[inp], out=out, gamma=r.uniform(0.5, 1.5, (M, n)),
+                    beta=_rand(r, M, n), mean=_rand(r, M, n), var=r.uniform(0.5, 2.0, (M, n)), eps=1e-5)
+
+    g = dict(members=M, image=(C, 4, 4), nodes=[
+        dict(_conv(r, M, C), name="k", inp=["x"], out="a"),
+        dict(op="avgpool", name="pool", inp=["a"], out="p", div=4),
+        bn("bnp", "p", "pb", C),
+        dict(op="gap", name="gap", inp=["pb"], out="v", div=4),
+        dict(op="dense", name="fc", inp=["v"], out="d", W=_rand(r, M, K, C), b=_rand(r, M, K)),
+        bn("bnd", "d", "y", K)])
+    img = _rand(r, C, 4, 4)
+    ref = og.forward(g, img)
+    f, log = cc.fuse(g)
+    assert ("case2", "bnd", "fc") in log and any(n["op"] == "bn" for n in f["nodes"])
+    _close(og.forward(f, img), ref, 1e-12)
+    for direction in ("forward", "backward"):
+        out, _ = cc.redistribute(f, direction)
+        assert all(n["div"] == 1 for n in out["nodes"] if n["op"] in ("avgpool", "gap"))
+        _close(og.forward(out, img), ref, 1e-11)
+    with pytest.raises(cc.CompileError, match="batch normalisation"):
+        cc.compile_network(g)
