@@ -6,7 +6,9 @@ random ciphertexts (uniform residues, seeded) at the top level goes through
 each operation separately:
 
   ntt_fwd / ntt_inv   every limb of every polynomial, in place
-  rotate              hoisted rotations by {0, +-1, +-31, +-32, +-33}
+  rotate              hoisted rotations by {0, +-1, +-31, +-32, +-33}, the
+                      batch in one call (keys reused across it), and one
+                      ciphertext per call (every call streams the keys)
   mac                 out[i] = sum over the 9 rotations of pt_t * Rot_t(ct_i)
   mul_relin           Relin(ct_i * ct_i)
   rescale             drop the top prime
@@ -144,6 +146,27 @@ def run(batch: int = 64, reps: int = 3, seed: int = 7, log=print) -> dict:
     record("rotate", ms, rot_bytes, {"ks_kernel_hbm_frac": round(ks_frac, 4)})
     res["rotate"]["kernels"] = kern
     res["key_switch_hbm_frac"] = round(ks_frac, 4)
+
+    # the same hoisted group one ciphertext per call (no key reuse across
+    # ciphertexts: every call streams all eight Galois keys -- the regime of a
+    # single client's request)
+    n1 = min(8, batch)
+
+    def rot1():
+        for i in range(n1):
+            ckks.rotate_many(ctx, keys, cts[i:i + 1], STEPS, outs[i * len(STEPS):(i + 1) * len(STEPS)])
+
+    rot1()
+    ms1 = timer(rot1, reps)
+    kern1, ks_frac1 = _profile(ckks, torch, rot1)
+    rot1_bytes = W * 2 * nl * n1 * (1 + len(STEPS)) + nz * key_bytes * n1
+    r = {"ms": round(ms1, 3), "us_per_ct": round(1e3 * ms1 / n1, 2),
+         "GBs": round(rot1_bytes / (ms1 * 1e-3) / 1e9, 1),
+         "hbm_frac": round(rot1_bytes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+         "ks_kernel_hbm_frac": round(ks_frac1, 4), "kernels": kern1, "ciphertexts": n1}
+    res["rotate_one_at_a_time"] = r
+    log(f"  rotate 1x  {ms1:9.3f} ms/{n1} cts {r['us_per_ct']:9.2f} us/ct  {r['GBs']:8.1f} GB/s  "
+        f"({100 * r['hbm_frac']:.1f}% HBM, key-switch kernels {100 * ks_frac1:.1f}%)")
 
     macs = [ctx.new_ct(level, 2) for _ in range(batch)]
     ckks.mac_plain_many(ctx, outs, pts, macs)
