@@ -327,4 +327,40 @@ class OracleNetwork:
                 grids[ly["out"]] = dict(gap=g["gap"], H=1, W=1)
             else:
                 grids[ly["out"]] = g
+        if self.spec.get("pack_output"):
+            K = self.spec["classes"]
+            st.update(-(1 << j) for j in range(max(1, math.ceil(math.log2(K)))))
         return sorted(st)
+
+    # ------------------------------------------------------------ packed output
+    def pack_logits(self, cts, gkeys):
+        """One image's K class ciphertexts (member m's logit at slot m*block)
+        -> one ciphertext with class k at slot m*block + k.  Each class
+        ciphertext is multiplied by the mask of the slots m*block, encoded at
+        2^(floor(log2 q_l - log2 s) - 7) for its level l and scale s (room for
+        the product under q_l), then a binary tree of rotations joins them:
+        at depth j, part 2i+1 moves right by 2^j (a rotation by -2^j) and is
+        added to part 2i, so after ceil(log2 K) depths class k sits at offset
+        k of every member's block."""
+        o = self.o
+        K = len(cts)
+        assert K <= self.B, "classes must fit in a member's block"
+        level, s = cts[0].level, cts[0].scale
+        ms = 2.0 ** (math.floor(math.log2(float(o.q[level])) - math.log2(s)) - 7)
+        v = self._vec()
+        for m in range(self.M):
+            v[m * self.B] = 1.0
+        mask = self.encode(v, level, ms)
+        parts = [o.mul_plain(c, mask) for c in cts]
+        j = 0
+        while len(parts) > 1:
+            nxt = []
+            for i in range(0, len(parts), 2):
+                a = parts[i]
+                if i + 1 < len(parts):
+                    step = -(1 << j)
+                    a = o.add(a, o.rotate(parts[i + 1], step, gkeys[o.galois_elt(step)]))
+                nxt.append(a)
+            parts = nxt
+            j += 1
+        return parts[0]

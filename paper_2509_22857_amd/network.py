@@ -204,6 +204,8 @@ class GpuNetwork:
                 if e is not None and e.kind in ("conv", "dense"):
                     steps.update(e.steps())
             self.layers.append(entry)
+        if spec.get("pack_output"):
+            steps.update(-(1 << j) for j in range(max(1, math.ceil(math.log2(spec["classes"])))))
         self.steps = sorted(steps)
         # tensors read by the layers after each layer
         self._later = {}
@@ -253,6 +255,43 @@ class GpuNetwork:
             z = self.ctx.decode(self.ctx.decrypt(keys, ct), M * B)
             res.append([z[m * B] for m in range(M)])
         return np.array(res).T
+
+    def pack_logits(self, keys: ckks.KeyPair, cts, stream=None):
+        """One image's K class ciphertexts -> one ciphertext with class k at
+        slot m*block + k (needs "pack_output" in the network description, for
+        the keys of the steps -2^j).  Each class ciphertext is multiplied by
+        the mask of the slots m*block, encoded at 2^(floor(log2 q_l - log2 s)
+        - 7) for its level l and scale s, then a binary tree of rotations
+        joins them: at depth j, part 2i+1 moves right by 2^j and is added to
+        part 2i."""
+        ctx = self.ctx
+        K, B, M = len(cts), self.spec["layout"]["block"], self.spec["members"]
+        if K > B:
+            raise ValueError("classes must fit in a member's block")
+        level, s = cts[0].level, cts[0].scale
+        ms = 2.0 ** (math.floor(math.log2(float(ctx.q[level])) - math.log2(s)) - 7)
+        v = np.zeros(ctx.N // 2)
+        v[[m * B for m in range(M)]] = 1.0
+        mask = ctx.encode(v, level, ms, stream=stream)
+        parts = [ctx.mul_plain(c, mask, stream=stream) for c in cts]
+        j = 0
+        while len(parts) > 1:
+            nxt = []
+            for i in range(0, len(parts), 2):
+                a = parts[i]
+                if i + 1 < len(parts):
+                    r = ctx.rotate(keys, parts[i + 1], [-(1 << j)], stream=stream)[0]
+                    a = ctx.add(a, r, stream=stream)
+                nxt.append(a)
+            parts = nxt
+            j += 1
+        return parts[0]
+
+    def decrypt_packed_logits(self, keys: ckks.KeyPair, ct) -> np.ndarray:
+        """A packed logits ciphertext -> [M][K] (class k of member m at slot m*block + k)."""
+        B, M, K = self.spec["layout"]["block"], self.spec["members"], self.spec["classes"]
+        z = self.ctx.decode(self.ctx.decrypt(keys, ct), M * B)
+        return np.array([[z[m * B + k] for k in range(K)] for m in range(M)])
 
     def decrypt_grid(self, keys: ckks.KeyPair, ct, layout) -> np.ndarray:
         """One channel ciphertext -> values on the valid grid [M][H][W]."""

@@ -307,3 +307,25 @@ def test_compiled_batch_normalised_network_bit_exact():
         assert np.array_equal(_coeff(ctx, a), b.data), k
     got = gnet.decrypt_logits(keys, gout[0])
     assert np.max(np.abs(got - forward(spec, imgs[0]))) < 1e-3
+
+
+def test_packed_logits_bit_exact():
+    """The class ciphertexts of an image joined into one (mask, then a
+    binary tree of rotations by -2^j): bit-exact with the oracle, class k of
+    member m at slot m*block + k within 1e-3 of the FP64 forward."""
+    spec = nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8, calib=4)
+    spec["pack_output"] = True
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[packed_logits] N=2^12 M=2 classes=10", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 41)
+    imgs = gen.images(19, 1, 3, 16, 16)
+    gout, _ = gnet.run(keys, gnet.encrypt_images(keys, imgs, 1300))
+    oout, _ = onet.run(sk, onet.encrypt_image(sk, imgs[0], 1300), rlk, gk)
+    gp = gnet.pack_logits(keys, gout[0])
+    op = onet.pack_logits(oout, gk)
+    assert gp.level == op.level and gp.scale == op.scale
+    assert np.array_equal(_coeff(ctx, gp), op.data)
+    from oracle.forward import forward
+    got = gnet.decrypt_packed_logits(keys, gp)
+    assert np.max(np.abs(got - forward(spec, imgs[0]))) < 1e-3

@@ -187,3 +187,29 @@ def test_hoisting_choice_of_the_benchmarked_networks():
     spec = nets.resnet_spec(seed=0, members=4, widths=(16, 32, 64), blocks=3, classes=100, image=(3, 32, 32),
                             k=64, calib=2)
     assert set(choose_hoisting(spec, ps.q, len(ps.p), D, D, D)) == {"double"}
+
+
+def test_packed_logits_decrypt_to_forward():
+    """The class ciphertexts joined into one (mask of the slots m*block, then
+    a binary tree of rotations by -2^j): class k of member m decrypts at slot
+    m*block + k to the FP64 forward, with the same precision as unpacked."""
+    ps = small_tower(logN=12, levels=4)
+    o = Oracle.from_params(ps)
+    D = 2.0 ** 30
+    spec = nets.vgg_spec(seed=2, widths=(4, 4), pool_after=(0,), classes=5, image=(3, 8, 8), k=4, calib=2)
+    spec["pack_output"] = True
+    net = OracleNetwork(o, spec, delta=D, target=D, in_scale=D)
+    assert {-1, -2, -4} <= set(net.steps())
+    sk = o.secret_key(17)
+    rlk = o.relin_key(sk)
+    gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in net.steps()}
+    img = gen.images(6, 1, 3, 8, 8)[0]
+    outs, _ = net.run(sk, net.encrypt_image(sk, img, 100), rlk, gk)
+    packed = net.pack_logits(outs, gk)
+    z = o.decrypt_decode(packed, sk)
+    B = spec["layout"]["block"]
+    ref = forward(spec, img)
+    got = np.array([[z[m * B + k] for k in range(5)] for m in range(spec["members"])])
+    assert np.max(np.abs(got - ref)) < 1e-3
+    # every other slot of a member's block holds (nearly) zero
+    assert np.max(np.abs(z[5:B])) < 1e-3
