@@ -251,7 +251,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
                                                            const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
                                                            int o_count, int accumulate,
                                                            const Prime *__restrict__ primes, int logN, int dbuf,
-                                                           ConvOut yo) {
+                                                           int skip_tap, ConvOut yo) {
     static_assert(OUTS % 4 == 0, "outputs per wave come in packed words of 4 offsets");
     constexpr int NW = OUTS / 4;
     extern __shared__ uint64_t sP[];  // [dbuf ? 2 : 1][kcent][kTile]
@@ -297,8 +297,13 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
                     (__attribute__((address_space(3))) void *)(buf + size_t(2 * pr) * kTile), 16, 0, 0);
         }
     };
+    // the identity tap's rotated inputs are P x, zero on the P limbs: a P-limb
+    // workgroup walks the other taps only (logical tap t -> stored tap phys(t))
+    const bool skip = skip_tap >= 0 && limb >= map.nlow;
+    const int ntl = skip ? ntap - 1 : ntap;
+    auto phys = [&](int t) { return skip && t >= skip_tap ? t + 1 : t; };
     uint64_t *const buf0 = sP, *const buf1 = dbuf ? sP + size_t(kcent) * kTile : sP;
-    if (dbuf) stage(0, buf0);
+    if (dbuf) stage(phys(0), buf0);
     const uint64_t *ixw0 = ioff + size_t(g0) * I + i_base;
     // The flat stream of blocks of kUnroll inputs, tap by tap.  Coefficients
     // travel two blocks ahead of their use in a ring of three register
@@ -311,7 +316,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     // its first input from Rb; past the last block the offset stays on the
     // last valid one
     int tp = 0, ip = 0;
-    size_t roff = 0;
+    size_t roff = size_t(phys(0)) * ctw;
     auto load_block = [&](uint64_t(&buf)[kUnroll]) {
         const uint64_t *rp = Rb + roff;
 #pragma unroll
@@ -326,17 +331,17 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
         if (ip + kUnroll < ni) {
             ip += kUnroll;
             roff += size_t(kUnroll) * rstride;
-        } else if (tp + 1 < ntap) {
+        } else if (tp + 1 < ntl) {
             ip = 0;
             ++tp;
-            roff = size_t(tp) * ctw;
+            roff = size_t(phys(tp)) * ctw;
         }
     };
     // the offset words of a block, one contiguous scalar load per group of 4
     // outputs (a row's ragged end reads into the next row, the last row into
     // kUnroll words of zero padding)
     int tk = 0, ik = 0;
-    size_t koff = 0;
+    size_t koff = size_t(phys(0)) * ngrp * I;
     auto load_index = [&](uint64_t(&kw)[NW][kUnroll]) {
         const uint64_t *ixw = ixw0 + koff;
 #pragma unroll
@@ -346,10 +351,10 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
         if (ik + kUnroll < ni) {
             ik += kUnroll;
             koff += kUnroll;
-        } else if (tk + 1 < ntap) {
+        } else if (tk + 1 < ntl) {
             ik = 0;
             ++tk;
-            koff = size_t(tk) * ngrp * I;
+            koff = size_t(phys(tk)) * ngrp * I;
         }
     };
     // the products of the block at (tc, ic): coefficients cr, index words kw,
@@ -397,15 +402,15 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     // them (a wait on a scalar load also waits for every LDS read in flight)
     auto step = [&](const uint64_t(&cr)[kUnroll], uint64_t(&nx)[kUnroll], const uint64_t(&kc)[NW][kUnroll],
                     uint64_t(&kn)[NW][kUnroll]) {
-        if (tc >= ntap) return;
+        if (tc >= ntl) return;
         uint64_t *const cur = (tc & 1) ? buf1 : buf0;
         if (ic == 0) {
             if (!dbuf) {
                 __syncthreads();
-                stage(tc, cur);
+                stage(phys(tc), cur);
             }
             __syncthreads();
-            if (dbuf && tc + 1 < ntap) stage(tc + 1, (tc & 1) ? buf0 : buf1);
+            if (dbuf && tc + 1 < ntl) stage(phys(tc + 1), (tc & 1) ? buf0 : buf1);
         }
         if (active) {
             load_block(nx);
@@ -427,7 +432,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     }
     // three blocks per iteration: coefficients rotate through three buffers,
     // index words through two
-    while (tc < ntap) {
+    while (tc < ntl) {
         step(ra, rc, ka, kb);
         step(rb, ra, kb, ka);
         step(rc, rb, ka, kb);
@@ -450,7 +455,8 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
 }
 
 using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, LimbMap, const uint64_t *, int,
-                        const uint64_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int, int, ConvOut);
+                        const uint64_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int, int, int,
+                        ConvOut);
 // kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images)
 // that holds them; outs = outputs per wave (8 or 16), a tuning choice between
 // accumulator registers (occupancy) and codebook re-reads per output group
@@ -771,6 +777,13 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
     CKC_TRY(R.alloc(8 * r_img * nchunk, s));
     if (L->ext) CKC_TRY(Y.alloc(8 * lctw * O * nchunk, s));
     const size_t lds = size_t(I) * kTile * 8;
+    // with the products in Q_l u P, the identity tap's rotated inputs (P x)
+    // are zero on the P limbs, which the contraction then skips
+    int skip_tap = -1;
+    if (L->ext)
+        for (int t = 0; t < ntap; ++t)
+            if (L->tap_step[t] == 0) skip_tap = t;
+    const double skipped = skip_tap >= 0 ? double(c->np) : 0.0;  // P limbs without the identity tap
     for (int img0 = 0; img0 < n_img; img0 += chunk) {
         const int ni_img = std::min(chunk, n_img - img0);
         if (!L->ioff.p)
@@ -819,14 +832,15 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                         const int ngroups = (O + outs - 1) / outs;
                         const ConvOut yo{Y.u64() + size_t(g0) * O * lctw, size_t(O) * lctw, ngroups, O};
                         CKC_PROF(PK_CONV_CONTRACT, s,
-                                 8.0 * N * nlim * (2.0 * gi * nic * ntap + 2.0 * gi * O * (ic0 > 0 ? 2 : 1) +
-                                                   double(ntap) * L->kcent),
-                                 2.0 * N * nlim * double(gi) * O * nic * ntap);
+                                 8.0 * N * (nlim * (2.0 * gi * nic * ntap + 2.0 * gi * O * (ic0 > 0 ? 2 : 1) +
+                                                    double(ntap) * L->kcent) -
+                                            skipped * (2.0 * gi * nic + L->kcent)),
+                                 2.0 * N * double(gi) * O * nic * (double(nlim) * ntap - skipped));
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile) * unsigned(nlim) * unsigned(ngroups)),
                                            dim3(128 * wg_imgs), lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi,
                                            nic, I, ic0, ntap, nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(),
                                            L->Opad / 4, bias_k, Ptrs{}, 0, 0, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN,
-                                           dbuf, yo);
+                                           dbuf, skip_tap, yo);
                         CKC_HIP(hipGetLastError());
                         continue;
                     }
@@ -836,14 +850,15 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                         for (int m = 0; m < gi; ++m)
                             for (int j = 0; j < oc; ++j) op.p[m * outs + j] = dest(g0 + m, o0 + j);
                         CKC_PROF(PK_CONV_CONTRACT, s,
-                                 8.0 * N * nlim * (2.0 * gi * nic * ntap + 2.0 * gi * oc * (ic0 > 0 ? 2 : 1) +
-                                                   double(ntap) * L->kcent),
-                                 2.0 * N * nlim * double(gi) * oc * nic * ntap);
+                                 8.0 * N * (nlim * (2.0 * gi * nic * ntap + 2.0 * gi * oc * (ic0 > 0 ? 2 : 1) +
+                                                    double(ntap) * L->kcent) -
+                                            skipped * (2.0 * gi * nic + L->kcent)),
+                                 2.0 * N * double(gi) * oc * nic * (double(nlim) * ntap - skipped));
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
                                            lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
                                            nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(), L->Opad / 4,
                                            bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN, dbuf,
-                                           ConvOut{nullptr, 0, 0, 0});
+                                           skip_tap, ConvOut{nullptr, 0, 0, 0});
                         CKC_HIP(hipGetLastError());
                     }
                 }
