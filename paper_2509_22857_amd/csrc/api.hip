@@ -181,18 +181,20 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
         CKC_REQUIRE(is_prime_u64(m), CKC_EINVAL, "modulus not prime");
         CKC_REQUIRE(seen.insert(m).second, CKC_EINVAL, "duplicate modulus");
     }
-    // sums of up to dnum (key inner product) or alpha / n_p (basis conversion)
-    // products of residues are accumulated in 128 bits without reduction
+    // sums of up to dnum + 1 (key inner product, with the P c0 term of the
+    // extended form) or alpha / n_p (basis conversion) products of residues
+    // are accumulated in 128 bits without reduction
     {
         uint64_t qmax = 0;
         for (int i = 0; i < n_q; ++i) qmax = std::max(qmax, q[i]);
         for (int i = 0; i < n_p; ++i) qmax = std::max(qmax, p[i]);
         const int dnum = (n_q + alpha - 1) / alpha;
-        const long double bound = (long double)qmax * (long double)qmax * (long double)std::max(dnum, std::max(alpha, n_p));
+        const long double bound =
+            (long double)qmax * (long double)qmax * (long double)std::max(dnum + 1, std::max(alpha, n_p));
         CKC_REQUIRE(bound < 0x1p127L * 2.0L, CKC_EUNSUPPORTED, "moduli too large for 128-bit accumulation of the digits");
         CKC_REQUIRE(dnum <= 16, CKC_EUNSUPPORTED, "at most 16 key-switching digits");
         const int kmax = 64 - __builtin_clzll(qmax);
-        CKC_REQUIRE(std::max(dnum, std::max(alpha, n_p)) <= prod_cap(kmax), CKC_EUNSUPPORTED,
+        CKC_REQUIRE(std::max(dnum + 1, std::max(alpha, n_p)) <= prod_cap(kmax), CKC_EUNSUPPORTED,
                     "too many digits for the carry-free accumulator at this modulus size");
     }
     auto c = std::make_unique<ckc_ctx>();
