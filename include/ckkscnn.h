@@ -77,8 +77,12 @@ const char *ckc_last_error(void);
  * Every modulus must be a prime < 2^62 with q = 1 mod 2N, all distinct.
  * alpha = primes per key-switching digit (dnum = ceil(n_q / alpha)); the
  * product of the special primes should exceed every digit's product for
- * small key-switching noise.  log_n in [12, 16].  Errors: CKC_EINVAL,
- * CKC_EUNSUPPORTED, CKC_ENOMEM, CKC_EDEVICE.
+ * small key-switching noise.  log_n in [12, 16].  Sums of products of
+ * residues are accumulated without reduction, so dnum + 1, alpha and n_p must
+ * each stay within what the largest modulus allows (2^(128 - 2k) - 1 products
+ * for k-bit moduli of 61 bits or more, 64 below), and dnum <= 16: otherwise
+ * CKC_EUNSUPPORTED.  Errors: CKC_EINVAL, CKC_EUNSUPPORTED, CKC_ENOMEM,
+ * CKC_EDEVICE.
  */
 int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint64_t *p, int n_p, int alpha,
                    ckc_ctx **out);
