@@ -213,3 +213,21 @@ def test_packed_logits_decrypt_to_forward():
     assert np.max(np.abs(got - ref)) < 1e-3
     # every other slot of a member's block holds (nearly) zero
     assert np.max(np.abs(z[5:B])) < 1e-3
+
+
+def test_tower_reuse_worked_example():
+    """Section 4.3's example: with q_i ~ Delta^2 (sublevel 2), an input at
+    sublevel 1 squared by the activation stays at sublevel 2 (no rescale); the
+    next convolution with weights at sublevel 1 reaches sublevel 3 > 2, so it
+    rescales, and the result is back at sublevel 1."""
+    from paper_2509_22857_amd.network import plan_network, sublevel
+    spec = nets.vgg_spec(seed=1, widths=(4, 4), pool_after=(), classes=2, image=(3, 8, 8), k=4, calib=1)
+    ps = resnet20_tower(levels=4)
+    D = 2.0 ** 30
+    plans, state = plan_network(spec, ps.q, D, D, D)
+    conv0, act0, conv1, act1 = plans[:4]
+    assert sublevel(float(ps.q[conv1.level]), D) == 2
+    assert sublevel(act0.in_scale, D) == 1 and not act0.rescale and sublevel(act0.out_scale, D) == 2
+    assert sublevel(conv1.in_scale, D) == 2 and sublevel(conv1.pt_scale, D) == 1
+    assert sublevel(conv1.out_scale, D) == 3 and conv1.rescale
+    assert sublevel(conv1.out_scale / float(ps.q[conv1.level]), D) == 1
