@@ -110,6 +110,24 @@ def test_tower_reuse_level_count_resnet20():
     assert used == 20 and rescales == 20
 
 
+def test_tower_reuse_halves_the_levels_resnet20():
+    """Section 4.4's law: with tower reuse the level count is ceil(L / 2) of
+    the count without it.  ResNet-20 on a chain of primes ~ Delta (every
+    multiplicative layer rescales) uses 39 levels; on q_i ~ Delta^2, 20."""
+    from workloads.params import balanced_chain, nearest_prime
+    spec = nets.resnet_spec(seed=0, members=1, widths=(16, 32, 64), blocks=3, classes=10, image=(3, 32, 32), k=4,
+                            calib=1)
+    two_n = 2 << 16
+    q = balanced_chain([30] * 48, two_n)
+    q = [nearest_prime(40, two_n, exclude=q)] + q
+    from paper_2509_22857_amd.network import plan_network
+    D = 2.0 ** 30
+    plans, state = plan_network(spec, q, D, D, D)
+    std = len(q) - 1 - state[spec["layers"][-1]["out"]][0]
+    tower, _ = _count_levels(spec, resnet20_tower(), D)
+    assert std == 39 and tower == 20 == -(-std // 2)
+
+
 def test_standard_chain_rescales_after_every_product():
     """With every prime ~ Delta (sublevel 1) the rule degenerates to the
     standard chain: one rescale per multiplicative layer (the tiny case)."""
