@@ -110,6 +110,16 @@ def test_tower_reuse_level_count_resnet20():
     assert used == 20 and rescales == 20
 
 
+@pytest.mark.parametrize("widths,blocks,levels", [((64, 128, 256, 512), 2, 18), ((16, 32, 64), 5, 32)])
+def test_tower_reuse_level_counts_resnet18_resnet32(widths, blocks, levels):
+    """Section 4.4's level table: ResNet-18 needs 18 levels and ResNet-32 32
+    with node fusing, weight redistribution and tower reuse."""
+    spec = nets.resnet_spec(seed=0, members=1, widths=widths, blocks=blocks, classes=10, image=(3, 32, 32), k=4,
+                            calib=1)
+    used, _ = _count_levels(spec, resnet20_tower(levels=levels + 2), 2.0 ** 30)
+    assert used == levels
+
+
 def test_tower_reuse_halves_the_levels_resnet20():
     """Section 4.4's law: with tower reuse the level count is ceil(L / 2) of
     the count without it.  ResNet-20 on a chain of primes ~ Delta (every
