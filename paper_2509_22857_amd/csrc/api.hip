@@ -183,7 +183,9 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
     }
     // sums of up to dnum + 1 (key inner product, with the P c0 term of the
     // extended form) or alpha / n_p (basis conversion) products of residues
-    // are accumulated in 128 bits without reduction
+    // are accumulated in 128 bits without reduction; their Montgomery
+    // reduction reduces the high word before adding mulhi(m, q), so it holds
+    // for every count within the accumulator's cap, up to q < 2^62
     {
         uint64_t qmax = 0;
         for (int i = 0; i < n_q; ++i) qmax = std::max(qmax, q[i]);

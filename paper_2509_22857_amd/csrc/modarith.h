@@ -147,18 +147,25 @@ CKC_HD uint64_t reduce128(u128v x, const Prime &P) {
 // Montgomery reduction of a carry-counted sum: the representative in [0, q)
 // of value * 2^-64 mod q, for a sum of at most NPROD products of residues
 // (each below q^2 < q 2^62).  With m = lo * qinv mod 2^64, value + m q is a
-// multiple of 2^64 whose quotient hi + mulhi(m, q) + [lo != 0] lies below
-// value / 2^64 + q < (NPROD / 4 + 1) q, so ceil(NPROD / 4) conditional
-// subtractions of q finish it.  Used where the sum's operands carry a factor
-// 2^64 (evaluation keys are stored times 2^64 mod q).
+// multiple of 2^64 whose quotient is hi + mulhi(m, q) + [lo != 0].  That
+// quotient can exceed 2^64 (hi < NPROD q / 4 and mulhi(m, q) < q: for q near
+// 2^62 and NPROD >= 12 the plain sum wraps), so hi is first brought below q
+// by ceil(NPROD / 4) - 1 conditional subtractions (hi < (NPROD / 4) q); the
+// quotient is then below 2q and one more subtraction finishes it.  Used where
+// the sum's operands carry a factor 2^64 (evaluation keys are stored times
+// 2^64 mod q).
+template <int NPROD>
+CKC_HD uint64_t redc_hi_lo(uint64_t hi, uint64_t lo, const Prime &P) {
+#pragma unroll
+    for (int i = 0; i < (NPROD + 3) / 4 - 1; ++i) hi = hi >= P.q ? hi - P.q : hi;
+    const uint64_t m = lo * P.qinv;
+    const uint64_t t = hi + mulhi64(m, P.q) + (lo != 0 ? 1ull : 0ull);
+    return t >= P.q ? t - P.q : t;
+}
 template <int NPROD>
 __device__ __forceinline__ uint64_t redc_accc(const accc &a, const Prime &P) {
     const u128v v = accc_value(a);
-    const uint64_t m = v.lo * P.qinv;
-    uint64_t t = v.hi + mulhi64(m, P.q) + (v.lo != 0 ? 1ull : 0ull);
-#pragma unroll
-    for (int i = 0; i < (NPROD + 3) / 4; ++i) t = t >= P.q ? t - P.q : t;
-    return t;
+    return redc_hi_lo<NPROD>(v.hi, v.lo, P);
 }
 
 // Reduce an arbitrary 64-bit word into [0, q) (Shoup multiplication by 1).
