@@ -177,27 +177,154 @@ def build_workload(args):
     return ps, spec
 
 
-def cpu_baseline(ps, spec, gpu_share_ratio: float):
-    """Oracle (as it stands) on a bounded sample: one key switch (rotation) at
-    the top level of the same parameters, scaled to a whole image by the
-    GPU's own ratio (image time / top-level rotation time)."""
-    from oracle.ckks import Oracle, Ct
+def _fit3(xs, ys):
+    """Quadratic through three points (x, y), as a callable."""
+    c = np.polyfit(np.array(xs, dtype=float), np.array(ys, dtype=float), 2)
+    return lambda x: float(max(np.polyval(c, x), min(ys)))
+
+
+def cpu_baseline(ps, spec, gpu_products_per_image=None):
+    """The oracle as it stands, timed on this host per operation class on the
+    workload's own chain, and composed into one image from the operation
+    counts of the oracle's evaluation of the network (its level schedule
+    gives every layer's level).  Timed classes: the key switch with and
+    without ModDown (the rotation and the extended rotation of a double-
+    hoisted convolution) and ModDown alone at three levels spanning the
+    schedule (a quadratic in the limb count between them), rescale at the
+    same levels, and per limb the negacyclic product (the oracle multiplies
+    in coefficient form), the automorphism, the multiplication by P and the
+    modular addition.  No GPU time enters the figure."""
+    import platform
+    from oracle.ckks import Ct, Oracle
+    from oracle.network import OracleNetwork
     from workloads import gen
     o = Oracle.from_params(ps)
-    t0 = time.time()
+    D = 2.0 ** ps.delta_log2
+    net = OracleNetwork(o, spec, D, D, D)
+    sch = net.schedule()
+    t_all = time.time()
     sk = o.secret_key(1)
     g = o.galois_elt(1)
     gk = o.galois_key(sk, g)
-    t_key = time.time() - t0
-    ct = Ct(gen.random_ct(3, ps.q, ps.L, ps.N), ps.L, 2.0 ** 30)
-    t1 = time.time()
-    o.rotate(ct, 1, gk)
-    t_rot = time.time() - t1
-    sec_per_image = t_rot * gpu_share_ratio
+    lv_used = sorted({s["level_in"] for s in sch})
+    levels = sorted({lv_used[0], lv_used[len(lv_used) // 2], lv_used[-1]})
+    N = ps.N
+    np_ = len(ps.p)
+    ks, ks_ext, mdown, resc = {}, {}, {}, {}
+    for lv in levels:
+        d = gen.random_ct(3, ps.q, lv, N)
+        a = time.time(); o.keyswitch(d[1], lv, gk, g); ks[lv] = time.time() - a
+        a = time.time(); o.keyswitch_ext(d[1], lv, gk, g); ks_ext[lv] = time.time() - a
+        x = gen.random_limbs(5, list(ps.q[:lv + 1]) + list(ps.p), N)
+        a = time.time(); o.moddown(x, lv); mdown[lv] = time.time() - a
+        a = time.time(); o.rescale(Ct(d, lv, D * D)); resc[lv] = time.time() - a
+    x1 = [lv + 1 for lv in levels]
+    if len(levels) < 3:
+        x1 = x1 + [x1[-1] + 1] * (3 - len(levels))
+    f_ks = _fit3(x1, [ks[lv] for lv in levels] + [ks[levels[-1]]] * (3 - len(levels)))
+    f_ext = _fit3(x1, [ks_ext[lv] for lv in levels] + [ks_ext[levels[-1]]] * (3 - len(levels)))
+    f_md = _fit3(x1, [mdown[lv] for lv in levels] + [mdown[levels[-1]]] * (3 - len(levels)))
+    f_rs = _fit3(x1, [resc[lv] for lv in levels] + [resc[levels[-1]]] * (3 - len(levels)))
+    a_ = gen.random_ct(9, ps.q, 0, N)[0, 0]
+    b_ = gen.random_ct(10, ps.q, 0, N)[0, 0]
+    reps = 8
+    a = time.time()
+    for _ in range(reps):
+        o.polymul(a_, b_, 0)
+    t_mul = (time.time() - a) / reps
+    a = time.time()
+    for _ in range(reps):
+        o.automorphism(a_, g, 0)
+    t_aut = (time.time() - a) / reps
+    P0 = 1
+    for pk in ps.p:
+        P0 = P0 * pk % ps.q[0]
+    a = time.time()
+    for _ in range(reps):
+        ((a_.astype(object) * P0) % ps.q[0]).astype(np.uint64)
+    t_P = (time.time() - a) / reps
+    q0 = np.uint64(ps.q[0])
+    a = time.time()
+    for _ in range(reps):
+        o._add(a_, b_, q0)
+    t_add = (time.time() - a) / reps
+    t_meas = time.time() - t_all
+
+    # the oracle's operations per image, layer by layer (OracleNetwork.run)
+    cnt = {"ks": 0.0, "ks_ext": 0.0, "moddown": 0.0, "rescale": 0.0, "limb_mul": 0.0, "limb_aut": 0.0,
+           "limb_P": 0.0, "limb_add": 0.0}
+    sec = {k: 0.0 for k in cnt}
+    per_level = {"ks": f_ks, "ks_ext": f_ext, "moddown": f_md, "rescale": f_rs}
+    per_limb = {"limb_mul": t_mul, "limb_aut": t_aut, "limb_P": t_P, "limb_add": t_add}
+
+    def add(kind, n, lv=None):
+        cnt[kind] += n
+        sec[kind] += n * (per_level[kind](lv + 1) if kind in per_level else per_limb[kind])
+
+    ch = {"x": spec["image"][0]}
+    products = 0.0
+    for ly, st in zip(spec["layers"], sch):
+        lv = st["level_in"]
+        nl, nt = lv + 1, lv + 1 + np_
+        op = ly["op"]
+        if op == "conv":
+            I, O, T = ly["in_ch"], ly["out_ch"], ly["ksize"] ** 2
+            ch[ly["out"]] = O
+            if T == 1:
+                add("limb_mul", O * I * 2 * nl); add("limb_add", O * I * 2 * nl)
+                products += O * I * 2 * nl
+            elif ly.get("hoist", "double") == "single":
+                add("ks", I * (T - 1), lv); add("limb_aut", I * (T - 1) * nl); add("limb_add", I * (T - 1) * nl)
+                add("limb_mul", O * I * T * 2 * nl); add("limb_add", O * I * T * 2 * nl)
+                products += O * I * T * 2 * nl
+            else:
+                add("ks_ext", I * (T - 1), lv)
+                add("limb_aut", I * (T - 1) * nl); add("limb_P", I * (T - 1) * nl + I * 2 * nl)
+                add("limb_add", I * (T - 1) * nl)
+                add("limb_mul", O * I * T * 2 * nt); add("limb_add", O * I * T * 2 * nt)
+                add("moddown", 2 * O, lv)
+                products += O * I * T * 2 * nt
+            if ly.get("bias") is not None:
+                add("limb_add", O * nl)
+            if ly.get("short") is not None:
+                sh = ly["short"]
+                add("limb_mul", O * sh["in_ch"] * 2 * nl); add("limb_add", O * sh["in_ch"] * 2 * nl + O * 2 * nl)
+                products += O * sh["in_ch"] * 2 * nl
+        elif op == "act":
+            C = ch[ly["inp"]]
+            ch[ly["out"]] = C
+            add("limb_mul", C * 4 * nl); add("limb_add", C * (1 + 2 + 2) * nl); add("ks", C, lv)
+        elif op == "dense":
+            C, K = ch[ly["inp"]], ly["w"].shape[1]
+            ch[ly["out"]] = K
+            nrot = int(math.log2(spec["image"][1])) + int(math.log2(spec["image"][2]))
+            add("ks", C * nrot, lv); add("limb_aut", C * nrot * nl); add("limb_add", C * nrot * 3 * nl)
+            add("limb_mul", K * C * 2 * nl); add("limb_add", K * C * 2 * nl + K * nl)
+            products += K * C * 2 * nl
+        elif op == "pool":
+            C = ch[ly["inp"]]
+            ch[ly["out"]] = C
+            add("ks", 3 * C, lv); add("limb_aut", 3 * C * nl); add("limb_add", 3 * C * 3 * nl)
+        if st["rescale"]:
+            add("rescale", ch[ly["out"]], lv)
+    sec_per_image = sum(sec.values())
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        model = platform.processor() or "unknown"
+    parts = ", ".join(f"{k} {cnt[k]:.4g} x -> {sec[k]:.1f} s" for k in cnt)
+    unit = (f"key switch {ks[levels[-1]]:.2f} s / extended {ks_ext[levels[-1]]:.2f} s / ModDown "
+            f"{mdown[levels[-1]]:.3f} s / rescale {resc[levels[-1]]:.3f} s at level {levels[-1]} "
+            f"(also timed at levels {levels[:-1]}); per limb: product {1e3 * t_mul:.2f} ms, automorphism "
+            f"{1e3 * t_aut:.2f} ms, times P {1e3 * t_P:.2f} ms, addition {1e3 * t_add:.3f} ms")
+    chk = ""
+    if gpu_products_per_image:
+        chk = (f"; limb-products of the convolutions and dense layer: oracle {products:.4g} per image, "
+               f"GPU counter {gpu_products_per_image / N:.4g} (the GPU skips the identity tap on the P limbs)")
     return {"value": 1.0 / sec_per_image, "unit": "images/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one top-level rotation (hybrid key switch, N=2^16, {len(ps.q)}+{len(ps.p)} primes) on the "
-                       f"oracle took {t_rot:.2f} s (its key generation {t_key:.2f} s, untimed); scaled to one image "
-                       f"by the GPU's image-time / top-level-rotation-time ratio {gpu_share_ratio:.1f}")}
+            "sample": (f"oracle (single-threaded C + numpy) on {model}, nproc {os.cpu_count()}; {t_meas:.1f} s of "
+                       f"timing: {unit}; composed per image from the oracle's operation counts: {parts}; "
+                       f"{sec_per_image:.0f} s per image{chk}")}
 
 
 def main():
@@ -209,7 +336,8 @@ def main():
     ap.add_argument("--images-per-pass", type=int, default=16,
                     help="images evaluated layer by layer together (bounds live ciphertexts)")
     ap.add_argument("--plain", type=int, default=2, help="images timed one at a time")
-    ap.add_argument("--check", type=int, default=4, help="images whose logits are checked against FP64")
+    ap.add_argument("--check", type=int, default=-1,
+                    help="images whose logits are checked against FP64 (default: every image of the step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-out", default=os.path.join(ROOT, "tuning_fresh.json"),
                     help="where --tune fresh writes the choices it measured")
@@ -236,7 +364,8 @@ def main():
         return
     if args.workload == "serving":
         from paper_2509_22857_amd import serve_bench
-        print(json.dumps(serve_bench.run(args, log)))
+        from oracle.forward import forward
+        print(json.dumps(serve_bench.run(args, log, reference=forward)))
         return
 
     if args.pack > 1:
@@ -336,7 +465,7 @@ def main():
     # accuracy of the timed outputs against the FP64 forward
     from oracle.forward import forward
     max_err, agree = 0.0, 0
-    nchk = min(args.check, B)
+    nchk = B if args.check < 0 else min(args.check, B)
     for i in range(nchk):
         got = net.decrypt_logits(keys, out[i])
         ref = forward(spec, imgs[i])
@@ -374,6 +503,9 @@ def main():
     if tr is not None:
         roof["traffic"] = round(tr["bytes_per_launch"])
         roof["traffic_unit"] = "bytes/launch"
+        roof["traffic_source"] = (f"replayed from profiles/{dom}_traffic.md: FETCH_SIZE and WRITE_SIZE counters of "
+                                  "an earlier run of the same kernel sources and launch choices on this workload, "
+                                  "not measured in this run")
     shares = {k: round(v / max(sum(tot.values()), 1e-9), 3) for k, v in tot.items()}
     busy = sum(tot.values()) / max(ms, 1e-9)
     log(f"profiled kernel time {sum(tot.values()) / 1e3:.2f}s of {ms / 1e3:.2f}s timed ({100 * busy:.1f}%)")
@@ -384,20 +516,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        # GPU time of one top-level rotation group member: measure a single rotation
-        one = ctx.new_ct(len(ps.q) - 1)
-        one.buf.copy_(cts[0][0].buf)
-        one.scale = cts[0][0].scale
-        ctx.rotate(keys, one, [1])
-        torch.cuda.synchronize()
-        a = time.time()
-        for _ in range(5):
-            ctx.rotate(keys, one, [1])
-        torch.cuda.synchronize()
-        t_rot_gpu = (time.time() - a) / 5
-        ratio = (sec_per_step / B) / t_rot_gpu
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(ps, spec, ratio)
+        cw = prof["conv_contract"]["work"] + prof["dense_mac"]["work"]
+        cpu = cpu_baseline(ps, spec, gpu_products_per_image=cw / (B * args.steps))
+        log(f"cpu baseline: {cpu}")
 
     res = {
         "metric": ("encrypted images/s (VGG-style, N=2^16, batched)" if args.workload == "vgg" else

@@ -52,8 +52,44 @@ class OracleNetwork:
     def encode(self, v, level, scale) -> Pt:
         return self.o.encode(v, level, scale)
 
+    # ------------------------------------------------------------ levels and scales (Section 4.3)
     def _rescale_needed(self, level, scale):
+        """Tower reuse: rescale iff the sublevel of the scale exceeds the
+        sublevel of the prime that would be dropped."""
         return level >= 1 and _lam(scale, self.delta) > _lam(float(self.o.q[level]), self.delta)
+
+    def _pt_scale(self, level, s):
+        """Plaintext scale of a convolution or dense layer whose input has
+        scale s at `level`: the product's scale divided by q_level is the
+        target scale."""
+        return (self.target * float(self.o.q[level])) / s
+
+    def _out_scale(self, ly, level, s):
+        """Scale of a layer's output before the optional rescale."""
+        op = ly["op"]
+        if op in ("conv", "dense"):
+            return s * self._pt_scale(level, s)
+        if op == "act":
+            return (s * s) / float(ly.get("a_absorb", 1.0))
+        return s
+
+    def schedule(self):
+        """The level and scale of every tensor, from the rules run() applies,
+        without ciphertexts: a list of dicts (name, op, level_in, scale_in,
+        scale_out before rescaling, rescale, level_out, scale_out_final)."""
+        state = {"x": (self.o.L, float(self.in_scale))}
+        out = []
+        for ly in self.spec["layers"]:
+            level, s = state[ly["inp"]]
+            S = self._out_scale(ly, level, s)
+            resc = ly["op"] != "pool" and self._rescale_needed(level, S)
+            lo, so = (level - 1, S / float(self.o.q[level])) if resc else (level, S)
+            if lo < 0:
+                raise ValueError("chain too short for this network")
+            state[ly["out"]] = (lo, so)
+            out.append(dict(name=ly["name"], op=ly["op"], level_in=level, scale_in=s, scale_out=S, rescale=resc,
+                            level_out=lo, scale_out_final=so))
+        return out
 
     # ------------------------------------------------------------ client
     def encrypt_image(self, sk: SecretKey, img: np.ndarray, stream_base: int):
@@ -212,7 +248,7 @@ class OracleNetwork:
                 for m in range(self.M):
                     v[m * self.B:(m + 1) * self.B] = ly["c"][m, ch]
                 y = o.add_plain(y, self.encode(v, y.level, y.scale))
-            y = Ct(y.data, y.level, (x.scale * x.scale) / float(ly.get("a_absorb", 1.0)))
+            y = Ct(y.data, y.level, self._out_scale(ly, x.level, x.scale))
             out.append(y)
         return out
 
@@ -278,7 +314,7 @@ class OracleNetwork:
             level, s = xs[0].level, xs[0].scale
             op = ly["op"]
             if op == "conv":
-                pt = (self.target * float(o.q[level])) / s
+                pt = self._pt_scale(level, s)
                 S = s * pt
                 outs, ngrid = self.conv(xs, grid, ly, pt, S, gkeys)
                 if ly.get("short") is not None:
@@ -290,7 +326,7 @@ class OracleNetwork:
             elif op == "act":
                 outs, ngrid = self.act(xs, ly, rlk), grid
             elif op == "dense":
-                pt = (self.target * float(o.q[level])) / s
+                pt = self._pt_scale(level, s)
                 outs, ngrid = self.dense(xs, grid, ly, pt, s * pt, gkeys), dict(gap=grid["gap"], H=1, W=1)
             elif op == "pool":
                 outs, ngrid = self.pool(xs, grid, gkeys)

@@ -11,7 +11,8 @@ run of primes of sizes b_1, b_2, ... the next prime is taken, among the nearest
 unused candidate above 2^b and the nearest unused candidate below 2^b, as the
 one that keeps sum(log2 q_i) - sum(b_i) closest to zero.  This greedy balance
 reproduces, in order, the four main chains the paper prints for VGG-16,
-ResNet-18, ResNet-20 and ResNet-32 (checked in tests/test_params.py).
+ResNet-18, ResNet-20 and ResNet-32 (checked in tests/test_oracle_pins.py,
+test_paper_chains_reproduced).
 
 Every consumer takes the explicit lists below; nothing downstream re-derives
 primes, so a change here changes both sides of a parity test alike.
