@@ -17,7 +17,15 @@ Written independently of the GPU runner from the paper's method:
   * dense: rotation sums over the grid, then per class the weighted sum of
     the channel sums, plus bias (member values at slot m*block);
   * tower reuse (Section 4.3): rescale after a multiplicative layer iff the
-    sublevel of its scale exceeds the sublevel of the prime to drop.
+    sublevel of its scale exceeds the sublevel of the prime to drop;
+  * slice-shared layout (layout flag "slice_shared"; Section 5.2: the
+    weights of one kernel column across the layer's filters share an
+    encoding): every member block keeps zero rows below its image, so a
+    vertical tap that leaves the image reads zeros and needs no mask; the
+    plaintext of a weight then depends only on its kernel column (the
+    horizontal mask), and the three taps of a column share it.  Keeping the
+    spare rows zero asks every layer to leave them zero: the activation's
+    constant term is placed on the image's grid only.
 """
 from __future__ import annotations
 
@@ -41,6 +49,16 @@ class OracleNetwork:
         self.W0 = spec["layout"]["row_stride"]
         self.M = spec["members"]
         self.input_grid = dict(gap=1, H=H, W=W)
+        self.slice_shared = bool(spec["layout"].get("slice_shared", False))
+
+    def _check_spare_rows(self, grid):
+        """Slice-shared layout: the row after the image's last row and the
+        row before its first (the previous block's last rows) must hold only
+        zeros at the grid's gap, i.e. a block has at least gap*(H + 1) rows."""
+        rows = self.B // self.W0
+        if rows < grid["gap"] * (grid["H"] + 1):
+            raise ValueError(f"slice-shared layout needs {grid['gap'] * (grid['H'] + 1)} rows per block, "
+                             f"the layout has {rows}")
 
     # ------------------------------------------------------------ slots
     def _slot(self, m, r, c, gap):
@@ -116,12 +134,19 @@ class OracleNetwork:
         level = xs[0].level
         cb, idx = ly["codebook"], ly["idx"]
 
+        # with the slice-shared layout a 3x3 weight's plaintext depends on its
+        # column only: vertical taps past the image read the zero rows
+        shared = self.slice_shared and k == 3
+        if shared:
+            self._check_spare_rows(grid)
+
         def mask(dh, dw, wvec):
             # a weight vector on the output slots whose input pixel is inside
+            # (slice-shared: whose input column is inside)
             v = self._vec()
             for m in range(self.M):
                 for r in range(Ho):
-                    if not 0 <= s * r + dh < H:
+                    if not shared and not 0 <= s * r + dh < H:
                         continue
                     for c in range(Wo):
                         if 0 <= s * c + dw < W:
@@ -159,7 +184,7 @@ class OracleNetwork:
                 for i in range(ly["in_ch"]):
                     for dh, dw in taps:
                         wvec = cb[dw + half][idx[oc, i, dh + half, dw + half]]
-                        key = (dh, dw, tuple(wvec))
+                        key = (0 if shared else dh, dw, tuple(wvec))
                         if key not in cache:
                             cache[key] = self.encode(mask(dh, dw, wvec), level, pt_scale)
                         term = o.mul_plain(rot[(i, dh, dw)], cache[key])
@@ -206,7 +231,7 @@ class OracleNetwork:
                 for i in range(ly["in_ch"]):
                     for dh, dw in taps:
                         wvec = cb[dw + half][idx[oc, i, dh + half, dw + half]]
-                        key = (dh, dw, tuple(wvec))
+                        key = (0 if shared else dh, dw, tuple(wvec))
                         if key not in cache:
                             cache[key] = o.encode_ext(mask(dh, dw, wvec), level, pt_scale)
                         pt = cache[key]
@@ -229,10 +254,29 @@ class OracleNetwork:
             outs[oc] = acc
         return outs, dict(gap=go, H=Ho, W=Wo)
 
-    def act(self, xs, ly, rlk):
+    def act(self, xs, ly, rlk, grid=None):
         o = self.o
         out = []
         for ch, x in enumerate(xs):
+            if self.slice_shared:
+                # the spare rows stay zero: b multiplies x (zero there), and c
+                # is placed on the grid's slots only
+                if self.M == 1:
+                    t = o.add_const(x, float(ly["b"][0, ch]))
+                else:
+                    v = self._vec()
+                    for m in range(self.M):
+                        v[m * self.B:(m + 1) * self.B] = ly["b"][m, ch]
+                    t = o.add_plain(x, self.encode(v, x.level, x.scale))
+                y = o.relin(o.tensor(x, t), rlk)
+                v = self._vec()
+                for m in range(self.M):
+                    for r in range(grid["H"]):
+                        for c in range(grid["W"]):
+                            v[self._slot(m, r, c, grid["gap"])] = ly["c"][m, ch]
+                y = o.add_plain(y, self.encode(v, y.level, y.scale))
+                out.append(Ct(y.data, y.level, self._out_scale(ly, x.level, x.scale)))
+                continue
             if self.M == 1:
                 t = o.add_const(x, float(ly["b"][0, ch]))
             else:
@@ -324,7 +368,7 @@ class OracleNetwork:
                     souts, _ = self.conv(sxs, sgrid, ly["short"], spt, 1.0, gkeys, with_bias=False)
                     outs = [o.add(a, b) for a, b in zip(outs, souts)]
             elif op == "act":
-                outs, ngrid = self.act(xs, ly, rlk), grid
+                outs, ngrid = self.act(xs, ly, rlk, grid), grid
             elif op == "dense":
                 pt = self._pt_scale(level, s)
                 outs, ngrid = self.dense(xs, grid, ly, pt, s * pt, gkeys), dict(gap=grid["gap"], H=1, W=1)
