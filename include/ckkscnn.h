@@ -171,6 +171,7 @@ int ckc_mul_plain(ckc_ctx *ctx, const ckc_ct *a, const ckc_pt *p, ckc_ct *out, v
 int ckc_tensor(ckc_ctx *ctx, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, void *stream);
 /* relinearise a 3-polynomial ciphertext (s^2 -> s) into a 2-polynomial one */
 int ckc_relin(ckc_ctx *ctx, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream);
+
 /* Hoisted rotations: one ModUp of in->c1 shared by every step; out[i] is the
  * left rotation of the slots by steps[i] (0 = copy).  The Galois
  * automorphism is applied after ModUp.  out[i] must not alias in. */
@@ -349,6 +350,21 @@ int ckc_layer_destroy(ckc_layer *layer);
  * events and sums them for one class. */
 int ckc_prof_enable(int on);
 int ckc_prof_query(const char *kernel, int64_t *launches, double *total_ms, double *bytes, double *work);
+
+/* Opt-in count of launches per kernel instantiation, so that a test can check
+ * which variant of a kernel a call ran.  Names are the kernel's base name with
+ * its template arguments and launch options, e.g. "conv_mac<8,4>+dbuf+fused"
+ * (contraction, 8 outputs per wave, 4 images per workgroup, double-buffered
+ * codebook tiles, all output groups in one launch), "conv_contract" (grouped
+ * form), "kip_ext_rot<7>" (extended key inner product of a rotation group,
+ * 7 digits; <0> is the generic digit count), "kip_ext<d>", "kip_b<d>".
+ * ckc_variant_enable(on) clears the counts and turns counting on or off;
+ * ckc_variant_count gives the launches counted for one name (0 if none);
+ * ckc_variant_list writes "name=count" lines into buf.
+ * Errors: CKC_EINVAL for null arguments or a list longer than cap bytes. */
+int ckc_variant_enable(int on);
+int ckc_variant_count(const char *name, int64_t *launches);
+int ckc_variant_list(char *buf, size_t cap);
 
 /* ------------------------------------------------------------------ tuning
  * Launch choices picked by an autotuner (process-wide; every choice gives

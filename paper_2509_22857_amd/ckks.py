@@ -106,6 +106,9 @@ _SIGS = [
     ("ckc_layer_destroy", C.c_int, [_vp]),
     ("ckc_prof_enable", C.c_int, [C.c_int]),
     ("ckc_prof_query", C.c_int, [C.c_char_p, C.POINTER(C.c_int64), _dblp, _dblp, _dblp]),
+    ("ckc_variant_enable", C.c_int, [C.c_int]),
+    ("ckc_variant_count", C.c_int, [C.c_char_p, C.POINTER(C.c_int64)]),
+    ("ckc_variant_list", C.c_int, [C.c_char_p, C.c_size_t]),
     ("ckc_tune_set", C.c_int, [C.c_char_p, C.c_int]),
     ("ckc_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
     ("ckc_stream_release", C.c_int, [C.c_void_p]),
@@ -606,6 +609,21 @@ def prof_query(name: str) -> dict:
     ms, by, wk = C.c_double(), C.c_double(), C.c_double()
     _check("ckc_prof_query", lib().ckc_prof_query(name.encode(), C.byref(n), C.byref(ms), C.byref(by), C.byref(wk)))
     return {"launches": int(n.value), "ms": ms.value, "bytes": by.value, "work": wk.value}
+
+
+def variant_enable(on: bool = True):
+    _check("ckc_variant_enable", lib().ckc_variant_enable(int(on)))
+
+
+def variant_counts() -> dict:
+    """Launches per kernel instantiation since variant_enable()."""
+    buf = C.create_string_buffer(1 << 16)
+    _check("ckc_variant_list", lib().ckc_variant_list(buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n = line.rsplit("=", 1)
+        out[name] = int(n)
+    return out
 
 
 def tune_set(knob: str, value: int):

@@ -408,6 +408,7 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
         // algorithmic bytes: every digit word, every key word and every output word once
         const double bytes = 8.0 * N * nt * (double(nb) * dnum + 2.0 * dnum + 2.0 * nb);
         CKC_PROF(PK_KIP, s, bytes, 2.0 * N * nt * dnum * nb);
+        count_variant("kip_b", dnum <= 8 ? dnum : 0);
         hipLaunchKernelGGL(kip_kernel(dnum), dim3(unsigned(N / 256), unsigned(nt)), dim3(256), 0, s, digits, nb, dnum,
                            nt, nl, key, c->nprimes(), ext, scat, acc.u64(), pl.u64(), c->dprimes(), c->logN);
     }
@@ -543,6 +544,7 @@ int hoisted_group_ext(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, in
             8.0 * N * (nt * (double(nb) * dnum + nrot * (2.0 * dnum + 2.0 * nb)) + double(nb) * nl);
         CKC_PROF(PK_KIP, s, bytes, 2.0 * N * nt * dnum * nb * nrot);
         const unsigned blocks = unsigned((N >> 8) * size_t(nt) * size_t(nrot));
+        count_variant("kip_ext_rot", dnum <= 8 ? dnum : 0);
         hipLaunchKernelGGL(kip_rot_kernel(dnum), dim3(blocks), dim3(256), 0, s, digits.u64(), nb, dnum, nt, nl, nrot,
                            kr, c->nprimes(), ext, in, dst[0], c->pmod.u64(), c->dprimes(), c->logN);
         CKC_HIP(hipGetLastError());
@@ -566,6 +568,7 @@ int hoisted_group_ext(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, in
             // algorithmic bytes: digits, key, c0 (Q limbs) and both outputs once
             const double bytes = 8.0 * N * (nt * (double(nb) * dnum + 2.0 * dnum + 2.0 * nb) + double(nb) * nl);
             CKC_PROF(PK_KIP, s, bytes, 2.0 * N * nt * dnum * nb);
+            count_variant("kip_ext", dnum <= 8 ? dnum : 0);
             hipLaunchKernelGGL(kip_ext_kernel(dnum), dim3(unsigned(N / 256), unsigned(nt)), dim3(256), 0, s,
                                digits.u64(), nb, dnum, nt, nl, it->second->u64(), c->nprimes(), ext, scat, in,
                                dst[si], c->pmod.u64(), c->dprimes(), c->logN);

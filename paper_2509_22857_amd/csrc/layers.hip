@@ -836,6 +836,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                                                     double(ntap) * L->kcent) -
                                             skipped * (2.0 * gi * nic + L->kcent)),
                                  2.0 * N * double(gi) * O * nic * (double(nlim) * ntap - skipped));
+                        count_variant("conv_mac", outs, wg_imgs, dbuf ? "+dbuf+fused" : "+fused");
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile) * unsigned(nlim) * unsigned(ngroups)),
                                            dim3(128 * wg_imgs), lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi,
                                            nic, I, ic0, ntap, nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(),
@@ -854,6 +855,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                                                     double(ntap) * L->kcent) -
                                             skipped * (2.0 * gi * nic + L->kcent)),
                                  2.0 * N * double(gi) * oc * nic * (double(nlim) * ntap - skipped));
+                        count_variant("conv_mac", outs, wg_imgs, dbuf ? "+dbuf" : "");
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
                                            lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
                                            nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(), L->Opad / 4,
@@ -874,6 +876,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                         CKC_PROF(PK_CONV_CONTRACT, s,
                                  8.0 * N * nlim * (2.0 * I * ntap + 2.0 * oc + double(ntap) * L->kcent),
                                  2.0 * N * nlim * double(oc) * I * ntap);
+                        count_variant("conv_contract");
                         hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nlim), 2 * ogroups),
                                            dim3(256), lds, s, Rimg, I, ntap, nlim, map, L->pts.u64(), L->kcent,
                                            (const int32_t *)L->og_off.p, (const int32_t *)L->g_c.p,

@@ -34,3 +34,12 @@ struct ProfScope {
 };
 
 #define CKC_PROF(kid, stream, bytes, work) ProfScope _prof_scope_##__LINE__((kid), (stream), (bytes), (work))
+
+// Opt-in count of launches per kernel instantiation (name plus template
+// arguments), so that tests can check which variant a call ran.  Off by
+// default; ckc_variant_enable turns it on and clears the counts.
+extern bool g_variant_on;
+void count_variant_slow(const char *base, int a, int b, const char *suffix);
+inline void count_variant(const char *base, int a = -1, int b = -1, const char *suffix = "") {
+    if (g_variant_on) count_variant_slow(base, a, b, suffix);
+}

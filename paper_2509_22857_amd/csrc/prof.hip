@@ -1,7 +1,10 @@
 // Launch timing registry behind ckc_prof_enable / ckc_prof_query.
+#include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "ckc_internal.h"
@@ -83,5 +86,46 @@ extern "C" int ckc_prof_query(const char *name, int64_t *launches, double *total
     *total_ms = ms;
     *bytes = by;
     *work = wk;
+    return CKC_OK;
+}
+
+bool g_variant_on = false;
+
+namespace {
+std::mutex g_vmu;
+std::map<std::string, int64_t> g_variants;
+}  // namespace
+
+void count_variant_slow(const char *base, int a, int b, const char *suffix) {
+    char name[96];
+    if (a < 0) snprintf(name, sizeof name, "%s%s", base, suffix);
+    else if (b < 0) snprintf(name, sizeof name, "%s<%d>%s", base, a, suffix);
+    else snprintf(name, sizeof name, "%s<%d,%d>%s", base, a, b, suffix);
+    std::lock_guard<std::mutex> lk(g_vmu);
+    ++g_variants[name];
+}
+
+extern "C" int ckc_variant_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_vmu);
+    g_variants.clear();
+    g_variant_on = on != 0;
+    return CKC_OK;
+}
+
+extern "C" int ckc_variant_count(const char *name, int64_t *launches) {
+    CKC_REQUIRE(name && launches, CKC_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_vmu);
+    auto it = g_variants.find(name);
+    *launches = it == g_variants.end() ? 0 : it->second;
+    return CKC_OK;
+}
+
+extern "C" int ckc_variant_list(char *buf, size_t cap) {
+    CKC_REQUIRE(buf && cap > 0, CKC_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_vmu);
+    std::string s;
+    for (auto &kv : g_variants) s += kv.first + "=" + std::to_string(kv.second) + "\n";
+    CKC_REQUIRE(s.size() < cap, CKC_EINVAL, "variant list does not fit the buffer");
+    snprintf(buf, cap, "%s", s.c_str());
     return CKC_OK;
 }

@@ -48,3 +48,16 @@ def test_test_fault_hook_argument_checks_without_gpu():
     with pytest.raises(ckks.CkcError, match="CKC_EINVAL"):
         ckks.set_test_fault(-1, -6)
     ckks.set_test_fault(0, 0)
+
+
+def test_variant_counter_without_gpu():
+    """The per-instantiation launch counter is host-side state: enabling it
+    clears it, an unknown name counts zero, and the list parses."""
+    ckks.variant_enable(True)
+    try:
+        assert ckks.variant_counts() == {}
+        n = ctypes.c_int64(-1)
+        assert ckks.lib().ckc_variant_count(b"conv_mac<8,4>+dbuf", ctypes.byref(n)) == 0
+        assert n.value == 0
+    finally:
+        ckks.variant_enable(False)

@@ -329,3 +329,31 @@ def test_packed_logits_bit_exact():
     from oracle.forward import forward
     got = gnet.decrypt_packed_logits(keys, gp)
     assert np.max(np.abs(got - forward(spec, imgs[0]))) < 1e-3
+
+
+def test_quantisation_aware_fitted_activation_network_bit_exact():
+    """A network trained with the quantisation-aware ReLU fit of Section 3.2
+    (d = 2, b = 10, c = 2: p(x) = (192 + 511 x + 240 x^2) / 2^10) at every
+    activation, through the post-training compiler: bit-exact with the oracle,
+    logits within 1e-3 of the FP64 forward of the compiled description."""
+    from oracle.forward import forward
+    from paper_2509_22857_amd import compiler as cc
+    from paper_2509_22857_amd import qafit
+    from workloads.graphs import bn_resnet_graph
+    act = qafit.coefficients(2, 10, 2.0)
+    assert tuple(np.round(act * 1024).astype(int)) == (192, 511, 240)
+    g = bn_resnet_graph(seed=8, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), act=act)
+    spec, _ = cc.compile_network(g, k=64)
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[qafit_network] N=2^12 M=2 widths=(4,8), fitted activation", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 51)
+    imgs = gen.images(61, 1, 3, 16, 16)
+    gout, _ = gnet.run(keys, gnet.encrypt_images(keys, imgs, 800))
+    oout, _ = onet.run(sk, onet.encrypt_image(sk, imgs[0], 800), rlk, gk)
+    for k, (a, b) in enumerate(zip(gout[0], oout)):
+        assert np.array_equal(_coeff(ctx, a), b.data), k
+    got = gnet.decrypt_logits(keys, gout[0])
+    ref = forward(spec, imgs[0])
+    assert np.max(np.abs(got - ref)) < 1e-3
+    assert got.mean(0).argmax() == ref.mean(0).argmax()

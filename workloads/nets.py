@@ -262,6 +262,21 @@ def vgg_spec(seed: int = 0, widths=(64, 64, 128, 128, 256), pool_after=(1, 3), c
     return set_hoisting(spec, hoist)
 
 
+def single_conv_spec(seed: int, I: int, O: int, k: int, M: int, H: int = 8, W: int = 8, block: int = 64,
+                     stride: int = 1, hoist: str = "double") -> dict:
+    """A network of one 3x3 convolution (codebook per kernel column with k
+    centroids in R^M, uniform in [-0.3, 0.3]; uniform centroid choices; a
+    bias per member and output), for layer-level parity cases."""
+    g = rng(seed)
+    codebook = g.uniform(-0.3, 0.3, (3, k, M))
+    idx = g.integers(0, k, (O, I, 3, 3)).astype(np.uint16)
+    bias = g.uniform(-0.5, 0.5, (M, O))
+    layer = dict(op="conv", name="conv", inp="x", out="c", out_ch=O, in_ch=I, ksize=3, stride=stride,
+                 codebook=codebook, idx=idx, bias=bias, hoist=hoist)
+    return dict(name=f"conv_{I}x{O}_k{k}", members=M, classes=0, image=(I, H, W),
+                layout=dict(block=block, row_stride=W), layers=[layer], k=k)
+
+
 def set_hoisting(spec: dict, hoist) -> dict:
     """Mark the key-switching form of every 3x3 convolution: hoist is None
     (the default, double hoisting), "single"/"double" for all, or one entry
