@@ -1,9 +1,12 @@
-"""Writes headline_conv_N65536.json: SHA-256 digests of the oracle's input and
-output ciphertexts for one convolution layer of the ResNet-20-style ensemble
-at the ring and chain it runs on.
+"""Writes SHA-256 digests of the oracle's input and output ciphertexts for one
+convolution layer of the ResNet-20-style ensemble at the ring and chain it
+runs on: headline_conv_N65536.json (one plaintext per tap and centroid,
+1024-slot blocks) and headline_conv_slice_N65536.json (the slice-shared
+layout: one plaintext per kernel column and centroid, 2048-slot blocks whose
+lower half is zero rows).
 
 Layer: 3x3, stride 1, 16 -> 16 channels, 32x32 images, 4 members in blocks of
-1024 slots, 64 centroids per kernel column in R^4, double-hoisted (rotated
+1024 or 2048 slots, 64 centroids per kernel column in R^4, double-hoisted (rotated
 inputs in Q_l u P, one ModDown per output), at the top level of the
 tower-reuse chain (N = 2^16, 21 Q primes, 3 P primes, 3 primes per digit, so
 7 digits).  Four images.
@@ -12,7 +15,7 @@ Each digest is over the ciphertext in coefficient form as little-endian
 uint64 words [npoly][level+1][N].  Everything here comes from the oracle and
 the seeded input generators only.  Run from the repository root:
 
-    python tests/golden/make_headline_conv.py [--procs 4]
+    python tests/golden/make_headline_conv.py [--procs 4] [--layout taps|slice]
 """
 from __future__ import annotations
 
@@ -27,10 +30,14 @@ from multiprocessing import Pool
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "headline_conv_N65536.json")
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = {"taps": os.path.join(HERE, "headline_conv_N65536.json"),
+       "slice": os.path.join(HERE, "headline_conv_slice_N65536.json")}
 
-CASE = dict(spec_seed=2016, key_seed=77, image_seed=78, images=4, I=16, O=16, k=64, M=4, H=32, W=32, block=1024,
-            stream_base=6000)
+CASES = {"taps": dict(spec_seed=2016, key_seed=77, image_seed=78, images=4, I=16, O=16, k=64, M=4, H=32, W=32,
+                      block=1024, stream_base=6000),
+         "slice": dict(spec_seed=2017, key_seed=79, image_seed=80, images=4, I=16, O=16, k=64, M=4, H=32, W=32,
+                       block=2048, slice_shared=True, stream_base=7000)}
 DELTA_LOG2 = 30
 
 
@@ -39,16 +46,23 @@ def digest(a) -> str:
     return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).hexdigest()
 
 
-def _one_image(n):
+def case_spec(c):
+    from workloads.nets import single_conv_spec
+    spec = single_conv_spec(c["spec_seed"], c["I"], c["O"], c["k"], c["M"], c["H"], c["W"], c["block"])
+    spec["layout"]["slice_shared"] = bool(c.get("slice_shared", False))
+    return spec
+
+
+def _one_image(job):
+    layout, n = job
     import numpy as np  # noqa: F401
     from oracle.ckks import Oracle
     from oracle.network import OracleNetwork
     from workloads import gen
-    from workloads.nets import single_conv_spec
     from workloads.params import resnet20_tower
-    c = CASE
+    c = CASES[layout]
     ps = resnet20_tower()
-    spec = single_conv_spec(c["spec_seed"], c["I"], c["O"], c["k"], c["M"], c["H"], c["W"], c["block"])
+    spec = case_spec(c)
     D = 2.0 ** DELTA_LOG2
     o = Oracle.from_params(ps)
     onet = OracleNetwork(o, spec, D, D, D)
@@ -67,14 +81,16 @@ def _one_image(n):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--procs", type=int, default=4)
+    ap.add_argument("--layout", default="slice", choices=sorted(CASES))
     args = ap.parse_args()
+    c = CASES[args.layout]
     with Pool(args.procs) as pool:
-        per_image = pool.map(_one_image, range(CASE["images"]))
+        per_image = pool.map(_one_image, [(args.layout, n) for n in range(c["images"])])
     rec = dict(source="oracle/ (tests/golden/make_headline_conv.py)", params="resnet20_tower()",
-               delta_log2=DELTA_LOG2, case=CASE, images=per_image)
-    with open(OUT, "w") as f:
+               delta_log2=DELTA_LOG2, case=c, images=per_image)
+    with open(OUT[args.layout], "w") as f:
         json.dump(rec, f, indent=1)
-    print("wrote", OUT)
+    print("wrote", OUT[args.layout])
 
 
 if __name__ == "__main__":
