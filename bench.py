@@ -153,15 +153,22 @@ def run_packed(args):
 
 def workload_key(args, tuned):
     knobs = {k: v for k, v in (tuned or {}).items() if k != "timings"}
-    return f"{args.workload}/batch{args.batch}/pass{args.images_per_pass}/" + json.dumps(knobs, sort_keys=True)
+    return (f"{args.workload}/{args.layout}/batch{args.batch}/pass{args.images_per_pass}/" +
+            json.dumps(knobs, sort_keys=True))
 
 
 VGG_HOISTING = ["single", "double", "double", "double", "single"]
 
 
 def build_workload(args):
+    """Parameters and network of the workload.  Layout: slice-shared (Section
+    5.2: one plaintext per kernel column and centroid, vertical padding from
+    zero rows, so each 32x32 image takes a block of 2048 slots, 64 rows of 32)
+    unless --layout taps (one plaintext per tap and centroid, blocks of 1024
+    slots) or slot packing, which needs the smaller blocks."""
     from workloads import nets
     from workloads.params import resnet20_tower
+    shared = getattr(args, "layout", "slice") == "slice" and getattr(args, "pack", 1) == 1
     if args.workload == "vgg":
         # VGG-style: 3->64, 64->64, pool, 64->128, 128->128, pool, 128->256, dense to 10; k = 16.
         # Per-layer key-switching form: what network.choose_hoisting picks for
@@ -170,10 +177,13 @@ def build_workload(args):
         # to which the three P limbs would add as many again) single-hoisted
         ps = resnet20_tower(levels=6)
         spec = nets.vgg_spec(seed=0, calib=8, hoist=VGG_HOISTING)
-        return ps, spec
-    ps = resnet20_tower()
-    spec = nets.resnet_spec(seed=0, members=4, widths=(16, 32, 64), blocks=3, classes=100, image=(3, 32, 32),
-                            k=64, calib=8)
+    else:
+        ps = resnet20_tower()
+        spec = nets.resnet_spec(seed=0, members=4, widths=(16, 32, 64), blocks=3, classes=100, image=(3, 32, 32),
+                                k=64, calib=8)
+    if shared:
+        spec["layout"]["block"] = 2048
+        spec["layout"]["slice_shared"] = True
     return ps, spec
 
 
@@ -344,6 +354,8 @@ def main():
     ap.add_argument("--tune", default="cached", choices=["cached", "fresh", "off"],
                     help="autotuner: stored choices for this workload if any (else tune), re-tune, or defaults")
     ap.add_argument("--workload", default="resnet20", choices=["resnet20", "vgg", "micro", "serving"])
+    ap.add_argument("--layout", default="slice", choices=["slice", "taps"],
+                    help="slice-shared codebook (default) or one plaintext per tap")
     ap.add_argument("--pack", type=int, default=1,
                     help="images per ciphertext (slot packing, a separate labelled row; resnet20 only)")
     ap.add_argument("--clients", type=int, default=4, help="serving: clients with their own keys")
@@ -538,6 +550,8 @@ def main():
         "config": {"workload": ("vgg_N65536" if args.workload == "vgg" else "resnet20_ensemble_N65536"),
                    "images_per_step": B,
                    "images_per_pass": min(B, args.images_per_pass), "members": spec["members"],
+                   "layout": ("slice-shared columns, " if spec["layout"].get("slice_shared") else "per-tap masks, ")
+                   + f"{spec['layout']['block']}-slot blocks",
                    "classes": spec["classes"], "k": spec["k"], "image": list(spec["image"]),
                    "levels": len(ps.q) - 1, "primes_q": len(ps.q), "primes_p": len(ps.p), "alpha": ps.alpha,
                    "tuned": ({k: v for k, v in tuned.items() if k != "timings"} if tuned else None)},

@@ -225,7 +225,18 @@ int ckc_mac_plain_many(ckc_ctx *ctx, const ckc_ct *in, const ckc_pt *pt, int n_t
  * and pooling leave gaps instead of re-packing (lazy mapping): the output of a
  * stride-s layer has gap*s.  Slots outside the valid grid hold values that
  * no consumer reads (every mask is zero there).
+ *
+ * flags & CKC_LAYOUT_SLICE_SHARED: the slice-shared layout (Section 5.2: the
+ * weights of one kernel column across a layer's filters share an encoding).
+ * Every member block keeps zero rows below its image -- at least gap*(height
+ * + 1) rows of row_stride slots per block, so the row after the image and
+ * the row before it (the previous block's last) read as zeros -- and a 3x3
+ * weight's plaintext then masks only the columns: one plaintext per (kernel
+ * column, centroid), shared by the column's three taps.  The spare rows stay
+ * zero through the network because every layer writes only its grid there
+ * (the activation places its constant term on the grid only).
  */
+#define CKC_LAYOUT_SLICE_SHARED 1
 typedef struct {
     int32_t block;      /* slots per ensemble member (power of two) */
     int32_t row_stride; /* slot distance of vertically adjacent pixels at gap 1 */
@@ -233,6 +244,7 @@ typedef struct {
     int32_t height;     /* valid grid height */
     int32_t width;      /* valid grid width */
     int32_t members;    /* ensemble members packed side by side */
+    int32_t flags;      /* CKC_LAYOUT_SLICE_SHARED or 0 */
 } ckc_layout;
 
 /*
@@ -244,7 +256,11 @@ typedef struct {
  * tap's column.  bias: [members][out_ch] or NULL.
  * Every (tap, centroid) pair is encoded once into a plaintext codebook at
  * `level` and scale pt_scale: the centroid's member values on the slots of
- * the output grid whose input pixel for that tap lies inside the image.
+ * the output grid whose input pixel for that tap lies inside the image.  In
+ * the slice-shared layout (in->flags & CKC_LAYOUT_SLICE_SHARED, 3x3 layers)
+ * every (kernel column, centroid) pair is encoded once instead, on the
+ * output slots whose input column lies inside the image, and the column's
+ * three taps share it (a third of the plaintexts).
  * The bias plaintext is encoded at bias_scale on the output grid.
  * The layer copies every host array.  Errors: CKC_EINVAL, CKC_ESHAPE,
  * CKC_ENOMEM, CKC_EDEVICE.
@@ -296,7 +312,8 @@ int ckc_eval_conv(ckc_ctx *ctx, const ckc_evk *evk, const ckc_layer *layer, cons
  * makes it monic): y = x^2 + b x + c per (channel, member),
  * evaluated as t = x + b, y = Relin(x * t) + c.  b and c: [members][channels];
  * for members == 1 they are added as constant polynomials, otherwise as
- * block-constant plaintexts.  The leading coefficient a_absorb is absorbed
+ * block-constant plaintexts; in the slice-shared layout c is placed on the
+ * layout's grid slots only (the spare rows stay zero).  The leading coefficient a_absorb is absorbed
  * into the scale: result scale = in_scale^2 / a_absorb (1.0 when the
  * coefficient was redistributed into the next layer).  Consumes no level.
  */

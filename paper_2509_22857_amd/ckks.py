@@ -38,10 +38,10 @@ class ckc_pt(C.Structure):
 
 class ckc_layout(C.Structure):
     _fields_ = [("block", C.c_int32), ("row_stride", C.c_int32), ("gap", C.c_int32), ("height", C.c_int32),
-                ("width", C.c_int32), ("members", C.c_int32)]
+                ("width", C.c_int32), ("members", C.c_int32), ("flags", C.c_int32)]
 
     def as_tuple(self):
-        return (self.block, self.row_stride, self.gap, self.height, self.width, self.members)
+        return (self.block, self.row_stride, self.gap, self.height, self.width, self.members, self.flags)
 
 
 _lib = None
@@ -132,11 +132,16 @@ def exported_names() -> list[str]:
 
 
 def lib():
-    """Load libckkscnn.so (raises if it has not been built)."""
+    """Load libckkscnn.so (raises if it has not been built).
+
+    torch is imported first: its wheel carries its own HIP and HSA runtime
+    libraries, which it must load before the library brings in the system
+    ones (loaded the other way round, torch finds no GPU)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        import torch  # noqa: F401  (load order, see above)
         L = C.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             f = getattr(L, name)
@@ -471,8 +476,11 @@ class Layer:
             pass
 
 
-def make_layout(block, row_stride, gap, height, width, members) -> ckc_layout:
-    return ckc_layout(int(block), int(row_stride), int(gap), int(height), int(width), int(members))
+LAYOUT_SLICE_SHARED = 1  # CKC_LAYOUT_SLICE_SHARED
+
+
+def make_layout(block, row_stride, gap, height, width, members, flags=0) -> ckc_layout:
+    return ckc_layout(int(block), int(row_stride), int(gap), int(height), int(width), int(members), int(flags))
 
 
 HOIST = {"single": 1, "double": 2}  # CKC_HOIST_SINGLE, CKC_HOIST_DOUBLE

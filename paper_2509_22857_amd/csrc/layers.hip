@@ -35,7 +35,9 @@ struct ckc_layer {
     double pt_scale = 1.0, bias_scale = 1.0;
     bool has_bias = false;
     std::vector<int32_t> tap_step;
-    DevMem pts;                        // conv: [ntap][kcent][nl][N]; dense: [K][C][nl][N]
+    DevMem pts;                        // conv: [npt][kcent][nl][N]; dense: [K][C][nl][N]
+    int npt = 0;                       // conv plaintext sets: one per tap, or one per kernel column
+    bool pt_shared = false;            // slice-shared layout: tap t uses the set of its column t % 3
     DevMem bias;                       // conv: [O][nl][N]; dense: [K][nl][N]
     DevMem og_off, g_c, g_moff, m_i;   // conv group lists (grouped form, any codebook size)
     DevMem ioff;                       // conv: [ntap][Opad/4][I] codebook row byte offsets, 16 bits each (direct form)
@@ -67,6 +69,14 @@ int check_layout(const ckc_ctx *c, const ckc_layout *L) {
                 "layout: bad grid");
     const int64_t last = int64_t(L->gap) * (int64_t(L->row_stride) * (L->height - 1) + (L->width - 1));
     CKC_REQUIRE(last < L->block, CKC_ESHAPE, "layout: grid does not fit in a block");
+    CKC_REQUIRE((L->flags & ~CKC_LAYOUT_SLICE_SHARED) == 0, CKC_EINVAL, "layout: unknown flags");
+    if (L->flags & CKC_LAYOUT_SLICE_SHARED) {
+        // the row below the image and the row above it (the previous block's
+        // last) must be spare rows, which hold zeros
+        CKC_REQUIRE(L->block % L->row_stride == 0 &&
+                        int64_t(L->block / L->row_stride) >= int64_t(L->gap) * (L->height + 1),
+                    CKC_ESHAPE, "layout: the slice-shared layout needs gap*(height+1) rows per block");
+    }
     return CKC_OK;
 }
 
@@ -135,9 +145,11 @@ constexpr int kGrpOut = 8;       // outputs per wave of the grouped form
 constexpr int kOutPerWg = 4 * kGrpOut;
 
 // One workgroup: 64 coefficients of one limb of one polynomial, 32 outputs.
-// R_img: [I][ntap][2][nl][N]; pts: [ntap][kcent][nl][N]; bias: [O][nl][N].
+// R_img: [I][ntap][2][nl][N]; pts: [npt][kcent][nl][N] (tap t reads set t, or
+// set t % 3 of its kernel column when pt_shared); bias: [O][nl][N].
 __global__ __launch_bounds__(256) void k_conv_contract(
-    const uint64_t *__restrict__ R, int I, int ntap, int nl, LimbMap map, const uint64_t *__restrict__ pts, int kcent,
+    const uint64_t *__restrict__ R, int I, int ntap, int pt_shared, int nl, LimbMap map,
+    const uint64_t *__restrict__ pts, int kcent,
     const int32_t *__restrict__ og_off, const int32_t *__restrict__ g_c, const int32_t *__restrict__ g_moff,
     const int32_t *__restrict__ m_i, const uint64_t *__restrict__ bias, Ptrs outs, int o_base, int o_count,
     const Prime *__restrict__ primes, int logN) {
@@ -186,7 +198,7 @@ __global__ __launch_bounds__(256) void k_conv_contract(
                     }
                 }
                 s = reduce64(s, P);
-                const uint64_t pv = pts[((size_t(t) * kcent + cc) * nl + limb) * N + k];
+                const uint64_t pv = pts[((size_t(pt_shared ? t % 3 : t) * kcent + cc) * nl + limb) * N + k];
                 acc[j] = add128(acc[j], mul64x64(s, pv));
                 if (++cnt[j] == prod_cap) {
                     acc[j] = u128v{reduce128(acc[j], P), 0};
@@ -251,7 +263,8 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
                                                            const uint64_t *__restrict__ bias, Ptrs outs, int o_base,
                                                            int o_count, int accumulate,
                                                            const Prime *__restrict__ primes, int logN, int dbuf,
-                                                           int skip_tap, ConvOut yo) {
+                                                           int skip_tap, int pt_shared, uint64_t seq_all,
+                                                           uint64_t seq_skip, ConvOut yo) {
     static_assert(OUTS % 4 == 0, "outputs per wave come in packed words of 4 offsets");
     constexpr int NW = OUTS / 4;
     extern __shared__ uint64_t sP[];  // [dbuf ? 2 : 1][kcent][kTile]
@@ -285,25 +298,34 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
 #pragma unroll
     for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, 0, 0, 0};
     int cnt = 0;
-    // codebook rows 2 pr and 2 pr + 1 of tap t: lane l brings words 2 (l & 31)
-    // and 2 (l & 31) + 1 of row 2 pr + (l >> 5) to LDS address 16 l past the
-    // pair (an odd last row leaves the upper half-wave idle)
-    auto stage = [&](int t, uint64_t *buf) {
+    // codebook rows 2 pr and 2 pr + 1 of plaintext set ps: lane l brings words
+    // 2 (l & 31) and 2 (l & 31) + 1 of row 2 pr + (l >> 5) to LDS address 16 l
+    // past the pair (an odd last row leaves the upper half-wave idle)
+    auto stage = [&](int ps, uint64_t *buf) {
         for (int pr = wave; 2 * pr < kcent; pr += 2 * IMGS) {
             const int c = 2 * pr + (lane >> 5);
             if (c < kcent)
                 __builtin_amdgcn_global_load_lds(
-                    (const void *)(pts + ((size_t(t) * kcent + c) * nl + limb) * N + col0 + 2 * (lane & 31)),
+                    (const void *)(pts + ((size_t(ps) * kcent + c) * nl + limb) * N + col0 + 2 * (lane & 31)),
                     (__attribute__((address_space(3))) void *)(buf + size_t(2 * pr) * kTile), 16, 0, 0);
         }
     };
-    // the identity tap's rotated inputs are P x, zero on the P limbs: a P-limb
-    // workgroup walks the other taps only (logical tap t -> stored tap phys(t))
+    // taps are visited in the order of a packed sequence (4 bits per visit):
+    // column by column when the taps of a kernel column share their
+    // plaintexts (one codebook tile serves the column's three taps), and
+    // without the identity tap on the P limbs, where its rotated inputs P x
+    // are zero (visit v -> stored tap phys(v))
     const bool skip = skip_tap >= 0 && limb >= map.nlow;
     const int ntl = skip ? ntap - 1 : ntap;
-    auto phys = [&](int t) { return skip && t >= skip_tap ? t + 1 : t; };
+    const uint64_t seq = skip ? seq_skip : seq_all;
+    auto phys = [&](int v) { return int((seq >> (4 * v)) & 15u); };
+    auto ptix = [&](int t) { return pt_shared ? t % 3 : t; };
+    // visit v starts a new plaintext set (a new codebook tile)
+    auto newset = [&](int v) { return v == 0 || ptix(phys(v)) != ptix(phys(v - 1)); };
     uint64_t *const buf0 = sP, *const buf1 = dbuf ? sP + size_t(kcent) * kTile : sP;
-    if (dbuf) stage(phys(0), buf0);
+    if (dbuf) stage(ptix(phys(0)), buf0);
+    int nset = 0;          // plaintext sets begun so far
+    uint64_t *cur = buf0;  // the current set's codebook tile
     const uint64_t *ixw0 = ioff + size_t(g0) * I + i_base;
     // The flat stream of blocks of kUnroll inputs, tap by tap.  Coefficients
     // travel two blocks ahead of their use in a ring of three register
@@ -403,14 +425,21 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     auto step = [&](const uint64_t(&cr)[kUnroll], uint64_t(&nx)[kUnroll], const uint64_t(&kc)[NW][kUnroll],
                     uint64_t(&kn)[NW][kUnroll]) {
         if (tc >= ntl) return;
-        uint64_t *const cur = (tc & 1) ? buf1 : buf0;
-        if (ic == 0) {
+        if (ic == 0 && newset(tc)) {
+            cur = (nset & 1) ? buf1 : buf0;
             if (!dbuf) {
                 __syncthreads();
-                stage(phys(tc), cur);
+                stage(ptix(phys(tc)), cur);
             }
             __syncthreads();
-            if (dbuf && tc + 1 < ntl) stage(phys(tc + 1), (tc & 1) ? buf0 : buf1);
+            if (dbuf) {
+                // the next set's tile goes into the other buffer, whose last
+                // readers (the previous set) are past the barrier
+                int v2 = tc + 1;
+                while (v2 < ntl && !newset(v2)) ++v2;
+                if (v2 < ntl) stage(ptix(phys(v2)), (nset & 1) ? buf0 : buf1);
+            }
+            ++nset;
         }
         if (active) {
             load_block(nx);
@@ -456,7 +485,21 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
 
 using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, LimbMap, const uint64_t *, int,
                         const uint64_t *, int, const uint64_t *, Ptrs, int, int, int, const Prime *, int, int, int,
-                        ConvOut);
+                        int, uint64_t, uint64_t, ConvOut);
+
+// visiting order of a layer's taps for the direct-form contraction, 4 bits
+// per visit: column by column when the taps of a column share their
+// plaintexts, else in stored order; without tap `skip` (when >= 0)
+uint64_t tap_sequence(const ckc_layer *L, int skip) {
+    uint64_t seq = 0;
+    int v = 0;
+    for (int j = 0; j < L->ntap; ++j) {
+        const int t = L->pt_shared ? (j % L->ksz) * L->ksz + j / L->ksz : j;
+        if (t == skip) continue;
+        seq |= uint64_t(t) << (4 * v++);
+    }
+    return seq;
+}
 // kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images)
 // that holds them; outs = outputs per wave (8 or 16), a tuning choice between
 // accumulator registers (occupancy) and codebook re-reads per output group
@@ -523,11 +566,17 @@ extern "C" int ckc_layer_create_conv_ex(ckc_ctx *c, const ckc_layout *in, int ou
     // (one ModDown per output) unless it is single-hoisted (one ModDown per
     // rotated input), so its plaintexts carry the P limbs too.
     L->ext = ksize > 1 && hoisting == CKC_HOIST_DOUBLE;
+    // slice-shared layout: the taps of one kernel column share its plaintexts
+    // (the zero rows stand in for the vertical mask), which are those of the
+    // column's middle tap
+    L->pt_shared = (in->flags & CKC_LAYOUT_SLICE_SHARED) && ksize == 3;
+    L->npt = L->pt_shared ? ksize : L->ntap;
     const size_t ppw = L->ext ? size_t(nl + c->np) * N : pw;  // words per codebook plaintext
-    CKC_TRY(L->pts.alloc(8 * ppw * L->ntap * n_centroids));
+    CKC_TRY(L->pts.alloc(8 * ppw * L->npt * n_centroids));
     std::vector<double> v(n);
     const ckc_layout &Lo = L->lout;
-    for (int t = 0; t < L->ntap; ++t) {
+    for (int ps = 0; ps < L->npt; ++ps) {
+        const int t = L->pt_shared ? half * ksize + ps : ps;
         const int dh = t / ksize - half, dw = t % ksize - half, col = t % ksize;
         for (int cc = 0; cc < n_centroids; ++cc) {
             std::fill(v.begin(), v.end(), 0.0);
@@ -543,8 +592,8 @@ extern "C" int ckc_layer_create_conv_ex(ckc_ctx *c, const ckc_layout *in, int ou
                     }
                 }
             }
-            CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(t) * n_centroids + cc) * ppw, s,
-                                L->ext));
+            CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(ps) * n_centroids + cc) * ppw,
+                                s, L->ext));
         }
     }
     if (bias) {
@@ -632,12 +681,22 @@ extern "C" int ckc_layer_create_act(ckc_ctx *c, const ckc_layout *layout, int ch
     CKC_TRY(L->bpt.alloc(8 * pw * channels));
     CKC_TRY(L->cpt.alloc(8 * pw * channels));
     std::vector<double> v(n);
+    // slice-shared layout: the spare rows stay zero, so the constant term goes
+    // on the grid's slots only (b multiplies x, which is zero there)
+    const bool grid_c = layout->flags & CKC_LAYOUT_SLICE_SHARED;
     for (int ch = 0; ch < channels; ++ch) {
+        if (grid_c) {
+            std::fill(v.begin(), v.end(), 0.0);
+            for (int m = 0; m < M; ++m)
+                for (int r = 0; r < layout->height; ++r)
+                    for (int q = 0; q < layout->width; ++q) v[slot_of(*layout, m, r, q)] = cc[size_t(m) * channels + ch];
+            CKC_TRY(encode_impl(c, v.data(), n, level, s2, L->cpt.u64() + size_t(ch) * pw, s));
+        }
         if (M == 1) {
             CKC_TRY(fill_const_pt(c, L->bpt.u64() + size_t(ch) * pw, b[ch], in_scale, nl, s));
-            CKC_TRY(fill_const_pt(c, L->cpt.u64() + size_t(ch) * pw, cc[ch], s2, nl, s));
+            if (!grid_c) CKC_TRY(fill_const_pt(c, L->cpt.u64() + size_t(ch) * pw, cc[ch], s2, nl, s));
         } else {
-            for (int which = 0; which < 2; ++which) {
+            for (int which = 0; which < (grid_c ? 1 : 2); ++which) {
                 const double *src = which == 0 ? b : cc;
                 std::fill(v.begin(), v.end(), 0.0);
                 for (int m = 0; m < M; ++m)
@@ -784,6 +843,10 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
         for (int t = 0; t < ntap; ++t)
             if (L->tap_step[t] == 0) skip_tap = t;
     const double skipped = skip_tap >= 0 ? double(c->np) : 0.0;  // P limbs without the identity tap
+    const uint64_t seq_all = tap_sequence(L, -1), seq_skip = tap_sequence(L, skip_tap);
+    // codebook rows the skip saves: the identity tap's own set, unless its
+    // column's other taps read that set too
+    const double skipped_pt = L->pt_shared ? 0.0 : double(L->kcent);
     for (int img0 = 0; img0 < n_img; img0 += chunk) {
         const int ni_img = std::min(chunk, n_img - img0);
         if (!L->ioff.p)
@@ -833,15 +896,15 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                         const ConvOut yo{Y.u64() + size_t(g0) * O * lctw, size_t(O) * lctw, ngroups, O};
                         CKC_PROF(PK_CONV_CONTRACT, s,
                                  8.0 * N * (nlim * (2.0 * gi * nic * ntap + 2.0 * gi * O * (ic0 > 0 ? 2 : 1) +
-                                                    double(ntap) * L->kcent) -
-                                            skipped * (2.0 * gi * nic + L->kcent)),
+                                                    double(L->npt) * L->kcent) -
+                                            skipped * (2.0 * gi * nic + skipped_pt)),
                                  2.0 * N * double(gi) * O * nic * (double(nlim) * ntap - skipped));
                         count_variant("conv_mac", outs, wg_imgs, dbuf ? "+dbuf+fused" : "+fused");
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile) * unsigned(nlim) * unsigned(ngroups)),
                                            dim3(128 * wg_imgs), lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi,
                                            nic, I, ic0, ntap, nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(),
                                            L->Opad / 4, bias_k, Ptrs{}, 0, 0, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN,
-                                           dbuf, skip_tap, yo);
+                                           dbuf, skip_tap, L->pt_shared ? 1 : 0, seq_all, seq_skip, yo);
                         CKC_HIP(hipGetLastError());
                         continue;
                     }
@@ -852,15 +915,16 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                             for (int j = 0; j < oc; ++j) op.p[m * outs + j] = dest(g0 + m, o0 + j);
                         CKC_PROF(PK_CONV_CONTRACT, s,
                                  8.0 * N * (nlim * (2.0 * gi * nic * ntap + 2.0 * gi * oc * (ic0 > 0 ? 2 : 1) +
-                                                    double(ntap) * L->kcent) -
-                                            skipped * (2.0 * gi * nic + L->kcent)),
+                                                    double(L->npt) * L->kcent) -
+                                            skipped * (2.0 * gi * nic + skipped_pt)),
                                  2.0 * N * double(gi) * oc * nic * (double(nlim) * ntap - skipped));
                         count_variant("conv_mac", outs, wg_imgs, dbuf ? "+dbuf" : "");
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
                                            lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
                                            nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(), L->Opad / 4,
                                            bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN, dbuf,
-                                           skip_tap, ConvOut{nullptr, 0, 0, 0});
+                                           skip_tap, L->pt_shared ? 1 : 0, seq_all, seq_skip,
+                                           ConvOut{nullptr, 0, 0, 0});
                         CKC_HIP(hipGetLastError());
                     }
                 }
@@ -874,11 +938,12 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                         for (int j = 0; j < oc; ++j) op.p[j] = dest(ii, o0 + j);
                         const unsigned ogroups = unsigned((oc + kOutPerWg - 1) / kOutPerWg);
                         CKC_PROF(PK_CONV_CONTRACT, s,
-                                 8.0 * N * nlim * (2.0 * I * ntap + 2.0 * oc + double(ntap) * L->kcent),
+                                 8.0 * N * nlim * (2.0 * I * ntap + 2.0 * oc + double(L->npt) * L->kcent),
                                  2.0 * N * nlim * double(oc) * I * ntap);
                         count_variant("conv_contract");
                         hipLaunchKernelGGL(k_conv_contract, dim3(unsigned(N / kTile), unsigned(nlim), 2 * ogroups),
-                                           dim3(256), lds, s, Rimg, I, ntap, nlim, map, L->pts.u64(), L->kcent,
+                                           dim3(256), lds, s, Rimg, I, ntap, L->pt_shared ? 1 : 0, nlim, map,
+                                           L->pts.u64(), L->kcent,
                                            (const int32_t *)L->og_off.p, (const int32_t *)L->g_c.p,
                                            (const int32_t *)L->g_moff.p, (const int32_t *)L->m_i.p, bias_k, op, o0,
                                            oc, c->dprimes(), c->logN);

@@ -240,6 +240,7 @@ extern "C" int ckc_batch_plan(ckc_ctx *c, const char *json, ckc_layer *const *la
             CKC_TRY(int_field(*lj, "height", &st.layout.height));
             CKC_TRY(int_field(*lj, "width", &st.layout.width));
             CKC_TRY(int_field(*lj, "members", &st.layout.members));
+            CKC_TRY(int_field(*lj, "flags", &st.layout.flags, false));
             CKC_REQUIRE(st.count == count_of[st.in], CKC_EINVAL, "plan: pooling keeps the channel count");
         } else {
             CKC_TRY(int_field(sj, "layer", &st.layer));

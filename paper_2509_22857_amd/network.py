@@ -124,7 +124,8 @@ def choose_hoisting(spec: dict, q, n_p: int, delta: float, target: float, in_sca
 def input_layout(spec: dict) -> ckks.ckc_layout:
     C, H, W = spec["image"]
     lay = spec["layout"]
-    return ckks.make_layout(lay["block"], lay["row_stride"], 1, H, W, spec["members"])
+    flags = ckks.LAYOUT_SLICE_SHARED if lay.get("slice_shared") else 0
+    return ckks.make_layout(lay["block"], lay["row_stride"], 1, H, W, spec["members"], flags)
 
 
 def image_slots(spec: dict, img: np.ndarray, N: int) -> list[np.ndarray]:
@@ -198,7 +199,7 @@ class GpuNetwork:
                 self.layouts[ly["out"]] = entry["main"].out_layout()
             elif ly["op"] == "pool":
                 self.layouts[ly["out"]] = ckks.make_layout(lay.block, lay.row_stride, 2 * lay.gap, lay.height // 2,
-                                                           lay.width // 2, lay.members)
+                                                           lay.width // 2, lay.members, lay.flags)
                 steps.update([lay.gap, lay.gap * lay.row_stride, lay.gap * (lay.row_stride + 1)])
             for e in entry.values():
                 if e is not None and e.kind in ("conv", "dense"):
@@ -413,7 +414,7 @@ class GpuNetwork:
                 lay = self.layouts[ly["inp"]]
                 st["count"] = count_of[ly["inp"]]
                 st["layout"] = {k: int(getattr(lay, k)) for k in ("block", "row_stride", "gap", "height", "width",
-                                                                   "members")}
+                                                                   "members", "flags")}
             else:
                 raise ValueError(f"unknown layer op {op}")
             count_of[ly["out"]] = st["count"]

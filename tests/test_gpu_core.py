@@ -208,3 +208,26 @@ def test_errors_are_reported(env):
     with pytest.raises(CkcError) as e:
         ctx.rescale(z)
     assert e.value.code == -2
+
+
+def test_library_loaded_and_context_created_before_torch_uses_the_device():
+    """Loading the library and creating a context before anything of torch
+    has touched the GPU leaves torch usable (the binding loads torch's HIP
+    runtime before the library's), and creating the context loads no code
+    object."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2509_22857_amd import ckks\n"
+            "ckks.lib()\n"
+            "from workloads.params import tiny\n"
+            "ctx = ckks.Context.from_params(tiny())\n"
+            "import torch\n"
+            "x = torch.ones(4, device='cuda'); torch.cuda.current_stream().synchronize()\n"
+            "keys = ctx.keygen(3, [1])\n"
+            "torch.cuda.synchronize(); print('ok', float(x.sum()))\n") % root
+    print("[ordering] library and context before torch's device set-up, in a child process", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0 and "ok 4.0" in r.stdout, r.stdout + r.stderr

@@ -357,3 +357,38 @@ def test_quantisation_aware_fitted_activation_network_bit_exact():
     ref = forward(spec, imgs[0])
     assert np.max(np.abs(got - ref)) < 1e-3
     assert got.mean(0).argmax() == ref.mean(0).argmax()
+
+
+def test_slice_shared_resnet_bit_exact():
+    """A ResNet-style ensemble in the slice-shared layout (blocks of 512 slots
+    for 16x16 images: 16 spare rows): every layer bit-exact with the oracle,
+    logits within 1e-3 of the FP64 forward; a third of the codebook
+    plaintexts of the 3x3 layers."""
+    spec = nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8, calib=4,
+                            block_slots=512)
+    spec["layout"]["slice_shared"] = True
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print("[slice_shared_resnet] N=2^12 M=2 widths=(4,8) block 512", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 9)
+    imgs = gen.images(3, 2, 3, 16, 16)
+    gin = gnet.encrypt_images(keys, imgs, 100)
+    gl = []
+    gout, _ = gnet.run(keys, gin, hook=lambda ly, outs: gl.append((ly["name"], _coeff(ctx, outs[0]))))
+    ol = []
+    oout, _ = onet.run(sk, onet.encrypt_image(sk, imgs[0], 100), rlk, gk,
+                       hook=lambda ly, outs: ol.append((ly["name"], outs[0].data)))
+    for (n1, a), (n2, b) in zip(gl, ol):
+        assert n1 == n2
+        assert np.array_equal(a, b), n1
+    from oracle.forward import forward
+    for n in range(2):
+        got = gnet.decrypt_logits(keys, gout[n])
+        ref = forward(spec, imgs[n])
+        assert np.max(np.abs(got - ref)) < 1e-3
+    plain = dict(spec, layout=dict(spec["layout"], slice_shared=False))
+    from paper_2509_22857_amd.network import GpuNetwork
+    full = GpuNetwork(ctx, plain, D, D, D)
+    for ly, e1, e2 in zip(spec["layers"], gnet.layers, full.layers):
+        if ly["op"] == "conv" and ly["ksize"] == 3:
+            assert e1["main"].nbytes() < 0.4 * e2["main"].nbytes(), ly["name"]

@@ -52,7 +52,9 @@ def _run_both(ps, spec, n_img, seed):
     sk = o.secret_key(seed)
     rlk = o.relin_key(sk)
     gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in onet.steps()}
-    for n in range(n_img):
+    # the first and last image of each 4-image contraction group (the GPU runs
+    # them all; the oracle, slow at this size, checks these)
+    for n in sorted({m for g0 in range(0, n_img, 4) for m in (g0, min(g0 + 3, n_img - 1))}):
         oin = onet.encrypt_image(sk, imgs[n], 5000 + n * 4096)
         oout, _ = onet.run(sk, oin, rlk, gk)
         assert len(oout) == len(gout[n])
@@ -109,3 +111,33 @@ def test_grouped_contraction_single_hoisted_stride_two():
     print("[variants] N=2^12 k=200 single-hoisted stride 2", flush=True)
     counts = _run_both(ps, spec, 2, 63)
     assert counts.get("conv_contract", 0) >= 1, counts
+
+
+def test_slice_shared_columns_four_image_groups():
+    """Slice-shared layout (one codebook tile per kernel column, visited
+    column by column; the P limbs skip the identity tap but keep its
+    column's tile): 8 digits, 7 images in a double-buffered 4-image group and
+    a ragged one, 16 spare rows under every 8x8 image."""
+    ps = small_tower(logN=12, levels=7, alpha=1)
+    spec = _conv_spec(211, I=8, O=12, k=64, M=2, block=128)
+    spec["layout"]["slice_shared"] = True
+    print("[variants] N=2^12 slice-shared dnum=8 I=8 O=12 k=64, 7 images", flush=True)
+    counts = _run_both(ps, spec, 7, 48)
+    assert counts.get("kip_ext_rot<8>", 0) >= 1, counts
+    assert counts.get("conv_mac<8,4>+dbuf+fused", 0) == 2, counts
+
+
+@pytest.mark.parametrize("hoist,k", [("double", 96), ("single", 200)])
+def test_slice_shared_columns_other_forms(hoist, k):
+    """Slice-shared layout with the single-buffered 4-image form (96
+    centroids) and with the grouped form of a single-hoisted layer (200
+    centroids), stride 2."""
+    ps = small_tower(logN=12, levels=3, alpha=2)
+    spec = _conv_spec(212, I=6, O=9, k=k, M=2, block=128, stride=2, hoist=hoist)
+    spec["layout"]["slice_shared"] = True
+    print(f"[variants] N=2^12 slice-shared {hoist} k={k} stride 2, 4 images", flush=True)
+    counts = _run_both(ps, spec, 4, 64)
+    if k <= 128:
+        assert counts.get("conv_mac<8,4>+fused", 0) == 1, counts
+    else:
+        assert counts.get("conv_contract", 0) >= 1, counts
