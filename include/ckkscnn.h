@@ -172,6 +172,24 @@ int ckc_tensor(ckc_ctx *ctx, const ckc_ct *a, const ckc_ct *b, ckc_ct *out, void
 /* relinearise a 3-polynomial ciphertext (s^2 -> s) into a 2-polynomial one */
 int ckc_relin(ckc_ctx *ctx, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream);
 
+/* ckc_relin without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops that must not call hipMalloc).
+ * Same arguments, kernels and results as ckc_relin (bit for bit).  Its scratch
+ * is one static device array of ckc_noalloc_capacity() bytes (256 MiB), which
+ * every GPU the library runs on holds until the process ends (its address is
+ * looked up at the first call on each device, which allocates nothing);
+ * ckc_relin_noalloc_bytes(ctx, level) gives the scratch a ciphertext at
+ * `level` needs (8N[dnum (l+1+n_P) + 4(l+1) + 2 n_P]
+ * bytes, each buffer rounded up to 256).  Nothing in the scratch needs to
+ * start at zero.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.
+ * Errors: as ckc_relin; CKC_ENOMEM if the level needs more scratch than the
+ * array holds (nothing is launched). */
+int ckc_relin_noalloc(ckc_ctx *ctx, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream);
+size_t ckc_relin_noalloc_bytes(const ckc_ctx *ctx, int level);
+size_t ckc_noalloc_capacity(void);
+
 /* Hoisted rotations: one ModUp of in->c1 shared by every step; out[i] is the
  * left rotation of the slots by steps[i] (0 = copy).  The Galois
  * automorphism is applied after ModUp.  out[i] must not alias in. */

@@ -75,6 +75,9 @@ _SIGS = [
     ("ckc_mul_plain", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_pt), C.POINTER(ckc_ct), _vp]),
     ("ckc_tensor", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
     ("ckc_relin", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
+    ("ckc_relin_noalloc", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
+    ("ckc_relin_noalloc_bytes", C.c_size_t, [_vp, C.c_int]),
+    ("ckc_noalloc_capacity", C.c_size_t, []),
     ("ckc_rotate", C.c_int, [_vp, _vp, C.POINTER(ckc_ct), _i32p, C.c_int, C.POINTER(ckc_ct), _vp]),
     ("ckc_rescale", C.c_int, [_vp, C.POINTER(ckc_ct), C.POINTER(ckc_ct), _vp]),
     ("ckc_mod_drop", C.c_int, [_vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
@@ -370,6 +373,15 @@ class Context:
         out = out or self.new_ct(a.level, 2, a.scale)
         sa, so = a.c(), out.c()
         _check("ckc_relin", lib().ckc_relin(self.h, keys.evk, C.byref(sa), C.byref(so), _stream(stream)))
+        out.update(so)
+        return out
+
+    def relin_noalloc(self, keys: "KeyPair", a: Ciphertext, out: Ciphertext, stream=None):
+        """ckc_relin without device allocation (scratch in the library's
+        static array); `out` must be given."""
+        sa, so = a.c(), out.c()
+        _check("ckc_relin_noalloc",
+               lib().ckc_relin_noalloc(self.h, keys.evk, C.byref(sa), C.byref(so), _stream(stream)))
         out.update(so)
         return out
 

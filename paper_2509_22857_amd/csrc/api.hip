@@ -311,6 +311,11 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
     CKC_TRY(c->p_to_q.inv.upload(inv.data(), 8 * n_p));
     CKC_TRY(c->p_to_q.invp.upload(invp.data(), 8 * n_p));
     CKC_TRY(c->p_to_q.hat.upload(hat.data(), 8 * hat.size()));
+    // ModUp tables of every level, so that no key switch builds one later
+    for (int l = 0; l < n_q; ++l) {
+        int rc = CKC_OK;
+        if (!modup_scale(c.get(), l, &rc)) return rc;
+    }
     *out = c.release();
     return CKC_OK;
 }
@@ -588,7 +593,7 @@ extern "C" int ckc_tensor(ckc_ctx *c, const ckc_ct *a, const ckc_ct *b, ckc_ct *
     return CKC_OK;
 }
 
-extern "C" int ckc_relin(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream) {
+int relin_impl(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream) {
     CKC_TRY(check_ct(c, in, "relin"));
     CKC_REQUIRE(evk && out && out->d, CKC_EINVAL, "null argument");
     CKC_REQUIRE(in->npoly == 3, CKC_ESHAPE, "relin needs a 3-poly ciphertext");
@@ -610,6 +615,23 @@ extern "C" int ckc_relin(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, ckc_c
     out->npoly = 2;
     out->scale = in->scale;
     return CKC_OK;
+}
+
+extern "C" int ckc_relin(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream) {
+    return relin_impl(c, evk, in, out, stream);
+}
+
+size_t relin_scratch_bytes(const ckc_ctx *c, int level) {
+    // digits [dnum][l+1+n_P][N], held throughout; then ModUp's coefficient
+    // copy [l+1][N] (released before) the key inner product's outputs
+    // [2][l+1] + [2][n_P] and ModDown's conversion [2][l+1] limbs
+    const size_t limb = 8 * c->N;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t nl = size_t(level) + 1, nt = nl + c->np;
+    const size_t digits = up(limb * nt * size_t(c->dnum_at(level)));
+    const size_t modup = up(limb * nl);
+    const size_t apply = up(limb * nl * 2) + up(limb * c->np * 2) + up(limb * nl * 2);
+    return digits + std::max(modup, apply);
 }
 
 extern "C" int ckc_rotate(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, const int32_t *steps, int n_steps,

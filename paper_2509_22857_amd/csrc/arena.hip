@@ -218,6 +218,25 @@ int arena_reserve_stream(hipStream_t s, size_t bytes) {
     return CKC_OK;
 }
 
+thread_local FixedScratch *t_fixed_scratch = nullptr;
+
+int fixed_alloc(FixedScratch *f, size_t bytes, void **p, size_t *off) {
+    CKC_REQUIRE(f->top + bytes <= f->cap, CKC_ENOMEM,
+                "fixed scratch exhausted: " + std::to_string(f->top + bytes) + " bytes needed, " +
+                    std::to_string(f->cap) + " available");
+    *p = f->base + f->top;
+    *off = f->top;
+    f->top += bytes;
+    f->high = std::max(f->high, f->top);
+    return CKC_OK;
+}
+
+void fixed_release(FixedScratch *f, size_t off, size_t bytes) {
+    // stack-wise: only the topmost buffer lowers the top (work on one stream
+    // runs in order, so a later buffer may reuse what queued kernels read)
+    if (off + bytes == f->top) f->top = off;
+}
+
 extern "C" int ckc_stream_release(void *stream) { return arena_trim_stream((hipStream_t)stream); }
 extern "C" int ckc_stream_reserve(void *stream, size_t bytes) {
     return arena_reserve_stream((hipStream_t)stream, bytes);

@@ -79,22 +79,41 @@ int arena_trim_stream(hipStream_t s);
 // grows the (idle) arena of (current device, s) to at least `bytes`
 int arena_reserve_stream(hipStream_t s, size_t bytes);
 
-// RAII scratch buffer from the stream's arena.
+// A fixed device region that, while installed on the calling thread, serves
+// every DevBuf of that thread stack-wise in place of the stream's arena: no
+// allocation API call is made, and a request beyond its capacity fails with
+// CKC_ENOMEM.  Used by the entry points that must not allocate.
+struct FixedScratch {
+    char *base = nullptr;
+    size_t cap = 0, top = 0, high = 0;
+};
+extern thread_local FixedScratch *t_fixed_scratch;
+int fixed_alloc(FixedScratch *f, size_t bytes, void **p, size_t *off);
+void fixed_release(FixedScratch *f, size_t off, size_t bytes);
+
+// RAII scratch buffer from the stream's arena (or the installed fixed region).
 struct DevBuf {
     void *p = nullptr;
     hipStream_t s = nullptr;
     Arena *a = nullptr;
-    size_t off = 0;
+    FixedScratch *f = nullptr;
+    size_t off = 0, bytes = 0;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() {
-        if (p) arena_release(a, off, p, s);
+        if (p && f) fixed_release(f, off, bytes);
+        else if (p) arena_release(a, off, p, s);
     }
-    int alloc(size_t bytes, hipStream_t st) {
+    int alloc(size_t nbytes, hipStream_t st) {
         s = st;
-        if (bytes == 0) bytes = 256;
-        return arena_alloc(st, bytes, &p, &a, &off);
+        if (nbytes == 0) nbytes = 256;
+        if (t_fixed_scratch) {
+            f = t_fixed_scratch;
+            bytes = (nbytes + 255) / 256 * 256;
+            return fixed_alloc(f, bytes, &p, &off);
+        }
+        return arena_alloc(st, nbytes, &p, &a, &off);
     }
     uint64_t *u64() const { return (uint64_t *)p; }
 };
@@ -204,5 +223,12 @@ const uint64_t *galois_table(ckc_ctx *c, uint64_t g, int *rc);
 uint64_t galois_element(const ckc_ctx *c, int64_t step);
 
 int rescale_impl(ckc_ctx *c, const uint64_t *in, int npoly, int level, uint64_t *out, hipStream_t s);
+// relinearisation (argument checks included) on the calling thread's scratch
+int relin_impl(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream);
+// scratch bytes relin_impl holds at once for a ciphertext at `level`
+size_t relin_scratch_bytes(const ckc_ctx *c, int level);
+// device address of the no-allocation entry points' static scratch on the
+// current device (looked up once per device)
+int noalloc_scratch(void **ptr);
 
 size_t words_ct(const ckc_ctx *c, int level, int npoly);
