@@ -383,8 +383,14 @@ void oc_decrypt(const oc_ctx *c, const int8_t *s, const uint64_t *ct, int npoly,
  * digit primes D = {q_i : i in [j*alpha, min(j*alpha+alpha-1, level)]}, Q_j
  * their product.  For every target prime t (q_0..q_level then P):
  *   t in D : the limb itself;
- *   else   : sum_{i in D} [d_i * (Q_j/q_i)^-1]_{q_i} * (Q_j/q_i mod t)  mod t
- * (fast basis conversion, no correction term).
+ *   else   : sum_{i in D} v_i * (Q_j/q_i mod t)  mod t,
+ *            v_i = [d_i * (Q_j/q_i)^-1]_{q_i} taken in (-q_i/2, q_i/2]
+ * (fast basis conversion, no correction term, centred: the digit is lifted
+ * to its centred representative plus u Q_j with |u| < |D|/2.  The key switch
+ * multiplies the digit by the key's error; a digit lifted from [0, Q_j)
+ * carries a mean of about Q_j/2 in every coefficient, and that constant
+ * polynomial times the error sums the error's coefficients, which in the
+ * slots near 1 grows like N^1.5.)
  * out: [level+1+np][N].
  */
 void oc_modup_digit(const oc_ctx *c, const uint64_t *d, int level, int alpha, int j, uint64_t *out) {
@@ -416,15 +422,22 @@ void oc_modup_digit(const oc_ctx *c, const uint64_t *d, int level, int alpha, in
         }
         uint64_t m = c->mod[t];
         uint64_t qhat_t[OC_MAXP]; /* Q_j/q_i mod t */
+        uint64_t Qj_t = 1 % m;    /* Q_j mod t */
         for (int a = 0; a < nd; ++a) {
             uint64_t prod = 1 % m;
             for (int b = 0; b < nd; ++b)
                 if (b != a) prod = mulmod(prod, c->mod[lo + b] % m, m);
             qhat_t[a] = prod;
+            Qj_t = mulmod(Qj_t, c->mod[lo + a] % m, m);
         }
         for (size_t k = 0; k < N; ++k) {
             uint64_t acc = 0;
-            for (int a = 0; a < nd; ++a) acc = addmod(acc, mulmod(y[(size_t)a * N + k] % m, qhat_t[a], m), m);
+            for (int a = 0; a < nd; ++a) {
+                uint64_t qa = c->mod[lo + a], v = y[(size_t)a * N + k];
+                acc = addmod(acc, mulmod(v % m, qhat_t[a], m), m);
+                /* v > qa/2 stands for v - qa: subtract qa (Q_j/qa) = Q_j */
+                if (v > qa / 2) acc = submod(acc, Qj_t, m);
+            }
             o[k] = acc;
         }
     }
@@ -434,7 +447,13 @@ void oc_modup_digit(const oc_ctx *c, const uint64_t *d, int level, int alpha, in
 /*
  * ModDown: x over q_0..q_level then P (coefficient form) ->
  *   [x_i - FastBConv_{P -> q_i}(x_P)] * P^-1 mod q_i,  i <= level
- * with FastBConv_{P->q}(x)= sum_k [x_k (P/p_k)^-1]_{p_k} (P/p_k mod q).
+ * with the centred fast conversion
+ *   FastBConv_{P->q}(x) = sum_k v_k (P/p_k mod q),
+ *   v_k = [x_k (P/p_k)^-1]_{p_k} taken in (-p_k/2, p_k/2],
+ * which is x_P + u P with |u| < np/2, so the division by P rounds to the
+ * nearest integer up to a symmetric error: an unbiased rounding (a biased
+ * one, such as the same sum over [0, p_k), adds a constant times (c1 part) s
+ * to the decryption, whose slot values grow like N^1.5 in the slots near 1).
  */
 void oc_moddown(const oc_ctx *c, const uint64_t *x, int level, uint64_t *out) {
     size_t N = c->N;
@@ -467,7 +486,12 @@ void oc_moddown(const oc_ctx *c, const uint64_t *x, int level, uint64_t *out) {
         uint64_t *o = out + (size_t)i * N;
         for (size_t k = 0; k < N; ++k) {
             uint64_t conv = 0;
-            for (int a = 0; a < np; ++a) conv = addmod(conv, mulmod(y[(size_t)a * N + k] % q, phat_q[a], q), q);
+            for (int a = 0; a < np; ++a) {
+                uint64_t pa = c->mod[nq + a], v = y[(size_t)a * N + k];
+                conv = addmod(conv, mulmod(v % q, phat_q[a], q), q);
+                /* v > pa/2 stands for v - pa: subtract pa (P/pa) = P */
+                if (v > pa / 2) conv = submod(conv, Pq, q);
+            }
             o[k] = mulmod(submod(xi[k], conv, q), Pinv, q);
         }
     }

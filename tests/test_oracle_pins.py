@@ -231,39 +231,71 @@ def test_const_residue_of_large_values():
 
 
 def test_modup_identity_bigint():
-    o = small_oracle(logN=4, bits=(40, 41, 42, 43, 44), pbits=(61, 61), alpha=2)
+    """ModUp of digit j lifts the digit to its centred representative plus
+    u Q_j with |u| < |D_j|/2: X (the value over the extended basis, centred)
+    is congruent to the digit mod Q_j, |X| < |D_j| Q_j / 2, and X / Q_j has
+    mean ~0 (a lift over [0, Q_j) has mean about |D_j|/2 and fails here)."""
+    o = small_oracle(logN=7, bits=(40, 41, 42, 43, 44), pbits=(61, 61), alpha=2)
     rng = np.random.default_rng(4)
     level = 4
     d = np.stack([rng.integers(0, q, o.N, dtype=np.uint64) for q in o.q])
     ext_mods = o.q[:level + 1] + o.p
+    M = 1
+    for m in ext_mods:
+        M *= m
     for j in range(3):
         lo, hi = 2 * j, min(2 * j + 1, level)
         D = o.q[lo:hi + 1]
-        Qj = int(np.prod([float(x) for x in D])) if False else 1
+        Qj = 1
         for x in D:
             Qj *= x
         up = o.modup_digit(d, level, j)
+        ratios = []
         for k in range(o.N):
             X, _ = crt([up[t, k] for t in range(len(ext_mods))], ext_mods)
+            if X > M // 2:
+                X -= M
             dhat, _ = crt([d[i, k] for i in range(lo, hi + 1)], D)
             assert X % Qj == dhat
-            assert X < len(D) * Qj  # X = dhat + u Q_j, 0 <= u < |D_j|
+            assert 2 * abs(X) < len(D) * Qj
+            ratios.append(X / Qj)
+        assert abs(np.mean(ratios)) < 0.1 * len(D)
 
 
-def test_moddown_identity_bigint():
-    o = small_oracle(logN=4, bits=(40, 41, 42), pbits=(60, 61), alpha=1)
+@pytest.mark.parametrize("bits,pbits", [((40, 41, 42), (60, 61)), ((50, 51, 52), (40, 41, 42))])
+def test_moddown_is_unbiased_rounded_division_bigint(bits, pbits):
+    """ModDown divides by P with rounding to the nearest integer up to the
+    fast conversion's carry, which is centred: with X the value of x over
+    Q u P, E = x - y P over Q is a lift of x_P with |E| < n_P P / 2, so
+    |y - X/P| < (n_P + 1)/2, and the error y - X/P has mean ~0 (a floor-type
+    conversion over [0, p_k) has mean about -(n_P/2) and fails here)."""
+    o = small_oracle(logN=8, bits=bits, pbits=pbits, alpha=1)
     rng = np.random.default_rng(5)
     level = 2
     ext = o.q[:level + 1] + o.p
     x = np.stack([rng.integers(0, m, o.N, dtype=np.uint64) for m in ext])
     y = o.moddown(x, level)
-    P = o.p[0] * o.p[1]
+    P = 1
+    for pa in o.p:
+        P *= pa
+    Q = o.q[0] * o.q[1] * o.q[2]
+    errs = []
     for k in range(o.N):
-        # E = x - y*P over Q must be a lift of x_P smaller than |P|*P
-        E, Q = crt([(int(x[i, k]) - int(y[i, k]) * P) % o.q[i] for i in range(level + 1)], o.q[:level + 1])
+        E, _ = crt([(int(x[i, k]) - int(y[i, k]) * P) % o.q[i] for i in range(level + 1)], o.q[:level + 1])
+        if E > Q // 2:
+            E -= Q
         for a, pa in enumerate(o.p):
             assert E % pa == int(x[level + 1 + a, k])
-        assert E < len(o.p) * P
+        assert 2 * abs(E) < len(o.p) * P
+        X, _ = crt([int(x[t, k]) for t in range(len(ext))], ext)
+        Y, _ = crt([int(y[i, k]) for i in range(level + 1)], o.q[:level + 1])
+        d = (Y - X // P) % Q  # y - floor(X / P), as a small centred integer
+        if d > Q // 2:
+            d -= Q
+        errs.append(d - (X % P) / P)
+    errs = np.array(errs)
+    assert np.max(np.abs(errs)) < (len(o.p) + 1) / 2
+    assert abs(errs.mean()) < 0.1
 
 
 def test_rescale_is_rounded_division_bigint():
@@ -446,3 +478,23 @@ def test_double_hoisted_convolution_decrypts_to_the_convolution():
         assert not np.array_equal(outs[oc].data, ref.data)
         assert np.max(np.abs(got - exact)) < 2e-6
         assert np.max(np.abs(per_rot - exact)) < 1e-4
+
+
+def test_key_switch_error_is_not_heavy_tailed_in_the_slots():
+    """A rotation's decryption error, slot by slot, is spread like noise
+    (largest slot about 6x the mean at N = 2^12): the key switch's digits and
+    its division by P are centred.  With digits lifted over [0, Q_j) the error
+    gathers a constant-times-sum term whose canonical embedding peaks in the
+    slots near 1 (ratio near 50 here, growing like N^1.5)."""
+    from workloads import gen
+    from workloads.params import resnet20_tower, ParamSet
+    base = resnet20_tower()
+    ps = ParamSet("t", 12, base.q, base.p, alpha=3, delta_log2=30)
+    o = Oracle.from_params(ps)
+    sk = o.secret_key(9)
+    z = gen.uniform_slots(5, ps.N // 2)
+    ct = o.encrypt(o.encode(z, o.L, 2.0 ** 30), sk, 3)
+    g = o.galois_elt(1)
+    r = o.rotate(ct, 1, o.galois_key(sk, g))
+    e = np.abs(o.decrypt_decode(r, sk) - np.roll(z, -1))
+    assert e.max() < 12 * e.mean()
