@@ -311,6 +311,15 @@ extern "C" int ckc_ctx_create(int log_n, const uint64_t *q, int n_q, const uint6
     CKC_TRY(c->p_to_q.inv.upload(inv.data(), 8 * n_p));
     CKC_TRY(c->p_to_q.invp.upload(invp.data(), 8 * n_p));
     CKC_TRY(c->p_to_q.hat.upload(hat.data(), 8 * hat.size()));
+    // centring of the P -> Q conversion: (-P) 2^64 mod q_i, and p_k >> 1
+    std::vector<uint64_t> neg_p(n_q), p_half(n_p);
+    for (int i = 0; i < n_q; ++i) {
+        const uint64_t qi = c->mods[i];
+        neg_p[i] = hmul((qi - pmod[2 * i]) % qi, (uint64_t)(((u128)1 << 64) % qi), qi);
+    }
+    for (int a = 0; a < n_p; ++a) p_half[a] = p[a] >> 1;
+    CKC_TRY(c->p_to_q.neg_s.upload(neg_p.data(), 8 * neg_p.size()));
+    CKC_TRY(c->p_to_q.s_half.upload(p_half.data(), 8 * p_half.size()));
     // ModUp tables of every level, so that no key switch builds one later
     for (int l = 0; l < n_q; ++l) {
         int rc = CKC_OK;

@@ -22,6 +22,8 @@ struct BconvIn {
     size_t src_bs;
     int ns;
     const uint64_t *hat;   // [limbs][ns]
+    const uint64_t *neg_s; // [limbs] (-S) 2^64 mod t: centring correction
+    const uint64_t *s_half;  // [ns] s_k >> 1
     const uint64_t *copy;  // limbs [copy_lo, copy_hi) come from here (NTT form), untransformed
     size_t copy_bs;
     int copy_lo, copy_hi;

@@ -380,7 +380,8 @@ int ks_modup_b(ckc_ctx *c, const uint64_t *x, size_t xs, int nb, int level, uint
         const int lo = j * c->alpha, ns = t->ns;
         // digit j: its own limbs are those of x; every other limb of Q u P is
         // the conversion of the digit, transformed
-        const BconvIn in{coeff.u64() + size_t(lo) * N, size_t(nl) * N, ns, t->hat.u64(), x, xs, lo, lo + ns};
+        const BconvIn in{coeff.u64() + size_t(lo) * N, size_t(nl) * N, ns, t->hat.u64(), t->neg_s.u64(),
+                         t->s_half.u64(), x, xs, lo, lo + ns};
         CKC_TRY(ntt_forward_ex(c, digits + size_t(j) * nt * N, nt, ext, nb, dig_bs, s, -1, -1, &in, nullptr));
     }
     return CKC_OK;
@@ -419,7 +420,8 @@ int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint
     const LimbMap pmap{0, c->nq};
     CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * nb, size_t(np) * N, s, c->p_to_q.iscale.u64()));
     Ptrs none{};
-    const BconvIn in{pl.u64(), size_t(np) * N, np, c->p_to_q.hat.u64(), nullptr, 0, -1, -1};
+    const BconvIn in{pl.u64(), size_t(np) * N, np, c->p_to_q.hat.u64(), c->p_to_q.neg_s.u64(),
+                     c->p_to_q.s_half.u64(), nullptr, 0, -1, -1};
     const CombineOut co{acc.u64(), size_t(nl) * N, c->pinv.u64(), add0 ? *add0 : none, add1 ? *add1 : none, out0,
                         out1, add0 ? 1 : 0, add1 ? 1 : 0, perm_add0 ? perm : nullptr};
     CKC_TRY(ntt_forward_ex(c, conv.u64(), nl, qmap(), 2 * nb, size_t(nl) * N, s, -1, -1, &in, &co));
@@ -592,7 +594,8 @@ int moddown_b(ckc_ctx *c, const uint64_t *y, int n, int level, const Ptrs *add0,
     CKC_TRY(ntt_inverse(c, pl.u64(), np, pmap, 2 * n, size_t(np) * N, s, c->p_to_q.iscale.u64(), y + size_t(nl) * N,
                         size_t(nt) * N));
     Ptrs none{};
-    const BconvIn in{pl.u64(), size_t(np) * N, np, c->p_to_q.hat.u64(), nullptr, 0, -1, -1};
+    const BconvIn in{pl.u64(), size_t(np) * N, np, c->p_to_q.hat.u64(), c->p_to_q.neg_s.u64(),
+                     c->p_to_q.s_half.u64(), nullptr, 0, -1, -1};
     const CombineOut co{y, size_t(nt) * N, c->pinv.u64(), add0 ? *add0 : none, none, out0, out1, add0 ? 1 : 0, 0,
                         nullptr};
     return ntt_forward_ex(c, conv.u64(), nl, qmap(), 2 * n, size_t(nl) * N, s, -1, -1, &in, &co);

@@ -151,6 +151,8 @@ struct BconvTable {
     DevMem inv;     // [ns] (S/s_i)^-1 mod s_i
     DevMem invp;    // [ns] Shoup companions
     DevMem hat;     // [nt][ns] S/s_i mod t
+    DevMem neg_s;   // [nt] (-S) 2^64 mod t: the centring correction of the conversion
+    DevMem s_half;  // [ns] s_i >> 1: a source value above it stands for value - s_i
     std::vector<uint64_t> iscale_h;  // [ns][2] N^-1 (S/s_i)^-1 mod s_i and its Shoup companion
     DevMem iscale;  // device copy: the last multiply of an INTT that feeds the conversion
 };

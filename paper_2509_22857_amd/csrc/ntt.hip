@@ -435,9 +435,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(uint64_t *__restrict__ da
 }
 
 // first forward pass fed by fast basis conversion: word i of output limb t is
-//   sum_{k < ns} y_k[i] * hat[t][k]  mod q_t
-// (the table holds hat times 2^64 mod q_t, and the sum ends in one
-// Montgomery reduction, which removes the factor)
+//   sum_{k < ns} v_k * hat[t][k]  mod q_t,  v_k = y_k[i] taken in (-s_k/2, s_k/2]
+// (centred source values: the conversion is then the centred lift plus u S
+// with |u| < ns/2, an unbiased rounding for ModDown and a zero-mean digit for
+// ModUp; a value above s_k/2 stands for value - s_k, so each subtracts
+// S = s_k hat_k, counted and applied as one more product by -S.  The table
+// holds hat and -S times 2^64 mod q_t, and the sum ends in one Montgomery
+// reduction, which removes the factor)
 // from the pre-scaled coefficient-form source limbs y_k (y = x (S/s_k)^-1 mod
 // s_k); limbs in [copy_lo, copy_hi) are copied from `copy` instead (their NTT
 // form is already known) and left alone by the second pass.  The number of
@@ -469,14 +473,24 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restric
     const Prime P = primes[pi];
     const uint64_t *W = tw + size_t(pi) * N, *Wp = twp + size_t(pi) * N;
     const uint64_t *src = in.src + size_t(blockIdx.z) * in.src_bs;
-    uint64_t h[NS];
+    uint64_t h[NS], half[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) h[k] = in.hat[size_t(limb) * NS + k];
-    auto ld = [src, h, N, P](size_t i) {
+    for (int k = 0; k < NS; ++k) {
+        h[k] = in.hat[size_t(limb) * NS + k];
+        half[k] = in.s_half[k];
+    }
+    const uint64_t negS = in.neg_s[limb];
+    auto ld = [src, h, half, negS, N, P](size_t i) {
         accc acc{0, 0, 0, 0, 0};
+        uint64_t neg = 0;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) macc(acc, src[size_t(k) * N + i], h[k]);
-        return redc_accc<NS>(acc, P);
+        for (int k = 0; k < NS; ++k) {
+            const uint64_t v = src[size_t(k) * N + i];
+            macc(acc, v, h[k]);
+            neg += v > half[k] ? 1 : 0;
+        }
+        macc(acc, neg, negS);
+        return redc_accc<NS + 1>(acc, P);
     };
     auto st = [a](size_t i, uint64_t v) { a[i] = v; };
     if (radix16(logN))

@@ -176,15 +176,21 @@ const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc) {
         invp[i] = h_shoup(inv[i], qi);
     }
     LimbMap m{level + 1, c->nq};
+    std::vector<uint64_t> neg_s(nt), s_half(ns);
+    for (int i = 0; i < ns; ++i) s_half[i] = c->mods[lo + i] >> 1;
     for (int tt = 0; tt < nt; ++tt) {
         const uint64_t qt = c->mods[m.prime(tt)];
+        const uint64_t r64 = uint64_t(((unsigned __int128)1 << 64) % qt);
+        uint64_t S = 1 % qt;
         for (int i = 0; i < ns; ++i) {
             uint64_t prod = 1 % qt;
             for (int j = 0; j < ns; ++j)
                 if (j != i) prod = h_mulmod(prod, c->mods[lo + j] % qt, qt);
             // times 2^64 mod q_t: the conversion ends in a Montgomery reduction
-            hat[size_t(tt) * ns + i] = h_mulmod(prod, uint64_t(((unsigned __int128)1 << 64) % qt), qt);
+            hat[size_t(tt) * ns + i] = h_mulmod(prod, r64, qt);
+            S = h_mulmod(S, c->mods[lo + i] % qt, qt);
         }
+        neg_s[tt] = h_mulmod((qt - S) % qt, r64, qt);
     }
     t->ns = ns;
     t->nt = nt;
@@ -198,6 +204,8 @@ const BconvTable *modup_table(ckc_ctx *c, int level, int digit, int *rc) {
     if ((*rc = t->inv.upload(inv.data(), 8 * ns)) != CKC_OK) return nullptr;
     if ((*rc = t->invp.upload(invp.data(), 8 * ns)) != CKC_OK) return nullptr;
     if ((*rc = t->hat.upload(hat.data(), 8 * hat.size())) != CKC_OK) return nullptr;
+    if ((*rc = t->neg_s.upload(neg_s.data(), 8 * neg_s.size())) != CKC_OK) return nullptr;
+    if ((*rc = t->s_half.upload(s_half.data(), 8 * s_half.size())) != CKC_OK) return nullptr;
     const BconvTable *r = t.get();
     c->modup_tabs[key] = std::move(t);
     *rc = CKC_OK;
