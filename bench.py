@@ -358,9 +358,10 @@ def main():
                     help="slice-shared codebook (default) or one plaintext per tap")
     ap.add_argument("--pack", type=int, default=1,
                     help="images per ciphertext (slot packing, a separate labelled row; resnet20 only)")
-    ap.add_argument("--clients", type=int, default=4, help="serving: clients with their own keys")
-    ap.add_argument("--serve-rates", default="2,5,10,20", help="serving: Poisson arrival rates (req/s)")
-    ap.add_argument("--serve-requests", type=int, default=16, help="serving: requests per rate")
+    ap.add_argument("--clients", type=int, default=8, help="serving: clients with their own keys")
+    ap.add_argument("--serve-rates", default="0.2,0.5,2,10",
+                    help="serving: Poisson arrival rates (req/s), below and above capacity")
+    ap.add_argument("--serve-requests", type=int, default=32, help="serving: requests per rate")
     ap.add_argument("--serve-max-images", type=int, default=8, help="serving: images per batch")
     ap.add_argument("--serve-streams", type=int, default=3, help="serving: concurrent batches")
     args = ap.parse_args()
@@ -424,6 +425,33 @@ def main():
         else:
             tuned = tune_network(net, keys, sample, cache=TUNING_FILE, key=key, log=log, write=False)
         log(f"autotune ({args.tune}) in {time.time() - t0:.1f}s: { {k: v for k, v in tuned.items() if k != 'timings'} }")
+        # per-layer key-switching form: measured (fresh) or the stored marks
+        # for this workload and layout; the marks are part of the network
+        # description, so a change rebuilds the layers (the keys stay valid:
+        # both forms rotate by the same steps)
+        from paper_2509_22857_amd.autotune import tune_hoisting
+        from workloads.nets import set_hoisting
+        hkey = f"{key}/{args.layout}/hoisting"
+        marks = None
+        if args.tune == "fresh":
+            t0 = time.time()
+            marks = tune_hoisting(net, keys, len(sample), log=log)
+            data = json.load(open(args.tune_out)) if os.path.exists(args.tune_out) else {}
+            data[hkey] = marks
+            with open(args.tune_out, "w") as f:
+                json.dump(data, f, indent=1)
+            log(f"hoisting tuned in {time.time() - t0:.1f}s: {marks}")
+        elif os.path.exists(TUNING_FILE):
+            marks = json.load(open(TUNING_FILE)).get(hkey)
+        current = [ly.get("hoist", "double") for ly in spec["layers"] if ly["op"] == "conv"]
+        if marks and marks != current:
+            del net
+            torch.cuda.empty_cache()
+            set_hoisting(spec, marks)
+            net = GpuNetwork(ctx, spec, delta, delta, delta)
+            torch.cuda.synchronize()
+            log(f"layers rebuilt with the tuned hoisting marks {marks}")
+        tuned["hoisting"] = marks or current
     for w in range(args.warmup):
         t0 = time.time()
         out, _ = net.run(keys, cts, images_per_pass=args.images_per_pass)

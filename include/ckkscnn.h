@@ -122,6 +122,22 @@ int ckc_evk_add_rotations(ckc_ctx *ctx, const ckc_sk *sk, ckc_evk *evk, const in
 int ckc_sk_destroy(ckc_sk *sk);
 int ckc_evk_destroy(ckc_evk *evk);
 size_t ckc_evk_bytes(const ckc_evk *evk);
+/* A key group: the key set of every image of a batched layer call, so that
+ * one call (ckc_eval_conv, _quad_act, _dense, _avgpool2) evaluates images of
+ * different clients together -- the serving loop's continuous batching across
+ * clients of one network.  keys: n_keys key sets of one context (the caller
+ * keeps them alive while the group is used); key_of_img[i] (in [0, n_keys))
+ * is the key set of image i of the call, which must then have exactly n_img
+ * images (for pooling, n_img equal groups of ciphertexts).  The calls split
+ * their key-switching batches where the key set changes and share every
+ * other launch (the contraction over the layer's codebook); each image's
+ * ciphertexts are the same as with its own key set alone.  Destroy with
+ * ckc_evk_destroy (the member key sets are untouched); ckc_evk_bytes of a
+ * group is 0.  The single-ciphertext and *_many entry points refuse groups.
+ * Errors: CKC_EINVAL for null arguments, a key index out of range, a member
+ * that is itself a group or key sets of different shapes. */
+int ckc_evk_group_create(const ckc_evk *const *keys, int n_keys, const int32_t *key_of_img, int n_img,
+                         ckc_evk **group);
 
 /* ------------------------------------------------------------------ client
  * Encoding (Section 2.2): n <= N/2 real slot values (host array), scaled by

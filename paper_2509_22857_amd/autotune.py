@@ -9,6 +9,11 @@ times one whole pass of the network over a representative batch at every
 allowed value (the other knobs at their best so far), keeps the fastest, and
 checks that the outputs did not change.  The result can be cached in a JSON
 file keyed by the workload name.
+
+tune_hoisting picks the key-switching form of each 3x3 convolution (double
+or single hoisting) by timing both on the device; that choice is part of the
+network description (the two forms differ in the low bits), so it is
+returned as marks for the description rather than set in the library.
 """
 from __future__ import annotations
 
@@ -79,3 +84,50 @@ def tune_network(net, keys, inputs, knobs=None, cache: str | None = None, key: s
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)
     return result
+
+
+def tune_hoisting(net, keys, n_img: int, reps: int = 2, log=None) -> list:
+    """The faster key-switching form of every 3x3 convolution of `net`,
+    measured: each layer is timed in its current form and in the other one
+    (a layer built for the occasion and freed after) on n_img images of
+    ciphertexts at the level and scale the planner gives it.  The two forms
+    give different low bits (the mark belongs to the network description,
+    which both evaluators follow), so the result is a list of marks, one per
+    convolution in order (1x1 layers: "double", which they ignore), for
+    workloads.nets.set_hoisting.  Replaces the instruction-count model of
+    network.choose_hoisting by timings on the device at hand."""
+    import torch
+    ctx = net.ctx
+    marks = []
+    for ly, p, ent in zip(net.spec["layers"], net.plans, net.layers):
+        if ly["op"] != "conv":
+            continue
+        if ly["ksize"] == 1:
+            marks.append("double")
+            continue
+        cur = ly.get("hoist", "double")
+        other = "single" if cur == "double" else "double"
+        lay = net.layouts[ly["inp"]]
+        alt = ckks.layer_create_conv(ctx, lay, ly["out_ch"], ly["in_ch"], ly["ksize"], ly["stride"], ly["codebook"],
+                                     ly["idx"], ly["bias"], p.level, p.pt_scale, p.bias_scale, hoisting=other)
+        ins = [ctx.new_ct(p.level, 2, p.in_scale) for _ in range(n_img * ly["in_ch"])]
+        for c in ins:
+            c.buf.zero_()
+        outs = [ctx.new_ct(p.level) for _ in range(n_img * ly["out_ch"])]
+        times = {}
+        for form, layer in ((cur, ent["main"]), (other, alt)):
+            ckks.eval_conv(ctx, keys, layer, ins, n_img, outs)  # warm the arena
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ckks.eval_conv(ctx, keys, layer, ins, n_img, outs)
+            torch.cuda.synchronize()
+            times[form] = (time.perf_counter() - t0) / reps
+        alt.close()
+        del ins, outs
+        best = min(times, key=times.get)
+        marks.append(best)
+        if log:
+            log(f"hoisting {ly['name']} (level {p.level}, {ly['in_ch']}->{ly['out_ch']}): "
+                f"double {times['double'] * 1e3:.1f} ms, single {times['single'] * 1e3:.1f} ms -> {best}")
+    return marks

@@ -112,6 +112,7 @@ _SIGS = [
     ("ckc_variant_enable", C.c_int, [C.c_int]),
     ("ckc_variant_count", C.c_int, [C.c_char_p, C.POINTER(C.c_int64)]),
     ("ckc_variant_list", C.c_int, [C.c_char_p, C.c_size_t]),
+    ("ckc_evk_group_create", C.c_int, [C.POINTER(_vp), C.c_int, _i32p, C.c_int, C.POINTER(_vp)]),
     ("ckc_tune_set", C.c_int, [C.c_char_p, C.c_int]),
     ("ckc_tune_get", C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
     ("ckc_stream_release", C.c_int, [C.c_void_p]),
@@ -409,6 +410,37 @@ class Context:
         _check("ckc_mod_drop", lib().ckc_mod_drop(self.h, C.byref(sa), to_level, C.byref(so), _stream(stream)))
         out.update(so)
         return out
+
+
+class KeyGroup:
+    """A key group (ckc_evk_group_create): the key set of every image of a
+    batched layer call.  keys: KeyPair objects (kept alive here); key_of_img:
+    index into keys per image.  Usable wherever the layer calls take keys."""
+
+    def __init__(self, keys, key_of_img):
+        self.keys = list(keys)
+        self.key_of_img = [int(k) for k in key_of_img]
+        arr = (_vp * len(self.keys))(*[k.evk for k in self.keys])
+        idx = (C.c_int32 * len(self.key_of_img))(*self.key_of_img)
+        h = _vp()
+        _check("ckc_evk_group_create",
+               lib().ckc_evk_group_create(arr, len(self.keys), idx, len(self.key_of_img), C.byref(h)))
+        self.evk = h
+
+    def slice(self, i, j) -> "KeyGroup":
+        """The group of images i .. j - 1."""
+        return KeyGroup(self.keys, self.key_of_img[i:j])
+
+    def evk_bytes(self) -> int:
+        return 0
+
+    def __del__(self):
+        try:
+            if getattr(self, "evk", None):
+                lib().ckc_evk_destroy(self.evk)
+                self.evk = None
+        except Exception:
+            pass
 
 
 class KeyPair:

@@ -450,6 +450,33 @@ extern "C" size_t ckc_evk_bytes(const ckc_evk *e) {
     return n * e->key_words * 8;
 }
 
+extern "C" int ckc_evk_group_create(const ckc_evk *const *keys, int n_keys, const int32_t *key_of_img, int n_img,
+                                    ckc_evk **group) {
+    CKC_REQUIRE(keys && key_of_img && group && n_keys >= 1 && n_img >= 1, CKC_EINVAL, "null or empty argument");
+    auto g = std::make_unique<ckc_evk>();
+    for (int k = 0; k < n_keys; ++k) {
+        CKC_REQUIRE(keys[k] && !keys[k]->is_group(), CKC_EINVAL, "a key group's members are key sets");
+        CKC_REQUIRE(keys[k]->dnum == keys[0]->dnum && keys[k]->key_words == keys[0]->key_words, CKC_EINVAL,
+                    "key sets of one group come from one context");
+        g->members.push_back(keys[k]);
+    }
+    for (int i = 0; i < n_img; ++i) {
+        CKC_REQUIRE(key_of_img[i] >= 0 && key_of_img[i] < n_keys, CKC_EINVAL, "key index out of range");
+        g->key_of_img.push_back(key_of_img[i]);
+    }
+    g->dnum = keys[0]->dnum;
+    g->key_words = keys[0]->key_words;
+    *group = g.release();
+    return CKC_OK;
+}
+
+int check_evk_images(const ckc_evk *e, int n_img, const char *what) {
+    CKC_REQUIRE(!e->is_group() || int(e->key_of_img.size()) == n_img, CKC_EINVAL,
+                std::string(what) + ": the key group covers " + std::to_string(e->key_of_img.size()) +
+                    " images, the call " + std::to_string(n_img));
+    return CKC_OK;
+}
+
 // ======================================================================= client
 extern "C" int ckc_encode(ckc_ctx *c, const double *slots, size_t n, int level, double scale, ckc_pt *out,
                           void *stream) {
@@ -603,6 +630,7 @@ extern "C" int ckc_tensor(ckc_ctx *c, const ckc_ct *a, const ckc_ct *b, ckc_ct *
 }
 
 int relin_impl(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, ckc_ct *out, void *stream) {
+    CKC_REQUIRE(!evk || !evk->is_group(), CKC_EINVAL, "relin: a key group serves layer calls only");
     CKC_TRY(check_ct(c, in, "relin"));
     CKC_REQUIRE(evk && out && out->d, CKC_EINVAL, "null argument");
     CKC_REQUIRE(in->npoly == 3, CKC_ESHAPE, "relin needs a 3-poly ciphertext");
@@ -645,6 +673,7 @@ size_t relin_scratch_bytes(const ckc_ctx *c, int level) {
 
 extern "C" int ckc_rotate(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in, const int32_t *steps, int n_steps,
                           ckc_ct *out, void *stream) {
+    CKC_REQUIRE(!evk || !evk->is_group(), CKC_EINVAL, "rotate: a key group serves layer calls only");
     CKC_TRY(check_ct(c, in, "rotate"));
     CKC_REQUIRE(evk && out && (n_steps == 0 || steps), CKC_EINVAL, "null argument");
     CKC_REQUIRE(in->npoly == 2, CKC_ESHAPE, "rotation needs a 2-poly ciphertext");

@@ -199,7 +199,28 @@ struct ckc_evk {
     size_t key_words = 0;           // words per key: dnum * 2 * nprimes * N
     std::unique_ptr<DevMem> relin;  // may be null
     std::map<uint64_t, std::unique_ptr<DevMem>> galois;  // Galois element -> key
+    // a key group (ckc_evk_group_create): the key set of every image of a
+    // batched layer call, by image index; the member key sets stay their
+    // owners'
+    std::vector<const ckc_evk *> members;
+    std::vector<int32_t> key_of_img;
+    bool is_group() const { return !members.empty(); }
 };
+// key set of image `img` of a layer call (a plain key set serves every image)
+inline const ckc_evk *evk_of(const ckc_evk *e, int img) {
+    return e->is_group() ? e->members[size_t(e->key_of_img[size_t(img)])] : e;
+}
+// items first .. first + n - 1 of a layer call, item i of image i / per_img:
+// how many of them, from `first`, share one key set (at least 1)
+inline int key_run(const ckc_evk *e, int first, int n, int per_img) {
+    if (!e->is_group()) return n;
+    const int32_t k = e->key_of_img[size_t(first / per_img)];
+    int r = 1;
+    while (r < n && e->key_of_img[size_t((first + r) / per_img)] == k) ++r;
+    return r;
+}
+// a layer call on n_img images accepts a plain key set or a group of n_img images
+int check_evk_images(const ckc_evk *e, int n_img, const char *what);
 
 // ---------------------------------------------------------------- launchers
 // (all asynchronous on the given stream; data pointers are device pointers)

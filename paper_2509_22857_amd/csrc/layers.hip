@@ -806,6 +806,7 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
     CKC_FAULT_POINT();
     CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
     CKC_REQUIRE(L->kind == LK_CONV, CKC_EINVAL, "not a convolution layer");
+    CKC_TRY(check_evk_images(evk, n_img, "eval_conv"));
     if (n_img == 0) return CKC_OK;
     CKC_TRY(check_inputs(in, n_img * L->I, L->level, "eval_conv"));
     for (int i = 0; i < n_img * L->O; ++i) CKC_REQUIRE(out[i].d, CKC_EINVAL, "eval_conv: null output");
@@ -859,11 +860,14 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
         const uint64_t *bias_k = L->ext ? nullptr : (L->has_bias ? L->bias.u64() : nullptr);
         for (int ic0 = 0; ic0 < I; ic0 += ichunk) {
             const int nic = std::min(ichunk, I - ic0);
-            // rotations, in KS batches: (image in chunk, input channel of the chunk)
+            // rotations, in KS batches: (image in chunk, input channel of the
+            // chunk); a batch shares one key set (a key group splits it)
             const int total = ni_img * nic;
             const int ksb = tune_value(TK_KS_BATCH);
-            for (int b0 = 0; b0 < total; b0 += ksb) {
-                const int nb = std::min(ksb, total - b0);
+            for (int b0 = 0, nb = 0; b0 < total; b0 += nb) {
+                nb = std::min(ksb, total - b0);
+                if (evk->is_group()) nb = key_run(evk, img0 * nic + b0, nb, nic);
+                const ckc_evk *ek = evk_of(evk, img0 + b0 / nic);
                 Ptrs ip;
                 std::vector<Ptrs> dst(ntap);
                 for (int b = 0; b < nb; ++b) {
@@ -873,9 +877,9 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                         dst[t].p[b] = R.u64() + size_t(im) * r_img + (size_t(ii) * ntap + t) * lctw;
                 }
                 if (L->ext)
-                    CKC_TRY(hoisted_group_ext(c, evk, ip, nb, L->level, L->tap_step, dst, s));
+                    CKC_TRY(hoisted_group_ext(c, ek, ip, nb, L->level, L->tap_step, dst, s));
                 else
-                    CKC_TRY(hoisted_group(c, evk, ip, nb, L->level, L->tap_step, dst, s));
+                    CKC_TRY(hoisted_group(c, ek, ip, nb, L->level, L->tap_step, dst, s));
             }
             if (L->ioff.p) {
                 // contraction: groups of up to conv_imgs images x conv_outs outputs
@@ -1002,7 +1006,9 @@ extern "C" int ckc_eval_quad_act(ckc_ctx *c, const ckc_evk *evk, const ckc_layer
     CKC_FAULT_POINT();
     CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
     CKC_REQUIRE(L->kind == LK_ACT, CKC_EINVAL, "not an activation layer");
-    CKC_REQUIRE(evk->relin, CKC_ENOKEY, "no relinearisation key");
+    CKC_TRY(check_evk_images(evk, n_img, "eval_quad_act"));
+    for (int i = 0; i < (evk->is_group() ? n_img : 1); ++i)
+        CKC_REQUIRE(evk_of(evk, i)->relin, CKC_ENOKEY, "no relinearisation key");
     if (n_img == 0) return CKC_OK;
     const int total = n_img * L->C;
     CKC_TRY(check_inputs(in, total, L->level, "eval_quad_act"));
@@ -1017,8 +1023,10 @@ extern "C" int ckc_eval_quad_act(ckc_ctx *c, const ckc_evk *evk, const ckc_layer
     DevBuf D, digits;
     CKC_TRY(D.alloc(8 * 3 * pw * nbmax, s));
     CKC_TRY(digits.alloc(8 * N * nt * dnum * nbmax, s));
-    for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
-        const int nb = std::min(kMaxBatch, total - b0);
+    for (int b0 = 0, nb = 0; b0 < total; b0 += nb) {
+        // a batch shares one relinearisation key (a key group splits it)
+        nb = key_run(evk, b0, std::min(kMaxBatch, total - b0), L->C);
+        const ckc_evk *ek = evk_of(evk, b0 / L->C);
         Ptrs xp, bp, cp, a0, a1, o0, o1;
         for (int b = 0; b < nb; ++b) {
             const int ch = (b0 + b) % L->C;
@@ -1037,7 +1045,7 @@ extern "C" int ckc_eval_quad_act(ckc_ctx *c, const ckc_evk *evk, const ckc_layer
         }
         CKC_HIP(hipGetLastError());
         CKC_TRY(ks_modup_b(c, D.u64() + 2 * pw, 3 * pw, nb, L->level, digits.u64(), s));
-        CKC_TRY(ks_apply_b(c, digits.u64(), nb, L->level, evk->relin->u64(), 1, &a0, &a1, false, o0, o1, s));
+        CKC_TRY(ks_apply_b(c, digits.u64(), nb, L->level, ek->relin->u64(), 1, &a0, &a1, false, o0, o1, s));
         CKC_TRY(ew_b(c, EW_ADD, o0, o0, &cp, nb, 1, nl, s));
     }
     const double sc = (in[0].scale * in[0].scale) / L->a_absorb;
@@ -1108,6 +1116,7 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
     CKC_FAULT_POINT();
     CKC_REQUIRE(c && evk && L && in && out && n_img >= 0, CKC_EINVAL, "null argument");
     CKC_REQUIRE(L->kind == LK_DENSE, CKC_EINVAL, "not a dense layer");
+    CKC_TRY(check_evk_images(evk, n_img, "eval_dense"));
     if (n_img == 0) return CKC_OK;
     const int C = L->C, K = L->K;
     CKC_TRY(check_inputs(in, n_img * C, L->level, "eval_dense"));
@@ -1136,15 +1145,17 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
         }
         // rotation sums: S <- S + Rot_step(S), steps in order
         for (int32_t st : L->sum_steps) {
-            for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
-                const int nb = std::min(kMaxBatch, total - b0);
+            for (int b0 = 0, nb = 0; b0 < total; b0 += nb) {
+                // a batch shares one key set (a key group splits it)
+                nb = key_run(evk, img0 * C + b0, std::min(kMaxBatch, total - b0), C);
+                const ckc_evk *ek = evk_of(evk, img0 + b0 / C);
                 Ptrs sp, tp;
                 for (int b = 0; b < nb; ++b) {
                     sp.p[b] = Sb.u64() + size_t(b0 + b) * ctw;
                     tp.p[b] = Tb.u64() + size_t(b) * ctw;
                 }
                 std::vector<Ptrs> dst{tp};
-                CKC_TRY(hoisted_group(c, evk, sp, nb, L->level, std::vector<int32_t>{st}, dst, s));
+                CKC_TRY(hoisted_group(c, ek, sp, nb, L->level, std::vector<int32_t>{st}, dst, s));
                 CKC_TRY(ew_b(c, EW_ADD, sp, sp, &tp, nb, 2, nl, s));
             }
         }
@@ -1181,6 +1192,10 @@ extern "C" int ckc_eval_avgpool2(ckc_ctx *c, const ckc_evk *evk, const ckc_layou
     CKC_REQUIRE(c && evk && layout && in && out && n >= 0, CKC_EINVAL, "null argument");
     CKC_TRY(check_layout(c, layout));
     CKC_REQUIRE(layout->height % 2 == 0 && layout->width % 2 == 0, CKC_ESHAPE, "pool: odd grid");
+    // with a key group of G images, ciphertext i belongs to image i / (n / G)
+    const int G = evk->is_group() ? int(evk->key_of_img.size()) : 1;
+    CKC_REQUIRE(n % G == 0, CKC_EINVAL, "eval_avgpool2: ciphertexts not a multiple of the key group's images");
+    const int per_img = n / G > 0 ? n / G : 1;
     if (n == 0) return CKC_OK;
     CKC_TRY(check_inputs(in, n, in[0].level, "eval_avgpool2"));
     hipStream_t s = S(stream);
@@ -1191,8 +1206,9 @@ extern "C" int ckc_eval_avgpool2(ckc_ctx *c, const ckc_evk *evk, const ckc_layou
     const int nbmax = std::min(kMaxBatch, n);
     DevBuf T;
     CKC_TRY(T.alloc(8 * ctw * 3 * nbmax, s));
-    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
-        const int nb = std::min(kMaxBatch, n - b0);
+    for (int b0 = 0, nb = 0; b0 < n; b0 += nb) {
+        nb = key_run(evk, b0, std::min(kMaxBatch, n - b0), per_img);
+        const ckc_evk *ek = evk_of(evk, b0 / per_img);
         Ptrs ip, op;
         std::vector<Ptrs> dst(3);
         for (int b = 0; b < nb; ++b) {
@@ -1200,7 +1216,7 @@ extern "C" int ckc_eval_avgpool2(ckc_ctx *c, const ckc_evk *evk, const ckc_layou
             op.p[b] = out[b0 + b].d;
             for (int j = 0; j < 3; ++j) dst[j].p[b] = T.u64() + (size_t(b) * 3 + j) * ctw;
         }
-        CKC_TRY(hoisted_group(c, evk, ip, nb, level, steps, dst, s));
+        CKC_TRY(hoisted_group(c, ek, ip, nb, level, steps, dst, s));
         CKC_TRY(ew_b(c, EW_ADD, op, ip, &dst[0], nb, 2, nl, s));
         CKC_TRY(ew_b(c, EW_ADD, op, op, &dst[1], nb, 2, nl, s));
         CKC_TRY(ew_b(c, EW_ADD, op, op, &dst[2], nb, 2, nl, s));

@@ -97,6 +97,7 @@ extern "C" int ckc_rotate_many(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in,
                                int n_steps, ckc_ct *out, void *stream) {
     CKC_REQUIRE(c && evk && in && out && n >= 0 && n_steps >= 0 && (n_steps == 0 || steps), CKC_EINVAL,
                 "null argument");
+    CKC_REQUIRE(!evk->is_group(), CKC_EINVAL, "rotate_many: a key group serves layer calls only");
     if (n == 0 || n_steps == 0) return CKC_OK;
     CKC_TRY(check_batch(c, in, n, 2, "rotate_many"));
     const int level = in[0].level;
@@ -133,6 +134,7 @@ extern "C" int ckc_rotate_many(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *in,
 extern "C" int ckc_mul_relin_many(ckc_ctx *c, const ckc_evk *evk, const ckc_ct *a, const ckc_ct *b, int n,
                                   ckc_ct *out, void *stream) {
     CKC_REQUIRE(c && evk && a && b && out && n >= 0, CKC_EINVAL, "null argument");
+    CKC_REQUIRE(!evk->is_group(), CKC_EINVAL, "mul_relin_many: a key group serves layer calls only");
     if (n == 0) return CKC_OK;
     CKC_REQUIRE(evk->relin, CKC_ENOKEY, "mul_relin_many: no relinearisation key");
     CKC_TRY(check_batch(c, a, n, 2, "mul_relin_many", false));

@@ -317,7 +317,8 @@ class GpuNetwork:
         if images_per_pass and len(inputs) > images_per_pass:
             outs, tensors = [], None
             for i in range(0, len(inputs), images_per_pass):
-                o, tensors = self.run(keys, inputs[i:i + images_per_pass], stream, keep, hook)
+                ki = keys.slice(i, i + images_per_pass) if isinstance(keys, ckks.KeyGroup) else keys
+                o, tensors = self.run(ki, inputs[i:i + images_per_pass], stream, keep, hook)
                 outs.extend(o)
             return outs, tensors
         it = self.stages(keys, inputs, stream, keep, hook)

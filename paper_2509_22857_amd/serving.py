@@ -7,20 +7,26 @@ evaluation keys on the device, and runs a single host loop that
   * admits queued requests in arrival order while the HBM budget covers the
     working set of the batch they would start (keys are already resident),
     and sizes the scratch arena of the batch's stream for its largest call;
-  * merges queued requests of the same client and network into one batch
-    (their images share every key-switching and contraction launch);
+  * merges queued requests of the same network into one batch, whichever
+    clients sent them: a key group gives every image its client's key set,
+    so one client's images share its key-switching launches and all of them
+    share every other launch (the contraction over the network's codebook,
+    ModDown, rescale);
   * runs every admitted batch on its own HIP stream, one layer per step, with
     at most `window` layers enqueued ahead of the GPU, so batches admitted
     while others are on the device overlap with them;
   * retires a batch when its last layer's event has completed (or, when a
     library call of the batch failed, once its enqueued work has drained,
-    marking its requests failed with the error), frees its
-    stream's scratch arena (the library keeps one per stream at its largest
-    size otherwise) and the blocks torch keeps cached, and releases its memory
-    reservation, which lets the next queued requests in.
+    marking its requests failed with the error) and releases its memory
+    reservation, which lets the next queued requests in.  A stream keeps its
+    scratch arena for its next batch (freeing device memory synchronises the
+    whole device and would stall the batches still running); the arenas count
+    against the budget and are freed only when an admission does not fit
+    otherwise.
 
 Each image's result does not depend on which other requests shared its batch
-or ran beside it (every kernel computes each ciphertext independently), so a
+or ran beside it (every kernel computes each ciphertext independently, and a
+key-switching launch only ever holds ciphertexts of one key set), so a
 request gives the same ciphertexts alone and in the mix.  Latency is measured
 from arrival to the moment the host sees the batch's last event complete.
 """
@@ -59,6 +65,7 @@ class _Batch:
     stream: object
     gen: object
     reserve: int
+    keys: object = None     # the batch's key set or key group
     events: collections.deque = field(default_factory=collections.deque)
     finished: bool = False
     result: object = None
@@ -77,6 +84,7 @@ class Server:
         self.max_images = max_images
         self.window = window
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.arena = {st: 0 for st in self.streams}  # scratch arena bytes each stream holds
         self.keys = {}          # (client, net) -> KeyPair
         self.reserved = 0
         self.key_bytes = 0
@@ -109,7 +117,7 @@ class Server:
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             progressed = False
-            # ---- admission: FIFO head, merged with later requests of the same client and network
+            # ---- admission: FIFO head, merged with later requests of the same network
             while queue and free_streams and not blocked:
                 head = queue[0]
                 net = self.networks[head.net]
@@ -120,48 +128,63 @@ class Server:
                     head.done = float("nan")
                     self.stats["rejected"] += 1
                     continue
-                # the head plus later requests of the same client and network,
-                # as many as the image limit and the whole budget allow
+                # the head plus later requests of the same network (any
+                # client), as many as the image limit and the budget allow
                 group, n_img = [], 0
                 for r in list(queue):
-                    if r.client == head.client and r.net == head.net and n_img + len(r.inputs) <= self.max_images \
+                    if r.net == head.net and n_img + len(r.inputs) <= self.max_images \
                             and net.working_set_bytes(n_img + len(r.inputs)) <= room:
                         group.append(r)
                         n_img += len(r.inputs)
-                need = net.working_set_bytes(n_img)
-                if self.reserved + need > self.budget - self.key_bytes:
-                    if waiting != head.rid:
-                        self.stats["waits_for_memory"] += 1  # requests that had to wait
-                        waiting = head.rid
-                    break
                 stream = free_streams[-1]
-                # the batch's largest scratch is allocated now, so its calls
-                # allocate nothing while it runs (part of the reservation).
-                # The budget counts bytes, not contiguous blocks: when the
-                # device cannot hand out the block after all, the group stays
-                # queued and admission resumes after the next retirement (or,
-                # with nothing running, after the cached blocks are returned)
-                try:
-                    ckks.stream_reserve(net.scratch_bytes(n_img), stream)
-                except ckks.CkcError as err:
-                    if "CKC_ENOMEM" not in str(err):
-                        raise
-                    self.stats["reserve_retries"] += 1
-                    ckks.stream_release(stream)
-                    torch.cuda.empty_cache()
-                    if running:
-                        blocked = True
+                scratch = net.scratch_bytes(n_img)
+                held = net.working_set_bytes(n_img) - scratch  # the batch's ciphertexts
+                grow = max(0, scratch - self.arena[stream])
+
+                def fits():
+                    return self.reserved + sum(self.arena.values()) + held + grow <= room
+                if not fits():
+                    # idle streams' arenas go first
+                    for st in free_streams:
+                        if st is not stream and self.arena[st] > 0:
+                            ckks.stream_release(st)
+                            self.arena[st] = 0
+                            self.stats["arena_releases"] += 1
+                    if not fits():
+                        if waiting != head.rid:
+                            self.stats["waits_for_memory"] += 1  # requests that had to wait
+                            waiting = head.rid
                         break
-                    if self.stats["reserve_retries_idle"] >= 1:
-                        # nothing else holds memory and it still does not fit
-                        queue.popleft()
-                        head.done = float("nan")
-                        head.error = str(err)
-                        self.stats["rejected"] += 1
-                        self.stats["reserve_retries_idle"] = 0
+                # the batch's largest scratch is allocated now, so its calls
+                # allocate nothing while it runs.  The budget counts bytes, not
+                # contiguous blocks: when the device cannot hand out the block
+                # after all, the group stays queued and admission resumes
+                # after the next retirement (or, with nothing running, after
+                # the cached blocks are returned)
+                if grow > 0:
+                    try:
+                        ckks.stream_reserve(scratch, stream)
+                        self.arena[stream] = scratch
+                    except ckks.CkcError as err:
+                        if "CKC_ENOMEM" not in str(err):
+                            raise
+                        self.stats["reserve_retries"] += 1
+                        ckks.stream_release(stream)
+                        self.arena[stream] = 0
+                        torch.cuda.empty_cache()
+                        if running:
+                            blocked = True
+                            break
+                        if self.stats["reserve_retries_idle"] >= 1:
+                            # nothing else holds memory and it still does not fit
+                            queue.popleft()
+                            head.done = float("nan")
+                            head.error = str(err)
+                            self.stats["rejected"] += 1
+                            self.stats["reserve_retries_idle"] = 0
+                            continue
+                        self.stats["reserve_retries_idle"] += 1
                         continue
-                    self.stats["reserve_retries_idle"] += 1
-                    continue
                 self.stats["reserve_retries_idle"] = 0
                 free_streams.pop()
                 for r in group:
@@ -171,10 +194,17 @@ class Server:
                 # inputs were written on the submitting stream
                 stream.wait_stream(torch.cuda.current_stream())
                 inputs = [row for r in group for row in r.inputs]
-                b = _Batch(next_bid, head.net, head.client, group, stream,
-                           net.stages(self.keys[(head.client, head.net)], inputs, stream=stream), need)
+                members = sorted({r.client for r in group})
+                if len(members) == 1:
+                    bkeys = self.keys[(members[0], head.net)]
+                else:
+                    bkeys = ckks.KeyGroup([self.keys[(c, head.net)] for c in members],
+                                          [members.index(r.client) for r in group for _ in r.inputs])
+                    self.stats["mixed_batches"] += 1
+                b = _Batch(next_bid, head.net, ",".join(members), group, stream,
+                           net.stages(bkeys, inputs, stream=stream), held, bkeys)
                 next_bid += 1
-                self.reserved += need
+                self.reserved += held
                 running.append(b)
                 max_running = max(max_running, len(running))
                 progressed = True
@@ -214,12 +244,10 @@ class Server:
                             i += len(r.inputs)
                             r.done = t_done
                     running.remove(b)
-                    # the stream's scratch arena and the blocks torch keeps
-                    # cached go with the reservation
-                    ckks.stream_release(b.stream)
-                    torch.cuda.empty_cache()
+                    # the stream keeps its arena for its next batch
                     free_streams.append(b.stream)
                     self.reserved -= b.reserve
+                    b.keys = None
                     blocked = False
                     progressed = True
             if not progressed:
@@ -228,6 +256,11 @@ class Server:
                 if pending and not queue and not running:
                     wait = max(0.0, min(0.05, pending[0].arrival - (clock() - t0)))
                 time.sleep(wait)
+        # the run is over: the streams' arenas go back to the device
+        for st in self.streams:
+            if self.arena[st] > 0:
+                ckks.stream_release(st)
+                self.arena[st] = 0
         served = [r for r in requests if r.done is not None and not math.isnan(r.done)]
         lat = np.array([r.done - r.arrival for r in served]) if served else np.zeros(1)
         span = (max(r.done for r in served) - min(r.arrival for r in requests)) if served else float("nan")
@@ -238,6 +271,8 @@ class Server:
             "rejected": int(self.stats["rejected"]),
             "failed": int(self.stats["failed"]),
             "waits_for_memory": int(self.stats["waits_for_memory"]),
+            "mixed_client_batches": int(self.stats["mixed_batches"]),
+            "arena_releases": int(self.stats["arena_releases"]),
             "reserve_retries": int(self.stats["reserve_retries"]),
             "batches": next_bid,
             "max_concurrent_batches": max_running,

@@ -392,3 +392,41 @@ def test_slice_shared_resnet_bit_exact():
     for ly, e1, e2 in zip(spec["layers"], gnet.layers, full.layers):
         if ly["op"] == "conv" and ly["ksize"] == 3:
             assert e1["main"].nbytes() < 0.4 * e2["main"].nbytes(), ly["name"]
+
+
+def test_tuned_hoisting_marks_bit_exact_and_replayed():
+    """The per-layer key-switching form picked by timing both forms on the
+    device (autotune.tune_hoisting) goes into the network description; the
+    network with those marks is bit-exact with the oracle following the same
+    marks, and a HIP-graph replay of a 2-image pass equals the eager pass."""
+    import torch
+    from paper_2509_22857_amd.autotune import tune_hoisting
+    from paper_2509_22857_amd.graph import GraphedPass
+    from paper_2509_22857_amd.network import GpuNetwork
+    spec = nets.vgg_spec(seed=4, widths=(4, 8, 8), pool_after=(0,), classes=5, image=(3, 16, 16), k=6, calib=4)
+    ps = small_tower(logN=12, levels=5)
+    D = 2.0 ** 30
+    print("[tuned_hoisting] N=2^12 small VGG", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 71)
+    marks = tune_hoisting(gnet, keys, 2)
+    assert len(marks) == sum(ly["op"] == "conv" for ly in spec["layers"])
+    assert set(marks) <= {"single", "double"}
+    nets.set_hoisting(spec, marks)
+    gnet = GpuNetwork(ctx, spec, D, D, D)
+    from oracle.network import OracleNetwork
+    onet = OracleNetwork(o, spec, D, D, D)
+    imgs = gen.images(72, 2, 3, 16, 16)
+    gin = gnet.encrypt_images(keys, imgs, 1500)
+    gout, _ = gnet.run(keys, gin)
+    oout, _ = onet.run(sk, onet.encrypt_image(sk, imgs[0], 1500), rlk, gk)
+    for j, (a, b) in enumerate(zip(gout[0], oout)):
+        assert np.array_equal(_coeff(ctx, a), b.data), j
+    torch.cuda.synchronize()
+    want = [[c.buf.clone() for c in row] for row in gout]
+    gp = GraphedPass(gnet, keys, 2)
+    for rep in range(2):
+        got = gp.run(gin)
+        torch.cuda.synchronize()
+        for wrow, grow in zip(want, got):
+            for w, g in zip(wrow, grow):
+                assert torch.equal(w, g.buf), rep
