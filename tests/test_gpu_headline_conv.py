@@ -23,7 +23,7 @@ def _digest(a) -> str:
     return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).hexdigest()
 
 
-@pytest.mark.parametrize("name", ["headline_conv_N65536.json"])
+@pytest.mark.parametrize("name", ["headline_conv_N65536.json", "headline_conv_slice_N65536.json"])
 def test_headline_conv_layer_matches_oracle_digests(name):
     from paper_2509_22857_amd import ckks
     from paper_2509_22857_amd.ckks import Context
