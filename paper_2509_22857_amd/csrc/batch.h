@@ -17,6 +17,7 @@ int copy_limbs(const uint64_t *src, size_t src_ps, uint64_t *dst, size_t dst_ps,
 // ntt_forward_ex): output limb t, word i = sum_k src[b][k][i] hat[t ns + k]
 // mod q_t, with src pre-scaled by (S/s_k)^-1 in coefficient form.
 constexpr int kMaxBconv = 8;
+constexpr int kMaxDnum = 16;  // key-switching digits
 struct BconvIn {
     const uint64_t *src;   // [batch][ns][N]
     size_t src_bs;
@@ -27,6 +28,10 @@ struct BconvIn {
     const uint64_t *copy;  // limbs [copy_lo, copy_hi) come from here (NTT form), untransformed
     size_t copy_bs;
     int copy_lo, copy_hi;
+    // with use_copyp, batch b's copied limbs come from copyp.p[b] + copy_off instead
+    Ptrs copyp;
+    size_t copy_off;
+    int use_copyp;
 };
 // ModDown epilogue of a forward NTT over [2 nb][nl][N] (batch z = 2 b + p):
 //   out_p.p[b][i][k] = (acc[z][i][k] - ntt[z][i][k]) P^-1 + add_p.p[b][i][perm0?(k)]
@@ -44,12 +49,28 @@ struct CombineOut {
 int ntt_forward_ex(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t bs, hipStream_t s,
                    int skip_lo, int skip_hi, const BconvIn *bin, const CombineOut *cout);
 
+// ModUp's forward transforms of every digit of nb inputs: digits [b][dnum][nt][N]
+// (nt = level + 1 + n_P), digit j converted from the pre-scaled coefficient-
+// form limbs coeff[b][j alpha ..] (stride coeff_bs) by table tabs[j], its own
+// limbs copied from the NTT-form input x[b] (stride xs).  One first-pass launch
+// covers all full digits (a partial last digit has one of its own) and one
+// second-pass launch covers every digit.
+struct BconvTable;
+int ntt_modup(const ckc_ctx *c, uint64_t *digits, int level, int nb, const uint64_t *coeff, size_t coeff_bs,
+              const uint64_t *x, size_t xs, const BconvTable *const *tabs, hipStream_t s,
+              const Ptrs *xp = nullptr, size_t x_off = 0);
+// the inverse transform reading batch b's input from src.p[b] + src_off
+int ntt_inverse_ptrs(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
+                     hipStream_t s, const uint64_t *scale2, const Ptrs &src, size_t src_off);
+
 // dst (contiguous, stride dst_bs words) <- src.p[b] + src_off for b < nb, `words` words each.
 int gather(const Ptrs &src, size_t src_off, uint64_t *dst, size_t dst_bs, size_t words, int nb, hipStream_t s);
 
 // Batched ModUp of nb polynomials x[b] = x + b*xs (NTT form, level+1 limbs)
 // into digits[b] = digits + b*dnum*nt*N, layout [dnum][nt][N] (NTT form).
 int ks_modup_b(ckc_ctx *c, const uint64_t *x, size_t xs, int nb, int level, uint64_t *digits, hipStream_t s);
+// the same with input b at xp.p[b] + x_off (no gathered copy)
+int ks_modup_p(ckc_ctx *c, const Ptrs &xp, size_t x_off, int nb, int level, uint64_t *digits, hipStream_t s);
 
 // Batched key inner product + ModDown.  For b < nb:
 //   u = ModDown(sum_j sigma_g(digit_j[b]) * key_j)

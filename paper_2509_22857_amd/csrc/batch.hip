@@ -33,8 +33,6 @@ __global__ void k_copy_pp(Ptrs src, Ptrs dst, size_t words) {
         d[k] = sp[k];
 }
 
-constexpr int kMaxDnum = 16;
-
 // key inner product with key reuse across the batch.  A Galois key is stored
 // permuted by sigma_g^-1 (key'[m] = key[pi_g^-1(m)]), and since sigma_g acts on
 // NTT-form values as a permutation commuting with pointwise products,
@@ -361,30 +359,41 @@ int gather(const Ptrs &src, size_t src_off, uint64_t *dst, size_t dst_bs, size_t
     return CKC_OK;
 }
 
-int ks_modup_b(ckc_ctx *c, const uint64_t *x, size_t xs, int nb, int level, uint64_t *digits, hipStream_t s) {
+namespace {
+// ModUp of nb inputs, read contiguously (x + b xs) or through a pointer
+// table (xp->p[b] + x_off)
+int ks_modup_impl(ckc_ctx *c, const uint64_t *x, size_t xs, const Ptrs *xp, size_t x_off, int nb, int level,
+                  uint64_t *digits, hipStream_t s) {
     const size_t N = c->N;
-    const int nl = level + 1, nt = nl + c->np, dnum = c->dnum_at(level);
+    const int nl = level + 1, dnum = c->dnum_at(level);
     CKC_REQUIRE(dnum <= kMaxDnum, CKC_EUNSUPPORTED, "too many key-switching digits");
-    const size_t dig_bs = size_t(dnum) * nt * N;
     int rc = CKC_OK;
     const uint64_t *scale = modup_scale(c, level, &rc);
     if (!scale) return rc;
     // coefficient form, already multiplied by each limb's (D_j / q_i)^-1
     DevBuf coeff;
     CKC_TRY(coeff.alloc(8 * N * nl * nb, s));
-    CKC_TRY(ntt_inverse(c, coeff.u64(), nl, qmap(), nb, size_t(nl) * N, s, scale, x, xs));
-    const LimbMap ext{nl, c->nq};
+    if (xp)
+        CKC_TRY(ntt_inverse_ptrs(c, coeff.u64(), nl, qmap(), nb, size_t(nl) * N, s, scale, *xp, x_off));
+    else
+        CKC_TRY(ntt_inverse(c, coeff.u64(), nl, qmap(), nb, size_t(nl) * N, s, scale, x, xs));
+    // digit j: its own limbs are those of x; every other limb of Q u P is the
+    // conversion of the digit, transformed (all digits in one launch pair)
+    const BconvTable *tabs[kMaxDnum];
     for (int j = 0; j < dnum; ++j) {
-        const BconvTable *t = modup_table(c, level, j, &rc);
-        if (!t) return rc;
-        const int lo = j * c->alpha, ns = t->ns;
-        // digit j: its own limbs are those of x; every other limb of Q u P is
-        // the conversion of the digit, transformed
-        const BconvIn in{coeff.u64() + size_t(lo) * N, size_t(nl) * N, ns, t->hat.u64(), t->neg_s.u64(),
-                         t->s_half.u64(), x, xs, lo, lo + ns};
-        CKC_TRY(ntt_forward_ex(c, digits + size_t(j) * nt * N, nt, ext, nb, dig_bs, s, -1, -1, &in, nullptr));
+        tabs[j] = modup_table(c, level, j, &rc);
+        if (!tabs[j]) return rc;
     }
-    return CKC_OK;
+    return ntt_modup(c, digits, level, nb, coeff.u64(), size_t(nl) * N, x, xs, tabs, s, xp, x_off);
+}
+}  // namespace
+
+int ks_modup_b(ckc_ctx *c, const uint64_t *x, size_t xs, int nb, int level, uint64_t *digits, hipStream_t s) {
+    return ks_modup_impl(c, x, xs, nullptr, 0, nb, level, digits, s);
+}
+
+int ks_modup_p(ckc_ctx *c, const Ptrs &xp, size_t x_off, int nb, int level, uint64_t *digits, hipStream_t s) {
+    return ks_modup_impl(c, nullptr, 0, &xp, x_off, nb, level, digits, s);
 }
 
 int ks_apply_b(ckc_ctx *c, const uint64_t *digits, int nb, int level, const uint64_t *key, uint64_t g,
@@ -475,12 +484,11 @@ int hoisted_group(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, int le
     const size_t pw = size_t(nl) * N;
     bool any = false;
     for (int32_t st : steps) any |= galois_element(c, st) != 1;
-    DevBuf x1, digits;
+    DevBuf digits;
     if (any) {
-        CKC_TRY(x1.alloc(8 * pw * nb, s));
-        CKC_TRY(gather(in, pw, x1.u64(), pw, pw, nb, s));
+        // ModUp of every input's c1, read in place
         CKC_TRY(digits.alloc(8 * N * nt * dnum * nb, s));
-        CKC_TRY(ks_modup_b(c, x1.u64(), pw, nb, level, digits.u64(), s));
+        CKC_TRY(ks_modup_p(c, in, pw, nb, level, digits.u64(), s));
     }
     for (size_t si = 0; si < steps.size(); ++si) {
         const uint64_t g = galois_element(c, steps[si]);
@@ -506,12 +514,11 @@ int hoisted_group_ext(ckc_ctx *c, const ckc_evk *evk, const Ptrs &in, int nb, in
     const size_t pw = size_t(nl) * N;
     bool any = false;
     for (int32_t st : steps) any |= galois_element(c, st) != 1;
-    DevBuf x1, digits;
+    DevBuf digits;
     if (any) {
-        CKC_TRY(x1.alloc(8 * pw * nb, s));
-        CKC_TRY(gather(in, pw, x1.u64(), pw, pw, nb, s));
+        // ModUp of every input's c1, read in place
         CKC_TRY(digits.alloc(8 * N * nt * dnum * nb, s));
-        CKC_TRY(ks_modup_b(c, x1.u64(), pw, nb, level, digits.u64(), s));
+        CKC_TRY(ks_modup_p(c, in, pw, nb, level, digits.u64(), s));
     }
     const LimbMap ext{nl, c->nq};
     // rotations whose outputs sit at one offset from the first step's for

@@ -447,22 +447,22 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(uint64_t *__restrict__ da
 // form is already known) and left alone by the second pass.  The number of
 // sources NS is a template argument: with a run-time count the compiler
 // executed every one of the kMaxBconv possible products under a mask.
+// Body of the pass for output block `a` (its limbs, stride N) and batch
+// index b of the sources.
 template <int NS>
-__global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restrict__ data, size_t bs, LimbMap map,
-                                                             const Prime *__restrict__ primes,
-                                                             const uint64_t *__restrict__ tw,
-                                                             const uint64_t *__restrict__ twp, int logN,
-                                                             BconvIn in) {
-    __shared__ uint64_t s[kElems + kElems / 16];
+__device__ __forceinline__ void bconv_cols(uint64_t *a0, int b, const BconvIn &in, LimbMap map,
+                                           const Prime *__restrict__ primes, const uint64_t *__restrict__ tw,
+                                           const uint64_t *__restrict__ twp, int logN, uint64_t *s) {
     const int limb = blockIdx.y;
     const size_t N = size_t(1) << logN;
-    uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N;
+    uint64_t *a = a0 + size_t(limb) * N;
     if (limb >= in.copy_lo && limb < in.copy_hi) {
         // this workgroup's words of the limb, in the same (row, column) tiling
         const int logN1 = logN - kLogN2;
         const int logC = 12 - logN1;
         const int col0 = blockIdx.x << logC;
-        const uint64_t *cp = in.copy + size_t(blockIdx.z) * in.copy_bs + size_t(limb) * N;
+        const uint64_t *cp =
+            (in.use_copyp ? in.copyp.p[b] + in.copy_off : in.copy + size_t(b) * in.copy_bs) + size_t(limb) * N;
         for (int e = threadIdx.x; e < kElems; e += kThreads) {
             const size_t i = size_t(e >> logC) * kN2 + col0 + (e & ((1 << logC) - 1));
             a[i] = cp[i];
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restric
     const int pi = map.prime(limb);
     const Prime P = primes[pi];
     const uint64_t *W = tw + size_t(pi) * N, *Wp = twp + size_t(pi) * N;
-    const uint64_t *src = in.src + size_t(blockIdx.z) * in.src_bs;
+    const uint64_t *src = in.src + size_t(b) * in.src_bs;
     uint64_t h[NS], half[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -499,13 +499,62 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restric
         cols_generic(ld, st, false, s, W, Wp, P.q, logN, blockIdx.x << (12 - (logN - kLogN2)), 0, 0);
 }
 
+template <int NS>
+__global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restrict__ data, size_t bs, LimbMap map,
+                                                             const Prime *__restrict__ primes,
+                                                             const uint64_t *__restrict__ tw,
+                                                             const uint64_t *__restrict__ twp, int logN,
+                                                             BconvIn in) {
+    __shared__ uint64_t s[kElems + kElems / 16];
+    bconv_cols<NS>(data + size_t(blockIdx.z) * bs, int(blockIdx.z), in, map, primes, tw, twp, logN, s);
+}
+
+// The same first pass for the ModUp of `ndig` digits of NS primes each in
+// one launch: batch index z = b ndig + j is digit j of input b, written to
+// data + b bs + j nt N (the digits' layout [b][dnum][nt][N]); digit j reads
+// the pre-scaled coefficient-form limbs j NS .. j NS + NS - 1 of input b and
+// copies its own limbs from the NTT-form input.
+struct DigitsIn {
+    const uint64_t *src;   // [batch][l+1][N], stride src_bs
+    size_t src_bs;
+    const uint64_t *copy;  // [batch][l+1][N] NTT form, stride copy_bs
+    size_t copy_bs;
+    int ndig, nt;
+    const uint64_t *hat[kMaxDnum], *neg_s[kMaxDnum], *s_half[kMaxDnum];
+    Ptrs copyp;  // with use_copyp, input b's NTT form at copyp.p[b] + copy_off
+    size_t copy_off;
+    int use_copyp;
+};
+template <int NS>
+__global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv_dig(uint64_t *__restrict__ data, size_t bs,
+                                                                 LimbMap map, const Prime *__restrict__ primes,
+                                                                 const uint64_t *__restrict__ tw,
+                                                                 const uint64_t *__restrict__ twp, int logN,
+                                                                 DigitsIn d) {
+    __shared__ uint64_t s[kElems + kElems / 16];
+    const int z = blockIdx.z, b = z / d.ndig, j = z - b * d.ndig, lo = j * NS;
+    const size_t N = size_t(1) << logN;
+    const BconvIn in{d.src + size_t(lo) * N, d.src_bs, NS, d.hat[j], d.neg_s[j], d.s_half[j], d.copy, d.copy_bs,
+                     lo, lo + NS, d.copyp, d.copy_off, d.use_copyp};
+    bconv_cols<NS>(data + size_t(b) * bs + size_t(j) * d.nt * N, b, in, map, primes, tw, twp, logN, s);
+}
+
+// Second forward pass.  Limbs in [skip_lo, skip_hi) are left alone; with
+// dig_n > 0 the batch is the digits of a ModUp ([b][dig_n][nt][N], z = b
+// dig_n + j) and digit j leaves its own limbs [j dig_alpha, min((j + 1)
+// dig_alpha, dig_nl)) alone instead.
 __global__ __launch_bounds__(kThreads) void k_fwd_rows(uint64_t *__restrict__ data, size_t bs, LimbMap map,
                                                        const Prime *__restrict__ primes,
                                                        const uint64_t *__restrict__ tw,
                                                        const uint64_t *__restrict__ twp, int logN, int skip_lo,
-                                                       int skip_hi) {
+                                                       int skip_hi, int dig_n, int dig_alpha, int dig_nl) {
     __shared__ uint64_t s[kElems + kElems / 16];
     const int limb = blockIdx.y;
+    if (dig_n > 0) {
+        const int j = int(blockIdx.z) % dig_n;
+        skip_lo = j * dig_alpha;
+        skip_hi = min(skip_lo + dig_alpha, dig_nl);
+    }
     if (limb >= skip_lo && limb < skip_hi) return;
     const int pi = map.prime(limb);
     const uint64_t q = primes[pi].q;
@@ -555,12 +604,14 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows_combine(const uint64_t *_
         rows_generic(ld, st, false, s, W, Wp, q, N, base);
 }
 
-// first inverse pass, reading from src (may equal data: in place)
+// first inverse pass, reading from src (may equal data: in place), or with
+// use_srcp from srcp.p[z] + src_off
 __global__ __launch_bounds__(kThreads) void k_inv_rows(uint64_t *__restrict__ data, size_t bs,
                                                        const uint64_t *src, size_t src_bs, LimbMap map,
                                                        const Prime *__restrict__ primes,
                                                        const uint64_t *__restrict__ itw,
-                                                       const uint64_t *__restrict__ itwp, int logN) {
+                                                       const uint64_t *__restrict__ itwp, int logN, Ptrs srcp,
+                                                       size_t src_off, int use_srcp) {
     __shared__ uint64_t s[kElems + kElems / 16];
     const int limb = blockIdx.y;
     const int pi = map.prime(limb);
@@ -568,7 +619,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(uint64_t *__restrict__ da
     const size_t N = size_t(1) << logN;
     const size_t base = size_t(blockIdx.x) * kElems;
     uint64_t *a = data + size_t(blockIdx.z) * bs + size_t(limb) * N + base;
-    const uint64_t *in = src + size_t(blockIdx.z) * src_bs + size_t(limb) * N + base;
+    const uint64_t *in =
+        (use_srcp ? srcp.p[blockIdx.z] + src_off : src + size_t(blockIdx.z) * src_bs) + size_t(limb) * N + base;
     const uint64_t *W = itw + size_t(pi) * N, *Wp = itwp + size_t(pi) * N;
     auto ld = [in](int e) { return in[e]; };
     auto st = [a](int e, uint64_t v) { a[e] = v; };
@@ -637,7 +689,61 @@ int ntt_forward_ex(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int n
                                c->twp.u64(), c->logN, *cout);
         else
             hipLaunchKernelGGL(k_fwd_rows, grid, dim3(kThreads), 0, s, d, bs, map, c->dprimes(), c->tw.u64(),
-                               c->twp.u64(), c->logN, lo, hi);
+                               c->twp.u64(), c->logN, lo, hi, 0, 0, 0);
+    }
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+int ntt_modup(const ckc_ctx *c, uint64_t *digits, int level, int nb, const uint64_t *coeff, size_t coeff_bs,
+              const uint64_t *x, size_t xs, const BconvTable *const *tabs, hipStream_t s, const Ptrs *xp,
+              size_t x_off) {
+    if (nb <= 0) return CKC_OK;
+    CKC_REQUIRE(c->logN >= 12 && c->logN <= 16, CKC_EUNSUPPORTED, "NTT supports 2^12 <= N <= 2^16");
+    const int nl = level + 1, nt = nl + c->np, alpha = c->alpha, dnum = c->dnum_at(level);
+    CKC_REQUIRE(dnum <= kMaxDnum && alpha <= kMaxBconv, CKC_EUNSUPPORTED, "too many key-switching digits");
+    const size_t N = c->N, dig_bs = size_t(dnum) * nt * N;
+    const int nfull = nl / alpha, last = nl - nfull * alpha;  // a partial last digit of `last` primes
+    const LimbMap ext{nl, c->nq};
+    {
+        // algorithmic bytes, per digit: its source limbs read, its own limbs
+        // read and written (copied), every other limb written once
+        const double W = 8.0 * double(N) * nb;
+        const double active = double(dnum) * nt - nl;  // limbs transformed (a digit's own limbs are copied)
+        CKC_PROF(PK_NTT_FWD, s, W * (2.0 * nl + double(dnum) * nt), 0.5 * double(N) * c->logN * active * nb);
+        if (nfull > 0) {
+            DigitsIn d{coeff, coeff_bs, x, xs, nfull, nt, {}, {}, {}, xp ? *xp : Ptrs{}, x_off, xp ? 1 : 0};
+            for (int j = 0; j < nfull; ++j) {
+                d.hat[j] = tabs[j]->hat.u64();
+                d.neg_s[j] = tabs[j]->neg_s.u64();
+                d.s_half[j] = tabs[j]->s_half.u64();
+            }
+            using DigFn = void (*)(uint64_t *, size_t, LimbMap, const Prime *, const uint64_t *, const uint64_t *,
+                                   int, DigitsIn);
+            static constexpr DigFn fns[kMaxBconv] = {
+                k_fwd_cols_bconv_dig<1>, k_fwd_cols_bconv_dig<2>, k_fwd_cols_bconv_dig<3>, k_fwd_cols_bconv_dig<4>,
+                k_fwd_cols_bconv_dig<5>, k_fwd_cols_bconv_dig<6>, k_fwd_cols_bconv_dig<7>, k_fwd_cols_bconv_dig<8>};
+            hipLaunchKernelGGL(fns[alpha - 1], dim3(unsigned(N / kElems), unsigned(nt), unsigned(nb * nfull)),
+                               dim3(kThreads), 0, s, digits, dig_bs, ext, c->dprimes(), c->tw.u64(), c->twp.u64(),
+                               c->logN, d);
+        }
+        if (last > 0) {
+            const int j = nfull, lo = j * alpha;
+            const BconvIn in{coeff + size_t(lo) * N, coeff_bs, last, tabs[j]->hat.u64(), tabs[j]->neg_s.u64(),
+                             tabs[j]->s_half.u64(), x, xs, lo, lo + last, xp ? *xp : Ptrs{}, x_off, xp ? 1 : 0};
+            using BconvFn = void (*)(uint64_t *, size_t, LimbMap, const Prime *, const uint64_t *, const uint64_t *,
+                                     int, BconvIn);
+            static constexpr BconvFn fns[kMaxBconv] = {k_fwd_cols_bconv<1>, k_fwd_cols_bconv<2>, k_fwd_cols_bconv<3>,
+                                                       k_fwd_cols_bconv<4>, k_fwd_cols_bconv<5>, k_fwd_cols_bconv<6>,
+                                                       k_fwd_cols_bconv<7>, k_fwd_cols_bconv<8>};
+            hipLaunchKernelGGL(fns[last - 1], dim3(unsigned(N / kElems), unsigned(nt), unsigned(nb)), dim3(kThreads),
+                               0, s, digits + size_t(j) * nt * N, dig_bs, ext, c->dprimes(), c->tw.u64(),
+                               c->twp.u64(), c->logN, in);
+        }
+        // the second pass of every digit of every input in one launch
+        hipLaunchKernelGGL(k_fwd_rows, dim3(unsigned(N / kElems), unsigned(nt), unsigned(nb * dnum)),
+                           dim3(kThreads), 0, s, digits, size_t(nt) * N, ext, c->dprimes(), c->tw.u64(),
+                           c->twp.u64(), c->logN, -1, -1, dnum, alpha, nl);
     }
     CKC_HIP(hipGetLastError());
     return CKC_OK;
@@ -655,7 +761,23 @@ int ntt_inverse(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbat
     const dim3 grid(unsigned(c->N / kElems), unsigned(nlimbs), unsigned(nbatch));
     CKC_PROF(PK_NTT_INV, s, 16.0 * double(c->N) * nlimbs * nbatch, 0.5 * double(c->N) * c->logN * nlimbs * nbatch);
     hipLaunchKernelGGL(k_inv_rows, grid, dim3(kThreads), 0, s, d, batch_stride, src ? src : d,
-                       src ? src_bs : batch_stride, map, c->dprimes(), c->itw.u64(), c->itwp.u64(), c->logN);
+                       src ? src_bs : batch_stride, map, c->dprimes(), c->itw.u64(), c->itwp.u64(), c->logN, Ptrs{},
+                       size_t(0), 0);
+    hipLaunchKernelGGL(k_inv_cols, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(), c->itw.u64(),
+                       c->itwp.u64(), c->ninv.u64(), scale2, c->logN);
+    CKC_HIP(hipGetLastError());
+    return CKC_OK;
+}
+
+int ntt_inverse_ptrs(const ckc_ctx *c, uint64_t *d, int nlimbs, LimbMap map, int nbatch, size_t batch_stride,
+                     hipStream_t s, const uint64_t *scale2, const Ptrs &src, size_t src_off) {
+    if (nlimbs <= 0 || nbatch <= 0) return CKC_OK;
+    CKC_REQUIRE(c->logN >= 12 && c->logN <= 16, CKC_EUNSUPPORTED, "NTT supports 2^12 <= N <= 2^16");
+    CKC_REQUIRE(nbatch <= kMaxBatch, CKC_EINVAL, "ntt_inverse_ptrs: at most 64 inputs");
+    const dim3 grid(unsigned(c->N / kElems), unsigned(nlimbs), unsigned(nbatch));
+    CKC_PROF(PK_NTT_INV, s, 16.0 * double(c->N) * nlimbs * nbatch, 0.5 * double(c->N) * c->logN * nlimbs * nbatch);
+    hipLaunchKernelGGL(k_inv_rows, grid, dim3(kThreads), 0, s, d, batch_stride, d, batch_stride, map, c->dprimes(),
+                       c->itw.u64(), c->itwp.u64(), c->logN, src, src_off, 1);
     hipLaunchKernelGGL(k_inv_cols, grid, dim3(kThreads), 0, s, d, batch_stride, map, c->dprimes(), c->itw.u64(),
                        c->itwp.u64(), c->ninv.u64(), scale2, c->logN);
     CKC_HIP(hipGetLastError());
