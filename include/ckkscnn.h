@@ -427,6 +427,8 @@ int ckc_variant_list(char *buf, size_t cap);
  *   "conv_fuse"  1: one contraction launch covers every output group of a 3x3
  *                layer (the groups of one coefficient tile share an XCD's
  *                L2); 0: one launch per output group
+ *   "conv_rows"  polynomials per contraction wave: 1, or 2 (each codebook
+ *                word read from LDS serves both polynomials' products)
  * Errors: CKC_EINVAL for an unknown knob or a value it does not allow. */
 int ckc_tune_set(const char *knob, int value);
 int ckc_tune_get(const char *knob, int *value);

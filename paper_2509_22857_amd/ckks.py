@@ -688,7 +688,8 @@ def tune_get(knob: str) -> int:
     return int(v.value)
 
 
-TUNE_KNOBS = {"conv_outs": (8, 16), "conv_imgs": (1, 2, 4), "ks_batch": (16, 32, 64), "conv_fuse": (1, 0)}
+TUNE_KNOBS = {"conv_outs": (8, 16), "conv_imgs": (1, 2, 4), "ks_batch": (16, 32, 64), "conv_fuse": (1, 0),
+              "conv_rows": (1, 2)}
 
 
 def stream_release(stream=None):

@@ -222,8 +222,11 @@ __global__ __launch_bounds__(256) void k_conv_contract(
 // at most kMaxCentLds centroids:
 //   y[m][o] = sum_t sum_i PT[t][idx[o][i][t]] * R[m][i][t] + bias_o
 // for up to IMGS images m and OUTS consecutive outputs o.  One
-// workgroup = one 64-coefficient column tile of one limb; wave w handles image
-// w >> 1 and polynomial w & 1 and keeps one accumulator per output.  Per tap
+// workgroup = one 64-coefficient column tile of one limb; with ROWS = 1 wave w
+// handles image w >> 1 and polynomial w & 1, with ROWS = 2 image w and both
+// polynomials (each codebook word read from LDS then serves two products,
+// for twice the accumulator registers); a wave keeps one accumulator per
+// output and polynomial.  Per tap
 // the tap's whole codebook tile (kcent x 64 words) is staged in LDS once and
 // read by every wave, so the codebook crosses HBM once per group of images and
 // outputs rather than once per image and polynomial.  The centroid choices
@@ -255,8 +258,8 @@ struct ConvOut {
     int ngroups;
     int O;
 };
-template <int OUTS, int IMGS>
-__global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restrict__ R, size_t r_img_words,
+template <int OUTS, int IMGS, int ROWS>
+__global__ __launch_bounds__(128 / ROWS * IMGS) void k_conv_mac(const uint64_t *__restrict__ R, size_t r_img_words,
                                                            int n_img, int ni, int I, int i_base, int ntap, int nl,
                                                            LimbMap map, const uint64_t *__restrict__ pts, int kcent,
                                                            const uint64_t *__restrict__ ioff, int ngrp,
@@ -266,7 +269,9 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
                                                            int skip_tap, int pt_shared, uint64_t seq_all,
                                                            uint64_t seq_skip, ConvOut yo) {
     static_assert(OUTS % 4 == 0, "outputs per wave come in packed words of 4 offsets");
+    static_assert(ROWS == 1 || ROWS == 2, "one or both polynomials per wave");
     constexpr int NW = OUTS / 4;
+    constexpr int NWAVE = 2 / ROWS * IMGS;
     extern __shared__ uint64_t sP[];  // [dbuf ? 2 : 1][kcent][kTile]
     const size_t N = size_t(1) << logN;
     int limb, tile;
@@ -285,24 +290,28 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     // wave index as a wave-uniform (scalar) value, so per-wave control flow and
     // index loads stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int img = wave >> 1, poly = wave & 1;
+    const int img = ROWS == 2 ? wave : wave >> 1, poly = ROWS == 2 ? 0 : wave & 1;
     const bool active = img < n_img;
     const size_t col0 = size_t(tile) * kTile;
     const size_t pw = size_t(nl) * N, ctw = 2 * pw;
     const Prime P = primes[map.prime(limb)];
-    const int pcap = prod_cap(P.k);
+    const int pcap = fold_cap(P.k);
+    const uint64_t r64 = P.r2;  // 2^64 mod q
     const size_t rstride = size_t(ntap) * ctw;  // R words between consecutive inputs
     const uint64_t *Rb = R + size_t(active ? img : 0) * r_img_words + size_t(poly) * pw + size_t(limb) * N + col0 + lane;
     const int g0 = o_base / 4;
-    accc acc[OUTS];
+    // acc[r][j]: output o_base + j, polynomial poly + r
+    accc acc[ROWS][OUTS];
 #pragma unroll
-    for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, 0, 0, 0};
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int j = 0; j < OUTS; ++j) acc[r][j] = accc{0, 0, 0, 0, 0};
     int cnt = 0;
     // codebook rows 2 pr and 2 pr + 1 of plaintext set ps: lane l brings words
     // 2 (l & 31) and 2 (l & 31) + 1 of row 2 pr + (l >> 5) to LDS address 16 l
     // past the pair (an odd last row leaves the upper half-wave idle)
     auto stage = [&](int ps, uint64_t *buf) {
-        for (int pr = wave; 2 * pr < kcent; pr += 2 * IMGS) {
+        for (int pr = wave; 2 * pr < kcent; pr += NWAVE) {
             const int c = 2 * pr + (lane >> 5);
             if (c < kcent)
                 __builtin_amdgcn_global_load_lds(
@@ -339,7 +348,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     // last valid one
     int tp = 0, ip = 0;
     size_t roff = size_t(phys(0)) * ctw;
-    auto load_block = [&](uint64_t(&buf)[kUnroll]) {
+    auto load_block = [&](uint64_t(&buf)[ROWS][kUnroll]) {
         const uint64_t *rp = Rb + roff;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -348,7 +357,8 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
             // and a copy waits for its load)
             size_t off = ip + u < ni ? size_t(u) * rstride : 0;
             asm("" : "+s"(off));
-            buf[u] = rp[off];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) buf[r][u] = rp[off + size_t(r) * pw];
         }
         if (ip + kUnroll < ni) {
             ip += kUnroll;
@@ -381,11 +391,20 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     };
     // the products of the block at (tc, ic): coefficients cr, index words kw,
     // codebook tile cb
-    auto block = [&](const uint64_t(&cr)[kUnroll], const uint64_t(&kw)[NW][kUnroll], const uint64_t *cb) {
+    auto block = [&](const uint64_t(&cr)[ROWS][kUnroll], const uint64_t(&kw)[NW][kUnroll], const uint64_t *cb) {
         const int i = ic;
         if (cnt + kUnroll > pcap) {
 #pragma unroll
-            for (int j = 0; j < OUTS; ++j) acc[j] = accc{0, 0, reduce128(accc_value(acc[j]), P), 0, 0};
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int j = 0; j < OUTS; ++j) {
+                    // macc_folded written out: through the call (or with the
+                    // fold's products as one asm block) the compiler gives
+                    // this kernel 14 more registers (occupancy 3, not 4)
+                    const u128v v = accc_value(acc[r][j]);
+                    acc[r][j] = accc{0, 0, v.lo, 0, 0};
+                    macc(acc[r][j], v.hi, r64);
+                }
             cnt = 0;
         }
         // codebook words of the next input are read while this input's
@@ -410,7 +429,9 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
                     for (int j = 0; j < 4; ++j) cn[4 * w + j] = word(kw[w][u + 1 < kUnroll ? u + 1 : u], j);
             }
 #pragma unroll
-            for (int j = 0; j < OUTS; ++j) macc(acc[j], cr[u], cv[j]);
+            for (int j = 0; j < OUTS; ++j)
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) macc(acc[r][j], cr[r][u], cv[j]);
             if (u + 1 < kUnroll) {
 #pragma unroll
                 for (int j = 0; j < OUTS; ++j) cv[j] = cn[j];
@@ -422,8 +443,8 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     // (and starts the next tap's transfer); the coefficients two blocks ahead
     // are fetched before the products, the next block's index words after
     // them (a wait on a scalar load also waits for every LDS read in flight)
-    auto step = [&](const uint64_t(&cr)[kUnroll], uint64_t(&nx)[kUnroll], const uint64_t(&kc)[NW][kUnroll],
-                    uint64_t(&kn)[NW][kUnroll]) {
+    auto step = [&](const uint64_t(&cr)[ROWS][kUnroll], uint64_t(&nx)[ROWS][kUnroll],
+                    const uint64_t(&kc)[NW][kUnroll], uint64_t(&kn)[NW][kUnroll]) {
         if (tc >= ntl) return;
         if (ic == 0 && newset(tc)) {
             cur = (nset & 1) ? buf1 : buf0;
@@ -452,7 +473,7 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
             ++tc;
         }
     };
-    uint64_t ra[kUnroll], rb[kUnroll], rc[kUnroll];
+    uint64_t ra[ROWS][kUnroll], rb[ROWS][kUnroll], rc[ROWS][kUnroll];
     uint64_t ka[NW][kUnroll], kb[NW][kUnroll];
     if (active) {
         load_block(ra);
@@ -471,16 +492,18 @@ __global__ __launch_bounds__(128 * IMGS) void k_conv_mac(const uint64_t *__restr
     }
     if (!active) return;
 #pragma unroll
-    for (int j = 0; j < OUTS; ++j) {
-        if (j >= o_count) continue;
-        const int o = o_base + j;
-        uint64_t y = reduce128(accc_value(acc[j]), P);
-        uint64_t *dst = (yo.ybase ? yo.ybase + size_t(img) * yo.y_img + size_t(o) * ctw : outs.p[img * OUTS + j]) +
-                        size_t(poly) * pw + size_t(limb) * N + col0 + lane;
-        if (accumulate) y = add_mod(y, *dst, P.q);
-        else if (poly == 0 && bias) y = add_mod(y, bias[(size_t(o) * nl + limb) * N + col0 + lane], P.q);
-        *dst = y;
-    }
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int j = 0; j < OUTS; ++j) {
+            if (j >= o_count) continue;
+            const int o = o_base + j, pl = poly + r;
+            uint64_t y = reduce128(accc_value(acc[r][j]), P);
+            uint64_t *dst = (yo.ybase ? yo.ybase + size_t(img) * yo.y_img + size_t(o) * ctw : outs.p[img * OUTS + j]) +
+                            size_t(pl) * pw + size_t(limb) * N + col0 + lane;
+            if (accumulate) y = add_mod(y, *dst, P.q);
+            else if (pl == 0 && bias) y = add_mod(y, bias[(size_t(o) * nl + limb) * N + col0 + lane], P.q);
+            *dst = y;
+        }
 }
 
 using ConvFn = void (*)(const uint64_t *, size_t, int, int, int, int, int, int, LimbMap, const uint64_t *, int,
@@ -502,11 +525,18 @@ uint64_t tap_sequence(const ckc_layer *L, int skip) {
 }
 // kernel for a group of gi images: the smallest workgroup (1, 2 or 4 images)
 // that holds them; outs = outputs per wave (8 or 16), a tuning choice between
-// accumulator registers (occupancy) and codebook re-reads per output group
-static ConvFn conv_kernel(int outs, int gi, int *imgs) {
+// accumulator registers (occupancy) and codebook re-reads per output group;
+// rows = polynomials per wave (1 or 2), between registers and LDS reads
+static ConvFn conv_kernel(int outs, int rows, int gi, int *imgs) {
     *imgs = gi <= 1 ? 1 : gi <= 2 ? 2 : 4;
-    if (outs == 16) return *imgs == 1 ? k_conv_mac<16, 1> : *imgs == 2 ? k_conv_mac<16, 2> : k_conv_mac<16, 4>;
-    return *imgs == 1 ? k_conv_mac<8, 1> : *imgs == 2 ? k_conv_mac<8, 2> : k_conv_mac<8, 4>;
+    if (rows == 2) {
+        if (outs == 16)
+            return *imgs == 1 ? k_conv_mac<16, 1, 2> : *imgs == 2 ? k_conv_mac<16, 2, 2> : k_conv_mac<16, 4, 2>;
+        return *imgs == 1 ? k_conv_mac<8, 1, 2> : *imgs == 2 ? k_conv_mac<8, 2, 2> : k_conv_mac<8, 4, 2>;
+    }
+    if (outs == 16)
+        return *imgs == 1 ? k_conv_mac<16, 1, 1> : *imgs == 2 ? k_conv_mac<16, 2, 1> : k_conv_mac<16, 4, 1>;
+    return *imgs == 1 ? k_conv_mac<8, 1, 1> : *imgs == 2 ? k_conv_mac<8, 2, 1> : k_conv_mac<8, 4, 1>;
 }
 
 int check_inputs(const ckc_ct *in, int n, int level, const char *what) {
@@ -883,11 +913,14 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
             }
             if (L->ioff.p) {
                 // contraction: groups of up to conv_imgs images x conv_outs outputs
-                const int outs = tune_value(TK_CONV_OUTS), wg_max = tune_value(TK_CONV_IMGS);
+                const int outs = tune_value(TK_CONV_OUTS), wg_max = tune_value(TK_CONV_IMGS),
+                          rows = tune_value(TK_CONV_ROWS);
                 for (int g0 = 0; g0 < ni_img; g0 += wg_max) {
                     const int gi = std::min(wg_max, ni_img - g0);
                     int wg_imgs = 1;
-                    const ConvFn fn = conv_kernel(outs, gi, &wg_imgs);
+                    const ConvFn fn = conv_kernel(outs, rows, gi, &wg_imgs);
+                    const unsigned threads = unsigned(128 / rows * wg_imgs);
+
                     // two codebook tiles (double buffered) when they fit in
                     // 64 KiB and the workgroup has four images' waves: with
                     // fewer waves per workgroup the doubled tile would cut the
@@ -903,9 +936,11 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                                                     double(L->npt) * L->kcent) -
                                             skipped * (2.0 * gi * nic + skipped_pt)),
                                  2.0 * N * double(gi) * O * nic * (double(nlim) * ntap - skipped));
-                        count_variant("conv_mac", outs, wg_imgs, dbuf ? "+dbuf+fused" : "+fused");
+                        count_variant("conv_mac", outs, wg_imgs,
+                                      dbuf ? (rows == 2 ? "+dbuf+fused+rows2" : "+dbuf+fused")
+                                           : (rows == 2 ? "+fused+rows2" : "+fused"));
                         hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile) * unsigned(nlim) * unsigned(ngroups)),
-                                           dim3(128 * wg_imgs), lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi,
+                                           dim3(threads), lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi,
                                            nic, I, ic0, ntap, nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(),
                                            L->Opad / 4, bias_k, Ptrs{}, 0, 0, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN,
                                            dbuf, skip_tap, L->pt_shared ? 1 : 0, seq_all, seq_skip, yo);
@@ -922,8 +957,9 @@ extern "C" int ckc_eval_conv(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L,
                                                     double(L->npt) * L->kcent) -
                                             skipped * (2.0 * gi * nic + skipped_pt)),
                                  2.0 * N * double(gi) * oc * nic * (double(nlim) * ntap - skipped));
-                        count_variant("conv_mac", outs, wg_imgs, dbuf ? "+dbuf" : "");
-                        hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(128 * wg_imgs),
+                        count_variant("conv_mac", outs, wg_imgs,
+                                      dbuf ? (rows == 2 ? "+dbuf+rows2" : "+dbuf") : (rows == 2 ? "+rows2" : ""));
+                        hipLaunchKernelGGL(fn, dim3(unsigned(N / kTile), unsigned(nlim)), dim3(threads),
                                            lds_mac, s, R.u64() + size_t(g0) * r_img, r_img, gi, nic, I, ic0, ntap,
                                            nlim, map, L->pts.u64(), L->kcent, L->ioff.u64(), L->Opad / 4,
                                            bias_k, op, o0, oc, ic0 > 0 ? 1 : 0, c->dprimes(), c->logN, dbuf,
@@ -1081,7 +1117,8 @@ __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ 
               poly = int(grp / (nchunk * unsigned(nl)));
     const size_t N = size_t(1) << logN, pw = size_t(nl) * N;
     const Prime P = primes[limb];
-    const int pcap = prod_cap(P.k);
+    const int pcap = fold_cap(P.k);
+    const uint64_t r64 = P.r2;  // 2^64 mod q
     {
         const size_t k = size_t(chunk) * 256 + threadIdx.x;
         accc acc[kDenseImg];
@@ -1095,7 +1132,11 @@ __global__ __launch_bounds__(256) void k_dense_mac(const uint64_t *__restrict__ 
                 if (i < nimg) macc(acc[i], Sb[((size_t(i) * C + ch) * 2 + poly) * pw + size_t(limb) * N + k], pv);
             if (++cnt == pcap) {
 #pragma unroll
-                for (int i = 0; i < kDenseImg; ++i) acc[i] = accc{0, 0, reduce128(accc_value(acc[i]), P), 0, 0};
+                for (int i = 0; i < kDenseImg; ++i) {
+                    const u128v v = accc_value(acc[i]);  // macc_folded, written out as in k_conv_mac
+                    acc[i] = accc{0, 0, v.lo, 0, 0};
+                    macc(acc[i], v.hi, r64);
+                }
                 cnt = 0;
             }
         }

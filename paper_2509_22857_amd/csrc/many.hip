@@ -65,7 +65,8 @@ __global__ __launch_bounds__(256) void k_mac_plain_b(Ptrs in, int T, Ptrs pt, Pt
     const size_t N = size_t(1) << logN;
     const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const Prime P = primes[limb];
-    const int pcap = prod_cap(P.k);
+    const int pcap = fold_cap(P.k);
+    const uint64_t r64 = P.r2;  // 2^64 mod q
     const size_t lo = size_t(limb) * N + k;
     uint64_t pv[kMacRegTerms];
 #pragma unroll
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void k_mac_plain_b(Ptrs in, int T, Ptrs pt, Pt
             auto step = [&](uint64_t x, uint64_t w) {
                 macc(acc, x, w);
                 if (++cnt == pcap) {
-                    acc = accc{0, 0, reduce128(accc_value(acc), P), 0, 0};
+                    acc = macc_folded(acc, r64);
                     cnt = 0;
                 }
             };

@@ -72,7 +72,7 @@ __device__ __forceinline__ void macc(accc &acc, uint64_t a, uint64_t b) {
         : "v"(a0), "v"(a1), "v"(b0), "v"(b1));
 #endif
 }
-__device__ __forceinline__ u128v accc_value(const accc &a) {
+CKC_HD u128v accc_value(const accc &a) {
     const uint64_t ml = a.m << 32;
     u128v r;
     r.lo = a.l + ml;
@@ -83,6 +83,30 @@ __device__ __forceinline__ u128v accc_value(const accc &a) {
 // largest number of products (plus one reduced residue) an accumulator may
 // take for a k-bit modulus
 CKC_HD int prod_cap(int k) { return k >= 61 ? (1 << (128 - 2 * k)) - 1 : 64; }
+
+// Only h can overflow: l and m count their carries.  Since the value is only
+// needed mod q, a fold replaces the value V = V_hi 2^64 + V_lo by V_lo +
+// V_hi (2^64 mod q): l = V_lo and one more product, V_hi times r = 2^64 mod q,
+// into an otherwise cleared accumulator, which leaves h below 2^62.  Every
+// product adds less than 2^(2k - 64) to h, so fold_cap(k) products may
+// follow a fold while h stays below 2^64 - 2^53, which leaves room in
+// accc_value for carry counts up to 2^20 (k <= 62, the largest modulus size
+// the library takes: at least 3).  A fold costs about two products, against
+// about eight for a full reduction; with every field but l restarting from
+// zero, the compiler can keep the accumulators in as few registers as with a
+// reduction.
+CKC_HD int fold_cap(int k) {
+    if (k <= 32) return 1 << 20;
+    const uint64_t room = ~uint64_t(0) - (uint64_t(1) << 53) - (uint64_t(1) << 62);
+    const uint64_t n = room >> (2 * k - 64);
+    return n > (1u << 20) ? 1 << 20 : int(n);
+}
+__device__ __forceinline__ accc macc_folded(const accc &acc, uint64_t r64) {
+    const u128v v = accc_value(acc);
+    accc f{0, 0, v.lo, 0, 0};
+    macc(f, v.hi, r64);
+    return f;
+}
 
 // Per-prime constants.
 struct Prime {

@@ -447,22 +447,27 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(uint64_t *__restrict__ da
 // form is already known) and left alone by the second pass.  The number of
 // sources NS is a template argument: with a run-time count the compiler
 // executed every one of the kMaxBconv possible products under a mask.
-// Body of the pass for output block `a` (its limbs, stride N) and batch
-// index b of the sources.
+// Body of the pass for output block `a0` (its limbs, stride N), with one
+// batch entry's pointers resolved: src its first source limb, copy its
+// NTT-form input (limb 0).  The per-entry pointers are resolved by the
+// kernels from their arguments, never through a local copy of a pointer
+// table (indexed at run time, such a copy lives in scratch memory: 608 bytes
+// per lane, twice the pass's time).
 template <int NS>
-__device__ __forceinline__ void bconv_cols(uint64_t *a0, int b, const BconvIn &in, LimbMap map,
-                                           const Prime *__restrict__ primes, const uint64_t *__restrict__ tw,
-                                           const uint64_t *__restrict__ twp, int logN, uint64_t *s) {
+__device__ __forceinline__ void bconv_cols(uint64_t *a0, const uint64_t *src, const uint64_t *hat,
+                                           const uint64_t *neg_s, const uint64_t *s_half, const uint64_t *copy,
+                                           int copy_lo, int copy_hi, LimbMap map, const Prime *__restrict__ primes,
+                                           const uint64_t *__restrict__ tw, const uint64_t *__restrict__ twp,
+                                           int logN, uint64_t *s) {
     const int limb = blockIdx.y;
     const size_t N = size_t(1) << logN;
     uint64_t *a = a0 + size_t(limb) * N;
-    if (limb >= in.copy_lo && limb < in.copy_hi) {
+    if (limb >= copy_lo && limb < copy_hi) {
         // this workgroup's words of the limb, in the same (row, column) tiling
         const int logN1 = logN - kLogN2;
         const int logC = 12 - logN1;
         const int col0 = blockIdx.x << logC;
-        const uint64_t *cp =
-            (in.use_copyp ? in.copyp.p[b] + in.copy_off : in.copy + size_t(b) * in.copy_bs) + size_t(limb) * N;
+        const uint64_t *cp = copy + size_t(limb) * N;
         for (int e = threadIdx.x; e < kElems; e += kThreads) {
             const size_t i = size_t(e >> logC) * kN2 + col0 + (e & ((1 << logC) - 1));
             a[i] = cp[i];
@@ -472,14 +477,13 @@ __device__ __forceinline__ void bconv_cols(uint64_t *a0, int b, const BconvIn &i
     const int pi = map.prime(limb);
     const Prime P = primes[pi];
     const uint64_t *W = tw + size_t(pi) * N, *Wp = twp + size_t(pi) * N;
-    const uint64_t *src = in.src + size_t(b) * in.src_bs;
     uint64_t h[NS], half[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        h[k] = in.hat[size_t(limb) * NS + k];
-        half[k] = in.s_half[k];
+        h[k] = hat[size_t(limb) * NS + k];
+        half[k] = s_half[k];
     }
-    const uint64_t negS = in.neg_s[limb];
+    const uint64_t negS = neg_s[limb];
     auto ld = [src, h, half, negS, N, P](size_t i) {
         accc acc{0, 0, 0, 0, 0};
         uint64_t neg = 0;
@@ -506,7 +510,10 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv(uint64_t *__restric
                                                              const uint64_t *__restrict__ twp, int logN,
                                                              BconvIn in) {
     __shared__ uint64_t s[kElems + kElems / 16];
-    bconv_cols<NS>(data + size_t(blockIdx.z) * bs, int(blockIdx.z), in, map, primes, tw, twp, logN, s);
+    const int b = blockIdx.z;
+    const uint64_t *cp = in.use_copyp ? in.copyp.p[b] + in.copy_off : in.copy + size_t(b) * in.copy_bs;
+    bconv_cols<NS>(data + size_t(b) * bs, in.src + size_t(b) * in.src_bs, in.hat, in.neg_s, in.s_half, cp,
+                   in.copy_lo, in.copy_hi, map, primes, tw, twp, logN, s);
 }
 
 // The same first pass for the ModUp of `ndig` digits of NS primes each in
@@ -534,9 +541,9 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols_bconv_dig(uint64_t *__res
     __shared__ uint64_t s[kElems + kElems / 16];
     const int z = blockIdx.z, b = z / d.ndig, j = z - b * d.ndig, lo = j * NS;
     const size_t N = size_t(1) << logN;
-    const BconvIn in{d.src + size_t(lo) * N, d.src_bs, NS, d.hat[j], d.neg_s[j], d.s_half[j], d.copy, d.copy_bs,
-                     lo, lo + NS, d.copyp, d.copy_off, d.use_copyp};
-    bconv_cols<NS>(data + size_t(b) * bs + size_t(j) * d.nt * N, b, in, map, primes, tw, twp, logN, s);
+    const uint64_t *cp = d.use_copyp ? d.copyp.p[b] + d.copy_off : d.copy + size_t(b) * d.copy_bs;
+    bconv_cols<NS>(data + size_t(b) * bs + size_t(j) * d.nt * N, d.src + size_t(b) * d.src_bs + size_t(lo) * N,
+                   d.hat[j], d.neg_s[j], d.s_half[j], cp, lo, lo + NS, map, primes, tw, twp, logN, s);
 }
 
 // Second forward pass.  Limbs in [skip_lo, skip_hi) are left alone; with

@@ -7,6 +7,7 @@ enum TuneKnob {
     TK_CONV_IMGS,      // most images per contraction workgroup: 1, 2 or 4
     TK_KS_BATCH,       // rotated inputs per key-switching launch in a convolution: 8 .. 64
     TK_CONV_FUSE,      // 1: one contraction launch covers every output group of a 3x3 layer
+    TK_CONV_ROWS,      // polynomials per contraction wave: 1, or 2 (one codebook read per two products)
     TK_COUNT
 };
 

@@ -17,8 +17,9 @@ constexpr KnobDef kDefs[TK_COUNT] = {
     {"conv_imgs", 4, 1, 4},
     {"ks_batch", 64, 8, 64},
     {"conv_fuse", 1, 0, 1},
+    {"conv_rows", 1, 1, 2},
 };
-std::atomic<int> g_val[TK_COUNT] = {{8}, {4}, {64}, {1}};
+std::atomic<int> g_val[TK_COUNT] = {{8}, {4}, {64}, {1}, {1}};
 
 bool allowed(int k, int v) {
     if (v < kDefs[k].lo || v > kDefs[k].hi) return false;

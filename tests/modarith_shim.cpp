@@ -34,3 +34,13 @@ extern "C" uint64_t shim_redc(int nprod, uint64_t hi, uint64_t lo, uint64_t q, u
         default: return ~0ull;
     }
 }
+
+extern "C" int shim_fold_cap(int k) { return fold_cap(k); }
+
+// the 128-bit value of a carry-counted accumulator
+extern "C" void shim_accc_value(uint64_t h, uint64_t m, uint64_t l, uint32_t cm, uint32_t cl, uint64_t *hi,
+                                uint64_t *lo) {
+    const u128v v = accc_value(accc{h, m, l, cm, cl});
+    *hi = v.hi;
+    *lo = v.lo;
+}

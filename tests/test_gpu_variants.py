@@ -141,3 +141,28 @@ def test_slice_shared_columns_other_forms(hoist, k):
         assert counts.get("conv_mac<8,4>+fused", 0) == 1, counts
     else:
         assert counts.get("conv_contract", 0) >= 1, counts
+
+
+@pytest.mark.parametrize("layout,k,fuse", [("taps", 64, 1), ("slice", 64, 0), ("taps", 96, 1)])
+def test_two_polynomials_per_contraction_wave(layout, k, fuse):
+    """conv_rows = 2: each contraction wave takes both polynomials of its
+    image (one codebook read from LDS per two products): double-buffered
+    and single-buffered 4-image groups, a ragged 3-image group, the fused
+    and the per-output-group launches, both layouts."""
+    from paper_2509_22857_amd import ckks
+    ps = small_tower(logN=12, levels=5, alpha=1)
+    spec = _conv_spec(220 + k, I=8, O=12, k=k, M=2, block=128 if layout == "slice" else 64)
+    spec["layout"]["slice_shared"] = layout == "slice"
+    print(f"[variants] N=2^12 conv_rows=2 {layout} k={k} fuse={fuse}, 7 images", flush=True)
+    ckks.tune_set("conv_rows", 2)
+    ckks.tune_set("conv_fuse", fuse)
+    try:
+        counts = _run_both(ps, spec, 7, 70 + k)
+    finally:
+        ckks.tune_set("conv_rows", 1)
+    dbuf = "+dbuf" if k <= 64 else ""
+    if fuse:
+        assert counts.get(f"conv_mac<8,4>{dbuf}+fused+rows2", 0) == 2, counts
+    else:
+        assert counts.get(f"conv_mac<8,4>{dbuf}+rows2", 0) >= 2, counts
+    assert not any(n.startswith("conv_mac") and not n.endswith("rows2") for n in counts), counts

@@ -105,3 +105,76 @@ def test_worst_case_quotient_exceeds_64_bits_near_2_62():
         hi, lo = V >> 64, V % 2 ** 64
         m = lo * qinv % 2 ** 64
         assert hi + (m * q >> 64) + 1 >= 2 ** 64, n
+
+
+def _shim_fold(shim):
+    shim.shim_fold_cap.restype = ctypes.c_int
+    shim.shim_fold_cap.argtypes = [ctypes.c_int]
+    shim.shim_accc_value.restype = None
+    shim.shim_accc_value.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                     ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(ctypes.c_uint64)]
+
+
+class _Acc:
+    """The carry-counted accumulator of modarith.h as exact integers: every
+    64-bit word and 32-bit counter is checked not to wrap where the device
+    code relies on it (h has no carry counter; l and m count theirs)."""
+
+    def __init__(self, l=0):
+        self.h = self.m = self.cm = self.cl = 0
+        self.l = l
+
+    def macc(self, a, b):
+        a0, a1, b0, b1 = a & 0xFFFFFFFF, a >> 32, b & 0xFFFFFFFF, b >> 32
+        self.l += a0 * b0
+        self.cl += self.l >> 64
+        self.l &= 2 ** 64 - 1
+        for t in (a0 * b1, a1 * b0):
+            self.m += t
+            self.cm += self.m >> 64
+            self.m &= 2 ** 64 - 1
+        self.h += a1 * b1
+        assert self.h < 2 ** 64, "h wrapped"
+        assert self.cl < 2 ** 32 and self.cm < 2 ** 32
+
+    def exact(self):
+        return self.l + (self.cl << 64) + (self.m << 32) + (self.cm << 96) + (self.h << 64)
+
+
+@pytest.mark.parametrize("bits", [30, 50, 60, 61, 62])
+def test_folded_accumulator_holds_long_sums(bits, shim):
+    """A long sum (a 512-input 3x3 contraction: 4608 products) accumulated
+    with a fold whenever fold_cap(k) products have gone in since the last
+    one: with operands at q - 1 (the largest h growth) and at random, h never
+    wraps, the library's accc_value never wraps, and the result is the sum
+    mod q."""
+    _shim_fold(shim)
+    q = prime_below(bits)
+    k = q.bit_length()
+    cap = shim.shim_fold_cap(k)
+    assert cap >= 3
+    r64 = 2 ** 64 % q
+    rnd = random.Random(bits)
+    hi, lo = ctypes.c_uint64(), ctypes.c_uint64()
+
+    def value(acc):
+        shim.shim_accc_value(acc.h, acc.m, acc.l, acc.cm, acc.cl, ctypes.byref(hi), ctypes.byref(lo))
+        v = (hi.value << 64) | lo.value
+        assert v == acc.exact(), "accc_value wrapped"
+        return v
+
+    for kind in ("max", "random"):
+        acc, cnt, want = _Acc(), 0, 0
+        for _ in range(4608):
+            if cnt == cap:
+                v = value(acc)
+                acc = _Acc(v & (2 ** 64 - 1))
+                acc.macc(v >> 64, r64)
+                cnt = 0
+            a, b = (q - 1, q - 1) if kind == "max" else (rnd.randrange(q), rnd.randrange(q))
+            acc.macc(a, b)
+            want += a * b
+            cnt += 1
+        assert value(acc) % q == want % q
+
