@@ -74,6 +74,31 @@ def test_tiny_network_decrypts_to_forward():
     assert np.max(np.abs(got - ref)) < 1e-5
 
 
+def test_activation_and_dense_network_decrypts_to_forward():
+    """The activation + pooled dense network of the headline act/dense digest
+    case, at N = 2^12: the oracle's logits (slot m B of each class
+    ciphertext) are the FP64 forward's."""
+    spec = nets.act_dense_spec(11, C=4, M=2, classes=3, H=8, W=8, block=64)
+    ps = small_tower(logN=12, levels=4)
+    o = Oracle.from_params(ps)
+    D = 2.0 ** 30
+    net = OracleNetwork(o, spec, delta=D, target=D, in_scale=D)
+    sk = o.secret_key(12)
+    rlk = o.relin_key(sk)
+    gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in net.steps()}
+    img = gen.images(13, 1, 4, 8, 8)[0]
+    outs, _ = net.run(sk, net.encrypt_image(sk, img, 100), rlk, gk)
+    got = np.array([[o.decrypt_decode(c, sk)[m * 64] for c in outs] for m in range(2)])
+    ref = forward(spec, img)
+    # the network written out: per member m, class k: the sum over channels
+    # and pixels of w[m][k][c] (x^2 + b x + c), plus the bias
+    act = img[None] ** 2 + spec["layers"][0]["b"][:, :, None, None] * img[None] + \
+        spec["layers"][0]["c"][:, :, None, None]
+    direct = np.einsum("mkc,mc->mk", spec["layers"][1]["w"], act.sum(axis=(2, 3))) + spec["layers"][1]["bias"]
+    assert ref.shape == (2, 3) and np.allclose(ref, direct, rtol=0, atol=1e-12)
+    assert np.max(np.abs(got - ref)) < 1e-4
+
+
 @pytest.mark.slow
 def test_small_resnet_ensemble_decrypts_to_forward():
     spec = nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8, calib=4)

@@ -277,6 +277,23 @@ def single_conv_spec(seed: int, I: int, O: int, k: int, M: int, H: int = 8, W: i
                 layout=dict(block=block, row_stride=W), layers=[layer], k=k)
 
 
+def act_dense_spec(seed: int, C: int, M: int, classes: int, H: int = 8, W: int = 8, block: int = 64) -> dict:
+    """A network of one monic quadratic activation (b, c per member and
+    channel, uniform in [-0.5, 0.5]) and the dense layer after global sum
+    pooling (weights normal(0, 0.05) / (H W), bias normal(0, 0.1)), for
+    layer-level parity cases of the activation, the slot-sum rotations and
+    the dense contraction."""
+    g = rng(seed)
+    b = g.uniform(-0.5, 0.5, (M, C))
+    c = g.uniform(-0.5, 0.5, (M, C))
+    w = g.normal(0.0, 0.05, (M, classes, C)) / (H * W)
+    bias = g.normal(0.0, 0.1, (M, classes))
+    layers = [dict(op="act", name="act", inp="x", out="y", b=b, c=c, a_absorb=1.0),
+              dict(op="dense", name="fc", inp="y", out="logits", w=w, bias=bias)]
+    return dict(name=f"act_dense_{C}_K{classes}", members=M, classes=classes, image=(C, H, W),
+                layout=dict(block=block, row_stride=W), layers=layers, k=0)
+
+
 def set_hoisting(spec: dict, hoist) -> dict:
     """Mark the key-switching form of every 3x3 convolution: hoist is None
     (the default, double hoisting), "single"/"double" for all, or one entry
