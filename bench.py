@@ -170,13 +170,14 @@ def build_workload(args):
     from workloads.params import resnet20_tower
     shared = getattr(args, "layout", "slice") == "slice" and getattr(args, "pack", 1) == 1
     if args.workload == "vgg":
-        # VGG-style: 3->64, 64->64, pool, 64->128, 128->128, pool, 128->256, dense to 10; k = 16.
+        # VGG-style: 3->64, 64->64, pool, 64->128, 128->128, pool, 128->256,
+        # dense over the flattened 256 x 8 x 8 map to 10 classes; k = 16.
         # Per-layer key-switching form: what network.choose_hoisting picks for
         # this network and chain (a test keeps the two in step): the first
         # layer (3 inputs, 64 outputs) and the last (level 2: three Q limbs,
         # to which the three P limbs would add as many again) single-hoisted
         ps = resnet20_tower(levels=6)
-        spec = nets.vgg_spec(seed=0, calib=8, hoist=VGG_HOISTING)
+        spec = nets.vgg_spec(seed=0, calib=8, hoist=VGG_HOISTING, dense="flatten")
     else:
         ps = resnet20_tower()
         spec = nets.resnet_spec(seed=0, members=4, widths=(16, 32, 64), blocks=3, classes=100, image=(3, 32, 32),

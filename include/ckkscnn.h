@@ -372,6 +372,22 @@ int ckc_eval_quad_act(ckc_ctx *ctx, const ckc_evk *evk, const ckc_layer *layer, 
 int ckc_layer_create_dense(ckc_ctx *ctx, const ckc_layout *in, int classes, int in_ch, const double *w,
                            const double *bias, int level, double pt_scale, double bias_scale, ckc_layer **out,
                            void *stream);
+/*
+ * Dense layer over the flattened feature map (every grid position its own
+ * weight; Section 5.1's lazy mapping leaves the map on the layout's grid):
+ * out[k] = SUM over the valid grid (the same rotation steps as above) of
+ * (sum_c PT[k][c] * in[c] + B[k]), where PT[k][c] holds w[m][k][c][r][col]
+ * in slot m*block + gap*(r*row_stride + col) and B[k] holds bias[m][k] in
+ * slot m*block, so member m's logit for class k is slot m*block of out[k].
+ * w: [members][classes][in_ch][height][width] (the layout's grid); bias:
+ * [members][classes] or NULL.  Result scale = in scale * pt_scale.  K x C
+ * plaintexts and K bias plaintexts are stored; ckc_eval_dense evaluates it
+ * (the products first, then K rotation sums instead of C).
+ * Errors: as ckc_layer_create_dense.
+ */
+int ckc_layer_create_dense_spatial(ckc_ctx *ctx, const ckc_layout *in, int classes, int in_ch, const double *w,
+                                   const double *bias, int level, double pt_scale, double bias_scale,
+                                   ckc_layer **out, void *stream);
 int ckc_eval_dense(ckc_ctx *ctx, const ckc_evk *evk, const ckc_layer *layer, const ckc_ct *in, int n_img,
                    ckc_ct *out, void *stream);
 

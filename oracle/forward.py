@@ -5,7 +5,8 @@ in float64 for every ensemble member, with the paper's operator semantics:
 zero-padded 'same' convolutions with stride (BN already folded), residual
 sums, monic quadratic activations scaled by a_absorb, 2x2 sum pooling
 (average divisor folded into the next layer), and a dense layer over the
-per-channel sum of the final grid (global average pooling folded into w).
+per-channel sum of the final grid (global average pooling folded into w)
+or, with a weight per grid position, over the flattened final map.
 Written without reference to the generator's calibration forward.
 """
 from __future__ import annotations
@@ -75,8 +76,11 @@ def forward(spec: dict, img: np.ndarray, capture: dict | None = None) -> np.ndar
             elif op == "pool":
                 y = x[:, 0::2, 0::2] + x[:, 0::2, 1::2] + x[:, 1::2, 0::2] + x[:, 1::2, 1::2]
             elif op == "dense":
-                s = x.sum(axis=(1, 2))
-                y = ly["w"][m] @ s + (0.0 if ly.get("bias") is None else ly["bias"][m])
+                if np.ndim(ly["w"]) == 5:  # a weight per grid position (the flattened map)
+                    y = np.einsum("kchw,chw->k", ly["w"][m], x)
+                else:
+                    y = ly["w"][m] @ x.sum(axis=(1, 2))
+                y = y + (0.0 if ly.get("bias") is None else ly["bias"][m])
             else:
                 raise ValueError(op)
             t[ly["out"]] = y

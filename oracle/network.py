@@ -15,7 +15,9 @@ Written independently of the GPU runner from the paper's method:
   * activation x^2 + b x + c: t = x + b, y = Relin(x * t) + c (Section 4.2
     makes it monic), scale s^2 / a_absorb;
   * dense: rotation sums over the grid, then per class the weighted sum of
-    the channel sums, plus bias (member values at slot m*block);
+    the channel sums, plus bias (member values at slot m*block); with a
+    weight per grid position (the flattened map), per class the weighted
+    products of the channels plus the bias first, then the rotation sums;
   * tower reuse (Section 4.3): rescale after a multiplicative layer iff the
     sublevel of its scale exceeds the sublevel of the prime to drop;
   * slice-shared layout (layout flag "slice_shared"; Section 5.2: the
@@ -301,6 +303,8 @@ class OracleNetwork:
         g, H, W = grid["gap"], grid["H"], grid["W"]
         steps = [g * (1 << j) for j in range(int(math.log2(W)))] + \
                 [g * self.W0 * (1 << j) for j in range(int(math.log2(H)))]
+        if np.ndim(ly["w"]) == 5:
+            return self._dense_spatial(xs, g, H, W, steps, ly, pt_scale, bias_scale, gkeys)
         sums = []
         for x in xs:
             S = x
@@ -334,6 +338,36 @@ class OracleNetwork:
                     for m in range(self.M):
                         v[m * self.B] = ly["bias"][m, kk]
                     acc = o.add_plain(acc, self.encode(v, level, bias_scale))
+            outs.append(acc)
+        return outs
+
+    def _dense_spatial(self, xs, g, H, W, steps, ly, pt_scale, bias_scale, gkeys):
+        """Dense layer over the flattened map: for class k, the product of
+        every channel with its weight map (w[m][k][c][r][col] at member m's
+        grid point (r, col)), summed over channels, plus the bias at slot
+        m*block; then the rotation sums over the grid, so slot m*block holds
+        the whole dot product."""
+        o = self.o
+        level = xs[0].level
+        K = ly["w"].shape[1]
+        outs = []
+        for kk in range(K):
+            acc = None
+            for c, x in enumerate(xs):
+                v = self._vec()
+                for m in range(self.M):
+                    for r in range(H):
+                        for col in range(W):
+                            v[m * self.B + g * (r * self.W0 + col)] = ly["w"][m, kk, c, r, col]
+                term = o.mul_plain(x, self.encode(v, level, pt_scale))
+                acc = term if acc is None else o.add(acc, term)
+            if ly.get("bias") is not None:
+                v = self._vec()
+                for m in range(self.M):
+                    v[m * self.B] = ly["bias"][m, kk]
+                acc = o.add_plain(acc, self.encode(v, level, bias_scale))
+            for st in steps:
+                acc = o.add(acc, o.rotate(acc, st, gkeys[o.galois_elt(st)]))
             outs.append(acc)
         return outs
 

@@ -100,6 +100,8 @@ _SIGS = [
     ("ckc_eval_quad_act", C.c_int, [_vp, _vp, _vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
     ("ckc_layer_create_dense", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, C.c_int, _dblp, _dblp, C.c_int,
                                          C.c_double, C.c_double, C.POINTER(_vp), _vp]),
+    ("ckc_layer_create_dense_spatial", C.c_int, [_vp, C.POINTER(ckc_layout), C.c_int, C.c_int, _dblp, _dblp,
+                                                 C.c_int, C.c_double, C.c_double, C.POINTER(_vp), _vp]),
     ("ckc_eval_dense", C.c_int, [_vp, _vp, _vp, C.POINTER(ckc_ct), C.c_int, C.POINTER(ckc_ct), _vp]),
     ("ckc_eval_avgpool2", C.c_int, [_vp, _vp, C.POINTER(ckc_layout), C.POINTER(ckc_ct), C.c_int,
                                     C.POINTER(ckc_ct), _vp]),
@@ -563,15 +565,18 @@ def layer_create_act(ctx: Context, layout: ckc_layout, channels, b, c, a_absorb,
 
 def layer_create_dense(ctx: Context, layout: ckc_layout, classes, in_ch, w, bias, level, pt_scale, bias_scale,
                        stream=None) -> Layer:
+    """w: [members][classes][in_ch] (after global average pooling) or
+    [members][classes][in_ch][height][width] (over the flattened grid:
+    ckc_layer_create_dense_spatial)."""
     ww, wp = _dbl(w)
     if bias is not None:
         bb, bbp = _dbl(bias)
     else:
         bbp = None
     h = _vp()
-    _check("ckc_layer_create_dense", lib().ckc_layer_create_dense(ctx.h, C.byref(layout), classes, in_ch, wp, bbp,
-                                                                  level, float(pt_scale), float(bias_scale),
-                                                                  C.byref(h), _stream(stream)))
+    fn = "ckc_layer_create_dense_spatial" if np.ndim(w) == 5 else "ckc_layer_create_dense"
+    _check(fn, getattr(lib(), fn)(ctx.h, C.byref(layout), classes, in_ch, wp, bbp, level, float(pt_scale),
+                                  float(bias_scale), C.byref(h), _stream(stream)))
     return Layer(ctx, h, "dense")
 
 

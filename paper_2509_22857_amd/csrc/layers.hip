@@ -49,6 +49,7 @@ struct ckc_layer {
     DevMem bpt, cpt;                   // [C][nl][N] NTT-form plaintexts (constants or block-constant vectors)
     // dense
     int K = 0;
+    bool spatial = false;              // weights per grid position: products first, slot sums of the K outputs
     std::vector<int32_t> sum_steps;
     DevMem dconst, bconst;             // dense with one member: [K][C][nl] and [K][nl] constant residues
     size_t bytes = 0;
@@ -741,16 +742,16 @@ extern "C" int ckc_layer_create_act(ckc_ctx *c, const ckc_layout *layout, int ch
     return CKC_OK;
 }
 
-extern "C" int ckc_layer_create_dense(ckc_ctx *c, const ckc_layout *in, int classes, int in_ch, const double *w,
-                                      const double *bias, int level, double pt_scale, double bias_scale,
-                                      ckc_layer **out, void *stream) {
-    CKC_REQUIRE(c && out && w, CKC_EINVAL, "null argument");
+namespace {
+// the fields both dense forms share: sizes, scales, output layout (one grid
+// point), and the rotation steps of the slot sums over the grid
+int dense_common(ckc_ctx *c, const ckc_layout *in, int classes, int in_ch, int level, double pt_scale,
+                 double bias_scale, std::unique_ptr<ckc_layer> &L) {
     CKC_TRY(check_layout(c, in));
     CKC_REQUIRE(is_pow2(in->height) && is_pow2(in->width), CKC_EUNSUPPORTED, "dense: grid sides must be powers of two");
     CKC_REQUIRE(classes >= 1 && in_ch >= 1, CKC_EINVAL, "bad sizes");
     CKC_REQUIRE(level >= 0 && level < c->nq, CKC_ELEVEL, "level out of range");
-    hipStream_t s = S(stream);
-    auto L = std::make_unique<ckc_layer>();
+    L = std::make_unique<ckc_layer>();
     L->kind = LK_DENSE;
     L->lin = *in;
     L->lout = *in;
@@ -762,6 +763,17 @@ extern "C" int ckc_layer_create_dense(ckc_ctx *c, const ckc_layout *in, int clas
     L->bias_scale = bias_scale;
     for (int j = 1; j < in->width; j <<= 1) L->sum_steps.push_back(in->gap * j);
     for (int j = 1; j < in->height; j <<= 1) L->sum_steps.push_back(in->gap * in->row_stride * j);
+    return CKC_OK;
+}
+}  // namespace
+
+extern "C" int ckc_layer_create_dense(ckc_ctx *c, const ckc_layout *in, int classes, int in_ch, const double *w,
+                                      const double *bias, int level, double pt_scale, double bias_scale,
+                                      ckc_layer **out, void *stream) {
+    CKC_REQUIRE(c && out && w, CKC_EINVAL, "null argument");
+    hipStream_t s = S(stream);
+    std::unique_ptr<ckc_layer> L;
+    CKC_TRY(dense_common(c, in, classes, in_ch, level, pt_scale, bias_scale, L));
     const int nl = level + 1, M = in->members;
     const size_t N = c->N, n = N / 2, pw = size_t(nl) * N;
     if (M == 1) {
@@ -802,6 +814,42 @@ extern "C" int ckc_layer_create_dense(ckc_ctx *c, const ckc_layout *in, int clas
         }
     }
     L->bytes = L->pts.bytes + L->bias.bytes + L->dconst.bytes + L->bconst.bytes;
+    *out = L.release();
+    return CKC_OK;
+}
+
+extern "C" int ckc_layer_create_dense_spatial(ckc_ctx *c, const ckc_layout *in, int classes, int in_ch,
+                                              const double *w, const double *bias, int level, double pt_scale,
+                                              double bias_scale, ckc_layer **out, void *stream) {
+    CKC_REQUIRE(c && out && w, CKC_EINVAL, "null argument");
+    hipStream_t s = S(stream);
+    std::unique_ptr<ckc_layer> L;
+    CKC_TRY(dense_common(c, in, classes, in_ch, level, pt_scale, bias_scale, L));
+    L->spatial = true;
+    const int nl = level + 1, M = in->members, H = in->height, W = in->width;
+    const size_t N = c->N, n = N / 2, pw = size_t(nl) * N;
+    CKC_TRY(L->pts.alloc(8 * pw * classes * in_ch));
+    std::vector<double> v(n, 0.0);
+    for (int k = 0; k < classes; ++k)
+        for (int ch = 0; ch < in_ch; ++ch) {
+            // w[m][k][ch][r][col] at member m's grid point (r, col)
+            for (int m = 0; m < M; ++m)
+                for (int r = 0; r < H; ++r)
+                    for (int col = 0; col < W; ++col)
+                        v[size_t(m) * in->block + size_t(in->gap) * (size_t(r) * in->row_stride + col)] =
+                            w[(((size_t(m) * classes + k) * in_ch + ch) * H + r) * W + col];
+            CKC_TRY(encode_impl(c, v.data(), n, level, pt_scale, L->pts.u64() + (size_t(k) * in_ch + ch) * pw, s));
+        }
+    if (bias) {
+        L->has_bias = true;
+        std::fill(v.begin(), v.end(), 0.0);
+        CKC_TRY(L->bias.alloc(8 * pw * classes));
+        for (int k = 0; k < classes; ++k) {
+            for (int m = 0; m < M; ++m) v[size_t(m) * in->block] = bias[size_t(m) * classes + k];
+            CKC_TRY(encode_impl(c, v.data(), n, level, bias_scale, L->bias.u64() + size_t(k) * pw, s));
+        }
+    }
+    L->bytes = L->pts.bytes + L->bias.bytes;
     *out = L.release();
     return CKC_OK;
 }
@@ -1175,7 +1223,9 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
         const int total = ni * C;
         DevBuf Sb, Tb, Z;
         CKC_TRY(Sb.alloc(8 * ctw * total, s));
-        CKC_TRY(Tb.alloc(8 * ctw * std::min(total, kMaxBatch), s));
+        // rotated copies of one batch of the summed ciphertexts (inputs, or
+        // in the spatial form the K outputs of each image)
+        CKC_TRY(Tb.alloc(8 * ctw * std::min(L->spatial ? ni * K : total, kMaxBatch), s));
         CKC_TRY(Z.alloc(8 * ctw * ni * K, s));
         // S = inputs
         for (int b0 = 0; b0 < total; b0 += kMaxBatch) {
@@ -1184,22 +1234,29 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
             for (int b = 0; b < nb; ++b) ip.p[b] = in[size_t(img0) * C + b0 + b].d;
             CKC_TRY(gather(ip, 0, Sb.u64() + size_t(b0) * ctw, ctw, ctw, nb, s));
         }
-        // rotation sums: S <- S + Rot_step(S), steps in order
-        for (int32_t st : L->sum_steps) {
-            for (int b0 = 0, nb = 0; b0 < total; b0 += nb) {
-                // a batch shares one key set (a key group splits it)
-                nb = key_run(evk, img0 * C + b0, std::min(kMaxBatch, total - b0), C);
-                const ckc_evk *ek = evk_of(evk, img0 + b0 / C);
-                Ptrs sp, tp;
-                for (int b = 0; b < nb; ++b) {
-                    sp.p[b] = Sb.u64() + size_t(b0 + b) * ctw;
-                    tp.p[b] = Tb.u64() + size_t(b) * ctw;
+        // rotation sums X <- X + Rot_step(X), steps in order, over the n
+        // ciphertexts at X (per image, `per` of them)
+        auto slot_sums = [&](uint64_t *X, int n, int per) -> int {
+            for (int32_t st : L->sum_steps) {
+                for (int b0 = 0, nb = 0; b0 < n; b0 += nb) {
+                    // a batch shares one key set (a key group splits it)
+                    nb = key_run(evk, img0 * per + b0, std::min(kMaxBatch, n - b0), per);
+                    const ckc_evk *ek = evk_of(evk, img0 + b0 / per);
+                    Ptrs sp, tp;
+                    for (int b = 0; b < nb; ++b) {
+                        sp.p[b] = X + size_t(b0 + b) * ctw;
+                        tp.p[b] = Tb.u64() + size_t(b) * ctw;
+                    }
+                    std::vector<Ptrs> dst{tp};
+                    CKC_TRY(hoisted_group(c, ek, sp, nb, L->level, std::vector<int32_t>{st}, dst, s));
+                    CKC_TRY(ew_b(c, EW_ADD, sp, sp, &tp, nb, 2, nl, s));
                 }
-                std::vector<Ptrs> dst{tp};
-                CKC_TRY(hoisted_group(c, ek, sp, nb, L->level, std::vector<int32_t>{st}, dst, s));
-                CKC_TRY(ew_b(c, EW_ADD, sp, sp, &tp, nb, 2, nl, s));
             }
-        }
+            return CKC_OK;
+        };
+        // grid-average form: the channels' slot sums first; spatial form:
+        // the products first, then the slot sums of the K outputs
+        if (!L->spatial) CKC_TRY(slot_sums(Sb.u64(), total, C));
         {
             CKC_PROF(PK_DENSE_MAC, s, 8.0 * N * nl * (2.0 * ni * C + double(K) * C + 2.0 * ni * K),
                      2.0 * N * nl * double(ni) * K * C);
@@ -1210,6 +1267,7 @@ extern "C" int ckc_eval_dense(ckc_ctx *c, const ckc_evk *evk, const ckc_layer *L
                            c->logN);
         }
         CKC_HIP(hipGetLastError());
+        if (L->spatial) CKC_TRY(slot_sums(Z.u64(), ni * K, K));
         for (int b0 = 0; b0 < ni * K; b0 += kMaxBatch) {
             const int nb = std::min(kMaxBatch, ni * K - b0);
             Ptrs op;

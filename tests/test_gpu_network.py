@@ -179,6 +179,36 @@ def test_small_vgg_bit_exact(hoist):
         assert np.max(np.abs(got - ref)) < 1e-3
 
 
+@pytest.mark.parametrize("members", [1, 2])
+def test_small_vgg_flattened_dense_bit_exact(members):
+    """VGG-style network whose dense layer weighs every position of the
+    flattened final map (ckc_layer_create_dense_spatial: the products with
+    the K x C weight maps first, then the rotation sums of the K outputs):
+    every layer bit-exact with the oracle, logits within 1e-3 of FP64; one
+    and two members."""
+    spec = nets.vgg_spec(seed=5, widths=(4, 4, 8, 8, 8), classes=5, image=(3, 16, 16), k=6, calib=4,
+                         members=members, dense="flatten")
+    ps = small_tower(logN=12, levels=6)
+    D = 2.0 ** 30
+    print(f"[vgg_flatten] N=2^12 widths=(4,4,8,8,8) members={members} dense over the flattened 4x4 map", flush=True)
+    ctx, gnet, keys, o, onet, sk, rlk, gk = _setup(ps, spec, D, D, D, 33)
+    imgs = gen.images(16, 2, 3, 16, 16)
+    gin = gnet.encrypt_images(keys, imgs, 950)
+    gl = []
+    gout, _ = gnet.run(keys, gin, hook=lambda ly, outs: gl.append((ly["name"], _coeff(ctx, outs[0]))))
+    oin = onet.encrypt_image(sk, imgs[0], 950)
+    ol = []
+    oout, _ = onet.run(sk, oin, rlk, gk, hook=lambda ly, outs: ol.append((ly["name"], outs[0].data)))
+    assert [n for n, _ in gl] == [n for n, _ in ol]
+    for (n1, a), (n2, b) in zip(gl, ol):
+        assert np.array_equal(a, b), n1
+    from oracle.forward import forward
+    for n in range(2):
+        ref = forward(spec, imgs[n])
+        got = gnet.decrypt_logits(keys, gout[n])
+        assert np.max(np.abs(got - ref)) < 1e-3
+
+
 def test_graphed_pass_replays_match_eager():
     """A network pass captured as a HIP graph and replayed for new inputs
     (eager work and synchronisations in between) gives the eager ciphertexts

@@ -99,6 +99,32 @@ def test_activation_and_dense_network_decrypts_to_forward():
     assert np.max(np.abs(got - ref)) < 1e-4
 
 
+def test_flattened_dense_network_decrypts_to_forward():
+    """A VGG-style network whose dense layer weighs every position of the
+    flattened final map (the products first, then the slot sums over the
+    grid): the oracle's logits are the FP64 forward's, and the forward's
+    dense is the dot product with the flattened map, written out."""
+    spec = nets.vgg_spec(seed=3, widths=(4, 6), pool_after=(0,), classes=3, image=(3, 8, 8), k=6, calib=4,
+                         dense="flatten")
+    assert np.shape(spec["layers"][-1]["w"]) == (1, 3, 6, 4, 4)
+    ps = small_tower(logN=12, levels=6)
+    o = Oracle.from_params(ps)
+    D = 2.0 ** 30
+    net = OracleNetwork(o, spec, delta=D, target=D, in_scale=D)
+    sk = o.secret_key(14)
+    rlk = o.relin_key(sk)
+    gk = {o.galois_elt(s): o.galois_key(sk, o.galois_elt(s)) for s in net.steps()}
+    img = gen.images(15, 1, 3, 8, 8)[0]
+    outs, _ = net.run(sk, net.encrypt_image(sk, img, 100), rlk, gk)
+    got = np.array([[o.decrypt_decode(c, sk)[0] for c in outs]])
+    cap = {}
+    ref = forward(spec, img, capture=cap)
+    fc = spec["layers"][-1]
+    fmap = cap[fc["inp"]][0]
+    assert np.allclose(ref[0], np.einsum("kchw,chw->k", fc["w"][0], fmap) + fc["bias"][0], rtol=0, atol=1e-12)
+    assert np.max(np.abs(got - ref)) < 1e-4
+
+
 @pytest.mark.slow
 def test_small_resnet_ensemble_decrypts_to_forward():
     spec = nets.resnet_spec(seed=1, members=2, widths=(4, 8), blocks=1, classes=10, image=(3, 16, 16), k=8, calib=4)

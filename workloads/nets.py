@@ -227,13 +227,16 @@ def resnet_spec(seed: int = 0, members: int = 4, widths=(16, 32, 64), blocks: in
 
 def vgg_spec(seed: int = 0, widths=(64, 64, 128, 128, 256), pool_after=(1, 3), classes: int = 10,
              image=(3, 32, 32), k: int = 16, calib: int = 8, members: int = 1, name: str | None = None,
-             pre_std: float = 0.5, hoist=None) -> dict:
+             pre_std: float = 0.5, hoist=None, dense: str = "gap") -> dict:
     """VGG-style network: one 3x3 convolution (stride 1) and one quadratic
     activation per entry of `widths`, 2x2 average pooling after the layers
-    listed in pool_after, global average pooling folded into the dense layer.
-    Weights N(0, 0.05) standardised per output channel (folded batch
-    normalisation); activation coefficients a ~ U[0.05, 0.2] and
-    b, c ~ U[-0.5, 0.5]; slice clustering with k centroids per layer."""
+    listed in pool_after, then the dense layer: over the global average
+    pooling (dense="gap", folded into its weights) or over the flattened
+    final map (dense="flatten": a weight N(0, 0.05) per class, channel and
+    position, unclustered).  Weights N(0, 0.05) standardised per output
+    channel (folded batch normalisation); activation coefficients
+    a ~ U[0.05, 0.2] and b, c ~ U[-0.5, 0.5]; slice clustering with k
+    centroids per layer."""
     g = rng(seed)
     M = members
     Cin, H, W = image
@@ -252,10 +255,15 @@ def vgg_spec(seed: int = 0, widths=(64, 64, 128, 128, 256), pool_after=(1, 3), c
             raw.append(("pool", dict(name=f"pool{li}", inp=cur_name, out=f"p{li}")))
             cur, cur_name = _avgpool2(cur), f"p{li}"
     Hf, Wf = cur.shape[3], cur.shape[4]
-    pooled = cur.sum(axis=(3, 4))
-    Wd = g.normal(0.0, 0.05, (M, classes, cin)) / (Hf * Wf)
-    bd = g.normal(0.0, 0.1, (M, classes))
-    logits = np.einsum("mbc,mkc->mbk", pooled, Wd) + bd[:, None, :]
+    if dense == "flatten":
+        Wd = g.normal(0.0, 0.05, (M, classes, cin, Hf, Wf))
+        bd = g.normal(0.0, 0.1, (M, classes))
+        logits = np.einsum("mbchw,mkchw->mbk", cur, Wd) + bd[:, None, :]
+    else:
+        pooled = cur.sum(axis=(3, 4))
+        Wd = g.normal(0.0, 0.05, (M, classes, cin)) / (Hf * Wf)
+        bd = g.normal(0.0, 0.1, (M, classes))
+        logits = np.einsum("mbc,mkc->mbk", pooled, Wd) + bd[:, None, :]
     s = 1.0 / max(_rms(logits), 1e-12)
     raw.append(("dense", dict(name="fc", inp=cur_name, out="logits", W=Wd * s, b=bd * s)))
     spec = _finalise(raw, name or f"vgg_{'-'.join(map(str, widths))}_M{M}_k{k}", M, classes, image, k, seed, None)
@@ -345,7 +353,8 @@ def _finalise(raw, name, M, classes, image, k, seed, block_slots):
         elif kind == "dense":
             W = d["W"].copy()
             if d["inp"] in act_scale:
-                W = W * act_scale[d["inp"]][:, None, :]
+                sc = act_scale[d["inp"]][:, None, :]
+                W = W * (sc[..., None, None] if W.ndim == 5 else sc)
             layers.append(dict(op="dense", name=d["name"], inp=d["inp"], out=d["out"], w=W, bias=d["b"].copy()))
         elif kind == "pool":
             layers.append(dict(op="pool", name=d["name"], inp=d["inp"], out=d["out"]))
