@@ -241,7 +241,8 @@ def test_graphed_pass_replays_match_eager():
 def test_native_runner_matches_python_orchestration():
     """The library's native runner (ckc_batch_plan / ckc_batch_run) executes
     the same layer program as the Python orchestration, bit for bit: a small
-    ResNet ensemble (residual shortcuts, stride 2) and a small VGG (pooling),
+    ResNet ensemble (residual shortcuts, stride 2) and a small VGG (pooling;
+    the dense after global average pooling, and over the flattened map),
     two requests under one key set batched together, a third under another
     key set in its own pass."""
     from paper_2509_22857_amd import ckks
@@ -251,6 +252,8 @@ def test_native_runner_matches_python_orchestration():
                                     calib=4), small_tower(logN=12, levels=6)),
         ("vgg", nets.vgg_spec(seed=2, widths=(4, 4, 8, 8, 8), classes=5, image=(3, 16, 16), k=6, calib=4),
          small_tower(logN=12, levels=6)),
+        ("vgg_flatten", nets.vgg_spec(seed=2, widths=(4, 4, 8, 8, 8), classes=5, image=(3, 16, 16), k=6, calib=4,
+                                      dense="flatten"), small_tower(logN=12, levels=6)),
     ]
     from paper_2509_22857_amd.ckks import Context
     from paper_2509_22857_amd.network import GpuNetwork
