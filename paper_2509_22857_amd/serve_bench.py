@@ -121,7 +121,15 @@ def run(args, log, reference=None) -> dict:
             cts = networks[net].encrypt_images(keys[(c, net)], img, stream_base=((ri + 1) << 24) + (i << 12))
             reqs.append(Request(i, c, net, cts, float(arr[i])))
         torch.cuda.synchronize()
-        stats = srv.serve(reqs)
+        last = [0]
+
+        def progress(t, done, total):
+            # a line about every eighth of the requests
+            if done == total or done * 8 // total != last[0] * 8 // total:
+                log(f"rate {rate} req/s: {done}/{total} served at {t:.0f} s")
+            last[0] = done
+
+        stats = srv.serve(reqs, progress=progress)
         torch.cuda.synchronize()
         per_net = {}
         for net in ("resnet18", "resnet20"):

@@ -98,9 +98,10 @@ class Server:
         self.key_bytes += nbytes
 
     # ------------------------------------------------------------------ loop
-    def serve(self, requests: list, clock=time.perf_counter) -> dict:
+    def serve(self, requests: list, clock=time.perf_counter, progress=None) -> dict:
         """Replay `requests` (sorted by arrival, seconds from the start) in
-        real time and return per-request timing plus aggregate statistics."""
+        real time and return per-request timing plus aggregate statistics.
+        progress(t, done, total), if given, is called at every retirement."""
         torch = self.torch
         self.stats = collections.Counter()
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -110,6 +111,7 @@ class Server:
         t0 = clock()
         next_bid = 0
         max_running = 0
+        n_done = 0
         waiting = None
         blocked = False  # a scratch reservation failed: admit again after a retirement
         while pending or queue or running:
@@ -250,6 +252,9 @@ class Server:
                     b.keys = None
                     blocked = False
                     progressed = True
+                    if progress is not None:
+                        n_done += len(b.reqs)
+                        progress(t_done, n_done, len(requests))
             if not progressed:
                 # nothing to enqueue: wait a little for the GPU or the next arrival
                 wait = 5e-4
