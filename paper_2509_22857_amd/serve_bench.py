@@ -145,7 +145,10 @@ def run(args, log, reference=None) -> dict:
         stats.update({"rate_req_s": rate, "per_network": per_net, "budget_GiB": round(srv.budget / 2**30, 1)})
         log(f"rate {rate:5.1f} req/s: {stats}")
         results.append(stats)
+        # the next rate starts from the same free memory: the request
+        # tensors go back to the device, not to torch's cache
         del reqs
+        torch.cuda.empty_cache()
     cap = max(r["images_per_s"] for r in results if r["images_per_s"] == r["images_per_s"])
     return {
         "metric": "serving p50/p99 latency and images/s (ResNet-18/20-style mix, N=2^16, Poisson arrivals)",
