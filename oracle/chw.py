@@ -1,0 +1,157 @@
+"""A network in the CHW layout, on the oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may import
+this module; the product path never does.
+
+Layout (Section 5.1, Data Layout, the alternative to the HW layout that
+packs several channels into one ciphertext): every channel of an image in one
+ciphertext, channel c's H x W grid in the slot block [c B, (c + 1) B) with
+B = H W, pixel (r, x) at slot c B + r W + x.  The C blocks fill the N/2
+slots (C B = N/2), so a rotation by a multiple of B turns the channel index
+cyclically.
+
+Convolution (3x3, 'same', stride 1, C -> C channels) is the diagonal form of
+a matrix-vector product over channels (Halevi and Shoup's diagonal
+method): with s_t = dh W + dw the slot offset of tap t = (dh + 1, dw + 1),
+
+    y = sum_{d < C} sum_{t < 9} P_{d,t} * Rot(x, d B + s_t),
+
+where Rot is the left rotation of the slots and P_{d,t} holds, on output
+block o, the weight w[o][(o + d) mod C][t] at every pixel (r, x) whose
+source pixel (r + dh, x + dw) lies on the grid and zero elsewhere (the zero
+padding of 'same').  The bias (b[o] on block o) is added before the rescale.
+Plaintexts are encoded at scale q_l Delta / s for an input at level l and
+scale s, so every layer's output returns to scale Delta (up to the float
+arithmetic of the scales).
+
+The other layers: the monic quadratic activation x^2 + b x + c (Section 2.3)
+as Relin(x (x) x) + x * P_b + P_c (b[c], c[c] on block c; P_b at the input's
+scale s, P_c at s^2), then a rescale; global sum pooling as log2(B) doubling
+rotations (slot c B then holds the sum of block c); the dense layer, one
+ciphertext per class k: x * P_k with P_k = w[k][c] at slot c B, log2(C)
+doubling rotations by multiples of B (slot 0 then holds the logit), the bias
+at slot 0, a rescale.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .ckks import Ct, Oracle, SecretKey
+
+
+def _taps():
+    """(dh, dw) of the 9 taps, tap t = 3 (dh + 1) + (dw + 1)."""
+    return [(t // 3 - 1, t % 3 - 1) for t in range(9)]
+
+
+class OracleChw:
+    def __init__(self, o: Oracle, spec: dict, delta: float):
+        self.o, self.spec, self.delta = o, spec, float(delta)
+        self.C, self.H, self.W = spec["image"]
+        self.B = self.H * self.W
+        self.n = o.N // 2
+        if self.C * self.B != self.n:
+            raise ValueError("the CHW layout here fills the slots: C H W must equal N/2")
+        if self.C & (self.C - 1) or self.B & (self.B - 1):
+            raise ValueError("C and H W must be powers of two (doubling rotations)")
+
+    # --------------------------------------------------------------- steps
+    def conv_steps(self) -> list[int]:
+        return [d * self.B + dh * self.W + dw for d in range(self.C) for (dh, dw) in _taps()]
+
+    def steps(self) -> list[int]:
+        pool = [1 << j for j in range(self.B.bit_length() - 1)]
+        chan = [self.B << j for j in range(self.C.bit_length() - 1)]
+        return sorted(set(self.conv_steps()) | set(pool) | set(chan))
+
+    # -------------------------------------------------------------- client
+    def slots_of(self, img: np.ndarray) -> np.ndarray:
+        z = np.zeros(self.n)
+        for c in range(self.C):
+            z[c * self.B:(c + 1) * self.B] = np.asarray(img[c], dtype=np.float64).reshape(-1)
+        return z
+
+    def encrypt_image(self, sk: SecretKey, img: np.ndarray, stream_id: int) -> Ct:
+        pt = self.o.encode(self.slots_of(img), self.o.L, self.delta)
+        return self.o.encrypt(pt, sk, stream_id)
+
+    def grid_of(self, z: np.ndarray) -> np.ndarray:
+        """[C][H][W] view of a decoded slot vector."""
+        return np.asarray(z[:self.n]).reshape(self.C, self.H, self.W)
+
+    # -------------------------------------------------------------- layers
+    def _diagonal(self, w: np.ndarray, d: int, dh: int, dw: int) -> np.ndarray:
+        z = np.zeros(self.n)
+        for oc in range(self.C):
+            ic = (oc + d) % self.C
+            for r in range(self.H):
+                if not 0 <= r + dh < self.H:
+                    continue
+                for x in range(self.W):
+                    if 0 <= x + dw < self.W:
+                        z[oc * self.B + r * self.W + x] = w[oc, ic, dh + 1, dw + 1]
+        return z
+
+    def _blocks(self, v: np.ndarray) -> np.ndarray:
+        z = np.zeros(self.n)
+        for c in range(self.C):
+            z[c * self.B:(c + 1) * self.B] = v[c]
+        return z
+
+    def conv(self, x: Ct, w: np.ndarray, b: np.ndarray, gk: dict) -> Ct:
+        o = self.o
+        pt_scale = float(o.q[x.level]) * self.delta / x.scale
+        acc = None
+        for d in range(self.C):
+            for (dh, dw) in _taps():
+                step = d * self.B + dh * self.W + dw
+                g = o.galois_elt(step)
+                rot = o.rotate(x, step, gk.get(g))
+                term = o.mul_plain(rot, o.encode(self._diagonal(w, d, dh, dw), x.level, pt_scale))
+                acc = term if acc is None else o.add(acc, term)
+        acc = o.add_plain(acc, o.encode(self._blocks(b), x.level, acc.scale))
+        return o.rescale(acc)
+
+    def act(self, x: Ct, b: np.ndarray, c: np.ndarray, rlk: np.ndarray) -> Ct:
+        o = self.o
+        sq = o.relin(o.tensor(x, x), rlk)
+        lin = o.mul_plain(x, o.encode(self._blocks(b), x.level, x.scale))
+        y = o.add(sq, lin)
+        y = o.add_plain(y, o.encode(self._blocks(c), x.level, y.scale))
+        return o.rescale(y)
+
+    def pool(self, x: Ct, gk: dict) -> Ct:
+        o = self.o
+        for j in range(self.B.bit_length() - 1):
+            step = 1 << j
+            x = o.add(x, o.rotate(x, step, gk[o.galois_elt(step)]))
+        return x
+
+    def dense(self, x: Ct, w: np.ndarray, bias: np.ndarray, gk: dict) -> list[Ct]:
+        o = self.o
+        pt_scale = float(o.q[x.level]) * self.delta / x.scale
+        outs = []
+        for k in range(w.shape[0]):
+            z = np.zeros(self.n)
+            z[np.arange(self.C) * self.B] = w[k]
+            y = o.mul_plain(x, o.encode(z, x.level, pt_scale))
+            for j in range(self.C.bit_length() - 1):
+                step = self.B << j
+                y = o.add(y, o.rotate(y, step, gk[o.galois_elt(step)]))
+            zb = np.zeros(self.n)
+            zb[0] = bias[k]
+            y = o.add_plain(y, o.encode(zb, y.level, y.scale))
+            outs.append(o.rescale(y))
+        return outs
+
+    def run(self, x: Ct, rlk: np.ndarray, gk: dict) -> dict:
+        """Every stage's output: conv1, act, conv2, pool (ciphertexts) and
+        logits (one ciphertext per class, the logit at slot 0)."""
+        s = self.spec
+        out = {}
+        out["conv1"] = self.conv(x, s["conv1_w"], s["conv1_b"], gk)
+        out["act"] = self.act(out["conv1"], s["act_b"], s["act_c"], rlk)
+        out["conv2"] = self.conv(out["act"], s["conv2_w"], s["conv2_b"], gk)
+        out["pool"] = self.pool(out["conv2"], gk)
+        out["logits"] = self.dense(out["pool"], s["fc_w"], s["fc_b"], gk)
+        return out

@@ -88,3 +88,19 @@ def forward(spec: dict, img: np.ndarray, capture: dict | None = None) -> np.ndar
                 capture.setdefault(ly["out"], []).append(y)
         outs.append(t[spec["layers"][-1]["out"]])
     return np.array(outs)
+
+
+def forward_chw(spec: dict, img: np.ndarray, capture: dict | None = None) -> np.ndarray:
+    """The CHW-layout network of workloads.nets.chw_spec in float64: 'same'
+    3x3 convolution, monic quadratic activation per channel, convolution,
+    global sum pooling, dense.  img: [C][H][W] -> logits [K]; with capture,
+    the intermediate tensors by stage name."""
+    x = np.asarray(img, dtype=np.float64)
+    y1 = _conv(x, spec["conv1_w"], spec["conv1_b"], 1)
+    a = y1 * y1 + spec["act_b"][:, None, None] * y1 + spec["act_c"][:, None, None]
+    y2 = _conv(a, spec["conv2_w"], spec["conv2_b"], 1)
+    pooled = y2.sum(axis=(1, 2))
+    logits = spec["fc_w"] @ pooled + spec["fc_b"]
+    if capture is not None:
+        capture.update(conv1=y1, act=a, conv2=y2, pool=pooled, logits=logits)
+    return logits

@@ -190,6 +190,20 @@ def small_tower(logN: int = 12, levels: int = 4, big_bits: int = 60,
                     alpha=alpha, delta_log2=delta_bits, note="test-only")
 
 
+@lru_cache(maxsize=None)
+def chw_chain(logN: int = 12, levels: int = 4, delta_bits: int = 40) -> ParamSet:
+    """A plain (non-tower) chain for the CHW-layout network: a 60-bit q_0 that
+    holds the logits, `levels` primes of delta_bits bits that the rescales
+    drop (one per layer), one 61-bit special prime, one prime per digit.
+    Test and measurement only."""
+    two_n = 2 << logN
+    q0 = nearest_prime(60, two_n)
+    q = [q0] + balanced_chain([delta_bits] * levels, two_n, exclude=[q0])
+    p = [nearest_prime(61, two_n, exclude=q)]
+    return ParamSet(f"chw_N{logN}_L{levels}", logN, tuple(q), tuple(p), alpha=1, delta_log2=delta_bits,
+                    note="test-only")
+
+
 def by_name(name: str) -> ParamSet:
     table = {"tiny": tiny, "mid": mid, "micro": micro}
     if name in table:
