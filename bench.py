@@ -338,6 +338,53 @@ def cpu_baseline(ps, spec, gpu_products_per_image=None):
                        f"{sec_per_image:.0f} s per image{chk}")}
 
 
+def run_chw(args):
+    """The CHW layout (every channel of an image in one ciphertext), a
+    separate labelled row: 32 channels of 32 x 32 fill the 2^15 slots of
+    N = 2^16; conv 32 -> 32 (288 rotations as one hoisted group, 288
+    plaintext products), quadratic activation, conv, sum pooling, dense to 10
+    classes, on a plain 4-level chain (60-bit q_0, 40-bit primes).  Images
+    run one at a time; every image's logits are checked against the float64
+    forward.  Prints its own JSON line."""
+    import torch
+    from oracle.forward import forward_chw
+    from paper_2509_22857_amd.chw import ChwNetwork
+    from paper_2509_22857_amd.ckks import Context
+    from workloads import gen
+    from workloads.nets import chw_spec
+    from workloads.params import chw_chain
+    ps = chw_chain(16, 4)
+    spec = chw_spec(0, C=32, H=32, W=32, classes=10)
+    ctx = Context.from_params(ps)
+    delta = 2.0 ** ps.delta_log2
+    net = ChwNetwork(ctx, spec, delta)
+    t0 = time.time()
+    keys = ctx.keygen(12345, net.steps)
+    torch.cuda.synchronize()
+    log(f"chw: {len(net.steps)} rotation keys, {keys.evk_bytes() / 2**30:.1f} GiB, {time.time() - t0:.1f}s")
+    B = args.batch
+    imgs = gen.images(777, B, *spec["image"])
+    cts = [net.encrypt_image(keys, imgs[i], (1 << 20) + i) for i in range(B)]
+    for i in range(min(args.warmup, B)):
+        net.run(keys, cts[i])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    outs = [net.run(keys, c)["logits"] for c in cts]
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    err = max(float(np.max(np.abs(net.decrypt_logits(keys, o) - forward_chw(spec, imgs[i])))) for i, o in enumerate(outs))
+    log(f"chw: {B} images in {dt:.2f}s, logits within {err:.2e} of FP64")
+    print(json.dumps({
+        "metric": "encrypted images/s (CHW layout network, N=2^16, one image per ciphertext)",
+        "value": round(B / dt, 4), "unit": "images/s", "n_gpus": 1, "steps": B, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / B, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "chw_N65536", "channels": 32, "image": [32, 32], "classes": 10,
+                   "levels": len(ps.q) - 1, "rotations_per_conv": len(net.rotation_steps()),
+                   "rotation_keys": len(net.steps), "key_GiB": round(keys.evk_bytes() / 2**30, 2)},
+        "accuracy": {"max_abs_logit_err": err}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,7 +401,7 @@ def main():
                     help="where --tune fresh writes the choices it measured")
     ap.add_argument("--tune", default="cached", choices=["cached", "fresh", "off"],
                     help="autotuner: stored choices for this workload if any (else tune), re-tune, or defaults")
-    ap.add_argument("--workload", default="resnet20", choices=["resnet20", "vgg", "micro", "serving"])
+    ap.add_argument("--workload", default="resnet20", choices=["resnet20", "vgg", "micro", "serving", "chw"])
     ap.add_argument("--layout", default="slice", choices=["slice", "taps"],
                     help="slice-shared codebook (default) or one plaintext per tap")
     ap.add_argument("--pack", type=int, default=1,
@@ -384,6 +431,9 @@ def main():
 
     if args.pack > 1:
         run_packed(args)
+        return
+    if args.workload == "chw":
+        run_chw(args)
         return
 
     import torch

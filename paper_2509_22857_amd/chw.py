@@ -1,0 +1,173 @@
+"""Networks in the CHW layout: every channel of an image in one ciphertext.
+
+Section 5.1 (Data Layout) names this packing as the alternative to the HW
+layout the paper keeps.  Channel c's H x W grid takes the slot block
+[c B, (c + 1) B), B = H W, pixel (r, x) at slot c B + r W + x, and the C
+blocks fill the N/2 slots, so a rotation by j B moves channel c + j onto
+block c (channel indices mod C).
+
+A 3x3 'same' convolution from C to C channels is then the diagonal method
+(Halevi and Shoup) over channels: for each channel distance j < C and tap
+(dh, dw) one rotation of the input by j B + dh W + dw, and one plaintext
+that carries, on output block o, the weight from input channel (o + j) mod C
+for that tap wherever the tap's source pixel is on the grid (zero
+elsewhere: the zero padding).  Its 9 C rotations are one hoisted rotation
+group (one ModUp of the input), its 9 C products plaintext multiply-
+accumulates; the bias joins before the rescale.  The plaintexts are encoded
+at scale q_l Delta / s for an input at level l and scale s, so every layer
+leaves scale Delta.
+
+Activation (monic quadratic x^2 + b x + c, Section 2.3): the relinearised
+square plus x times the plaintext of b (at scale s) plus the plaintext of c
+(at scale s^2), then a rescale.  Pooling: log2(B) doubling rotations leave
+the sum of block c at slot c B.  Dense: per class, the pooled ciphertext
+times the plaintext of that class's weights (at slots c B), log2(C)
+doubling rotations by multiples of B leave the logit at slot 0, bias, rescale.
+
+Every step runs in the library's kernels through its C-ABI (hoisted
+rotation groups, plaintext MACs, products with relinearisation, additions,
+rescales); this module only builds the plaintext slot vectors and sequences
+the calls.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ckks
+
+_TAPS = [(dh, dw) for dh in (-1, 0, 1) for dw in (-1, 0, 1)]  # tap t = 3 (dh + 1) + (dw + 1)
+_MAC_TERMS = 64  # most terms of one ckc_mac_plain_many output
+
+
+class ChwNetwork:
+    """The network of workloads.nets.chw_spec (conv, activation, conv, sum
+    pooling, dense) on one context."""
+
+    def __init__(self, ctx: ckks.Context, spec: dict, delta: float):
+        self.ctx, self.spec, self.delta = ctx, spec, float(delta)
+        self.C, self.H, self.W = spec["image"]
+        self.B = self.H * self.W
+        self.slots = ctx.N // 2
+        if self.C * self.B != self.slots:
+            raise ValueError(f"CHW layout: C H W = {self.C * self.B} must equal N/2 = {self.slots}")
+        if self.C & (self.C - 1) or self.B & (self.B - 1):
+            raise ValueError("CHW layout: C and H W must be powers of two")
+        self.logB, self.logC = self.B.bit_length() - 1, self.C.bit_length() - 1
+        # valid-source masks per tap, [9][H][W]
+        r = np.arange(self.H)[:, None]
+        x = np.arange(self.W)[None, :]
+        self.masks = np.stack([((r + dh >= 0) & (r + dh < self.H) & (x + dw >= 0) & (x + dw < self.W))
+                               .astype(np.float64) for dh, dw in _TAPS])
+        # encoded plaintexts by (layer, index, level, scale): a layer's inputs
+        # arrive at one level and scale every time, so each is encoded once
+        self._pts = {}
+
+    def _pt(self, key, level: int, scale: float, slots, stream=None) -> ckks.Plaintext:
+        k = (key, level, scale)
+        if k not in self._pts:
+            self._pts[k] = self.ctx.encode(slots() if callable(slots) else slots, level, scale, stream=stream)
+        return self._pts[k]
+
+    # ------------------------------------------------------------------ keys
+    def rotation_steps(self) -> list[int]:
+        """The conv group's steps (channel distance major, tap minor)."""
+        return [j * self.B + dh * self.W + dw for j in range(self.C) for dh, dw in _TAPS]
+
+    @property
+    def steps(self) -> list[int]:
+        """Every rotation step a run needs keys for (the identity excluded)."""
+        st = set(self.rotation_steps())
+        st.update(1 << i for i in range(self.logB))
+        st.update(self.B << i for i in range(self.logC))
+        st.discard(0)
+        return sorted(st)
+
+    # ---------------------------------------------------------------- client
+    def encrypt_image(self, keys: ckks.KeyPair, img: np.ndarray, stream_id: int) -> ckks.Ciphertext:
+        z = np.asarray(img, dtype=np.float64).reshape(self.C * self.B)
+        L = len(self.ctx.q) - 1
+        return self.ctx.encrypt(keys, self.ctx.encode(z, L, self.delta), stream_id)
+
+    def decrypt_grid(self, keys: ckks.KeyPair, ct: ckks.Ciphertext) -> np.ndarray:
+        z = self.ctx.decode(self.ctx.decrypt(keys, ct))
+        return z.reshape(self.C, self.H, self.W)
+
+    def decrypt_logits(self, keys: ckks.KeyPair, cts) -> np.ndarray:
+        return np.array([self.ctx.decode(self.ctx.decrypt(keys, c), 1)[0] for c in cts])
+
+    # ---------------------------------------------------------------- layers
+    def _per_block(self, v) -> np.ndarray:
+        return np.repeat(np.asarray(v, dtype=np.float64), self.B)
+
+    def _diag_slots(self, w: np.ndarray, j: int, t: int) -> np.ndarray:
+        """Slots of the plaintext for channel distance j and tap t."""
+        dh, dw = _TAPS[t]
+        wj = w[np.arange(self.C), (np.arange(self.C) + j) % self.C, dh + 1, dw + 1]  # [C]: output o
+        return (wj[:, None, None] * self.masks[t][None]).reshape(-1)
+
+    def conv(self, keys, x: ckks.Ciphertext, w: np.ndarray, b: np.ndarray, name: str = "conv",
+             stream=None) -> ckks.Ciphertext:
+        ctx = self.ctx
+        lv = x.level
+        pt_scale = float(ctx.q[lv]) * self.delta / x.scale
+        steps = self.rotation_steps()
+        rots = ckks.rotate_many(ctx, keys, [x], steps, stream=stream)
+        pts = [self._pt((name, j, t), lv, pt_scale, lambda j=j, t=t: self._diag_slots(w, j, t), stream)
+               for j in range(self.C) for t in range(9)]
+        acc = None
+        for a in range(0, len(steps), _MAC_TERMS):
+            part = ckks.mac_plain_many(ctx, rots[a:a + _MAC_TERMS], pts[a:a + _MAC_TERMS], stream=stream)[0]
+            acc = part if acc is None else ctx.add(acc, part, stream=stream)
+        acc = ctx.add_plain(acc, self._pt((name, "bias"), lv, acc.scale, lambda: self._per_block(b), stream),
+                            stream=stream)
+        return ctx.rescale(acc, stream=stream)
+
+    def act(self, keys, x: ckks.Ciphertext, b: np.ndarray, c: np.ndarray, name: str = "act",
+            stream=None) -> ckks.Ciphertext:
+        ctx = self.ctx
+        sq = ckks.mul_relin_many(ctx, keys, [x], [x], stream=stream)[0]
+        lin = ctx.mul_plain(x, self._pt((name, "b"), x.level, x.scale, lambda: self._per_block(b), stream),
+                            stream=stream)
+        y = ctx.add(sq, lin, stream=stream)
+        y = ctx.add_plain(y, self._pt((name, "c"), x.level, y.scale, lambda: self._per_block(c), stream),
+                          stream=stream)
+        return ctx.rescale(y, stream=stream)
+
+    def pool(self, keys, x: ckks.Ciphertext, stream=None) -> ckks.Ciphertext:
+        ctx = self.ctx
+        for i in range(self.logB):
+            x = ctx.add(x, ctx.rotate(keys, x, [1 << i], stream=stream)[0], stream=stream)
+        return x
+
+    def dense(self, keys, x: ckks.Ciphertext, w: np.ndarray, bias: np.ndarray, name: str = "fc",
+              stream=None) -> list:
+        ctx = self.ctx
+        lv = x.level
+        pt_scale = float(ctx.q[lv]) * self.delta / x.scale
+
+        def at(pos, v):
+            z = np.zeros(self.slots)
+            z[pos] = v
+            return z
+
+        outs = []
+        for k in range(w.shape[0]):
+            wk = self._pt((name, k), lv, pt_scale, lambda k=k: at(slice(None, None, self.B), w[k]), stream)
+            y = ctx.mul_plain(x, wk, stream=stream)
+            for i in range(self.logC):
+                y = ctx.add(y, ctx.rotate(keys, y, [self.B << i], stream=stream)[0], stream=stream)
+            bk = self._pt((name, "bias", k), lv, y.scale, lambda k=k: at(0, bias[k]), stream)
+            y = ctx.add_plain(y, bk, stream=stream)
+            outs.append(ctx.rescale(y, stream=stream))
+        return outs
+
+    def run(self, keys, x: ckks.Ciphertext, stream=None) -> dict:
+        """Outputs of every stage: conv1, act, conv2, pool and logits (one
+        ciphertext per class, the logit at slot 0)."""
+        s = self.spec
+        out = {"conv1": self.conv(keys, x, s["conv1_w"], s["conv1_b"], "conv1", stream)}
+        out["act"] = self.act(keys, out["conv1"], s["act_b"], s["act_c"], "act", stream)
+        out["conv2"] = self.conv(keys, out["act"], s["conv2_w"], s["conv2_b"], "conv2", stream)
+        out["pool"] = self.pool(keys, out["conv2"], stream)
+        out["logits"] = self.dense(keys, out["pool"], s["fc_w"], s["fc_b"], "fc", stream)
+        return out
