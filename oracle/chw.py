@@ -6,9 +6,10 @@ this module; the product path never does.
 Layout (Section 5.1, Data Layout, the alternative to the HW layout that
 packs several channels into one ciphertext): every channel of an image in one
 ciphertext, channel c's H x W grid in the slot block [c B, (c + 1) B) with
-B = H W, pixel (r, x) at slot c B + r W + x.  The C blocks fill the N/2
-slots (C B = N/2), so a rotation by a multiple of B turns the channel index
-cyclically.
+B = H W, pixel (r, x) at slot c B + r W + x.  When C B is less than N/2
+the C blocks are repeated to fill the N/2 slots (R = N / (2 C B) copies,
+every slot vector of the network periodic with period C B), so a rotation by
+a multiple of B turns the channel index cyclically.
 
 Convolution (3x3, 'same', stride 1, C -> C channels) is the diagonal form of
 a matrix-vector product over channels (Halevi and Shoup's diagonal
@@ -50,10 +51,11 @@ class OracleChw:
         self.C, self.H, self.W = spec["image"]
         self.B = self.H * self.W
         self.n = o.N // 2
-        if self.C * self.B != self.n:
-            raise ValueError("the CHW layout here fills the slots: C H W must equal N/2")
         if self.C & (self.C - 1) or self.B & (self.B - 1):
             raise ValueError("C and H W must be powers of two (doubling rotations)")
+        if self.C * self.B > self.n:
+            raise ValueError("C H W must not exceed N/2")
+        self.R = self.n // (self.C * self.B)  # copies of the channel blocks
 
     # --------------------------------------------------------------- steps
     def conv_steps(self) -> list[int]:
@@ -65,11 +67,15 @@ class OracleChw:
         return sorted(set(self.conv_steps()) | set(pool) | set(chan))
 
     # -------------------------------------------------------------- client
+    def _tile(self, z: np.ndarray) -> np.ndarray:
+        """The first C B slots repeated over all N/2."""
+        return np.tile(z[:self.C * self.B], self.R)
+
     def slots_of(self, img: np.ndarray) -> np.ndarray:
         z = np.zeros(self.n)
         for c in range(self.C):
             z[c * self.B:(c + 1) * self.B] = np.asarray(img[c], dtype=np.float64).reshape(-1)
-        return z
+        return self._tile(z)
 
     def encrypt_image(self, sk: SecretKey, img: np.ndarray, stream_id: int) -> Ct:
         pt = self.o.encode(self.slots_of(img), self.o.L, self.delta)
@@ -77,7 +83,7 @@ class OracleChw:
 
     def grid_of(self, z: np.ndarray) -> np.ndarray:
         """[C][H][W] view of a decoded slot vector."""
-        return np.asarray(z[:self.n]).reshape(self.C, self.H, self.W)
+        return np.asarray(z[:self.C * self.B]).reshape(self.C, self.H, self.W)
 
     # -------------------------------------------------------------- layers
     def _diagonal(self, w: np.ndarray, d: int, dh: int, dw: int) -> np.ndarray:
@@ -90,13 +96,13 @@ class OracleChw:
                 for x in range(self.W):
                     if 0 <= x + dw < self.W:
                         z[oc * self.B + r * self.W + x] = w[oc, ic, dh + 1, dw + 1]
-        return z
+        return self._tile(z)
 
     def _blocks(self, v: np.ndarray) -> np.ndarray:
         z = np.zeros(self.n)
         for c in range(self.C):
             z[c * self.B:(c + 1) * self.B] = v[c]
-        return z
+        return self._tile(z)
 
     def conv(self, x: Ct, w: np.ndarray, b: np.ndarray, gk: dict) -> Ct:
         o = self.o

@@ -3,8 +3,9 @@
 Section 5.1 (Data Layout) names this packing as the alternative to the HW
 layout the paper keeps.  Channel c's H x W grid takes the slot block
 [c B, (c + 1) B), B = H W, pixel (r, x) at slot c B + r W + x, and the C
-blocks fill the N/2 slots, so a rotation by j B moves channel c + j onto
-block c (channel indices mod C).
+blocks fill the N/2 slots, repeated N / (2 C B) times when they are fewer
+(every slot vector periodic with period C B), so a rotation by j B moves
+channel c + j onto block c (channel indices mod C).
 
 A 3x3 'same' convolution from C to C channels is then the diagonal method
 (Halevi and Shoup) over channels: for each channel distance j < C and tap
@@ -48,10 +49,11 @@ class ChwNetwork:
         self.C, self.H, self.W = spec["image"]
         self.B = self.H * self.W
         self.slots = ctx.N // 2
-        if self.C * self.B != self.slots:
-            raise ValueError(f"CHW layout: C H W = {self.C * self.B} must equal N/2 = {self.slots}")
         if self.C & (self.C - 1) or self.B & (self.B - 1):
             raise ValueError("CHW layout: C and H W must be powers of two")
+        if self.C * self.B > self.slots:
+            raise ValueError(f"CHW layout: C H W = {self.C * self.B} exceeds N/2 = {self.slots}")
+        self.copies = self.slots // (self.C * self.B)
         self.logB, self.logC = self.B.bit_length() - 1, self.C.bit_length() - 1
         # valid-source masks per tap, [9][H][W]
         r = np.arange(self.H)[:, None]
@@ -84,12 +86,12 @@ class ChwNetwork:
 
     # ---------------------------------------------------------------- client
     def encrypt_image(self, keys: ckks.KeyPair, img: np.ndarray, stream_id: int) -> ckks.Ciphertext:
-        z = np.asarray(img, dtype=np.float64).reshape(self.C * self.B)
+        z = np.tile(np.asarray(img, dtype=np.float64).reshape(self.C * self.B), self.copies)
         L = len(self.ctx.q) - 1
         return self.ctx.encrypt(keys, self.ctx.encode(z, L, self.delta), stream_id)
 
     def decrypt_grid(self, keys: ckks.KeyPair, ct: ckks.Ciphertext) -> np.ndarray:
-        z = self.ctx.decode(self.ctx.decrypt(keys, ct))
+        z = self.ctx.decode(self.ctx.decrypt(keys, ct), self.C * self.B)
         return z.reshape(self.C, self.H, self.W)
 
     def decrypt_logits(self, keys: ckks.KeyPair, cts) -> np.ndarray:
@@ -97,13 +99,13 @@ class ChwNetwork:
 
     # ---------------------------------------------------------------- layers
     def _per_block(self, v) -> np.ndarray:
-        return np.repeat(np.asarray(v, dtype=np.float64), self.B)
+        return np.tile(np.repeat(np.asarray(v, dtype=np.float64), self.B), self.copies)
 
     def _diag_slots(self, w: np.ndarray, j: int, t: int) -> np.ndarray:
         """Slots of the plaintext for channel distance j and tap t."""
         dh, dw = _TAPS[t]
         wj = w[np.arange(self.C), (np.arange(self.C) + j) % self.C, dh + 1, dw + 1]  # [C]: output o
-        return (wj[:, None, None] * self.masks[t][None]).reshape(-1)
+        return np.tile((wj[:, None, None] * self.masks[t][None]).reshape(-1), self.copies)
 
     def conv(self, keys, x: ckks.Ciphertext, w: np.ndarray, b: np.ndarray, name: str = "conv",
              stream=None) -> ckks.Ciphertext:
@@ -152,7 +154,7 @@ class ChwNetwork:
 
         outs = []
         for k in range(w.shape[0]):
-            wk = self._pt((name, k), lv, pt_scale, lambda k=k: at(slice(None, None, self.B), w[k]), stream)
+            wk = self._pt((name, k), lv, pt_scale, lambda k=k: at(slice(0, self.C * self.B, self.B), w[k]), stream)
             y = ctx.mul_plain(x, wk, stream=stream)
             for i in range(self.logC):
                 y = ctx.add(y, ctx.rotate(keys, y, [self.B << i], stream=stream)[0], stream=stream)

@@ -5,7 +5,8 @@ definition of the same network (oracle/chw.py): the input and every stage's
 output ciphertext bit-identical, with equal levels and scales, and the
 decrypted logits within 1e-6 of the float64 forward.  Shapes: 8 channels of
 16 x 16 (72 rotations per convolution, two MAC calls) and 32 channels of
-8 x 8 (288 rotations, five MAC calls, the last one ragged)."""
+8 x 8 (288 rotations, five MAC calls, the last one ragged) fill the 2048
+slots of N = 2^12; 4 channels of 16 x 16 fill half of them, repeated twice."""
 import numpy as np
 import pytest
 
@@ -16,7 +17,7 @@ from workloads.params import chw_chain
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("C,H,W", [(8, 16, 16), (32, 8, 8)])
+@pytest.mark.parametrize("C,H,W", [(8, 16, 16), (32, 8, 8), (4, 16, 16)])
 def test_chw_network_bit_exact_with_oracle(C, H, W):
     from oracle.chw import OracleChw
     from oracle.ckks import Oracle

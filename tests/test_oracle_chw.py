@@ -2,8 +2,9 @@
 forward: the decrypted output of every stage (two 'same' convolutions in the
 diagonal form over channels, the quadratic activation, sum pooling, the
 dense layer) matches the forward's tensors, and the forward's convolution
-matches scipy's 2-D correlation.  A diagonal taken the wrong way round (input
-channel o - d instead of o + d) is caught."""
+matches scipy's 2-D correlation, also with the channel blocks repeated (4
+channels of 16 x 16 fill half the slots, so two copies).  A diagonal taken
+the wrong way round (input channel o - d instead of o + d) is caught."""
 import numpy as np
 import pytest
 from scipy.signal import correlate2d
@@ -36,7 +37,7 @@ def _setup(C, H, W, seed=5):
     return o, spec, net, sk, gk, img
 
 
-@pytest.mark.parametrize("C,H,W", [(8, 16, 16), (2, 32, 32)])
+@pytest.mark.parametrize("C,H,W", [(8, 16, 16), (2, 32, 32), (4, 16, 16)])
 def test_chw_network_decrypts_to_the_forward(C, H, W):
     o, spec, net, sk, gk, img = _setup(C, H, W)
     out = net.run(net.encrypt_image(sk, img, 100), o.relin_key(sk), gk)
