@@ -7,20 +7,24 @@ Layout (Section 5.1, Data Layout, the alternative to the HW layout that
 packs several channels into one ciphertext): every channel of an image in one
 ciphertext, channel c's H x W grid in the slot block [c B, (c + 1) B) with
 B = H W, pixel (r, x) at slot c B + r W + x.  When C B is less than N/2
-the C blocks are repeated to fill the N/2 slots (R = N / (2 C B) copies,
-every slot vector of the network periodic with period C B), so a rotation by
-a multiple of B turns the channel index cyclically.
+the C blocks are repeated to fill the N/2 slots (every slot vector of a
+C-channel tensor periodic with period C B), so a rotation by j B brings
+channel (c + j) mod C onto block c.
 
-Convolution (3x3, 'same', stride 1, C -> C channels) is the diagonal form of
-a matrix-vector product over channels (Halevi and Shoup's diagonal
-method): with s_t = dh W + dw the slot offset of tap t = (dh + 1, dw + 1),
+Convolution (3x3, 'same', stride 1, C_in -> C_out channels, both powers of
+two) is the diagonal form of a matrix-vector product over channels (Halevi
+and Shoup's diagonal method): with s_t = dh W + dw the slot offset of tap
+t = (dh + 1, dw + 1),
 
-    y = sum_{d < C} sum_{t < 9} P_{d,t} * Rot(x, d B + s_t),
+    y = sum_{d < C_in} sum_{t < 9} P_{d,t} * Rot(x, d B + s_t),
 
-where Rot is the left rotation of the slots and P_{d,t} holds, on output
-block o, the weight w[o][(o + d) mod C][t] at every pixel (r, x) whose
-source pixel (r + dh, x + dw) lies on the grid and zero elsewhere (the zero
-padding of 'same').  The bias (b[o] on block o) is added before the rescale.
+where Rot is the left rotation of the slots and P_{d,t} holds, on every
+block o of the slot vector, the weight w[o mod C_out][(o + d) mod C_in][t]
+at every pixel (r, x) whose source pixel (r + dh, x + dw) lies on the grid,
+and zero elsewhere (the zero padding of 'same').  As d runs over C_in
+values, (o + d) mod C_in runs over every input channel, so block o receives
+output channel o mod C_out: the output is periodic with period C_out B.  The
+bias (b[o mod C_out] on block o) is added before the rescale.
 Plaintexts are encoded at scale q_l Delta / s for an input at level l and
 scale s, so every layer's output returns to scale Delta (up to the float
 arithmetic of the scales).
@@ -28,8 +32,9 @@ arithmetic of the scales).
 The other layers: the monic quadratic activation x^2 + b x + c (Section 2.3)
 as Relin(x (x) x) + x * P_b + P_c (b[c], c[c] on block c; P_b at the input's
 scale s, P_c at s^2), then a rescale; global sum pooling as log2(B) doubling
-rotations (slot c B then holds the sum of block c); the dense layer, one
-ciphertext per class k: x * P_k with P_k = w[k][c] at slot c B, log2(C)
+rotations (slot c B then holds the sum of block c); the dense layer over C
+channels, one ciphertext per class k: x * P_k with P_k = w[k][c] at slot
+c B (c < C), log2(C)
 doubling rotations by multiples of B (slot 0 then holds the logit), the bias
 at slot 0, a rescale.
 """
@@ -51,64 +56,64 @@ class OracleChw:
         self.C, self.H, self.W = spec["image"]
         self.B = self.H * self.W
         self.n = o.N // 2
-        if self.C & (self.C - 1) or self.B & (self.B - 1):
-            raise ValueError("C and H W must be powers of two (doubling rotations)")
-        if self.C * self.B > self.n:
-            raise ValueError("C H W must not exceed N/2")
-        self.R = self.n // (self.C * self.B)  # copies of the channel blocks
+        self.nblk = self.n // self.B  # slot blocks
+        self.widths = [self.C, spec["conv1_w"].shape[0], spec["conv2_w"].shape[0]]
+        for c in self.widths + [self.B]:
+            if c & (c - 1):
+                raise ValueError("channel counts and H W must be powers of two (doubling rotations)")
+        if max(self.widths) * self.B > self.n:
+            raise ValueError("channels x H x W must not exceed N/2")
 
     # --------------------------------------------------------------- steps
-    def conv_steps(self) -> list[int]:
-        return [d * self.B + dh * self.W + dw for d in range(self.C) for (dh, dw) in _taps()]
+    def conv_steps(self, c_in: int) -> list[int]:
+        return [d * self.B + dh * self.W + dw for d in range(c_in) for (dh, dw) in _taps()]
 
     def steps(self) -> list[int]:
         pool = [1 << j for j in range(self.B.bit_length() - 1)]
-        chan = [self.B << j for j in range(self.C.bit_length() - 1)]
-        return sorted(set(self.conv_steps()) | set(pool) | set(chan))
+        chan = [self.B << j for j in range(self.widths[2].bit_length() - 1)]
+        return sorted(set(self.conv_steps(self.widths[0])) | set(self.conv_steps(self.widths[1])) | set(pool)
+                      | set(chan))
 
     # -------------------------------------------------------------- client
-    def _tile(self, z: np.ndarray) -> np.ndarray:
-        """The first C B slots repeated over all N/2."""
-        return np.tile(z[:self.C * self.B], self.R)
-
     def slots_of(self, img: np.ndarray) -> np.ndarray:
         z = np.zeros(self.n)
-        for c in range(self.C):
-            z[c * self.B:(c + 1) * self.B] = np.asarray(img[c], dtype=np.float64).reshape(-1)
-        return self._tile(z)
+        for blk in range(self.nblk):
+            z[blk * self.B:(blk + 1) * self.B] = np.asarray(img[blk % self.C], dtype=np.float64).reshape(-1)
+        return z
 
     def encrypt_image(self, sk: SecretKey, img: np.ndarray, stream_id: int) -> Ct:
         pt = self.o.encode(self.slots_of(img), self.o.L, self.delta)
         return self.o.encrypt(pt, sk, stream_id)
 
-    def grid_of(self, z: np.ndarray) -> np.ndarray:
-        """[C][H][W] view of a decoded slot vector."""
-        return np.asarray(z[:self.C * self.B]).reshape(self.C, self.H, self.W)
+    def grid_of(self, z: np.ndarray, channels: int) -> np.ndarray:
+        """[channels][H][W] view of a decoded slot vector."""
+        return np.asarray(z[:channels * self.B]).reshape(channels, self.H, self.W)
 
     # -------------------------------------------------------------- layers
     def _diagonal(self, w: np.ndarray, d: int, dh: int, dw: int) -> np.ndarray:
+        c_out, c_in = w.shape[0], w.shape[1]
         z = np.zeros(self.n)
-        for oc in range(self.C):
-            ic = (oc + d) % self.C
+        for blk in range(self.nblk):
+            oc, ic = blk % c_out, (blk + d) % c_in
             for r in range(self.H):
                 if not 0 <= r + dh < self.H:
                     continue
                 for x in range(self.W):
                     if 0 <= x + dw < self.W:
-                        z[oc * self.B + r * self.W + x] = w[oc, ic, dh + 1, dw + 1]
-        return self._tile(z)
+                        z[blk * self.B + r * self.W + x] = w[oc, ic, dh + 1, dw + 1]
+        return z
 
     def _blocks(self, v: np.ndarray) -> np.ndarray:
         z = np.zeros(self.n)
-        for c in range(self.C):
-            z[c * self.B:(c + 1) * self.B] = v[c]
-        return self._tile(z)
+        for blk in range(self.nblk):
+            z[blk * self.B:(blk + 1) * self.B] = v[blk % len(v)]
+        return z
 
     def conv(self, x: Ct, w: np.ndarray, b: np.ndarray, gk: dict) -> Ct:
         o = self.o
         pt_scale = float(o.q[x.level]) * self.delta / x.scale
         acc = None
-        for d in range(self.C):
+        for d in range(w.shape[1]):
             for (dh, dw) in _taps():
                 step = d * self.B + dh * self.W + dw
                 g = o.galois_elt(step)
@@ -136,12 +141,13 @@ class OracleChw:
     def dense(self, x: Ct, w: np.ndarray, bias: np.ndarray, gk: dict) -> list[Ct]:
         o = self.o
         pt_scale = float(o.q[x.level]) * self.delta / x.scale
+        C = w.shape[1]
         outs = []
         for k in range(w.shape[0]):
             z = np.zeros(self.n)
-            z[np.arange(self.C) * self.B] = w[k]
+            z[np.arange(C) * self.B] = w[k]
             y = o.mul_plain(x, o.encode(z, x.level, pt_scale))
-            for j in range(self.C.bit_length() - 1):
+            for j in range(C.bit_length() - 1):
                 step = self.B << j
                 y = o.add(y, o.rotate(y, step, gk[o.galois_elt(step)]))
             zb = np.zeros(self.n)

@@ -2,19 +2,22 @@
 
 Section 5.1 (Data Layout) names this packing as the alternative to the HW
 layout the paper keeps.  Channel c's H x W grid takes the slot block
-[c B, (c + 1) B), B = H W, pixel (r, x) at slot c B + r W + x, and the C
-blocks fill the N/2 slots, repeated N / (2 C B) times when they are fewer
-(every slot vector periodic with period C B), so a rotation by j B moves
-channel c + j onto block c (channel indices mod C).
+[c B, (c + 1) B), B = H W, pixel (r, x) at slot c B + r W + x; the N/2
+slots hold N / (2 B) blocks, block b carrying channel b mod C (a C-channel
+tensor is periodic with period C B), so a rotation by j B moves channel
+(c + j) mod C onto block c.
 
-A 3x3 'same' convolution from C to C channels is then the diagonal method
-(Halevi and Shoup) over channels: for each channel distance j < C and tap
-(dh, dw) one rotation of the input by j B + dh W + dw, and one plaintext
-that carries, on output block o, the weight from input channel (o + j) mod C
+A 3x3 'same' convolution from C_in to C_out channels (powers of two) is
+then the diagonal method (Halevi and Shoup) over channels: for each channel
+distance j < C_in and tap (dh, dw) one rotation of the input by
+j B + dh W + dw, and one plaintext that carries, on every block b, the
+weight of output channel b mod C_out from input channel (b + j) mod C_in
 for that tap wherever the tap's source pixel is on the grid (zero
-elsewhere: the zero padding).  Its 9 C rotations are one hoisted rotation
-group (one ModUp of the input), its 9 C products plaintext multiply-
-accumulates; the bias joins before the rescale.  The plaintexts are encoded
+elsewhere: the zero padding).  Over the C_in distances block b meets every
+input channel once, so it receives output channel b mod C_out and the output
+is again periodic.  The 9 C_in rotations are one hoisted rotation group (one
+ModUp of the input), the 9 C_in products plaintext multiply-accumulates; the
+bias joins before the rescale.  The plaintexts are encoded
 at scale q_l Delta / s for an input at level l and scale s, so every layer
 leaves scale Delta.
 
@@ -41,20 +44,22 @@ _MAC_TERMS = 64  # most terms of one ckc_mac_plain_many output
 
 
 class ChwNetwork:
-    """The network of workloads.nets.chw_spec (conv, activation, conv, sum
-    pooling, dense) on one context."""
+    """The network of workloads.nets.chw_spec (conv C -> C1, activation,
+    conv C1 -> C2, sum pooling, dense) on one context."""
 
     def __init__(self, ctx: ckks.Context, spec: dict, delta: float):
         self.ctx, self.spec, self.delta = ctx, spec, float(delta)
         self.C, self.H, self.W = spec["image"]
         self.B = self.H * self.W
         self.slots = ctx.N // 2
-        if self.C & (self.C - 1) or self.B & (self.B - 1):
-            raise ValueError("CHW layout: C and H W must be powers of two")
-        if self.C * self.B > self.slots:
-            raise ValueError(f"CHW layout: C H W = {self.C * self.B} exceeds N/2 = {self.slots}")
-        self.copies = self.slots // (self.C * self.B)
-        self.logB, self.logC = self.B.bit_length() - 1, self.C.bit_length() - 1
+        self.nblocks = self.slots // self.B
+        widths = (self.C, spec["conv1_w"].shape[0], spec["conv2_w"].shape[0])
+        if any(c & (c - 1) for c in widths) or self.B & (self.B - 1):
+            raise ValueError("CHW layout: channel counts and H W must be powers of two")
+        if max(widths) * self.B > self.slots:
+            raise ValueError(f"CHW layout: {max(widths)} channels of {self.B} slots exceed N/2 = {self.slots}")
+        self.widths = widths
+        self.logB = self.B.bit_length() - 1
         # valid-source masks per tap, [9][H][W]
         r = np.arange(self.H)[:, None]
         x = np.arange(self.W)[None, :]
@@ -71,51 +76,54 @@ class ChwNetwork:
         return self._pts[k]
 
     # ------------------------------------------------------------------ keys
-    def rotation_steps(self) -> list[int]:
-        """The conv group's steps (channel distance major, tap minor)."""
-        return [j * self.B + dh * self.W + dw for j in range(self.C) for dh, dw in _TAPS]
+    def rotation_steps(self, c_in: int) -> list[int]:
+        """A convolution's rotation group over c_in input channels (channel
+        distance major, tap minor)."""
+        return [j * self.B + dh * self.W + dw for j in range(c_in) for dh, dw in _TAPS]
 
     @property
     def steps(self) -> list[int]:
         """Every rotation step a run needs keys for (the identity excluded)."""
-        st = set(self.rotation_steps())
+        st = set(self.rotation_steps(self.widths[0])) | set(self.rotation_steps(self.widths[1]))
         st.update(1 << i for i in range(self.logB))
-        st.update(self.B << i for i in range(self.logC))
+        st.update(self.B << i for i in range(self.widths[2].bit_length() - 1))
         st.discard(0)
         return sorted(st)
 
     # ---------------------------------------------------------------- client
     def encrypt_image(self, keys: ckks.KeyPair, img: np.ndarray, stream_id: int) -> ckks.Ciphertext:
-        z = np.tile(np.asarray(img, dtype=np.float64).reshape(self.C * self.B), self.copies)
+        z = np.tile(np.asarray(img, dtype=np.float64).reshape(self.C * self.B), self.slots // (self.C * self.B))
         L = len(self.ctx.q) - 1
         return self.ctx.encrypt(keys, self.ctx.encode(z, L, self.delta), stream_id)
 
-    def decrypt_grid(self, keys: ckks.KeyPair, ct: ckks.Ciphertext) -> np.ndarray:
-        z = self.ctx.decode(self.ctx.decrypt(keys, ct), self.C * self.B)
-        return z.reshape(self.C, self.H, self.W)
+    def decrypt_grid(self, keys: ckks.KeyPair, ct: ckks.Ciphertext, channels: int) -> np.ndarray:
+        z = self.ctx.decode(self.ctx.decrypt(keys, ct), channels * self.B)
+        return z.reshape(channels, self.H, self.W)
 
     def decrypt_logits(self, keys: ckks.KeyPair, cts) -> np.ndarray:
         return np.array([self.ctx.decode(self.ctx.decrypt(keys, c), 1)[0] for c in cts])
 
     # ---------------------------------------------------------------- layers
     def _per_block(self, v) -> np.ndarray:
-        return np.tile(np.repeat(np.asarray(v, dtype=np.float64), self.B), self.copies)
+        v = np.asarray(v, dtype=np.float64)
+        return np.repeat(v[np.arange(self.nblocks) % len(v)], self.B)
 
     def _diag_slots(self, w: np.ndarray, j: int, t: int) -> np.ndarray:
         """Slots of the plaintext for channel distance j and tap t."""
         dh, dw = _TAPS[t]
-        wj = w[np.arange(self.C), (np.arange(self.C) + j) % self.C, dh + 1, dw + 1]  # [C]: output o
-        return np.tile((wj[:, None, None] * self.masks[t][None]).reshape(-1), self.copies)
+        blk = np.arange(self.nblocks)
+        wb = w[blk % w.shape[0], (blk + j) % w.shape[1], dh + 1, dw + 1]  # weight per block
+        return (wb[:, None, None] * self.masks[t][None]).reshape(-1)
 
     def conv(self, keys, x: ckks.Ciphertext, w: np.ndarray, b: np.ndarray, name: str = "conv",
              stream=None) -> ckks.Ciphertext:
         ctx = self.ctx
         lv = x.level
         pt_scale = float(ctx.q[lv]) * self.delta / x.scale
-        steps = self.rotation_steps()
+        steps = self.rotation_steps(w.shape[1])
         rots = ckks.rotate_many(ctx, keys, [x], steps, stream=stream)
         pts = [self._pt((name, j, t), lv, pt_scale, lambda j=j, t=t: self._diag_slots(w, j, t), stream)
-               for j in range(self.C) for t in range(9)]
+               for j in range(w.shape[1]) for t in range(9)]
         acc = None
         for a in range(0, len(steps), _MAC_TERMS):
             part = ckks.mac_plain_many(ctx, rots[a:a + _MAC_TERMS], pts[a:a + _MAC_TERMS], stream=stream)[0]
@@ -152,11 +160,12 @@ class ChwNetwork:
             z[pos] = v
             return z
 
+        C = w.shape[1]
         outs = []
         for k in range(w.shape[0]):
-            wk = self._pt((name, k), lv, pt_scale, lambda k=k: at(slice(0, self.C * self.B, self.B), w[k]), stream)
+            wk = self._pt((name, k), lv, pt_scale, lambda k=k: at(slice(0, C * self.B, self.B), w[k]), stream)
             y = ctx.mul_plain(x, wk, stream=stream)
-            for i in range(self.logC):
+            for i in range(C.bit_length() - 1):
                 y = ctx.add(y, ctx.rotate(keys, y, [self.B << i], stream=stream)[0], stream=stream)
             bk = self._pt((name, "bias", k), lv, y.scale, lambda k=k: at(0, bias[k]), stream)
             y = ctx.add_plain(y, bk, stream=stream)

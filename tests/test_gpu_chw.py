@@ -6,7 +6,8 @@ output ciphertext bit-identical, with equal levels and scales, and the
 decrypted logits within 1e-6 of the float64 forward.  Shapes: 8 channels of
 16 x 16 (72 rotations per convolution, two MAC calls) and 32 channels of
 8 x 8 (288 rotations, five MAC calls, the last one ragged) fill the 2048
-slots of N = 2^12; 4 channels of 16 x 16 fill half of them, repeated twice."""
+slots of N = 2^12; 4 channels of 16 x 16 fill half of them, repeated twice;
+and convolutions that widen and narrow the channels (4 -> 8 -> 2)."""
 import numpy as np
 import pytest
 
@@ -17,8 +18,8 @@ from workloads.params import chw_chain
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("C,H,W", [(8, 16, 16), (32, 8, 8), (4, 16, 16)])
-def test_chw_network_bit_exact_with_oracle(C, H, W):
+@pytest.mark.parametrize("C,C1,C2,H,W", [(8, 8, 8, 16, 16), (32, 32, 32, 8, 8), (4, 4, 4, 16, 16), (4, 8, 2, 16, 16)])
+def test_chw_network_bit_exact_with_oracle(C, C1, C2, H, W):
     from oracle.chw import OracleChw
     from oracle.ckks import Oracle
     from oracle.forward import forward_chw
@@ -26,8 +27,8 @@ def test_chw_network_bit_exact_with_oracle(C, H, W):
     from paper_2509_22857_amd.ckks import Context
     ps = chw_chain(12, 4)
     D = 2.0 ** ps.delta_log2
-    spec = chw_spec(7, C=C, H=H, W=W, classes=4)
-    print(f"[chw] N=2^12 C={C} H={H} W={W}", flush=True)
+    spec = chw_spec(7, C=C, H=H, W=W, classes=4, C1=C1, C2=C2)
+    print(f"[chw] N=2^12 channels {C}-{C1}-{C2} H={H} W={W}", flush=True)
     ctx = Context.from_params(ps)
     net = ChwNetwork(ctx, spec, D)
     keys = ctx.keygen(21, net.steps)

@@ -302,20 +302,23 @@ def act_dense_spec(seed: int, C: int, M: int, classes: int, H: int = 8, W: int =
                 layout=dict(block=block, row_stride=W), layers=layers, k=0)
 
 
-def chw_spec(seed: int, C: int = 8, H: int = 16, W: int = 16, classes: int = 4) -> dict:
+def chw_spec(seed: int, C: int = 8, H: int = 16, W: int = 16, classes: int = 4, C1: int | None = None,
+             C2: int | None = None) -> dict:
     """A small network for the CHW layout (every channel of an image in one
-    ciphertext): 3x3 'same' convolution C -> C (weights normal(0, 1 / (3 sqrt
-    C)), bias uniform in [-0.2, 0.2]), monic quadratic activation (b, c
-    uniform in [-0.5, 0.5] per channel), a second such convolution, global sum
-    pooling and the dense layer (weights normal(0, 0.05) / (H W), bias
-    normal(0, 0.1)).  Input images have C channels of H x W pixels."""
+    ciphertext): 3x3 'same' convolution C -> C1 (weights normal(0, 1 / (3
+    sqrt(in channels))), bias uniform in [-0.2, 0.2]), monic quadratic
+    activation (b, c uniform in [-0.5, 0.5] per channel), a second
+    convolution C1 -> C2, global sum pooling and the dense layer (weights
+    normal(0, 0.05) / (H W), bias normal(0, 0.1)).  Input images have C
+    channels of H x W pixels; C1 and C2 default to C."""
     g = rng(seed)
-    sd = 1.0 / (3.0 * np.sqrt(C))
-    return dict(name=f"chw_{C}x{H}x{W}_K{classes}", layout="chw", image=(C, H, W), classes=classes,
-                conv1_w=g.normal(0.0, sd, (C, C, 3, 3)), conv1_b=g.uniform(-0.2, 0.2, C),
-                act_b=g.uniform(-0.5, 0.5, C), act_c=g.uniform(-0.5, 0.5, C),
-                conv2_w=g.normal(0.0, sd, (C, C, 3, 3)), conv2_b=g.uniform(-0.2, 0.2, C),
-                fc_w=g.normal(0.0, 0.05, (classes, C)) / (H * W), fc_b=g.normal(0.0, 0.1, classes))
+    C1 = C if C1 is None else C1
+    C2 = C1 if C2 is None else C2
+    return dict(name=f"chw_{C}-{C1}-{C2}x{H}x{W}_K{classes}", layout="chw", image=(C, H, W), classes=classes,
+                conv1_w=g.normal(0.0, 1.0 / (3.0 * np.sqrt(C)), (C1, C, 3, 3)), conv1_b=g.uniform(-0.2, 0.2, C1),
+                act_b=g.uniform(-0.5, 0.5, C1), act_c=g.uniform(-0.5, 0.5, C1),
+                conv2_w=g.normal(0.0, 1.0 / (3.0 * np.sqrt(C1)), (C2, C1, 3, 3)), conv2_b=g.uniform(-0.2, 0.2, C2),
+                fc_w=g.normal(0.0, 0.05, (classes, C2)) / (H * W), fc_b=g.normal(0.0, 0.1, classes))
 
 
 def set_hoisting(spec: dict, hoist) -> dict:
