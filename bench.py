@@ -380,7 +380,7 @@ def run_chw(args):
         "ms_per_step": round(1e3 * dt / B, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": "chw_N65536", "channels": 32, "image": [32, 32], "classes": 10,
-                   "levels": len(ps.q) - 1, "rotations_per_conv": len(net.rotation_steps(spec["image"][0])),
+                   "levels": len(ps.q) - 1, "rotations_per_conv": sum(1 for t in net.rotation_steps(spec["image"][0]) if t),
                    "rotation_keys": len(net.steps), "key_GiB": round(keys.evk_bytes() / 2**30, 2)},
         "accuracy": {"max_abs_logit_err": err}}))
 

@@ -23,8 +23,16 @@ block o of the slot vector, the weight w[o mod C_out][(o + d) mod C_in][t]
 at every pixel (r, x) whose source pixel (r + dh, x + dw) lies on the grid,
 and zero elsewhere (the zero padding of 'same').  As d runs over C_in
 values, (o + d) mod C_in runs over every input channel, so block o receives
-output channel o mod C_out: the output is periodic with period C_out B.  The
-bias (b[o mod C_out] on block o) is added before the rescale.
+output channel o mod C_out: the output is periodic with period C_out B.  It
+is evaluated in baby-step giant-step order (the rotation by d B taken out of
+the inner sum; Q_{d,t} is P_{d,t} rotated right by d B, so that
+Rot(Q * Rot(x, s_t), d B) = P * Rot(x, d B + s_t)):
+
+    y = sum_{d < C_in} Rot(sum_{t < 9} Q_{d,t} * Rot(x, s_t), d B),
+
+8 rotations of x (one per tap off the centre) and C_in - 1 rotations of the
+inner sums, instead of 9 C_in - 1.  The bias (b[o mod C_out] on block o) is
+added before the rescale.
 Plaintexts are encoded at scale q_l Delta / s for an input at level l and
 scale s, so every layer's output returns to scale Delta (up to the float
 arithmetic of the scales).
@@ -66,7 +74,8 @@ class OracleChw:
 
     # --------------------------------------------------------------- steps
     def conv_steps(self, c_in: int) -> list[int]:
-        return [d * self.B + dh * self.W + dw for d in range(c_in) for (dh, dw) in _taps()]
+        """The baby steps (taps) and giant steps (channel distances)."""
+        return [dh * self.W + dw for (dh, dw) in _taps()] + [d * self.B for d in range(1, c_in)]
 
     def steps(self) -> list[int]:
         pool = [1 << j for j in range(self.B.bit_length() - 1)]
@@ -112,14 +121,17 @@ class OracleChw:
     def conv(self, x: Ct, w: np.ndarray, b: np.ndarray, gk: dict) -> Ct:
         o = self.o
         pt_scale = float(o.q[x.level]) * self.delta / x.scale
+        baby = [o.rotate(x, dh * self.W + dw, gk.get(o.galois_elt(dh * self.W + dw))) for (dh, dw) in _taps()]
         acc = None
         for d in range(w.shape[1]):
-            for (dh, dw) in _taps():
-                step = d * self.B + dh * self.W + dw
-                g = o.galois_elt(step)
-                rot = o.rotate(x, step, gk.get(g))
-                term = o.mul_plain(rot, o.encode(self._diagonal(w, d, dh, dw), x.level, pt_scale))
-                acc = term if acc is None else o.add(acc, term)
+            inner = None
+            for t, (dh, dw) in enumerate(_taps()):
+                q = np.roll(self._diagonal(w, d, dh, dw), d * self.B)  # q[i] = P[i - d B]
+                term = o.mul_plain(baby[t], o.encode(q, x.level, pt_scale))
+                inner = term if inner is None else o.add(inner, term)
+            if d:
+                inner = o.rotate(inner, d * self.B, gk[o.galois_elt(d * self.B)])
+            acc = inner if acc is None else o.add(acc, inner)
         acc = o.add_plain(acc, o.encode(self._blocks(b), x.level, acc.scale))
         return o.rescale(acc)
 

@@ -15,9 +15,12 @@ weight of output channel b mod C_out from input channel (b + j) mod C_in
 for that tap wherever the tap's source pixel is on the grid (zero
 elsewhere: the zero padding).  Over the C_in distances block b meets every
 input channel once, so it receives output channel b mod C_out and the output
-is again periodic.  The 9 C_in rotations are one hoisted rotation group (one
-ModUp of the input), the 9 C_in products plaintext multiply-accumulates; the
-bias joins before the rescale.  The plaintexts are encoded
+is again periodic.  The rotation by j B is taken out of each distance's sum
+(baby-step giant-step): the 9 tap rotations of the input are one hoisted
+rotation group (one ModUp), each distance j sums its 9 products with the
+plaintexts rotated right by j B in one plaintext multiply-accumulate, and
+that sum is rotated by j B; 8 + C_in - 1 rotations instead of 9 C_in - 1,
+and as many Galois keys.  The bias joins before the rescale.  The plaintexts are encoded
 at scale q_l Delta / s for an input at level l and scale s, so every layer
 leaves scale Delta.
 
@@ -40,7 +43,6 @@ import numpy as np
 from . import ckks
 
 _TAPS = [(dh, dw) for dh in (-1, 0, 1) for dw in (-1, 0, 1)]  # tap t = 3 (dh + 1) + (dw + 1)
-_MAC_TERMS = 64  # most terms of one ckc_mac_plain_many output
 
 
 class ChwNetwork:
@@ -77,9 +79,10 @@ class ChwNetwork:
 
     # ------------------------------------------------------------------ keys
     def rotation_steps(self, c_in: int) -> list[int]:
-        """A convolution's rotation group over c_in input channels (channel
-        distance major, tap minor)."""
-        return [j * self.B + dh * self.W + dw for j in range(c_in) for dh, dw in _TAPS]
+        """A convolution's rotations over c_in input channels: the 9 taps
+        (the centre is the identity), then the channel distances 1 .. c_in - 1
+        (multiples of B)."""
+        return [dh * self.W + dw for dh, dw in _TAPS] + [j * self.B for j in range(1, c_in)]
 
     @property
     def steps(self) -> list[int]:
@@ -120,14 +123,18 @@ class ChwNetwork:
         ctx = self.ctx
         lv = x.level
         pt_scale = float(ctx.q[lv]) * self.delta / x.scale
-        steps = self.rotation_steps(w.shape[1])
-        rots = ckks.rotate_many(ctx, keys, [x], steps, stream=stream)
-        pts = [self._pt((name, j, t), lv, pt_scale, lambda j=j, t=t: self._diag_slots(w, j, t), stream)
-               for j in range(w.shape[1]) for t in range(9)]
+        taps = [dh * self.W + dw for dh, dw in _TAPS]
+        baby = ckks.rotate_many(ctx, keys, [x], taps, stream=stream)
         acc = None
-        for a in range(0, len(steps), _MAC_TERMS):
-            part = ckks.mac_plain_many(ctx, rots[a:a + _MAC_TERMS], pts[a:a + _MAC_TERMS], stream=stream)[0]
-            acc = part if acc is None else ctx.add(acc, part, stream=stream)
+        for j in range(w.shape[1]):
+            # the plaintexts of distance j rotated right by j B (slot i holds
+            # slot i - j B), so that the sum's rotation by j B lines them up
+            pts = [self._pt((name, j, t), lv, pt_scale, lambda j=j, t=t: np.roll(self._diag_slots(w, j, t), j * self.B),
+                            stream) for t in range(9)]
+            inner = ckks.mac_plain_many(ctx, baby, pts, stream=stream)[0]
+            if j:
+                inner = ctx.rotate(keys, inner, [j * self.B], stream=stream)[0]
+            acc = inner if acc is None else ctx.add(acc, inner, stream=stream)
         acc = ctx.add_plain(acc, self._pt((name, "bias"), lv, acc.scale, lambda: self._per_block(b), stream),
                             stream=stream)
         return ctx.rescale(acc, stream=stream)

@@ -1,13 +1,13 @@
 """The CHW layout on the GPU (paper_2509_22857_amd/chw.py: every channel of
-an image in one ciphertext, convolutions in the diagonal form over channels
-as one hoisted rotation group and plaintext MACs) against the oracle's
-definition of the same network (oracle/chw.py): the input and every stage's
-output ciphertext bit-identical, with equal levels and scales, and the
-decrypted logits within 1e-6 of the float64 forward.  Shapes: 8 channels of
-16 x 16 (72 rotations per convolution, two MAC calls) and 32 channels of
-8 x 8 (288 rotations, five MAC calls, the last one ragged) fill the 2048
-slots of N = 2^12; 4 channels of 16 x 16 fill half of them, repeated twice;
-and convolutions that widen and narrow the channels (4 -> 8 -> 2)."""
+an image in one ciphertext, convolutions in the diagonal form over channels,
+evaluated baby-step giant-step: one hoisted group of the 9 tap rotations,
+one 9-term plaintext MAC and one rotation per channel distance) against the
+oracle's definition of the same network (oracle/chw.py): the input and every
+stage's output ciphertext bit-identical, with equal levels and scales, and
+the decrypted logits within 1e-6 of the float64 forward.  Shapes: 8 channels
+of 16 x 16 and 32 channels of 8 x 8 fill the 2048 slots of N = 2^12; 4
+channels of 16 x 16 fill half of them, repeated twice; and convolutions that
+widen and narrow the channels (4 -> 8 -> 2)."""
 import numpy as np
 import pytest
 
